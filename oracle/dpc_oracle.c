@@ -1,0 +1,650 @@
+/*
+ * dpc_oracle.c -- plain FP64 CPU oracle for the PECANN density-peaks hot path
+ * (Yu, Engels, Huang, Shun, "PECANN: Parallel Efficient Clustering with
+ * Graph-Based Approximate Nearest Neighbor Search", arXiv 2312.03940).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  The GPU library never
+ * includes, links or calls it; the two share no source, header or table.
+ *
+ * Every routine is either the plain definition written out (brute force, FP64,
+ * distances by direct differences -- never the |x|^2+|y|^2-2x.y expansion) or,
+ * where the method is itself a heuristic (greedy beam search, robust prune,
+ * batched Vamana insertion, the doubling rounds), the algorithm's steps in the
+ * paper's order.  Nothing is blocked, fused or reordered beyond that.
+ * OpenMP is used only to run independent queries side by side; each query's
+ * arithmetic is sequential and deterministic.
+ *
+ * Conventions (readings of the paper that it leaves open; each is listed with
+ * its justification in the design notes):
+ *   - a point's k nearest neighbours exclude the point itself (the worked
+ *     example of Sec. 3, step 2, names c as the nearest neighbour of a);
+ *   - every "closest"/"smallest" order is (distance, index) ascending, so
+ *     distance ties go to the lower index;
+ *   - the density rank is a total order: i ranks above j iff D_k(i) < D_k(j),
+ *     or they are equal and i < j (Sec. 3, step 3, ranks b, c, a, d, f, e);
+ *   - "higher density" in Def. 1 and Alg. 3 means "strictly higher in that
+ *     rank" (the worked example's dependents c->b and f->d need this);
+ *   - noise is rho < rho_min, strictly (Sec. 2.1 and Sec. 4.2);
+ *   - labels are the index of the root reached along dependent pointers.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { ODT_F32 = 0, ODT_U8 = 1 };
+enum { OM_L2 = 0, OM_COSINE = 1 };
+
+typedef struct {
+  const void *x;   /* n rows, row i starts at element i*stride */
+  int64_t n;
+  int32_t d;
+  int32_t dtype;   /* ODT_F32 or ODT_U8 */
+  int32_t metric;  /* OM_L2 or OM_COSINE */
+  int64_t stride;  /* elements between consecutive rows */
+} opoints;
+
+/* ------------------------------------------------------------------------ */
+/* Distance D(x_i, x_j) (Sec. 2.1; Euclidean in the paper's experiments).    */
+/* L2:     sqrt(sum_t (x_it - x_jt)^2), by direct differences.               */
+/* cosine: 1 - x_i.x_j / (|x_i| |x_j|); a zero vector is at distance 1.      */
+/* u8 rows are integers, so their squared L2 distance is summed exactly in   */
+/* int64 before the single FP64 square root.                                 */
+/* ------------------------------------------------------------------------ */
+static double dist_l2_f32(const float *a, const float *b, int32_t d) {
+  /* eight interleaved partial sums: a fixed, deterministic summation order */
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int32_t t = 0;
+  for (; t + 8 <= d; t += 8)
+    for (int u = 0; u < 8; ++u) {
+      double e = (double)a[t + u] - (double)b[t + u];
+      s[u] += e * e;
+    }
+  for (; t < d; ++t) {
+    double e = (double)a[t] - (double)b[t];
+    s[0] += e * e;
+  }
+  double tot = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  return sqrt(tot);
+}
+
+static double dist_l2_u8(const uint8_t *a, const uint8_t *b, int32_t d) {
+  int64_t s = 0;
+  for (int32_t t = 0; t < d; ++t) {
+    int32_t e = (int32_t)a[t] - (int32_t)b[t];
+    s += (int64_t)(e * e);
+  }
+  return sqrt((double)s);
+}
+
+static double dist_cos_f32(const float *a, const float *b, int32_t d) {
+  double dot = 0, na = 0, nb = 0;
+  for (int32_t t = 0; t < d; ++t) {
+    double u = a[t], v = b[t];
+    dot += u * v;
+    na += u * u;
+    nb += v * v;
+  }
+  if (na == 0.0 || nb == 0.0) return 1.0;
+  return 1.0 - dot / (sqrt(na) * sqrt(nb));
+}
+
+static double dist_cos_u8(const uint8_t *a, const uint8_t *b, int32_t d) {
+  int64_t dot = 0, na = 0, nb = 0;
+  for (int32_t t = 0; t < d; ++t) {
+    int64_t u = a[t], v = b[t];
+    dot += u * v;
+    na += u * u;
+    nb += v * v;
+  }
+  if (na == 0 || nb == 0) return 1.0;
+  return 1.0 - (double)dot / (sqrt((double)na) * sqrt((double)nb));
+}
+
+static double D(const opoints *P, int64_t i, int64_t j) {
+  if (P->dtype == ODT_U8) {
+    const uint8_t *x = (const uint8_t *)P->x;
+    const uint8_t *a = x + i * P->stride, *b = x + j * P->stride;
+    return P->metric == OM_L2 ? dist_l2_u8(a, b, P->d) : dist_cos_u8(a, b, P->d);
+  } else {
+    const float *x = (const float *)P->x;
+    const float *a = x + i * P->stride, *b = x + j * P->stride;
+    return P->metric == OM_L2 ? dist_l2_f32(a, b, P->d) : dist_cos_f32(a, b, P->d);
+  }
+}
+
+double oracle_distance(const opoints *P, int64_t i, int64_t j) { return D(P, i, j); }
+
+/* (distance, index) order */
+static int before(double da, int64_t ia, double db, int64_t ib) {
+  return da < db || (da == db && ia < ib);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact k nearest neighbours (Sec. 4.1 "Brute Force"): the k smallest       */
+/* (D(i,j), j) over j != i, ascending.  Fills idx/dist rows of length k for  */
+/* each query (queries==NULL means all points).  Returns 0, or -1 if k is    */
+/* out of range.                                                             */
+/* ------------------------------------------------------------------------ */
+int oracle_knn(const opoints *P, const int64_t *queries, int64_t nq, int32_t k,
+               int64_t *idx, double *dist) {
+  if (k < 1 || k > P->n - 1) return -1;
+  if (!queries) nq = P->n;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t qq = 0; qq < nq; ++qq) {
+    int64_t i = queries ? queries[qq] : qq;
+    int64_t *bi = idx + qq * k;
+    double *bd = dist + qq * k;
+    int32_t m = 0; /* entries held, kept sorted ascending */
+    for (int64_t j = 0; j < P->n; ++j) {
+      if (j == i) continue;
+      double dj = D(P, i, j);
+      if (m == k && !before(dj, j, bd[k - 1], bi[k - 1])) continue;
+      int32_t pos = (m < k) ? m++ : k - 1;
+      while (pos > 0 && before(dj, j, bd[pos - 1], bi[pos - 1])) {
+        bd[pos] = bd[pos - 1];
+        bi[pos] = bi[pos - 1];
+        --pos;
+      }
+      bd[pos] = dj;
+      bi[pos] = j;
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Density rank (Sec. 3 step 3): order points by (D_k, index) ascending,     */
+/* i.e. by kth density rho = 1/D_k descending with ties to the lower index.  */
+/* rank[i] = position of i in that order (0 = densest).                      */
+/* ------------------------------------------------------------------------ */
+static const double *g_sort_key; /* qsort has no context argument */
+static int cmp_by_key_then_id(const void *a, const void *b) {
+  int64_t i = *(const int64_t *)a, j = *(const int64_t *)b;
+  double ki = g_sort_key[i], kj = g_sort_key[j];
+  if (ki < kj) return -1;
+  if (ki > kj) return 1;
+  return (i > j) - (i < j);
+}
+
+void oracle_rank(int64_t n, const double *dk, int64_t *order, int64_t *rank) {
+  for (int64_t i = 0; i < n; ++i) order[i] = i;
+  g_sort_key = dk;
+  qsort(order, (size_t)n, sizeof(int64_t), cmp_by_key_then_id);
+  g_sort_key = NULL;
+  for (int64_t r = 0; r < n; ++r) rank[order[r]] = r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact dependent point (Def. 1): lambda_i = argmin over points ranked      */
+/* strictly above i of (D(i,j), j); delta_i = D(i, lambda_i).  The top-ranked */
+/* point has lambda = -1 and delta = +inf.                                   */
+/* ------------------------------------------------------------------------ */
+void oracle_dependent_exact(const opoints *P, const int64_t *rank,
+                            const int64_t *queries, int64_t nq, int64_t *dep,
+                            double *delta) {
+  if (!queries) nq = P->n;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t qq = 0; qq < nq; ++qq) {
+    int64_t i = queries ? queries[qq] : qq;
+    int64_t best = -1;
+    double bd = INFINITY;
+    for (int64_t j = 0; j < P->n; ++j) {
+      if (rank[j] >= rank[i]) continue;
+      double dj = D(P, i, j);
+      if (best < 0 || before(dj, j, bd, best)) {
+        best = j;
+        bd = dj;
+      }
+    }
+    dep[qq] = best;
+    delta[qq] = best < 0 ? INFINITY : bd;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Noise, centers and labels (Alg. 2, lines after ComputeDepPts; Sec. 4.2).  */
+/*   noise:   rho_i < rho_min (strict);                                      */
+/*   center_mode 0 (product): the n_c non-noise points with the largest      */
+/*            gamma_i = rho_i * delta_i, ties to the lower index; a product   */
+/*            that is not a number (inf * 0) counts as 0;                    */
+/*   center_mode 1 (threshold): non-noise points with delta_i >= delta_min;  */
+/*   labels:  non-noise, non-center points are joined with their dependent;  */
+/*            every point is labelled with the index of the root it reaches  */
+/*            (a center, a noise point, or the point with no dependent).     */
+/* Returns 0, or -1 on bad arguments.                                        */
+/* ------------------------------------------------------------------------ */
+static const double *g_gamma;
+static int cmp_gamma_desc(const void *a, const void *b) {
+  int64_t i = *(const int64_t *)a, j = *(const int64_t *)b;
+  double gi = g_gamma[i], gj = g_gamma[j];
+  if (gi > gj) return -1;
+  if (gi < gj) return 1;
+  return (i > j) - (i < j);
+}
+
+int oracle_cluster(int64_t n, const double *rho, const int64_t *dep,
+                   const double *delta, int32_t center_mode, int64_t n_c,
+                   double delta_min, double rho_min, int64_t *labels,
+                   uint8_t *is_center) {
+  uint8_t *noise = (uint8_t *)calloc((size_t)n, 1);
+  if (!noise) return -1;
+  for (int64_t i = 0; i < n; ++i) {
+    noise[i] = rho[i] < rho_min;
+    is_center[i] = 0;
+  }
+  if (center_mode == 0) {
+    double *gamma = (double *)malloc(sizeof(double) * (size_t)n);
+    int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    if (!gamma || !cand) { free(noise); free(gamma); free(cand); return -1; }
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      double g = rho[i] * delta[i];
+      gamma[i] = isnan(g) ? 0.0 : g;
+      if (!noise[i]) cand[m++] = i;
+    }
+    g_gamma = gamma;
+    qsort(cand, (size_t)m, sizeof(int64_t), cmp_gamma_desc);
+    g_gamma = NULL;
+    for (int64_t r = 0; r < m && r < n_c; ++r) is_center[cand[r]] = 1;
+    free(gamma);
+    free(cand);
+  } else {
+    for (int64_t i = 0; i < n; ++i)
+      if (!noise[i] && delta[i] >= delta_min) is_center[i] = 1;
+  }
+  /* union step: parent = dependent for joined points, self for roots */
+  int64_t *parent = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+  if (!parent) { free(noise); return -1; }
+  for (int64_t i = 0; i < n; ++i)
+    parent[i] = (noise[i] || is_center[i] || dep[i] < 0) ? i : dep[i];
+  /* find step: walk to the root */
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t r = i, steps = 0;
+    while (parent[r] != r) {
+      r = parent[r];
+      if (++steps > n) { free(parent); free(noise); return -1; } /* cycle */
+    }
+    labels[i] = r;
+  }
+  free(parent);
+  free(noise);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Greedy beam search (Alg. 1) for query point q over a graph given as       */
+/* adj[v*R + t] (t < deg[v]).  The beam keeps the L closest (D, index)        */
+/* entries; each step expands the closest unexpanded beam entry, adds its     */
+/* out-neighbours to the beam and truncates.  Returns the k closest of beam  */
+/* and visited set.  Point `excl` (normally q itself, or -1) may serve as a  */
+/* start and is expanded, but never takes a beam slot and is never returned: */
+/* the worked example of Sec. 3.1 (round 1 of d finds {e, f} with k_dep = 2) */
+/* holds only with the query excluded from its own beam.                     */
+/* Optionally records the visited set (expanded points) in expansion order.  */
+/* Returns the number of results written (<= k), or -1 on allocation error.  */
+/* ------------------------------------------------------------------------ */
+typedef struct { double d; int64_t id; } cand_t;
+
+static int64_t add_to_beam(cand_t *beam, int64_t m, double d, int64_t id) {
+  /* sorted insert; caller guarantees capacity and non-membership */
+  int64_t pos = m;
+  while (pos > 0 && before(d, id, beam[pos - 1].d, beam[pos - 1].id)) {
+    beam[pos] = beam[pos - 1];
+    --pos;
+  }
+  beam[pos].d = d;
+  beam[pos].id = id;
+  return m + 1;
+}
+
+int32_t oracle_greedy_search(const opoints *P, const int32_t *adj,
+                             const int32_t *deg, int32_t R, int64_t q,
+                             int64_t excl, const int64_t *starts, int32_t ns,
+                             int32_t L, int32_t k, int64_t *out_ids,
+                             double *out_d, int64_t *vis_ids, double *vis_d,
+                             int32_t max_vis, int32_t *n_vis) {
+  int64_t n = P->n;
+  uint8_t *in_beam = (uint8_t *)calloc((size_t)n, 1);
+  uint8_t *visited = (uint8_t *)calloc((size_t)n, 1);
+  cand_t *beam = (cand_t *)malloc(sizeof(cand_t) * (size_t)(L + R + ns + 1));
+  /* visited list: expanded points with their distances, expansion order */
+  cand_t *vlist = (cand_t *)malloc(sizeof(cand_t) * (size_t)(n + 1));
+  if (!in_beam || !visited || !beam || !vlist) {
+    free(in_beam); free(visited); free(beam); free(vlist);
+    return -1;
+  }
+  int64_t m = 0, nv = 0;
+
+  /* L <- S.  The excluded point, if a start, is expanded at once. */
+  int64_t pending_excl = -1;
+  for (int32_t s = 0; s < ns; ++s) {
+    int64_t v = starts[s];
+    if (v == excl) { pending_excl = v; continue; }
+    if (in_beam[v]) continue;
+    in_beam[v] = 1;
+    m = add_to_beam(beam, m, D(P, q, v), v);
+  }
+  if (m > L) { for (int64_t t = L; t < m; ++t) in_beam[beam[t].id] = 0; m = L; }
+
+  for (;;) {
+    int64_t pstar;
+    double pd;
+    if (pending_excl >= 0) {
+      pstar = pending_excl;
+      pd = 0.0;
+      pending_excl = -1;
+    } else {
+      /* p* <- closest beam entry not yet visited */
+      int64_t t = 0;
+      while (t < m && visited[beam[t].id]) ++t;
+      if (t == m) break;
+      pstar = beam[t].id;
+      pd = beam[t].d;
+    }
+    /* L <- L u Nout(p*) */
+    for (int32_t e = 0; e < deg[pstar]; ++e) {
+      int64_t v = adj[pstar * (int64_t)R + e];
+      if (v < 0 || v == excl || in_beam[v]) continue;
+      in_beam[v] = 1;
+      m = add_to_beam(beam, m, D(P, q, v), v);
+    }
+    /* V <- V u {p*} */
+    visited[pstar] = 1;
+    if (pstar != excl) { vlist[nv].d = pd; vlist[nv].id = pstar; ++nv; }
+    /* keep the L closest */
+    if (m > L) {
+      for (int64_t t = L; t < m; ++t) in_beam[beam[t].id] = 0;
+      m = L;
+    }
+  }
+
+  /* k closest of L u V (V entries not in L lie beyond every beam entry) */
+  int32_t cnt = 0;
+  {
+    cand_t *all = (cand_t *)malloc(sizeof(cand_t) * (size_t)(m + nv + 1));
+    int64_t na = 0;
+    for (int64_t t = 0; t < m; ++t) na = add_to_beam(all, na, beam[t].d, beam[t].id);
+    for (int64_t t = 0; t < nv; ++t)
+      if (!in_beam[vlist[t].id]) na = add_to_beam(all, na, vlist[t].d, vlist[t].id);
+    for (int64_t t = 0; t < na && cnt < k; ++t) {
+      out_ids[cnt] = all[t].id;
+      out_d[cnt] = all[t].d;
+      ++cnt;
+    }
+    free(all);
+  }
+  if (n_vis) {
+    int32_t w = 0;
+    for (int64_t t = 0; t < nv && w < max_vis; ++t, ++w) {
+      if (vis_ids) vis_ids[w] = vlist[t].id;
+      if (vis_d) vis_d[w] = vlist[t].d;
+    }
+    *n_vis = (int32_t)nv;
+  }
+  free(in_beam); free(visited); free(beam); free(vlist);
+  return cnt;
+}
+
+/* ------------------------------------------------------------------------ */
+/* RobustPrune(p, V, alpha, R) of DiskANN (Sec. 3.2 defers to it):           */
+/*   V <- V \ {p}, sorted by (D(p,v), v);                                    */
+/*   repeatedly move the closest surviving v* to the output (stop at R) and  */
+/*   drop every surviving v' with alpha * D(v*, v') <= D(p, v').             */
+/* Duplicates in the candidate list are ignored.  Returns the out-degree.    */
+/* ------------------------------------------------------------------------ */
+int32_t oracle_robust_prune(const opoints *P, int64_t p, const int64_t *cand,
+                            int32_t nc, double alpha, int32_t R,
+                            int64_t *out) {
+  cand_t *v = (cand_t *)malloc(sizeof(cand_t) * (size_t)(nc + 1));
+  uint8_t *alive = (uint8_t *)malloc((size_t)nc + 1);
+  if (!v || !alive) { free(v); free(alive); return -1; }
+  int64_t m = 0;
+  for (int32_t t = 0; t < nc; ++t) {
+    int64_t c = cand[t];
+    if (c == p || c < 0) continue;
+    int dup = 0;
+    for (int64_t u = 0; u < m; ++u) if (v[u].id == c) { dup = 1; break; }
+    if (dup) continue;
+    m = add_to_beam(v, m, D(P, p, c), c);
+  }
+  for (int64_t t = 0; t < m; ++t) alive[t] = 1;
+  int32_t nout = 0;
+  for (int64_t t = 0; t < m && nout < R; ++t) {
+    if (!alive[t]) continue;
+    int64_t vs = v[t].id;
+    out[nout++] = vs;
+    alive[t] = 0;
+    if (nout == R) break;
+    for (int64_t u = t + 1; u < m; ++u) {
+      if (!alive[u]) continue;
+      if (alpha * D(P, vs, v[u].id) <= v[u].d) alive[u] = 0;
+    }
+  }
+  free(v);
+  free(alive);
+  return nout;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Batched Vamana construction (Sec. 3.2 and Sec. 4.1, after ParlayANN):     */
+/*   points are inserted in the order perm[]; perm[0] alone first, then      */
+/*   batches of size 1, 2, 4, ... capped at max(1, floor(batch_frac * n));   */
+/*   every search of a batch sees the graph as it was when the batch began;  */
+/*   start set S = the first min(num_starts, inserted) points of perm;       */
+/*   for each point p of the batch: V_p = visited set of the greedy search   */
+/*   for p (beam L), Nout(p) = RobustPrune(p, V_p, alpha, R);                */
+/*   then for each target q, the batch's new in-edges (sources in ascending  */
+/*   index) are appended to Nout(q) if they fit in R, otherwise             */
+/*   Nout(q) = RobustPrune(q, Nout(q) u new, alpha, R).                      */
+/* adj must hold n*R entries; unused slots are set to -1.  Returns 0 or -1. */
+/* ------------------------------------------------------------------------ */
+typedef struct { int64_t tgt, src; } edge_t;
+static int cmp_edge(const void *a, const void *b) {
+  const edge_t *x = (const edge_t *)a, *y = (const edge_t *)b;
+  if (x->tgt != y->tgt) return (x->tgt > y->tgt) - (x->tgt < y->tgt);
+  return (x->src > y->src) - (x->src < y->src);
+}
+
+int oracle_vamana_build(const opoints *P, int32_t R, int32_t L, double alpha,
+                        const int64_t *perm, int32_t num_starts,
+                        double batch_frac, int32_t *adj, int32_t *deg) {
+  int64_t n = P->n;
+  for (int64_t i = 0; i < n * (int64_t)R; ++i) adj[i] = -1;
+  for (int64_t i = 0; i < n; ++i) deg[i] = 0;
+  int64_t cap = (int64_t)floor(batch_frac * (double)n);
+  if (cap < 1) cap = 1;
+  int64_t inserted = 1; /* perm[0] is in the graph, with no edges */
+  int64_t bsize = 1;
+  int64_t *new_out = (int64_t *)malloc(sizeof(int64_t) * (size_t)(cap * R + 1));
+  int32_t *new_deg = (int32_t *)malloc(sizeof(int32_t) * (size_t)(cap + 1));
+  edge_t *edges = (edge_t *)malloc(sizeof(edge_t) * (size_t)(cap * R + 1));
+  int64_t *vis = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+  int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(R + cap * R + 1));
+  if (!new_out || !new_deg || !edges || !vis || !tmp) {
+    free(new_out); free(new_deg); free(edges); free(vis); free(tmp);
+    return -1;
+  }
+  while (inserted < n) {
+    int64_t b0 = inserted;
+    int64_t nb = bsize < cap ? bsize : cap;
+    if (nb > n - b0) nb = n - b0;
+    int32_t ns = (int32_t)(inserted < num_starts ? inserted : num_starts);
+    int err = 0;
+    /* searches and forward prunes, all against the batch-start graph */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < nb; ++t) {
+      int64_t p = perm[b0 + t];
+      int64_t *myvis = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+      int64_t dummy_id;
+      double dummy_d;
+      int32_t nvis = 0;
+      if (!myvis) { err = 1; continue; }
+      if (oracle_greedy_search(P, adj, deg, R, p, p, perm, ns, L, 0, &dummy_id,
+                               &dummy_d, myvis, NULL, (int32_t)n, &nvis) < 0) {
+        err = 1;
+      } else {
+        int32_t no = oracle_robust_prune(P, p, myvis, nvis, alpha, R,
+                                         new_out + t * R);
+        new_deg[t] = no < 0 ? 0 : no;
+        if (no < 0) err = 1;
+      }
+      free(myvis);
+    }
+    if (err) { free(new_out); free(new_deg); free(edges); free(vis); free(tmp); return -1; }
+    /* write the new points' out-edges; gather reverse edges */
+    int64_t ne = 0;
+    for (int64_t t = 0; t < nb; ++t) {
+      int64_t p = perm[b0 + t];
+      for (int32_t e = 0; e < new_deg[t]; ++e) {
+        adj[p * R + e] = (int32_t)new_out[t * R + e];
+        edges[ne].tgt = new_out[t * R + e];
+        edges[ne].src = p;
+        ++ne;
+      }
+      deg[p] = new_deg[t];
+    }
+    qsort(edges, (size_t)ne, sizeof(edge_t), cmp_edge);
+    /* per target: append or prune */
+    int64_t e0 = 0;
+    while (e0 < ne) {
+      int64_t e1 = e0;
+      int64_t q = edges[e0].tgt;
+      while (e1 < ne && edges[e1].tgt == q) ++e1;
+      int64_t add = e1 - e0;
+      if (deg[q] + add <= R) {
+        for (int64_t e = e0; e < e1; ++e) adj[q * R + deg[q]++] = (int32_t)edges[e].src;
+      } else {
+        int32_t nc = 0;
+        for (int32_t e = 0; e < deg[q]; ++e) tmp[nc++] = adj[q * R + e];
+        for (int64_t e = e0; e < e1; ++e) tmp[nc++] = edges[e].src;
+        int32_t no = oracle_robust_prune(P, q, tmp, nc, alpha, R, vis);
+        if (no < 0) { free(new_out); free(new_deg); free(edges); free(vis); free(tmp); return -1; }
+        for (int32_t e = 0; e < R; ++e) adj[q * R + e] = e < no ? (int32_t)vis[e] : -1;
+        deg[q] = no;
+      }
+      e0 = e1;
+    }
+    inserted += nb;
+    bsize *= 2;
+  }
+  free(new_out); free(new_deg); free(edges); free(vis); free(tmp);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* ComputeDepPts (Alg. 3) over a graph index.                                */
+/*   1. DPBruteForce over each point's kNN list N_i (the list's distances    */
+/*      are recomputed here);                                               */
+/*   2. U <- unfinished points, excluding the top-ranked point (Sec. 3.1:   */
+/*      it has no dependent and is skipped);                                 */
+/*   3. k_dep <- L_d; while |U| > threshold and k_dep <= kdep_cap:          */
+/*        for i in U: C = FindKnn(i, k_dep) (Alg. 1 with S = {i}, beam width */
+/*        max(k_dep, L_min), i excluded); lambda_i = DPBruteForce(i, C);     */
+/*        k_dep <- 2 k_dep; U <- still unfinished;                           */
+/*   4. DPBruteForce(i, P) for every i still in U.                           */
+/* kdep_cap bounds the doubling (the loop of Alg. 3 is unbounded); points   */
+/* left when it is reached go to step 4, which is exact.  With adj == NULL   */
+/* step 3 is skipped (the paper's brute-force instantiation).               */
+/* rounds_out (optional) receives |U| before each round and after the last. */
+/* Returns the number of doubling rounds run, or -1.                         */
+/* ------------------------------------------------------------------------ */
+static int64_t dp_bruteforce_list(const opoints *P, int64_t i, const int64_t *rank,
+                                  const int64_t *cand, int64_t nc, double *dout) {
+  int64_t best = -1;
+  double bd = INFINITY;
+  for (int64_t t = 0; t < nc; ++t) {
+    int64_t j = cand[t];
+    if (j < 0 || rank[j] >= rank[i]) continue;
+    double dj = D(P, i, j);
+    if (best < 0 || before(dj, j, bd, best)) { best = j; bd = dj; }
+  }
+  *dout = bd;
+  return best;
+}
+
+int32_t oracle_dependent_alg3(const opoints *P, const int32_t *adj,
+                              const int32_t *deg, int32_t R,
+                              const int64_t *rank, const int64_t *knn, int32_t k,
+                              int32_t L_d, int64_t threshold, int32_t L_min,
+                              int32_t kdep_cap, int64_t *dep, double *delta,
+                              int64_t *rounds_out, int32_t max_rounds_out) {
+  int64_t n = P->n;
+  int64_t top = 0;
+  for (int64_t i = 1; i < n; ++i) if (rank[i] < rank[top]) top = i;
+  int64_t *U = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+  if (!U) return -1;
+  int64_t nu = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (i == top) { dep[i] = -1; delta[i] = INFINITY; continue; }
+    double d;
+    int64_t l = dp_bruteforce_list(P, i, rank, knn + i * (int64_t)k, k, &d);
+    dep[i] = l;
+    delta[i] = l < 0 ? INFINITY : d;
+    if (l < 0) U[nu++] = i;
+  }
+  int32_t rounds = 0;
+  int64_t kdep = L_d;
+  if (adj) {
+    while (nu > threshold && kdep <= kdep_cap && kdep <= n - 1) {
+      if (rounds_out && rounds < max_rounds_out) rounds_out[rounds] = nu;
+      int err = 0;
+      int32_t beam = (int32_t)(kdep > L_min ? kdep : L_min);
+#pragma omp parallel for schedule(dynamic, 1)
+      for (int64_t t = 0; t < nu; ++t) {
+        int64_t i = U[t];
+        int64_t *ids = (int64_t *)malloc(sizeof(int64_t) * (size_t)kdep);
+        double *ds = (double *)malloc(sizeof(double) * (size_t)kdep);
+        if (!ids || !ds) { err = 1; free(ids); free(ds); continue; }
+        int64_t s = i;
+        int32_t c = oracle_greedy_search(P, adj, deg, R, i, i, &s, 1, beam,
+                                         (int32_t)kdep, ids, ds, NULL, NULL, 0, NULL);
+        if (c < 0) err = 1;
+        else {
+          double d;
+          int64_t l = dp_bruteforce_list(P, i, rank, ids, c, &d);
+          if (l >= 0) { dep[i] = l; delta[i] = d; }
+        }
+        free(ids);
+        free(ds);
+      }
+      if (err) { free(U); return -1; }
+      int64_t w = 0;
+      for (int64_t t = 0; t < nu; ++t) if (dep[U[t]] < 0) U[w++] = U[t];
+      nu = w;
+      kdep *= 2;
+      ++rounds;
+    }
+  }
+  if (rounds_out && rounds < max_rounds_out) rounds_out[rounds] = nu;
+  /* final brute force over all of P */
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t t = 0; t < nu; ++t) {
+    int64_t i = U[t];
+    /* DPBruteForce(x_i, P): every point is a candidate */
+    int64_t best = -1;
+    double bd = INFINITY;
+    for (int64_t j = 0; j < n; ++j) {
+      if (rank[j] >= rank[i]) continue;
+      double dj = D(P, i, j);
+      if (best < 0 || before(dj, j, bd, best)) { best = j; bd = dj; }
+    }
+    dep[i] = best;
+    delta[i] = best < 0 ? INFINITY : bd;
+  }
+  free(U);
+  return rounds;
+}
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
