@@ -1,0 +1,233 @@
+/*
+ * pecann.h -- C ABI of libpecann.so, the MI355X (gfx950) hot path of PECANN's
+ * density peaks clustering (Yu, Engels, Huang, Shun, arXiv 2312.03940).
+ *
+ * The calls follow the paper's statement of the problem (Alg. 2): build a graph
+ * index over the point set (BuildIndex), find every point's k nearest neighbours
+ * and its density (the Find-Knn and F_density loops), compute every point's
+ * dependent point (ComputeDepPts, Alg. 3), then noise, centers and cluster labels
+ * (the F_noise / F_center / union-find steps).  The dependent forest (dep, delta)
+ * is returned so that a caller can re-cut the dendrogram (Sec. 1) by calling
+ * pecann_cluster again.
+ *
+ * Conventions shared by every call
+ *   - Device pointers: every array argument documented "device" is GPU memory
+ *     owned by the caller (for example a torch tensor); the library allocates
+ *     nothing and keeps no state between calls.
+ *   - Streams: every call is asynchronous on `stream` (a hipStream_t; NULL is
+ *     the null stream).  Outputs are valid once the stream has synchronised.
+ *     Argument errors are returned synchronously before anything is launched;
+ *     a launch failure returns PECANN_EHIP; a fault inside a kernel surfaces at
+ *     the caller's next synchronisation.
+ *   - Errors: no exception crosses the ABI.  On error the outputs are
+ *     unspecified.  pecann_last_error() gives a thread-local description.
+ *   - Workspace: calls that need scratch memory take (ws, ws_bytes); the
+ *     matching *_workspace_size() gives the minimum.  ws must be 256-byte
+ *     aligned.  A workspace may be reused across calls on the same stream.
+ *   - Orders: every "closest"/"smallest" order is (distance, index) ascending.
+ *     The density rank is the total order of (D_k, index) ascending, i.e. rho
+ *     descending with ties to the lower index (Sec. 3, step 3).  A rank key is
+ *     the 64-bit value (float bits of the squared L2 distance -- or of the
+ *     cosine distance -- to the k-th neighbour) << 32 | index, so that a
+ *     smaller key means a strictly higher density.
+ *   - Determinism: identical inputs on the same device give identical outputs.
+ */
+#ifndef PECANN_H
+#define PECANN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PECANN_OK = 0,
+  PECANN_EINVAL = 1,       /* an argument is out of range or misaligned */
+  PECANN_EWORKSPACE = 2,   /* ws is NULL or smaller than *_workspace_size() */
+  PECANN_EHIP = 3,         /* a HIP runtime call or launch failed */
+  PECANN_EUNSUPPORTED = 4  /* valid but not supported combination */
+} pecann_status;
+
+/* Element type of a row store. */
+typedef enum {
+  PECANN_F32 = 0,     /* IEEE float32 */
+  PECANN_U8 = 1,      /* unsigned 8-bit integer */
+  PECANN_BF16 = 2,    /* bfloat16, round-to-nearest-even from float32 */
+  PECANN_FP8E4M3 = 3  /* OCP float8 e4m3 with a float32 scale per row */
+} pecann_dtype;
+
+/* Distance D(x, y) (Sec. 2.1; the paper's experiments use Euclidean). */
+typedef enum {
+  PECANN_L2 = 0,     /* sqrt(sum (x_t - y_t)^2) */
+  PECANN_COSINE = 1  /* 1 - x.y / (|x| |y|) */
+} pecann_metric;
+
+typedef enum { PECANN_CENTER_PRODUCT = 0, PECANN_CENTER_THRESHOLD = 1 } pecann_center_mode;
+
+/* ---------------------------------------------------------------------------
+ * Prepared point set.
+ *
+ * pecann_prepare_vectors converts the caller's rows once into a "prepared"
+ * buffer, owned by the caller, that every later call reads:
+ *   search rows  n rows of the search element type (F32, U8, BF16 or FP8E4M3),
+ *                each padded with zeros to a multiple of 16 bytes;
+ *   rerank rows  n float32 rows padded to 16 bytes, present when the search
+ *                type is BF16 or FP8E4M3 (used to re-score candidates so that
+ *                every reported distance and every ordering is float32);
+ *   row scale    n floats (FP8E4M3 only): row t of the search copy holds
+ *                x_t / scale_t with scale_t = max_j |x_tj| / 448;
+ *   for PECANN_COSINE every row is divided by its norm first, so that
+ *   D = 1 - x.y on the prepared rows (a zero row stays zero: D = 1).
+ * Only the sizes matter to the caller: pecann_prepared_bytes() gives the
+ * buffer size for (n, d, metric, search type).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int64_t n;             /* number of points, 2 <= n < 2^31 */
+  int32_t d;             /* dimensions, 1 <= d <= 4096 */
+  int32_t metric;        /* pecann_metric */
+  int32_t search_dtype;  /* pecann_dtype of the search rows */
+  int32_t reserved;      /* must be 0 */
+  const void *prep;      /* device: buffer written by pecann_prepare_vectors */
+} pecann_dataset;
+
+/* Bytes of the prepared buffer; 0 if the combination is invalid. */
+size_t pecann_prepared_bytes(int64_t n, int32_t d, int32_t metric, int32_t search_dtype);
+
+/* Convert the caller's rows x (device; n rows of d elements of x_dtype, F32 or
+ * U8, consecutive rows x_row_stride elements apart) into the prepared buffer
+ * `prep` (device, prep_bytes >= pecann_prepared_bytes()).  U8 search rows
+ * require U8 input and the L2 metric (they are then an exact copy).
+ * No distance computation happens here: this is the step that makes the
+ * reduced-precision copies of the point set P (Sec. 2.1). */
+pecann_status pecann_prepare_vectors(const void *x, int32_t x_dtype, int64_t x_row_stride,
+                                     int64_t n, int32_t d, int32_t metric,
+                                     int32_t search_dtype, void *prep, size_t prep_bytes,
+                                     void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Graph index: BuildIndex of Alg. 2 with the batched Vamana construction of
+ * Sec. 3.2 / Sec. 4.1, in the two-pass schedule of DiskANN's Vamana (the
+ * paper defers the construction details to it): pass 1 prunes with alpha = 1,
+ * pass 2 with the given alpha (passes = 1: a single pass with the given alpha).
+ *
+ * Points are inserted in the order perm (device, n distinct int32 indices; NULL
+ * means a permutation drawn from `seed` with SplitMix64-driven Fisher-Yates).
+ * The first pass starts the graph with perm[0] alone; then (and in the second
+ * pass from perm[0] on) batches of 1, 2, 4, ... points capped at max_batch
+ * (0 selects floor(n / 50), the paper's 0.02 n).  Every search of a batch sees the graph as it
+ * was when the batch began.  The start set S of a batch is the first
+ * min(num_starts, points in the graph) points of perm (the random multi-start
+ * of Sec. 3.2).  For each point p of the batch: V_p = the points expanded by a
+ * greedy beam search (Alg. 1, beam width L) for p from S, p excluded, at most
+ * visited_cap of them (the earliest expanded);
+ * Nout(p) = RobustPrune(p, V_p u Nout(p), alpha, R).  Then each target q
+ * receives the batch's new in-edges not already present, in ascending source
+ * index: appended if they fit in R, otherwise
+ * Nout(q) = RobustPrune(q, Nout(q) u new, alpha, R).  RobustPrune is DiskANN's:
+ * repeatedly keep the closest surviving candidate c* and drop every candidate
+ * c with alpha * D(c*, c) <= D(p, c) (compared as alpha^2 * D^2 <= D^2 for L2).
+ * Distances use the search rows.
+ *
+ * Output adj (device, n*R int32): row v holds Nout(v) in adj[v*R .. v*R+deg[v]),
+ * the rest -1; deg (device, n int32).
+ * Limits: 1 <= R <= 128, 1 <= L <= 1024, alpha >= 1, 1 <= num_starts <= 64,
+ * max_batch >= 0, L <= visited_cap <= 2048, passes in {0 (= 2), 1, 2}.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t R;            /* degree bound */
+  int32_t L;            /* build beam width */
+  float alpha;          /* prune slack, >= 1 */
+  int32_t num_starts;   /* random start points */
+  int32_t max_batch;    /* batch size cap in points (0: floor(n / 50)) */
+  int32_t visited_cap;  /* candidates kept per insertion (0 = 2L) */
+  int32_t passes;       /* 2 (default, 0 means 2): alpha = 1 then alpha; 1: alpha only */
+  int32_t reserved;     /* must be 0 */
+} pecann_build_params;
+
+size_t pecann_build_graph_workspace_size(const pecann_dataset *ds, const pecann_build_params *bp);
+pecann_status pecann_build_graph(const pecann_dataset *ds, const pecann_build_params *bp,
+                                 const int32_t *perm, uint64_t seed, int32_t *adj,
+                                 int32_t *deg, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * k nearest neighbours and kth density (Alg. 2, Find-Knn and F_density loops;
+ * Sec. 4.2 "kth density": rho_i = 1 / D(x_i, k-th neighbour)).
+ *
+ * With a graph (adj != NULL): for every point i a greedy beam search (Alg. 1)
+ * with beam width L_search from S = {i}, i itself expanded first but never
+ * occupying a beam slot nor returned (Sec. 3, step 2 starts the search at the
+ * query point; its nearest neighbour is another point).  With BF16/FP8 search
+ * rows the `rerank` closest beam entries are re-scored from float32 rows and
+ * the k closest of them reported.  A search that returns fewer than k points
+ * falls back to an exact search for that point (Sec. 4.1).
+ * Without a graph (adj == NULL): exact brute force over all other points (the
+ * paper's BruteForce index); distances always from float32 (or exact U8) rows.
+ *
+ * Outputs (device): knn_idx[n*k] int32 and knn_dist[n*k] float (distances D,
+ * not squared), ascending; rho[n] float (+inf when D_k = 0); rank_key[n]
+ * uint64 (see conventions).  Limits: 1 <= k <= min(n-1, 64);
+ * k <= L_search <= 1024; k <= rerank <= L_search.
+ * ------------------------------------------------------------------------- */
+size_t pecann_knn_density_workspace_size(const pecann_dataset *ds, int32_t k, int32_t L_search);
+pecann_status pecann_knn_density(const pecann_dataset *ds, const int32_t *adj,
+                                 const int32_t *deg, int32_t R, int32_t k, int32_t L_search,
+                                 int32_t rerank, int32_t *knn_idx, float *knn_dist,
+                                 float *rho, uint64_t *rank_key, void *ws, size_t ws_bytes,
+                                 void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Dependent points: ComputeDepPts of Alg. 3 (Def. 1: the closest point of
+ * strictly higher density, here strictly smaller rank key).
+ *   1. DPBruteForce over each point's own kNN list (its distances are reused);
+ *      the densest point gets dep = -1, delta = +inf and is skipped (Sec. 3.1);
+ *   2. with a graph: rounds with k_dep = L_d, 2 L_d, 4 L_d, ... while more than
+ *      `threshold` points are unfinished and k_dep <= min(kdep_cap, n-1):
+ *      for each unfinished i, greedy beam search from S = {i} with beam
+ *      max(k_dep, L_search), then DPBruteForce over the k_dep closest found;
+ *   3. DPBruteForce over all of P for every point still unfinished (exact).
+ * Without a graph (adj == NULL) step 2 is skipped: the exact instantiation.
+ * Outputs (device): dep[n] int32 (-1 = none) and delta[n] float (D to dep,
+ * +inf for none).  stats (device, may be NULL) receives int32 counts: [0] the
+ * unfinished points after step 1, [1 + r] those after round r for r < 30,
+ * [31] the points handled by step 3.
+ * Limits: L_d > k, threshold >= 0, L_d <= kdep_cap <= 1024.
+ * ------------------------------------------------------------------------- */
+size_t pecann_dependent_search_workspace_size(const pecann_dataset *ds, int32_t kdep_cap,
+                                              int32_t L_search);
+pecann_status pecann_dependent_search(const pecann_dataset *ds, const int32_t *adj,
+                                      const int32_t *deg, int32_t R, const uint64_t *rank_key,
+                                      const int32_t *knn_idx, const float *knn_dist,
+                                      int32_t k, int32_t L_d, int32_t L_search,
+                                      int32_t threshold, int32_t kdep_cap, int32_t *dep,
+                                      float *delta, int32_t *stats, void *ws,
+                                      size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Noise, centers and labels (Alg. 2 after ComputeDepPts; Sec. 4.2).
+ *   noise:   rho_i < rho_min (strict);
+ *   centers: PECANN_CENTER_PRODUCT -- the n_c non-noise points with the
+ *            largest gamma_i = rho_i * delta_i (float32 product; inf*0 counts
+ *            as 0), ties to the lower index; PECANN_CENTER_THRESHOLD -- the
+ *            non-noise points with delta_i >= delta_min;
+ *   labels:  every non-noise, non-center point joins its dependent's cluster;
+ *            labels[i] = index of the root reached along dep (a center, a
+ *            noise point, or the point with dep = -1).
+ * Inputs rho, dep, delta (device, n).  Outputs labels[n] int32, is_center[n]
+ * uint8 (device).  Limits: 1 <= n_c <= n in product mode.
+ * ------------------------------------------------------------------------- */
+size_t pecann_cluster_workspace_size(int64_t n);
+pecann_status pecann_cluster(int64_t n, const float *rho, const int32_t *dep,
+                             const float *delta, int32_t center_mode, int32_t n_c,
+                             float delta_min, float rho_min, int32_t *labels,
+                             uint8_t *is_center, void *ws, size_t ws_bytes, void *stream);
+
+const char *pecann_status_string(pecann_status s);
+/* Thread-local description of the last error returned on this thread. */
+const char *pecann_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PECANN_H */

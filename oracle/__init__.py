@@ -86,7 +86,7 @@ def load():
         lib.oracle_greedy_search.restype = i32
         lib.oracle_robust_prune.argtypes = [P, i64, vp, i32, f64, i32, vp]
         lib.oracle_robust_prune.restype = i32
-        lib.oracle_vamana_build.argtypes = [P, i32, i32, f64, vp, i32, f64, vp, vp]
+        lib.oracle_vamana_build.argtypes = [P, i32, i32, f64, vp, i32, i64, i32, vp, vp]
         lib.oracle_vamana_build.restype = ctypes.c_int
         lib.oracle_dependent_alg3.argtypes = [P, vp, vp, i32, vp, vp, i32, i32, i64, i32,
                                               i32, vp, vp, vp, i32]
@@ -209,9 +209,10 @@ def robust_prune(P: Points, p: int, cand, alpha: float, R: int):
     return out[:c].copy()
 
 
-def batch_schedule(n: int, batch_frac: float = 0.02):
-    """Batch boundaries of the batched insertion: perm[0] alone, then 1, 2, 4, ... capped."""
-    cap = max(1, int(np.floor(batch_frac * n)))
+def batch_schedule(n: int, max_batch: int = 0):
+    """Batch boundaries of the first insertion pass: perm[0] alone, then 1, 2, 4, ... capped
+    at max_batch (0: floor(n / 50), the paper's 0.02 n)."""
+    cap = max(1, max_batch if max_batch > 0 else n // 50)
     bounds = [(0, 1)]
     ins, b = 1, 1
     while ins < n:
@@ -223,12 +224,13 @@ def batch_schedule(n: int, batch_frac: float = 0.02):
 
 
 def vamana_build(P: Points, R: int, L: int, alpha: float, perm, num_starts: int = 8,
-                 batch_frac: float = 0.02):
+                 max_batch: int = 0, passes: int = 2):
+    """passes=2: DiskANN's schedule (alpha = 1, then alpha); passes=1: alpha only."""
     perm = np.ascontiguousarray(perm, dtype=np.int64)
     adj = np.empty((P.n, R), dtype=np.int32)
     deg = np.empty(P.n, dtype=np.int32)
-    if load().oracle_vamana_build(P.ref, R, L, alpha, _ptr(perm), num_starts, batch_frac,
-                                  _ptr(adj), _ptr(deg)) != 0:
+    if load().oracle_vamana_build(P.ref, R, L, alpha, _ptr(perm), num_starts, max_batch,
+                                  passes, _ptr(adj), _ptr(deg)) != 0:
         raise MemoryError("oracle_vamana_build")
     return adj, deg
 
@@ -274,11 +276,12 @@ def exact_dpc(X: np.ndarray, k: int, n_c: int, metric: int = L2, center_mode: in
 
 def anns_dpc(X: np.ndarray, k: int, n_c: int, R: int, L_build: int, alpha: float, perm,
              L_search: int, L_d: int, threshold: int, num_starts: int = 8,
-             batch_frac: float = 0.02, kdep_cap: int = 1 << 30, metric: int = L2,
-             center_mode: int = 0, delta_min: float = 0.0, rho_min: float = 0.0):
+             max_batch: int = 0, kdep_cap: int = 1 << 30, metric: int = L2,
+             center_mode: int = 0, delta_min: float = 0.0, rho_min: float = 0.0,
+             passes: int = 2):
     """Alg. 2 over a Vamana index: build, Alg. 1 kNN from S = {i}, kth density, Alg. 3, cluster."""
     P = Points(X, metric)
-    adj, deg = vamana_build(P, R, L_build, alpha, perm, num_starts, batch_frac)
+    adj, deg = vamana_build(P, R, L_build, alpha, perm, num_starts, max_batch, passes)
     n = P.n
     idx = np.empty((n, k), dtype=np.int64)
     dist = np.empty((n, k), dtype=np.float64)

@@ -432,17 +432,21 @@ int32_t oracle_robust_prune(const opoints *P, int64_t p, const int64_t *cand,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Batched Vamana construction (Sec. 3.2 and Sec. 4.1, after ParlayANN):     */
-/*   points are inserted in the order perm[]; perm[0] alone first, then      */
-/*   batches of size 1, 2, 4, ... capped at max(1, floor(batch_frac * n));   */
-/*   every search of a batch sees the graph as it was when the batch began;  */
-/*   start set S = the first min(num_starts, inserted) points of perm;       */
-/*   for each point p of the batch: V_p = visited set of the greedy search   */
-/*   for p (beam L), Nout(p) = RobustPrune(p, V_p, alpha, R);                */
-/*   then for each target q, the batch's new in-edges (sources in ascending  */
-/*   index) are appended to Nout(q) if they fit in R, otherwise             */
-/*   Nout(q) = RobustPrune(q, Nout(q) u new, alpha, R).                      */
-/* adj must hold n*R entries; unused slots are set to -1.  Returns 0 or -1. */
+/* Batched Vamana construction (Sec. 3.2 and Sec. 4.1, after ParlayANN), with  */
+/* the two-pass schedule of DiskANN's Vamana (first pass alpha = 1, then the    */
+/* given alpha) when passes == 2:                                            */
+/*   points are inserted in the order perm[]; in the first pass perm[0] alone  */
+/*   starts the graph, then batches of size 1, 2, 4, ... capped at max_batch   */
+/*   (0: floor(n / 50), the paper's 0.02 n); a later pass walks the batches   */
+/*   starting with perm[0] itself.  Every search of a batch sees the graph as  */
+/*   it was when the batch began; the start set S is the first                */
+/*   min(num_starts, inserted) points of perm;                                */
+/*   for each point p of the batch: V_p = visited set of the greedy search for */
+/*   p (beam L, p excluded), Nout(p) = RobustPrune(p, V_p u Nout(p), alpha, R); */
+/*   then for each target q, the batch's new in-edges (sources in ascending     */
+/*   index, those already present skipped) are appended to Nout(q) if they fit */
+/*   in R, otherwise Nout(q) = RobustPrune(q, Nout(q) u new, alpha, R).        */
+/* adj must hold n*R entries; unused slots are set to -1.  Returns 0 or -1.   */
 /* ------------------------------------------------------------------------ */
 typedef struct { int64_t tgt, src; } edge_t;
 static int cmp_edge(const void *a, const void *b) {
@@ -452,15 +456,13 @@ static int cmp_edge(const void *a, const void *b) {
 }
 
 int oracle_vamana_build(const opoints *P, int32_t R, int32_t L, double alpha,
-                        const int64_t *perm, int32_t num_starts,
-                        double batch_frac, int32_t *adj, int32_t *deg) {
+                        const int64_t *perm, int32_t num_starts, int64_t max_batch,
+                        int32_t passes, int32_t *adj, int32_t *deg) {
   int64_t n = P->n;
   for (int64_t i = 0; i < n * (int64_t)R; ++i) adj[i] = -1;
   for (int64_t i = 0; i < n; ++i) deg[i] = 0;
-  int64_t cap = (int64_t)floor(batch_frac * (double)n);
+  int64_t cap = max_batch > 0 ? max_batch : n / 50;
   if (cap < 1) cap = 1;
-  int64_t inserted = 1; /* perm[0] is in the graph, with no edges */
-  int64_t bsize = 1;
   int64_t *new_out = (int64_t *)malloc(sizeof(int64_t) * (size_t)(cap * R + 1));
   int32_t *new_deg = (int32_t *)malloc(sizeof(int32_t) * (size_t)(cap + 1));
   edge_t *edges = (edge_t *)malloc(sizeof(edge_t) * (size_t)(cap * R + 1));
@@ -470,71 +472,85 @@ int oracle_vamana_build(const opoints *P, int32_t R, int32_t L, double alpha,
     free(new_out); free(new_deg); free(edges); free(vis); free(tmp);
     return -1;
   }
-  while (inserted < n) {
-    int64_t b0 = inserted;
-    int64_t nb = bsize < cap ? bsize : cap;
-    if (nb > n - b0) nb = n - b0;
-    int32_t ns = (int32_t)(inserted < num_starts ? inserted : num_starts);
-    int err = 0;
-    /* searches and forward prunes, all against the batch-start graph */
+  int rc = 0;
+  for (int32_t pass = 0; pass < passes && rc == 0; ++pass) {
+    const double a = (passes > 1 && pass == 0) ? 1.0 : alpha;
+    /* first pass: perm[0] starts the graph unsearched; later passes search it too */
+    int64_t inserted = pass == 0 ? 1 : 0;
+    int64_t bsize = 1;
+    while (inserted < n) {
+      int64_t b0 = inserted;
+      int64_t nb = bsize < cap ? bsize : cap;
+      if (nb > n - b0) nb = n - b0;
+      int64_t in_graph = pass == 0 ? inserted : n;
+      int32_t ns = (int32_t)(in_graph < num_starts ? in_graph : num_starts);
+      int err = 0;
+      /* searches and forward prunes, all against the batch-start graph */
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t t = 0; t < nb; ++t) {
-      int64_t p = perm[b0 + t];
-      int64_t *myvis = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-      int64_t dummy_id;
-      double dummy_d;
-      int32_t nvis = 0;
-      if (!myvis) { err = 1; continue; }
-      if (oracle_greedy_search(P, adj, deg, R, p, p, perm, ns, L, 0, &dummy_id,
-                               &dummy_d, myvis, NULL, (int32_t)n, &nvis) < 0) {
-        err = 1;
-      } else {
-        int32_t no = oracle_robust_prune(P, p, myvis, nvis, alpha, R,
-                                         new_out + t * R);
-        new_deg[t] = no < 0 ? 0 : no;
-        if (no < 0) err = 1;
+      for (int64_t t = 0; t < nb; ++t) {
+        int64_t p = perm[b0 + t];
+        int64_t *myvis = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + R));
+        int64_t dummy_id;
+        double dummy_d;
+        int32_t nvis = 0;
+        if (!myvis) { err = 1; continue; }
+        if (oracle_greedy_search(P, adj, deg, R, p, p, perm, ns, L, 0, &dummy_id,
+                                 &dummy_d, myvis, NULL, (int32_t)n, &nvis) < 0) {
+          err = 1;
+        } else {
+          for (int32_t e = 0; e < deg[p]; ++e) myvis[nvis++] = adj[p * R + e];
+          int32_t no = oracle_robust_prune(P, p, myvis, nvis, a, R, new_out + t * R);
+          new_deg[t] = no < 0 ? 0 : no;
+          if (no < 0) err = 1;
+        }
+        free(myvis);
       }
-      free(myvis);
-    }
-    if (err) { free(new_out); free(new_deg); free(edges); free(vis); free(tmp); return -1; }
-    /* write the new points' out-edges; gather reverse edges */
-    int64_t ne = 0;
-    for (int64_t t = 0; t < nb; ++t) {
-      int64_t p = perm[b0 + t];
-      for (int32_t e = 0; e < new_deg[t]; ++e) {
-        adj[p * R + e] = (int32_t)new_out[t * R + e];
-        edges[ne].tgt = new_out[t * R + e];
-        edges[ne].src = p;
-        ++ne;
+      if (err) { rc = -1; break; }
+      /* write the batch's out-edges; gather reverse edges */
+      int64_t ne = 0;
+      for (int64_t t = 0; t < nb; ++t) {
+        int64_t p = perm[b0 + t];
+        for (int32_t e = 0; e < R; ++e)
+          adj[p * R + e] = e < new_deg[t] ? (int32_t)new_out[t * R + e] : -1;
+        deg[p] = new_deg[t];
+        for (int32_t e = 0; e < new_deg[t]; ++e) {
+          edges[ne].tgt = new_out[t * R + e];
+          edges[ne].src = p;
+          ++ne;
+        }
       }
-      deg[p] = new_deg[t];
-    }
-    qsort(edges, (size_t)ne, sizeof(edge_t), cmp_edge);
-    /* per target: append or prune */
-    int64_t e0 = 0;
-    while (e0 < ne) {
-      int64_t e1 = e0;
-      int64_t q = edges[e0].tgt;
-      while (e1 < ne && edges[e1].tgt == q) ++e1;
-      int64_t add = e1 - e0;
-      if (deg[q] + add <= R) {
-        for (int64_t e = e0; e < e1; ++e) adj[q * R + deg[q]++] = (int32_t)edges[e].src;
-      } else {
+      qsort(edges, (size_t)ne, sizeof(edge_t), cmp_edge);
+      /* per target: append the sources not yet present, or prune */
+      int64_t e0 = 0;
+      while (e0 < ne && rc == 0) {
+        int64_t e1 = e0;
+        int64_t q = edges[e0].tgt;
+        while (e1 < ne && edges[e1].tgt == q) ++e1;
         int32_t nc = 0;
         for (int32_t e = 0; e < deg[q]; ++e) tmp[nc++] = adj[q * R + e];
-        for (int64_t e = e0; e < e1; ++e) tmp[nc++] = edges[e].src;
-        int32_t no = oracle_robust_prune(P, q, tmp, nc, alpha, R, vis);
-        if (no < 0) { free(new_out); free(new_deg); free(edges); free(vis); free(tmp); return -1; }
-        for (int32_t e = 0; e < R; ++e) adj[q * R + e] = e < no ? (int32_t)vis[e] : -1;
-        deg[q] = no;
+        int32_t nold = nc;
+        for (int64_t e = e0; e < e1; ++e) {
+          int present = 0;
+          for (int32_t u = 0; u < nold; ++u) if (tmp[u] == edges[e].src) { present = 1; break; }
+          if (!present) tmp[nc++] = edges[e].src;
+        }
+        if (nc <= R) {
+          for (int32_t e = nold; e < nc; ++e) adj[q * R + e] = (int32_t)tmp[e];
+          deg[q] = nc;
+        } else {
+          int32_t no = oracle_robust_prune(P, q, tmp, nc, a, R, vis);
+          if (no < 0) { rc = -1; break; }
+          for (int32_t e = 0; e < R; ++e) adj[q * R + e] = e < no ? (int32_t)vis[e] : -1;
+          deg[q] = no;
+        }
+        e0 = e1;
       }
-      e0 = e1;
+      inserted += nb;
+      bsize *= 2;
     }
-    inserted += nb;
-    bsize *= 2;
   }
   free(new_out); free(new_deg); free(edges); free(vis); free(tmp);
-  return 0;
+  return rc;
 }
 
 /* ------------------------------------------------------------------------ */

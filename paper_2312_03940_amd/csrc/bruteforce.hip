@@ -1,0 +1,158 @@
+// Exact (brute-force) kernels, float32 (or exact uint8) distances:
+//   K1 bf_knn  -- exact k nearest neighbours of a list of queries over all points
+//                 (the paper's BruteForce index, Sec. 4.1; also the fallback when
+//                 a graph search returns fewer than k points);
+//   K7 bf_dep  -- DPBruteForce(x_i, P) of Alg. 3 for the unfinished points: the
+//                 closest point of strictly smaller rank key, split into chunks
+//                 of candidates whose partial argmins meet in a 64-bit atomic min.
+#include <type_traits>
+
+#include "beam.hpp"
+
+namespace pecann {
+
+// Engine over exact rows: the search rows themselves when they are float32 or
+// uint8, else the float32 rerank rows.
+template <int DT, int G>
+using ExactEngine = typename std::conditional<(DT == PECANN_F32 || DT == PECANN_U8), Engine<DT, G>,
+                                              Engine32<G>>::type;
+
+template <int DT, int G>
+__global__ __launch_bounds__(64) void bf_knn_kernel(BfKnnParams p) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int k = p.k;
+  const int kp = (k + 15) & ~15;
+  SortedList top;
+  top.a = (uint64_t *)smem;
+  top.b = top.a + kp;
+  top.tmp = top.b + kp;
+  top.fa = (uint8_t *)(top.tmp + 64);
+  top.fb = top.fa + kp;
+  top.cap = k;
+  using E = ExactEngine<DT, G>;
+  constexpr int NPL = E::NPL;
+  E eng;
+  const int l = lane_id();
+  const int count = p.item_count ? *p.item_count : p.nitems;
+  for (;;) {
+    const int it = next_item(p.head);
+    if (it >= count) break;
+    const int32_t qid = p.items ? p.items[it] : it;
+    eng.load_query(p.rows, qid);
+    top.m = 0;
+    wave_lds_sync();
+    for (int base = 0; base < p.n; base += NPL) {
+      int32_t row = base + l / G;
+      if (row >= p.n || row == qid) row = -1;
+      const float m = eng.measure(p.rows, row);
+      const uint64_t key = row >= 0 ? make_key(m, row) : kNoKey;
+      uint64_t kk = shfl_u64(key, (l % NPL) * G);
+      if (l >= NPL) kk = kNoKey;
+      top.merge(kk);
+    }
+    const int64_t o = (int64_t)qid * k;
+    for (int t = l; t < k; t += kWave) {
+      const uint64_t kt = top.a[t];
+      p.knn_idx[o + t] = key_id(kt);
+      p.knn_dist[o + t] = measure_to_dist(key_measure(kt), p.rows.metric);
+    }
+    if (l == 0) {
+      const uint64_t kk = top.a[k - 1];
+      p.rho[qid] = 1.0f / measure_to_dist(key_measure(kk), p.rows.metric);
+      p.rank_key[qid] = (kk & 0xffffffff00000000ull) | (uint32_t)qid;
+    }
+    wave_lds_sync();
+  }
+}
+
+size_t bf_knn_lds_bytes(int k) {
+  const size_t kp = (size_t)((k + 15) & ~15);
+  return 8 * (2 * kp + 64) + 2 * kp;
+}
+
+template <int DT, int G>
+__global__ __launch_bounds__(64) void bf_dep_kernel(BfDepParams p) {
+  __shared__ int32_t cidx[64];
+  using E = ExactEngine<DT, G>;
+  constexpr int NPL = E::NPL;
+  E eng;
+  const int l = lane_id();
+  const int count = *p.ucount;
+  const int total = count * p.nchunks;
+  for (;;) {
+    const int it = next_item(p.head);
+    if (it >= total) break;
+    const int u = it / p.nchunks;
+    const int ch = it - u * p.nchunks;
+    const int32_t qid = p.ulist[u];
+    const uint64_t ki = p.key[qid];
+    eng.load_query(p.rows, qid);
+    const int j0 = ch * p.chunk;
+    const int j1 = min(p.n, j0 + p.chunk);
+    uint64_t best = kNoKey;
+    for (int base = j0; base < j1; base += kWave) {
+      const int j = base + l;
+      const bool ok = j < j1 && p.key[j] < ki;
+      const uint64_t bm = ballot(ok);
+      if (bm == 0) continue;
+      const int c = __popcll(bm);
+      if (ok) cidx[lanes_below(bm)] = j;
+      wave_lds_sync();
+      for (int b2 = 0; b2 < c; b2 += NPL) {
+        const int ci = b2 + l / G;
+        const int32_t row = ci < c ? cidx[ci] : -1;
+        const float m = eng.measure(p.rows, row);
+        if ((l % G) == 0 && row >= 0) {
+          const uint64_t kk = make_key(m, row);
+          best = kk < best ? kk : best;
+        }
+      }
+      wave_lds_sync();
+    }
+    best = wave_min_u64(best);
+    if (l == 0 && best != kNoKey) atomicMin(&p.best[u], (unsigned long long)best);
+  }
+}
+
+template <int DT, int G>
+static hipError_t launch_bf_knn_t(const BfKnnParams &p, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((bf_knn_kernel<DT, G>), dim3(grid), dim3(64), bf_knn_lds_bytes(p.k), st, p);
+  return hipGetLastError();
+}
+template <int DT, int G>
+static hipError_t launch_bf_dep_t(const BfDepParams &p, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((bf_dep_kernel<DT, G>), dim3(grid), dim3(64), 0, st, p);
+  return hipGetLastError();
+}
+
+#define PECANN_DISPATCH_G(FN, DT, ...)                      \
+  switch (G) {                                              \
+    case 4: return FN<DT, 4>(__VA_ARGS__);                  \
+    case 8: return FN<DT, 8>(__VA_ARGS__);                  \
+    case 16: return FN<DT, 16>(__VA_ARGS__);                \
+    case 32: return FN<DT, 32>(__VA_ARGS__);                \
+    case 64: return FN<DT, 64>(__VA_ARGS__);                \
+    default: return hipErrorInvalidValue;                   \
+  }
+
+hipError_t launch_bf_knn(int32_t dt, int G, const BfKnnParams &p, int grid, hipStream_t st) {
+  switch (dt) {
+    case PECANN_F32: PECANN_DISPATCH_G(launch_bf_knn_t, PECANN_F32, p, grid, st)
+    case PECANN_U8: PECANN_DISPATCH_G(launch_bf_knn_t, PECANN_U8, p, grid, st)
+    case PECANN_BF16: PECANN_DISPATCH_G(launch_bf_knn_t, PECANN_BF16, p, grid, st)
+    case PECANN_FP8E4M3: PECANN_DISPATCH_G(launch_bf_knn_t, PECANN_FP8E4M3, p, grid, st)
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_bf_dep(int32_t dt, int G, const BfDepParams &p, int grid, hipStream_t st) {
+  switch (dt) {
+    case PECANN_F32: PECANN_DISPATCH_G(launch_bf_dep_t, PECANN_F32, p, grid, st)
+    case PECANN_U8: PECANN_DISPATCH_G(launch_bf_dep_t, PECANN_U8, p, grid, st)
+    case PECANN_BF16: PECANN_DISPATCH_G(launch_bf_dep_t, PECANN_BF16, p, grid, st)
+    case PECANN_FP8E4M3: PECANN_DISPATCH_G(launch_bf_dep_t, PECANN_FP8E4M3, p, grid, st)
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pecann

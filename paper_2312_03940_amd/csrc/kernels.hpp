@@ -1,0 +1,164 @@
+// Internal interface between the C-ABI layer (pecann_abi.hip) and the kernel
+// translation units.  Every launcher enqueues on the given stream and returns
+// the launch status; none synchronises.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pecann.h"
+
+namespace pecann {
+
+// Lane-group width G of the gather-distance engine for a row format: the
+// smallest power of two >= 4 that leaves at most 64 floats of query per lane.
+int engine_group(int32_t search_dtype, int32_t d);
+
+struct RowsDesc {  // host copy of the row description (mirrors Rows)
+  const uint8_t *xs;
+  int64_t xs_stride;
+  const float *scale;
+  const float *xr;
+  int64_t xr_stride;
+  int32_t nch;
+  int32_t nch_r;
+  int32_t d;
+  int32_t metric;
+};
+
+enum SearchMode { MODE_KNN = 0, MODE_DEP = 1, MODE_BUILD = 2 };
+
+struct SearchParams {
+  RowsDesc rows;
+  const int32_t *adj;
+  const int32_t *deg;
+  int32_t R;
+  int32_t n;
+  const int32_t *items;       // point per work item (nullptr: item index is the point)
+  const int32_t *item_count;  // device count of items (nullptr: nitems)
+  int32_t nitems;
+  int32_t *head;              // device work-queue head, 0 at launch
+  const int32_t *starts;      // start points besides the query itself
+  int32_t nstarts;
+  int32_t L;                  // beam width
+  int32_t hbits;              // log2 of visited-hash slots
+  int32_t mode;
+  int32_t rerank;             // entries re-scored in float32 (0: none)
+  // MODE_KNN
+  int32_t k;
+  int32_t *knn_idx;
+  float *knn_dist;
+  float *rho;
+  uint64_t *rank_key;
+  int32_t *fb_list;           // queries with fewer than k results
+  int32_t *fb_count;
+  // MODE_DEP
+  int32_t kdep;
+  const uint64_t *key_in;
+  int32_t *dep;
+  float *delta;
+  int32_t *u_out;
+  int32_t *u_out_count;
+  int32_t threshold;
+  // MODE_BUILD
+  uint64_t *vis;              // [item][vcap] keys of expanded points
+  int32_t *vis_count;         // [item] expansions (may exceed vcap)
+  int32_t vcap;
+};
+
+size_t search_lds_bytes(int L, int hbits);
+hipError_t launch_search(int32_t dt, int G, const SearchParams &p, int grid, hipStream_t s);
+
+// Exact (brute-force) kNN over all points for a list of queries.
+struct BfKnnParams {
+  RowsDesc rows;
+  int32_t n;
+  int32_t k;
+  const int32_t *items;       // nullptr: all points
+  const int32_t *item_count;  // nullptr: nitems
+  int32_t nitems;
+  int32_t *head;
+  int32_t *knn_idx;
+  float *knn_dist;
+  float *rho;
+  uint64_t *rank_key;
+};
+size_t bf_knn_lds_bytes(int k);
+hipError_t launch_bf_knn(int32_t dt, int G, const BfKnnParams &p, int grid, hipStream_t s);
+
+// Exact dependent point for a list of unfinished points: chunked argmin over
+// the points of strictly smaller rank key.
+struct BfDepParams {
+  RowsDesc rows;
+  int32_t n;
+  const int32_t *ulist;
+  const int32_t *ucount;
+  int32_t chunk;
+  int32_t nchunks;
+  int32_t *head;
+  const uint64_t *key;
+  unsigned long long *best;  // [u] packed (measure, index), ~0 at launch
+};
+hipError_t launch_bf_dep(int32_t dt, int G, const BfDepParams &p, int grid, hipStream_t s);
+
+// RobustPrune for a batch of new points (forward) and the reverse-edge merge.
+struct PruneParams {
+  RowsDesc rows;
+  int32_t n;
+  int32_t R;
+  float alpha;
+  int32_t *adj;
+  int32_t *deg;
+  // forward
+  const int32_t *perm;        // batch point of item t is perm[b0 + t]
+  int32_t b0;
+  int32_t nb;
+  const uint64_t *vis;
+  const int32_t *vis_count;
+  int32_t vcap;
+  // reverse
+  const int32_t *tlist;
+  const int32_t *ntargets;
+  const int32_t *toff;
+  const int32_t *tcnt;
+  const int32_t *seg;
+  int32_t *rcnt;
+  int32_t capin;              // max new in-edges merged per target
+  int32_t *head;
+  int32_t *overflow;          // counts truncations (candidates beyond capacity)
+};
+size_t prune_lds_bytes(int ccap, int R);
+hipError_t launch_prune_forward(int32_t dt, int G, const PruneParams &p, int grid, hipStream_t s);
+hipError_t launch_prune_reverse(int32_t dt, int G, const PruneParams &p, int grid, hipStream_t s);
+
+// Plain (non-templated) kernels.
+hipError_t launch_prepare(const void *x, int32_t x_dtype, int64_t x_stride, int64_t n, int32_t d,
+                          int32_t metric, int32_t sdt, const RowsDesc &rows, uint8_t *xs,
+                          float *xr, float *scale, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
+hipError_t launch_identity_perm(int32_t *p, int64_t n, hipStream_t s);
+hipError_t launch_rev_count(const int32_t *adj, const int32_t *deg, const int32_t *perm, int32_t b0,
+                            int32_t nb, int32_t R, int32_t *rcnt, int32_t *ntargets,
+                            int32_t *tlist, int32_t *tidx, int32_t *ticket, hipStream_t s);
+hipError_t launch_rev_alloc(const int32_t *tlist, const int32_t *ntargets, const int32_t *rcnt,
+                            int32_t *toff, int32_t *tcnt, int32_t *cursor, int32_t maxt,
+                            hipStream_t s);
+hipError_t launch_rev_scatter(const int32_t *adj, const int32_t *deg, const int32_t *perm,
+                              int32_t b0, int32_t nb, int32_t R, const int32_t *tidx,
+                              const int32_t *toff, const int32_t *ticket, int32_t *seg,
+                              hipStream_t s);
+hipError_t launch_min_key(const uint64_t *key, int64_t n, uint64_t *out, hipStream_t s);
+hipError_t launch_dep_in_knn(int64_t n, int32_t k, const uint64_t *key, const uint64_t *minkey,
+                             const int32_t *knn_idx, const float *knn_dist, int32_t *dep,
+                             float *delta, int32_t *ulist, int32_t *ucount, hipStream_t s);
+hipError_t launch_bf_dep_finalize(const int32_t *ulist, const int32_t *ucount,
+                                  const unsigned long long *best, int32_t metric, int32_t *dep,
+                                  float *delta, int32_t maxu, hipStream_t s);
+hipError_t launch_copy_count(const int32_t *src, int32_t *dst, int32_t nmax, hipStream_t s);
+hipError_t launch_cluster(int64_t n, const float *rho, const int32_t *dep, const float *delta,
+                          int32_t center_mode, int32_t n_c, float delta_min, float rho_min,
+                          int32_t *labels, uint8_t *is_center, uint64_t *gkey, int32_t *flag,
+                          hipStream_t s);
+
+}  // namespace pecann

@@ -1,0 +1,417 @@
+// Non-templated kernels of the hot path:
+//   K0  prepare       -- search/rerank copies of the point set (BF16, FP8, U8, F32)
+//   K9a-c rev_*       -- group a batch's reverse edges by target (count, allocate, scatter)
+//   K5  dep_in_knn    -- DPBruteForce over each point's kNN list (Alg. 3, first loop)
+//   K7' bf_dep_finalize, min_key, fills
+//   K10 select_centers (radix select of the n_c largest rho*delta) + noise mask
+//   K11 labels        -- roots of the dependent forest by pointer jumping
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+
+namespace pecann {
+
+// ---------------------------------------------------------------------------
+// K0: one wavefront per row.  Reads the caller's row (F32 or U8), divides by
+// its norm for the cosine metric, writes the float32 rerank row (if any) and
+// the search row: F32 copy, U8 copy, BF16 round-to-nearest-even, or FP8 e4m3
+// of x / scale with scale = max|x| / 448 (OCP e4m3 largest normal).
+// Padding up to the 16-byte row stride is written as zeros.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__global__ __launch_bounds__(256) void prepare_kernel(const void *x, int32_t x_dtype, int64_t x_stride,
+                                                      int64_t n, int32_t d, int32_t metric,
+                                                      int32_t sdt, RowsDesc r, uint8_t *xs,
+                                                      float *xr, float *scale) {
+  const int l = lane_id();
+  const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (row >= n) return;
+  constexpr int kMaxPerLane = 64;  // d <= 4096
+  float v[kMaxPerLane];
+  float ss = 0.f, mx = 0.f;
+#pragma unroll
+  for (int t = 0; t < kMaxPerLane; ++t) {
+    const int e = l + 64 * t;
+    float f = 0.f;
+    if (e < d) {
+      if (x_dtype == PECANN_U8) f = (float)((const uint8_t *)x)[row * x_stride + e];
+      else f = ((const float *)x)[row * x_stride + e];
+    }
+    v[t] = f;
+    ss = fmaf(f, f, ss);
+  }
+  if (metric == PECANN_COSINE) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) ss += __shfl_xor(ss, m);
+    const float inv = ss > 0.f ? 1.0f / sqrtf(ss) : 0.f;
+#pragma unroll
+    for (int t = 0; t < kMaxPerLane; ++t) v[t] *= inv;
+  }
+  if (xr) {
+    float *o = xr + row * r.xr_stride;
+    for (int t = 0; t < kMaxPerLane; ++t) {
+      const int e = l + 64 * t;
+      if (e < r.xr_stride) o[e] = e < d ? v[t] : 0.f;
+    }
+  }
+  uint8_t *o = xs + row * r.xs_stride;
+  if (sdt == PECANN_F32) {
+    float *of = (float *)o;
+    const int64_t cap = r.xs_stride / 4;
+    for (int t = 0; t < kMaxPerLane; ++t) {
+      const int e = l + 64 * t;
+      if (e < cap) of[e] = e < d ? v[t] : 0.f;
+    }
+  } else if (sdt == PECANN_U8) {
+    for (int t = 0; t < kMaxPerLane; ++t) {
+      const int e = l + 64 * t;
+      if (e < r.xs_stride) o[e] = e < d ? (uint8_t)v[t] : (uint8_t)0;
+    }
+  } else if (sdt == PECANN_BF16) {
+    uint16_t *ob = (uint16_t *)o;
+    const int64_t cap = r.xs_stride / 2;
+    for (int t = 0; t < kMaxPerLane; ++t) {
+      const int e = l + 64 * t;
+      if (e < cap) ob[e] = e < d ? f32_to_bf16_rne(v[t]) : (uint16_t)0;
+    }
+  } else {  // FP8 e4m3
+#pragma unroll
+    for (int t = 0; t < kMaxPerLane; ++t) mx = fmaxf(mx, fabsf(v[t]));
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
+    const float inv = mx > 0.f ? 448.0f / mx : 1.0f;
+    if (l == 0) scale[row] = 1.0f / inv;
+    for (int t = 0; t < kMaxPerLane; ++t) {
+      const int e = l + 64 * t;
+      if (e < r.xs_stride) {
+        const float f = e < d ? fminf(448.0f, fmaxf(-448.0f, v[t] * inv)) : 0.f;
+        const int w = __builtin_amdgcn_cvt_pk_fp8_f32(f, 0.f, 0, false);
+        o[e] = (uint8_t)(w & 0xff);
+      }
+    }
+  }
+}
+
+hipError_t launch_prepare(const void *x, int32_t x_dtype, int64_t x_stride, int64_t n, int32_t d,
+                          int32_t metric, int32_t sdt, const RowsDesc &rows, uint8_t *xs,
+                          float *xr, float *scale, hipStream_t s) {
+  const int64_t blocks = (n + 3) / 4;
+  hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, x_dtype, x_stride,
+                     n, d, metric, sdt, rows, xs, xr, scale);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fills (graph-capture safe: kernels, not memset nodes).
+// ---------------------------------------------------------------------------
+__global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void fill_u64_kernel(uint64_t *p, uint64_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void identity_kernel(int32_t *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (int32_t)i;
+}
+static unsigned grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_identity_perm(int32_t *p, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(identity_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K9a-c: reverse edges of a batch grouped by target.
+//   count:   rcnt[q] += 1 per edge (p -> q); the first edge to reach q puts q in
+//            the target list; each edge keeps its arrival ticket;
+//   alloc:   each target reserves a segment of rcnt[q] slots;
+//   scatter: source p goes to slot (segment of q) + ticket.
+// Arrival order is not deterministic; the merge sorts each segment by index.
+// ---------------------------------------------------------------------------
+__global__ void rev_count_kernel(const int32_t *adj, const int32_t *deg, const int32_t *perm,
+                                 int32_t b0, int32_t nb, int32_t R, int32_t *rcnt,
+                                 int32_t *ntargets, int32_t *tlist, int32_t *tidx,
+                                 int32_t *ticket) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nb * R) return;
+  const int t = (int)(i / R), e = (int)(i % R);
+  const int32_t p = perm[b0 + t];
+  if (e >= deg[p]) return;
+  const int32_t q = adj[(int64_t)p * R + e];
+  const int slot = atomicAdd(&rcnt[q], 1);
+  ticket[i] = slot;
+  if (slot == 0) {
+    const int u = atomicAdd(ntargets, 1);
+    tlist[u] = q;
+    tidx[q] = u;
+  }
+}
+__global__ void rev_alloc_kernel(const int32_t *tlist, const int32_t *ntargets, const int32_t *rcnt,
+                                 int32_t *toff, int32_t *tcnt, int32_t *cursor, int32_t maxt) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= maxt || u >= *ntargets) return;
+  const int c = rcnt[tlist[u]];
+  tcnt[u] = c;
+  toff[u] = atomicAdd(cursor, c);
+}
+__global__ void rev_scatter_kernel(const int32_t *adj, const int32_t *deg, const int32_t *perm,
+                                   int32_t b0, int32_t nb, int32_t R, const int32_t *tidx,
+                                   const int32_t *toff, const int32_t *ticket, int32_t *seg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nb * R) return;
+  const int t = (int)(i / R), e = (int)(i % R);
+  const int32_t p = perm[b0 + t];
+  if (e >= deg[p]) return;
+  const int32_t q = adj[(int64_t)p * R + e];
+  seg[toff[tidx[q]] + ticket[i]] = p;
+}
+hipError_t launch_rev_count(const int32_t *adj, const int32_t *deg, const int32_t *perm, int32_t b0,
+                            int32_t nb, int32_t R, int32_t *rcnt, int32_t *ntargets,
+                            int32_t *tlist, int32_t *tidx, int32_t *ticket, hipStream_t s) {
+  const int64_t tot = (int64_t)nb * R;
+  hipLaunchKernelGGL(rev_count_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, adj,
+                     deg, perm, b0, nb, R, rcnt, ntargets, tlist, tidx, ticket);
+  return hipGetLastError();
+}
+hipError_t launch_rev_alloc(const int32_t *tlist, const int32_t *ntargets, const int32_t *rcnt,
+                            int32_t *toff, int32_t *tcnt, int32_t *cursor, int32_t maxt,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(rev_alloc_kernel, dim3((unsigned)((maxt + 255) / 256)), dim3(256), 0, s,
+                     tlist, ntargets, rcnt, toff, tcnt, cursor, maxt);
+  return hipGetLastError();
+}
+hipError_t launch_rev_scatter(const int32_t *adj, const int32_t *deg, const int32_t *perm,
+                              int32_t b0, int32_t nb, int32_t R, const int32_t *tidx,
+                              const int32_t *toff, const int32_t *ticket, int32_t *seg,
+                              hipStream_t s) {
+  const int64_t tot = (int64_t)nb * R;
+  hipLaunchKernelGGL(rev_scatter_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, adj,
+                     deg, perm, b0, nb, R, tidx, toff, ticket, seg);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Smallest rank key (the densest point), one workgroup.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void min_key_kernel(const uint64_t *key, int64_t n, uint64_t *out) {
+  __shared__ uint64_t part[16];
+  uint64_t m = kNoKey;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) m = key[i] < m ? key[i] : m;
+  m = wave_min_u64(m);
+  if (lane_id() == 0) part[threadIdx.x / 64] = m;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    uint64_t v = threadIdx.x < 16 ? part[threadIdx.x] : kNoKey;
+    v = wave_min_u64(v);
+    if (threadIdx.x == 0) *out = v;
+  }
+}
+hipError_t launch_min_key(const uint64_t *key, int64_t n, uint64_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(min_key_kernel, dim3(1), dim3(1024), 0, s, key, n, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K5: DPBruteForce over the kNN list.  The list is in (distance, index) order,
+// so the first entry of strictly smaller rank key is the argmin.  The densest
+// point gets no dependent; the others left without one join the unfinished list.
+// ---------------------------------------------------------------------------
+__global__ void dep_in_knn_kernel(int64_t n, int32_t k, const uint64_t *key, const uint64_t *minkey,
+                                  const int32_t *knn_idx, const float *knn_dist, int32_t *dep,
+                                  float *delta, int32_t *ulist, int32_t *ucount) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t ki = key[i];
+  if (ki == *minkey) {
+    dep[i] = -1;
+    delta[i] = __int_as_float(0x7f800000);
+    return;
+  }
+  for (int t = 0; t < k; ++t) {
+    const int32_t j = knn_idx[i * k + t];
+    if (j >= 0 && key[j] < ki) {
+      dep[i] = j;
+      delta[i] = knn_dist[i * k + t];
+      return;
+    }
+  }
+  dep[i] = -1;
+  delta[i] = __int_as_float(0x7f800000);
+  ulist[atomicAdd(ucount, 1)] = (int32_t)i;
+}
+hipError_t launch_dep_in_knn(int64_t n, int32_t k, const uint64_t *key, const uint64_t *minkey,
+                             const int32_t *knn_idx, const float *knn_dist, int32_t *dep,
+                             float *delta, int32_t *ulist, int32_t *ucount, hipStream_t s) {
+  hipLaunchKernelGGL(dep_in_knn_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, k,
+                     key, minkey, knn_idx, knn_dist, dep, delta, ulist, ucount);
+  return hipGetLastError();
+}
+
+__global__ void bf_dep_finalize_kernel(const int32_t *ulist, const int32_t *ucount,
+                                       const unsigned long long *best, int32_t metric, int32_t *dep,
+                                       float *delta, int32_t maxu) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= maxu || u >= *ucount) return;
+  const uint64_t b = best[u];
+  if (b == kNoKey) return;
+  const int32_t i = ulist[u];
+  dep[i] = key_id(b);
+  delta[i] = measure_to_dist(key_measure(b), metric);
+}
+hipError_t launch_bf_dep_finalize(const int32_t *ulist, const int32_t *ucount,
+                                  const unsigned long long *best, int32_t metric, int32_t *dep,
+                                  float *delta, int32_t maxu, hipStream_t s) {
+  hipLaunchKernelGGL(bf_dep_finalize_kernel, dim3((unsigned)((maxu + 255) / 256)), dim3(256), 0, s,
+                     ulist, ucount, best, metric, dep, delta, maxu);
+  return hipGetLastError();
+}
+
+__global__ void copy_count_kernel(const int32_t *src, int32_t *dst) {
+  if (threadIdx.x == 0) *dst = *src;
+}
+hipError_t launch_copy_count(const int32_t *src, int32_t *dst, int32_t, hipStream_t s) {
+  hipLaunchKernelGGL(copy_count_kernel, dim3(1), dim3(64), 0, s, src, dst);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K10 + K11: noise, centers, labels.
+// gkey[i] = 0 for noise; else (bits(gamma_i) << 32) | (0xffffffff - i), so the
+// n_c largest keys are the n_c largest gamma with ties to the lower index.
+// ---------------------------------------------------------------------------
+__global__ void gamma_kernel(int64_t n, const float *rho, const float *delta, int32_t center_mode,
+                             float delta_min, float rho_min, uint64_t *gkey, uint8_t *is_center) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool noise = rho[i] < rho_min;
+  if (center_mode == PECANN_CENTER_PRODUCT) {
+    float g = rho[i] * delta[i];
+    if (g != g) g = 0.f;  // inf * 0
+    gkey[i] = noise ? 0ull : (((uint64_t)__float_as_uint(g) << 32) | (uint32_t)(0xffffffffu - (uint32_t)i));
+    is_center[i] = 0;
+  } else {
+    gkey[i] = noise ? 1ull : 0ull;  // noise flag for the label step
+    is_center[i] = (!noise && delta[i] >= delta_min) ? 1 : 0;
+  }
+}
+
+// Radix select (8 passes of 8 bits) of the n_c-th largest key; marks centers.
+__global__ __launch_bounds__(1024) void select_kernel(int64_t n, int32_t n_c, const uint64_t *gkey,
+                                                       uint8_t *is_center) {
+  __shared__ int32_t hist[256];
+  __shared__ uint64_t s_prefix;
+  __shared__ int32_t s_need;
+  __shared__ int32_t s_nonnoise;
+  if (threadIdx.x == 0) { s_prefix = 0; s_need = n_c; s_nonnoise = 0; }
+  __syncthreads();
+  {
+    int c = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) c += gkey[i] != 0;
+    c = wave_sum_i32(c);
+    if (lane_id() == 0) atomicAdd(&s_nonnoise, c);
+  }
+  __syncthreads();
+  uint64_t thr;
+  if (s_nonnoise <= n_c) {
+    thr = 1;  // every non-noise point is a center
+  } else {
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      for (int b = threadIdx.x; b < 256; b += 1024) hist[b] = 0;
+      __syncthreads();
+      const uint64_t prefix = s_prefix;
+      const uint64_t hmask = shift == 56 ? 0ull : (~0ull << (shift + 8));
+      for (int64_t i = threadIdx.x; i < n; i += 1024) {
+        const uint64_t k = gkey[i];
+        if ((k & hmask) == prefix) atomicAdd(&hist[(k >> shift) & 0xff], 1);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int need = s_need;
+        int b = 255;
+        for (; b > 0; --b) {
+          if (hist[b] >= need) break;
+          need -= hist[b];
+        }
+        s_need = need;
+        s_prefix = prefix | ((uint64_t)b << shift);
+      }
+      __syncthreads();
+    }
+    thr = s_prefix;
+  }
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const uint64_t k = gkey[i];
+    is_center[i] = (k != 0 && k >= thr) ? 1 : 0;
+  }
+}
+
+__global__ void parent_kernel(int64_t n, const int32_t *dep, const uint8_t *is_center,
+                              const uint64_t *gkey, const float *rho, float rho_min,
+                              int32_t *labels) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool noise = rho[i] < rho_min;
+  const int32_t d = dep[i];
+  const bool root = noise || is_center[i] || d < 0 || d >= n;  // out-of-range ids end a path
+  labels[i] = root ? (int32_t)i : d;
+}
+
+// Pointer jumping: every value ever stored is an ancestor on the same path, so
+// concurrent updates only speed convergence.  `flag` records a path that did not
+// end within the step bound (a cycle: dependent pointers that do not go up).
+__global__ void jump_kernel(int64_t n, int32_t *labels, int32_t *flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t cur = __hip_atomic_load(&labels[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int64_t step = 0; step <= n; ++step) {
+    const int32_t nxt = __hip_atomic_load(&labels[cur], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (nxt == cur) {
+      __hip_atomic_store(&labels[i], cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    cur = nxt;
+    __hip_atomic_store(&labels[i], cur, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  atomicAdd(flag, 1);
+}
+
+hipError_t launch_cluster(int64_t n, const float *rho, const int32_t *dep, const float *delta,
+                          int32_t center_mode, int32_t n_c, float delta_min, float rho_min,
+                          int32_t *labels, uint8_t *is_center, uint64_t *gkey, int32_t *flag,
+                          hipStream_t s) {
+  const unsigned b = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(gamma_kernel, dim3(b), dim3(256), 0, s, n, rho, delta, center_mode, delta_min,
+                     rho_min, gkey, is_center);
+  if (center_mode == PECANN_CENTER_PRODUCT)
+    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(1024), 0, s, n, n_c, gkey, is_center);
+  hipLaunchKernelGGL(parent_kernel, dim3(b), dim3(256), 0, s, n, dep, is_center, gkey, rho, rho_min,
+                     labels);
+  hipLaunchKernelGGL(jump_kernel, dim3(b), dim3(256), 0, s, n, labels, flag);
+  return hipGetLastError();
+}
+
+}  // namespace pecann

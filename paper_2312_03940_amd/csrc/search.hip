@@ -1,0 +1,239 @@
+// K2 greedy beam search (Alg. 1), one wavefront per query, persistent over a
+// device work queue.  Three epilogues share the walk:
+//   MODE_KNN   kNN + kth density of a point (Alg. 2 Find-Knn / F_density),
+//   MODE_DEP   one doubling round of ComputeDepPts (Alg. 3),
+//   MODE_BUILD the search of a batched Vamana insertion (visited set V).
+//
+// LDS per wavefront: two beam buffers of L keys + flags, 64 keys of merge
+// scratch, 64 ids of distance work, and the visited hash.
+#include "beam.hpp"
+
+namespace pecann {
+
+namespace {
+
+struct Lds {
+  SortedList beam;
+  IdHash hash;
+  int32_t *cid;  // 64 ids awaiting distances
+};
+
+__device__ __forceinline__ Lds carve(uint8_t *smem, int L, int hbits) {
+  Lds s;
+  uint64_t *p = (uint64_t *)smem;
+  s.beam.a = p;
+  s.beam.b = p + L;
+  s.beam.tmp = p + 2 * L;
+  s.cid = (int32_t *)(p + 2 * L + 64);
+  uint8_t *f = (uint8_t *)(s.cid + 64);
+  const int Lp = (L + 15) & ~15;
+  s.beam.fa = f;
+  s.beam.fb = f + Lp;
+  s.hash.slot = (int32_t *)(f + 2 * Lp);
+  s.hash.bits = hbits;
+  s.beam.cap = L;
+  s.beam.m = 0;
+  return s;
+}
+
+// Distances for the ids given one per lane (-1 = none), then merge into the beam.
+template <int DT, int G>
+__device__ __forceinline__ void score_and_merge(const Engine<DT, G> &eng, const Rows &rows, Lds &s,
+                                                int32_t myid) {
+  constexpr int NPL = Engine<DT, G>::NPL;
+  const int l = lane_id();
+  const uint64_t bm = ballot(myid >= 0);
+  const int c = __popcll(bm);
+  if (c == 0) return;
+  if (myid >= 0) s.cid[lanes_below(bm)] = myid;
+  wave_lds_sync();
+  const int grp = l / G;
+  const bool leader = (l % G) == 0;
+  for (int base = 0; base < c; base += NPL) {
+    const int ci = base + grp;
+    const int32_t row = ci < c ? s.cid[ci] : -1;
+    const float m = eng.measure(rows, row);
+    if (leader && ci < c) s.beam.tmp[ci] = make_key(m, row);
+  }
+  wave_lds_sync();
+  const uint64_t key = l < c ? s.beam.tmp[l] : kNoKey;
+  wave_lds_sync();
+  s.beam.merge(key);
+}
+
+// Add the out-neighbours of point v to the beam (ids seen before are skipped).
+template <int DT, int G>
+__device__ __forceinline__ void expand(const Engine<DT, G> &eng, const SearchParams &p, Lds &s,
+                                       int32_t v) {
+  const int dg = min(p.deg[v], p.R);
+  const int32_t *row = p.adj + (int64_t)v * p.R;
+  for (int e0 = 0; e0 < dg; e0 += kWave) {
+    const int e = e0 + lane_id();
+    int32_t nb = e < dg ? row[e] : -1;
+    if (nb >= p.n) nb = -1;  // ids outside the point set are ignored
+    if (nb >= 0 && !s.hash.insert(nb)) nb = -1;
+    score_and_merge<DT, G>(eng, p.rows, s, nb);
+  }
+}
+
+// Re-score the first r beam entries from float32 rows and sort them (into beam.a).
+template <int G>
+__device__ __forceinline__ void rerank_beam(const SearchParams &p, Lds &s, int32_t qid, int r) {
+  constexpr int NPL = Engine32<G>::NPL;
+  Engine32<G> e32;
+  e32.load_query(p.rows, qid);
+  const int l = lane_id();
+  for (int base = 0; base < r; base += NPL) {
+    const int ci = base + l / G;
+    const int32_t row = ci < r ? key_id(s.beam.a[ci]) : -1;
+    const float m = e32.measure(p.rows, row);
+    if ((l % G) == 0 && ci < r) s.beam.b[ci] = make_key(m, row);
+  }
+  wave_lds_sync();
+  lds_rank_sort(s.beam.b, s.beam.a, r);
+}
+
+}  // namespace
+
+template <int DT, int G>
+__global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  Lds s = carve(smem, p.L, p.hbits);
+  const int l = lane_id();
+  const int count = p.item_count ? *p.item_count : p.nitems;
+  constexpr bool kNeedRerank = (DT == PECANN_BF16 || DT == PECANN_FP8E4M3);
+
+  if (p.mode == MODE_DEP && count <= p.threshold) {
+    // Few enough points are left: this round is skipped and the list carried over.
+    if (blockIdx.x == 0) {
+      for (int u = l; u < count; u += kWave) p.u_out[u] = p.items[u];
+      if (l == 0) *p.u_out_count = count;
+    }
+    return;
+  }
+
+  Engine<DT, G> eng;
+  for (;;) {
+    const int it = next_item(p.head);
+    if (it >= count) break;
+    const int32_t qid = p.items ? p.items[it] : it;
+
+    s.hash.clear();
+    s.beam.m = 0;
+    wave_lds_sync();
+    eng.load_query(p.rows, qid);
+    if (l == 0) s.hash.insert(qid);  // the query never takes a beam slot
+    wave_lds_sync();
+
+    // S = {query} u starts, or S = starts for an insertion.  A query that is
+    // itself a start is expanded at once (it never takes a beam slot).
+    bool self_start = (p.mode != MODE_BUILD);
+    for (int s0 = 0; s0 < p.nstarts && !self_start; s0 += kWave)
+      self_start = ballot(s0 + l < p.nstarts && p.starts[s0 + l] == qid) != 0;
+    if (self_start) expand<DT, G>(eng, p, s, qid);
+    for (int s0 = 0; s0 < p.nstarts; s0 += kWave) {
+      int32_t id = s0 + l < p.nstarts ? p.starts[s0 + l] : -1;
+      if (id >= 0 && !s.hash.insert(id)) id = -1;
+      score_and_merge<DT, G>(eng, p.rows, s, id);
+    }
+
+    int nv = 0;
+    for (;;) {
+      const int j = s.beam.first_unflagged();
+      if (j < 0) break;
+      const uint64_t kj = s.beam.a[j];
+      wave_lds_sync();
+      if (l == 0) {
+        s.beam.fa[j] = 1;
+        if (p.mode == MODE_BUILD && nv < p.vcap) p.vis[(int64_t)it * p.vcap + nv] = kj;
+      }
+      ++nv;
+      wave_lds_sync();
+      expand<DT, G>(eng, p, s, key_id(kj));
+    }
+
+    const int m = s.beam.m;
+    if (p.mode == MODE_BUILD) {
+      if (l == 0) p.vis_count[it] = nv;
+    } else if (p.mode == MODE_KNN) {
+      int mm = m;
+      if (kNeedRerank && m > 0) {
+        mm = min(m, p.rerank);
+        rerank_beam<G>(p, s, qid, mm);
+      }
+      if (mm < p.k) {
+        if (l == 0) {
+          const int slot = atomicAdd(p.fb_count, 1);
+          p.fb_list[slot] = qid;
+        }
+      } else {
+        const int64_t o = (int64_t)qid * p.k;
+        for (int t = l; t < p.k; t += kWave) {
+          const uint64_t kt = s.beam.a[t];
+          p.knn_idx[o + t] = key_id(kt);
+          p.knn_dist[o + t] = measure_to_dist(key_measure(kt), p.rows.metric);
+        }
+        if (l == 0) {
+          const uint64_t kk = s.beam.a[p.k - 1];
+          const float dk = measure_to_dist(key_measure(kk), p.rows.metric);
+          p.rho[qid] = 1.0f / dk;
+          p.rank_key[qid] = (kk & 0xffffffff00000000ull) | (uint32_t)qid;
+        }
+      }
+    } else {  // MODE_DEP
+      int c = min(m, p.kdep);
+      if (kNeedRerank && c > 0) rerank_beam<G>(p, s, qid, c);
+      const uint64_t ki = p.key_in[qid];
+      uint64_t best = kNoKey;
+      for (int t = l; t < c; t += kWave) {
+        const uint64_t kt = s.beam.a[t];
+        if (p.key_in[key_id(kt)] < ki && kt < best) best = kt;
+      }
+      best = wave_min_u64(best);
+      if (l == 0) {
+        if (best != kNoKey) {
+          p.dep[qid] = key_id(best);
+          p.delta[qid] = measure_to_dist(key_measure(best), p.rows.metric);
+        } else {
+          const int slot = atomicAdd(p.u_out_count, 1);
+          p.u_out[slot] = qid;
+        }
+      }
+    }
+    wave_lds_sync();
+  }
+}
+
+size_t search_lds_bytes(int L, int hbits) {
+  const size_t Lp = (size_t)((L + 15) & ~15);
+  return 8 * (2 * (size_t)L + 64) + 4 * 64 + 2 * Lp + 4 * ((size_t)1 << hbits);
+}
+
+template <int DT, int G>
+static hipError_t launch_search_t(const SearchParams &p, int grid, hipStream_t st) {
+  const size_t lds = search_lds_bytes(p.L, p.hbits);
+  hipLaunchKernelGGL((search_kernel<DT, G>), dim3(grid), dim3(64), lds, st, p);
+  return hipGetLastError();
+}
+
+#define PECANN_DISPATCH_G(FN, DT, ...)                      \
+  switch (G) {                                              \
+    case 4: return FN<DT, 4>(__VA_ARGS__);                  \
+    case 8: return FN<DT, 8>(__VA_ARGS__);                  \
+    case 16: return FN<DT, 16>(__VA_ARGS__);                \
+    case 32: return FN<DT, 32>(__VA_ARGS__);                \
+    case 64: return FN<DT, 64>(__VA_ARGS__);                \
+    default: return hipErrorInvalidValue;                   \
+  }
+
+hipError_t launch_search(int32_t dt, int G, const SearchParams &p, int grid, hipStream_t st) {
+  switch (dt) {
+    case PECANN_F32: PECANN_DISPATCH_G(launch_search_t, PECANN_F32, p, grid, st)
+    case PECANN_U8: PECANN_DISPATCH_G(launch_search_t, PECANN_U8, p, grid, st)
+    case PECANN_BF16: PECANN_DISPATCH_G(launch_search_t, PECANN_BF16, p, grid, st)
+    case PECANN_FP8E4M3: PECANN_DISPATCH_G(launch_search_t, PECANN_FP8E4M3, p, grid, st)
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pecann

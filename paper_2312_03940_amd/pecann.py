@@ -1,0 +1,228 @@
+"""Thin ctypes binding of libpecann.so (include/pecann.h).
+
+Argument marshalling only: tensors are passed as raw device pointers together
+with torch's current HIP stream; every step of the computation runs in the
+library's kernels.  There is no fallback: if the library is missing, or no
+GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpecann.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "pecann.h")
+
+F32, U8, BF16, FP8E4M3 = 0, 1, 2, 3
+L2, COSINE = 0, 1
+CENTER_PRODUCT, CENTER_THRESHOLD = 0, 1
+DTYPES = {"f32": F32, "u8": U8, "bf16": BF16, "fp8": FP8E4M3}
+METRICS = {"l2": L2, "cosine": COSINE}
+
+
+class PecannError(RuntimeError):
+    pass
+
+
+class _Dataset(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("metric", ctypes.c_int32),
+                ("search_dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("prep", ctypes.c_void_p)]
+
+
+class _BuildParams(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_int32), ("L", ctypes.c_int32), ("alpha", ctypes.c_float),
+                ("num_starts", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("visited_cap", ctypes.c_int32), ("passes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def header_functions():
+    """Names of the functions declared in include/pecann.h."""
+    with open(HEADER) as f:
+        txt = f.read()
+    return sorted(set(re.findall(r"\b(pecann_[a-z_0-9]+)\s*\(", txt)))
+
+
+def load():
+    """Load libpecann.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise PecannError(f"{LIB_PATH} is missing: build it with `python -m paper_2312_03940_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
+    D = ctypes.POINTER(_Dataset)
+    B = ctypes.POINTER(_BuildParams)
+    sig = {
+        "pecann_prepared_bytes": (sz, [i64, i32, i32, i32]),
+        "pecann_prepare_vectors": (ctypes.c_int, [vp, i32, i64, i64, i32, i32, i32, vp, sz, vp]),
+        "pecann_build_graph_workspace_size": (sz, [D, B]),
+        "pecann_build_graph": (ctypes.c_int, [D, B, vp, ctypes.c_uint64, vp, vp, vp, sz, vp]),
+        "pecann_knn_density_workspace_size": (sz, [D, i32, i32]),
+        "pecann_knn_density": (ctypes.c_int, [D, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp, sz,
+                                              vp]),
+        "pecann_dependent_search_workspace_size": (sz, [D, i32, i32]),
+        "pecann_dependent_search": (ctypes.c_int, [D, vp, vp, i32, vp, vp, vp, i32, i32, i32, i32,
+                                                   i32, vp, vp, vp, vp, sz, vp]),
+        "pecann_cluster_workspace_size": (sz, [i64]),
+        "pecann_cluster": (ctypes.c_int, [i64, vp, vp, vp, i32, i32, f32, f32, vp, vp, vp, sz, vp]),
+        "pecann_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "pecann_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        lib = load()
+        raise PecannError(f"{lib.pecann_status_string(rc).decode()}: {lib.pecann_last_error().decode()}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise PecannError("tensors must live on the GPU")
+
+
+def _ws(nbytes: int, device):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+class Dataset:
+    """A prepared point set (pecann_prepare_vectors output) kept on the GPU."""
+
+    def __init__(self, x: torch.Tensor, metric="l2", search_dtype="f32"):
+        _need_cuda(x)
+        lib = load()
+        if x.dim() != 2:
+            raise PecannError("x must be 2-D (n, d)")
+        if x.dtype == torch.float32:
+            xdt = F32
+        elif x.dtype == torch.uint8:
+            xdt = U8
+        else:
+            raise PecannError("x must be float32 or uint8")
+        if x.stride(1) != 1:
+            x = x.contiguous()
+        self.n, self.d = x.shape
+        self.metric = METRICS[metric] if isinstance(metric, str) else int(metric)
+        self.search_dtype = DTYPES[search_dtype] if isinstance(search_dtype, str) else int(search_dtype)
+        nb = lib.pecann_prepared_bytes(self.n, self.d, self.metric, self.search_dtype)
+        if nb == 0:
+            raise PecannError("invalid (n, d, metric, search dtype)")
+        self.prep = torch.empty(nb, dtype=torch.uint8, device=x.device)
+        _check(lib.pecann_prepare_vectors(_ptr(x), xdt, x.stride(0), self.n, self.d, self.metric,
+                                          self.search_dtype, _ptr(self.prep), nb, _stream()))
+        self.device = x.device
+
+    @property
+    def struct(self):
+        return _Dataset(self.n, self.d, self.metric, self.search_dtype, 0, self.prep.data_ptr())
+
+
+def build_graph(ds: Dataset, R: int, L: int, alpha: float, num_starts: int = 8,
+                max_batch: int = 0, visited_cap: int = 0, perm: torch.Tensor | None = None,
+                seed: int = 0, passes: int = 2, ws: torch.Tensor | None = None):
+    """Batched Vamana construction.  -> (adj int32 [n, R], deg int32 [n])."""
+    lib = load()
+    s = ds.struct
+    bp = _BuildParams(R, L, alpha, num_starts, max_batch, visited_cap, passes, 0)
+    need = lib.pecann_build_graph_workspace_size(ctypes.byref(s), ctypes.byref(bp))
+    if need == 0:
+        raise PecannError("invalid build parameters")
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, ds.device)
+    if perm is not None:
+        _need_cuda(perm)
+        if perm.dtype != torch.int32 or perm.numel() != ds.n:
+            raise PecannError("perm must be int32 with n entries")
+    adj = torch.empty((ds.n, R), dtype=torch.int32, device=ds.device)
+    deg = torch.empty(ds.n, dtype=torch.int32, device=ds.device)
+    _check(lib.pecann_build_graph(ctypes.byref(s), ctypes.byref(bp), _ptr(perm), seed, _ptr(adj),
+                                  _ptr(deg), _ptr(ws), ws.numel(), _stream()))
+    return adj, deg
+
+
+def knn_density(ds: Dataset, k: int, adj=None, deg=None, L_search: int = 64, rerank: int | None = None,
+                ws: torch.Tensor | None = None, out=None):
+    """kNN + kth density.  -> (knn_idx int32 [n,k], knn_dist f32 [n,k], rho f32 [n], rank_key int64 [n])."""
+    lib = load()
+    s = ds.struct
+    R = 0 if adj is None else adj.shape[1]
+    if rerank is None:
+        rerank = min(L_search, max(k, 2 * k))
+    need = lib.pecann_knn_density_workspace_size(ctypes.byref(s), k, L_search)
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, ds.device)
+    if out is None:
+        out = (torch.empty((ds.n, k), dtype=torch.int32, device=ds.device),
+               torch.empty((ds.n, k), dtype=torch.float32, device=ds.device),
+               torch.empty(ds.n, dtype=torch.float32, device=ds.device),
+               torch.empty(ds.n, dtype=torch.int64, device=ds.device))
+    idx, dist, rho, key = out
+    _check(lib.pecann_knn_density(ctypes.byref(s), _ptr(adj), _ptr(deg), R, k, L_search, rerank,
+                                  _ptr(idx), _ptr(dist), _ptr(rho), _ptr(key), _ptr(ws), ws.numel(),
+                                  _stream()))
+    return idx, dist, rho, key
+
+
+def dependent_search(ds: Dataset, rank_key, knn_idx, knn_dist, adj=None, deg=None, L_d: int = 32,
+                     L_search: int = 64, threshold: int = 300, kdep_cap: int = 1024,
+                     ws: torch.Tensor | None = None, out=None):
+    """Alg. 3.  -> (dep int32 [n], delta f32 [n], stats int32 [32])."""
+    lib = load()
+    s = ds.struct
+    k = knn_idx.shape[1]
+    R = 0 if adj is None else adj.shape[1]
+    need = lib.pecann_dependent_search_workspace_size(ctypes.byref(s), kdep_cap, L_search)
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, ds.device)
+    if out is None:
+        out = (torch.empty(ds.n, dtype=torch.int32, device=ds.device),
+               torch.empty(ds.n, dtype=torch.float32, device=ds.device),
+               torch.zeros(32, dtype=torch.int32, device=ds.device))
+    dep, delta, stats = out
+    _check(lib.pecann_dependent_search(ctypes.byref(s), _ptr(adj), _ptr(deg), R, _ptr(rank_key),
+                                       _ptr(knn_idx), _ptr(knn_dist), k, L_d, L_search, threshold,
+                                       kdep_cap, _ptr(dep), _ptr(delta), _ptr(stats), _ptr(ws),
+                                       ws.numel(), _stream()))
+    return dep, delta, stats
+
+
+def cluster(rho, dep, delta, n_c: int = 1, center_mode: int = CENTER_PRODUCT,
+            delta_min: float = 0.0, rho_min: float = 0.0, ws: torch.Tensor | None = None, out=None):
+    """Noise, centers, labels.  -> (labels int32 [n], is_center uint8 [n])."""
+    lib = load()
+    n = rho.numel()
+    need = lib.pecann_cluster_workspace_size(n)
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, rho.device)
+    if out is None:
+        out = (torch.empty(n, dtype=torch.int32, device=rho.device),
+               torch.empty(n, dtype=torch.uint8, device=rho.device))
+    labels, isc = out
+    _check(lib.pecann_cluster(n, _ptr(rho), _ptr(dep), _ptr(delta), center_mode, n_c, delta_min,
+                              rho_min, _ptr(labels), _ptr(isc), _ptr(ws), ws.numel(), _stream()))
+    return labels, isc

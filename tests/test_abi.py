@@ -1,0 +1,88 @@
+"""Host-side checks of the C ABI: the library loads, exports every function the
+header declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import subprocess
+
+import pytest
+
+from paper_2312_03940_amd import pecann
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pecann.LIB_PATH):
+        pytest.fail("libpecann.so is not built (run __graft_entry__.build())")
+    return pecann.load()
+
+
+def test_exports_every_declared_function(lib):
+    names = pecann.header_functions()
+    assert len(names) >= 12
+    for nm in names:
+        assert hasattr(lib, nm), f"{nm} declared in include/pecann.h but not exported"
+    out = subprocess.run(["nm", "-D", "--defined-only", pecann.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    for nm in names:
+        assert nm in exported
+
+
+def test_header_is_plain_c():
+    # the boundary compiles as C with no HIP or torch types
+    src = os.path.join(ROOT, "include", "pecann.h")
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-x", "c", src],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_prepared_bytes_layout(lib):
+    # search rows padded to 16 bytes; float32 rerank rows only for BF16/FP8; FP8 scale
+    def up(v):  # sections start on 256-byte boundaries
+        return (v + 255) // 256 * 256
+
+    n = 1000
+    assert lib.pecann_prepared_bytes(n, 16, pecann.L2, pecann.F32) == up(64 * n)
+    assert lib.pecann_prepared_bytes(n, 784, pecann.L2, pecann.U8) == up(784 * n)
+    bf = lib.pecann_prepared_bytes(n, 128, pecann.L2, pecann.BF16)
+    assert bf == up(256 * n) + up(512 * n)
+    f8 = lib.pecann_prepared_bytes(n, 1024, pecann.COSINE, pecann.FP8E4M3)
+    assert f8 == up(1024 * n) + up(4096 * n) + up(4 * n)
+    assert lib.pecann_prepared_bytes(n, 5, pecann.L2, pecann.U8) == up(16 * n)
+    assert lib.pecann_prepared_bytes(n, 7, pecann.L2, pecann.F32) == up(32 * n)
+    # invalid combinations
+    assert lib.pecann_prepared_bytes(1, 16, pecann.L2, pecann.F32) == 0
+    assert lib.pecann_prepared_bytes(n, 0, pecann.L2, pecann.F32) == 0
+    assert lib.pecann_prepared_bytes(n, 4097, pecann.L2, pecann.F32) == 0
+    assert lib.pecann_prepared_bytes(n, 16, pecann.COSINE, pecann.U8) == 0
+    assert lib.pecann_prepared_bytes(n, 16, 7, pecann.F32) == 0
+
+
+def test_argument_errors_are_synchronous(lib):
+    ds = pecann._Dataset(100, 16, pecann.L2, pecann.F32, 0, None)
+    bp = pecann._BuildParams(16, 32, 1.2, 4, 0, 0, 2, 0)
+    # NULL prep pointer is rejected before any launch
+    rc = lib.pecann_build_graph(ctypes.byref(ds), ctypes.byref(bp), None, 0, None, None, None, 0, None)
+    assert rc == 1 and b"prep" in lib.pecann_last_error()
+    ds2 = pecann._Dataset(100, 16, pecann.L2, pecann.F32, 0, 256)
+    bad = pecann._BuildParams(16, 32, 0.9, 4, 0, 0, 2, 0)
+    rc = lib.pecann_build_graph(ctypes.byref(ds2), ctypes.byref(bad), None, 0, None, None, None, 0,
+                                None)
+    assert rc == 1 and b"alpha" in lib.pecann_last_error()
+    assert lib.pecann_build_graph_workspace_size(ctypes.byref(ds2), ctypes.byref(bad)) == 0
+    assert lib.pecann_build_graph_workspace_size(ctypes.byref(ds2), ctypes.byref(bp)) > 0
+    # k out of range
+    rc = lib.pecann_knn_density(ctypes.byref(ds2), None, None, 0, 100, 64, 64, None, None, None, None,
+                                None, 0, None)
+    assert rc == 1
+    # cluster: n_c out of range, bad mode
+    rc = lib.pecann_cluster(10, 256, 256, 256, 0, 11, 0.0, 0.0, 256, 256, 256, 1 << 20, None)
+    assert rc == 1 and b"n_c" in lib.pecann_last_error()
+    rc = lib.pecann_cluster(10, 256, 256, 256, 5, 1, 0.0, 0.0, 256, 256, 256, 1 << 20, None)
+    assert rc == 1
+    # workspace too small
+    rc = lib.pecann_cluster(10, 256, 256, 256, 0, 1, 0.0, 0.0, 256, 256, 256, 8, None)
+    assert rc == 2
+    assert lib.pecann_status_string(2) == b"workspace too small"

@@ -1,0 +1,282 @@
+"""GPU path vs the CPU oracle, element by element, through the C ABI.
+
+Integer-grid inputs make every float32 squared distance an exact integer, so the
+GPU's float32 arithmetic and the oracle's FP64 agree exactly on every comparison:
+there the bar is bit-exact indices, graphs and labels, and distances within float32
+rounding of a square root.  Float inputs use the margin rule (a decision may differ
+only where the oracle's own gap is below float32 resolution).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import metrics
+from paper_2312_03940_amd import datagen, pecann
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    pecann.load()
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _exact_gpu(X, k, n_c, dev, metric="l2", sdt="f32"):
+    ds = pecann.Dataset(_t(X, dev), metric, sdt)
+    idx, dist, rho, key = pecann.knn_density(ds, k)
+    dep, delta, stats = pecann.dependent_search(ds, key, idx, dist)
+    labels, isc = pecann.cluster(rho, dep, delta, n_c=n_c)
+    return dict(knn_idx=_np(idx), knn_dist=_np(dist), rho=_np(rho),
+                key=_np(key).view(np.uint64), dep=_np(dep), delta=_np(delta), labels=_np(labels),
+                is_center=_np(isc).astype(bool), stats=_np(stats))
+
+
+# ----------------------------------------------------------------------------
+# K0 prepare
+# ----------------------------------------------------------------------------
+def _bf16_rne(x):
+    u = x.astype(np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    return r
+
+
+def _fp8_e4m3_decode(b):
+    """OCP e4m3fn: 1 sign, 4 exponent (bias 7), 3 mantissa; S.1111.111 is NaN."""
+    b = b.astype(np.int64)
+    s = np.where(b & 0x80, -1.0, 1.0)
+    e = (b >> 3) & 0xF
+    m = b & 0x7
+    val = np.where(e == 0, m / 8.0 * 2.0 ** -6, (1 + m / 8.0) * 2.0 ** (e - 7))
+    val = np.where((e == 15) & (m == 7), np.nan, val)
+    return s * val
+
+
+def _prep_rows(ds, nbytes_row, n):
+    return _np(ds.prep)[: n * nbytes_row].reshape(n, nbytes_row)
+
+
+@pytest.mark.parametrize("d", [16, 7, 130])
+def test_prepare_f32_and_u8_copies(dev, d):
+    rng = np.random.default_rng(d)
+    n = 333
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    ds = pecann.Dataset(_t(X, dev), "l2", "f32")
+    stride = (d * 4 + 15) // 16 * 16
+    rows = _prep_rows(ds, stride, n).view(np.float32)
+    assert np.array_equal(rows[:, :d], X)
+    assert np.all(rows[:, d:] == 0)
+    U = rng.integers(0, 256, (n, d)).astype(np.uint8)
+    dsu = pecann.Dataset(_t(U, dev), "l2", "u8")
+    su = (d + 15) // 16 * 16
+    ru = _prep_rows(dsu, su, n)
+    assert np.array_equal(ru[:, :d], U) and np.all(ru[:, d:] == 0)
+
+
+def test_prepare_bf16_rne(dev):
+    rng = np.random.default_rng(1)
+    n, d = 257, 128
+    X = (rng.standard_normal((n, d)) * 10).astype(np.float32)
+    X[0, :4] = [1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -2.5, 0.0]  # exact ties round to even
+    ds = pecann.Dataset(_t(X, dev), "l2", "bf16")
+    rows = _prep_rows(ds, 256, n).view(np.uint16)
+    assert np.array_equal(rows, _bf16_rne(X))
+
+
+def test_prepare_fp8_scaled(dev):
+    rng = np.random.default_rng(2)
+    n, d = 300, 1024
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    ds = pecann.Dataset(_t(X, dev), "cosine", "fp8")
+    prep = _np(ds.prep)
+    codes = prep[: n * d].reshape(n, d)
+    off_xr = (n * d + 255) // 256 * 256
+    xr = prep[off_xr: off_xr + n * d * 4].view(np.float32).reshape(n, d)
+    off_sc = off_xr + (n * d * 4 + 255) // 256 * 256
+    scale = prep[off_sc: off_sc + 4 * n].view(np.float32)
+    Xn = X / np.linalg.norm(X, axis=1, keepdims=True)
+    assert np.allclose(xr, Xn, rtol=2e-6, atol=1e-7)
+    assert np.allclose(scale, np.abs(xr).max(axis=1) / 448.0, rtol=1e-6)
+    dec = _fp8_e4m3_decode(codes) * scale[:, None]
+    # e4m3: relative step 2^-3 for normals -> error <= 2^-4 relative (plus subnormal floor)
+    err = np.abs(dec - xr)
+    bound = np.maximum(np.abs(xr) * 2.0 ** -4, scale[:, None] * 2.0 ** -10) * 1.0001
+    assert np.all(err <= bound)
+    assert not np.isnan(dec).any()
+
+
+# ----------------------------------------------------------------------------
+# exact mode (K1 + K5 + K7 + K10 + K11)
+# ----------------------------------------------------------------------------
+def test_worked_example(dev):
+    X = np.array([[5, 1], [4, 3], [4, 2], [1, 2], [1, 0], [0, 3]], dtype=np.float32)
+    g = _exact_gpu(X, 1, 2, dev)
+    assert list(g["knn_idx"][:, 0]) == [2, 2, 1, 5, 3, 3]
+    assert list(g["dep"]) == [2, -1, 1, 2, 3, 3]
+    assert np.allclose(g["delta"][[0, 2, 3, 4, 5]], [math.sqrt(2), 1, 3, 2, math.sqrt(2)], rtol=1e-7)
+    assert np.isinf(g["delta"][1])
+    lab, isc = pecann.cluster(_t(g["rho"], dev), _t(g["dep"], dev), _t(g["delta"], dev), n_c=2,
+                              center_mode=pecann.CENTER_THRESHOLD, delta_min=2.5,
+                              rho_min=float(np.float32(1 / math.sqrt(2))))
+    assert list(_np(lab)) == [1, 1, 1, 3, 4, 3]
+    assert list(_np(isc)) == [0, 1, 0, 1, 0, 0]
+
+
+@pytest.mark.parametrize("n,d,k,nc", [(10_000, 16, 10, 10), (3001, 5, 7, 4), (2000, 64, 64, 8),
+                                      (130, 3, 1, 3)])
+def test_exact_integer_grid_bit_exact(dev, n, d, k, nc):
+    X, _ = datagen.mixture(n, d, nc, seed=n + d, grid=511 if d * 511 ** 2 < 2 ** 24 else 300)
+    ref = oracle.exact_dpc(X, k=k, n_c=nc)
+    g = _exact_gpu(X, k, nc, dev)
+    assert np.array_equal(g["knn_idx"], ref["knn_idx"])
+    assert np.allclose(g["knn_dist"], ref["knn_dist"], rtol=1e-7, atol=0)
+    order = np.lexsort((np.arange(n), g["key"] >> np.uint64(32)))
+    assert np.array_equal(order, ref["order"])
+    assert np.array_equal(g["dep"], ref["dep"])
+    fin = np.isfinite(ref["delta"])
+    assert np.allclose(g["delta"][fin], ref["delta"][fin], rtol=1e-7)
+    assert np.array_equal(g["labels"], ref["labels"])
+    assert np.array_equal(g["is_center"], ref["is_center"])
+
+
+def test_exact_c1_float_margin_rule(dev):
+    X, _ = datagen.config1()
+    k, nc = 10, 10
+    ref = oracle.exact_dpc(X, k=k, n_c=nc)
+    _, dext = oracle.knn(oracle.Points(X), k + 1)
+    g = _exact_gpu(X, k, nc, dev)
+    # float32 vs FP64: a kNN slot may differ only where the oracle's neighbouring
+    # distances are closer than float32 summation can resolve (2 gamma_{d+2})
+    eps = 2 * (16 + 2) * 2.0 ** -24
+    gap = np.abs(np.diff(dext, axis=1)) <= eps * dext[:, 1:]
+    tight = gap[:, :k].copy()
+    tight[:, 1:] |= gap[:, : k - 1]
+    same = g["knn_idx"] == ref["knn_idx"]
+    assert np.all(same | tight)
+    assert np.allclose(g["knn_dist"], ref["knn_dist"], rtol=1e-5)
+    assert np.array_equal(g["labels"], ref["labels"])
+
+
+# ----------------------------------------------------------------------------
+# graph path: search on a given graph, build, doubling rounds
+# ----------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def grid_case():
+    n, d = 3000, 16
+    X, _ = datagen.mixture(n, d, 8, seed=99, grid=511)
+    P = oracle.Points(X)
+    perm = datagen.permutation(n, 5)
+    return dict(X=X, P=P, perm=perm, n=n)
+
+
+@pytest.mark.parametrize("alpha", [1.0, 2.0])
+def test_build_graph_bit_exact(dev, grid_case, alpha):
+    X, P, perm = grid_case["X"], grid_case["P"], grid_case["perm"]
+    R, L = 16, 32
+    adj_o, deg_o = oracle.vamana_build(P, R, L, alpha, perm, num_starts=4)
+    ds = pecann.Dataset(_t(X, dev), "l2", "f32")
+    adj, deg = pecann.build_graph(ds, R, L, alpha, num_starts=4, visited_cap=1024,
+                                  perm=_t(perm, dev))
+    assert np.array_equal(_np(deg), deg_o)
+    assert np.array_equal(_np(adj), adj_o)
+
+
+def test_search_and_dependent_rounds_bit_exact(dev, grid_case):
+    X, P, perm, n = grid_case["X"], grid_case["P"], grid_case["perm"], grid_case["n"]
+    R, L, k = 16, 32, 10
+    adj_o, deg_o = oracle.vamana_build(P, R, L, 2.0, perm, num_starts=4)
+    ref = oracle.anns_dpc(X, k=k, n_c=8, R=R, L_build=L, alpha=2.0, perm=perm, L_search=24,
+                          L_d=16, threshold=20, num_starts=4, kdep_cap=256)
+    assert np.array_equal(ref["adj"], adj_o)
+    ds = pecann.Dataset(_t(X, dev), "l2", "f32")
+    adj, deg = _t(adj_o, dev), _t(deg_o, dev)
+    idx, dist, rho, key = pecann.knn_density(ds, k, adj, deg, L_search=24)
+    assert np.array_equal(_np(idx), ref["knn_idx"])
+    assert np.allclose(_np(dist), ref["knn_dist"], rtol=1e-7)
+    dep, delta, stats = pecann.dependent_search(ds, key, idx, dist, adj, deg, L_d=16, L_search=24,
+                                                threshold=20, kdep_cap=256)
+    assert np.array_equal(_np(dep), ref["dep"])
+    st = _np(stats)
+    uc = ref["ucount"]
+    assert st[0] == uc[0]
+    for r in range(1, len(uc)):
+        assert st[r] == uc[r]
+    labels, _ = pecann.cluster(rho, dep, delta, n_c=8)
+    assert np.array_equal(_np(labels), ref["labels"])
+
+
+def test_threshold_n_forces_fallback_exact(dev, grid_case):
+    X, P, perm, n = grid_case["X"], grid_case["P"], grid_case["perm"], grid_case["n"]
+    ref = oracle.exact_dpc(X, k=10, n_c=8)
+    ds = pecann.Dataset(_t(X, dev), "l2", "f32")
+    adj, deg = pecann.build_graph(ds, 16, 32, 1.2, perm=_t(perm, dev))
+    idx, dist, rho, key = pecann.knn_density(ds, 10)  # exact kNN
+    dep, delta, stats = pecann.dependent_search(ds, key, idx, dist, adj, deg, L_d=16, L_search=24,
+                                                threshold=n, kdep_cap=256)
+    assert np.array_equal(_np(dep), ref["dep"])
+    st = _np(stats)
+    assert st[31] == st[0]  # every unfinished point went to the brute-force step
+
+
+def test_isolated_vertices_fall_back_to_exact(dev, grid_case):
+    X, n = grid_case["X"], grid_case["n"]
+    ref = oracle.exact_dpc(X, k=5, n_c=8)
+    ds = pecann.Dataset(_t(X, dev), "l2", "f32")
+    adj = torch.full((n, 8), -1, dtype=torch.int32, device=dev)
+    deg = torch.zeros(n, dtype=torch.int32, device=dev)
+    idx, dist, rho, key = pecann.knn_density(ds, 5, adj, deg, L_search=16)
+    assert np.array_equal(_np(idx), ref["knn_idx"])
+
+
+def test_build_is_deterministic(dev):
+    X, _ = datagen.config2(n=6000)
+    ds = pecann.Dataset(_t(X, dev), "l2", "f32")
+    a1, d1 = pecann.build_graph(ds, 32, 64, 1.2, seed=3)
+    a2, d2 = pecann.build_graph(ds, 32, 64, 1.2, seed=3)
+    assert torch.equal(a1, a2) and torch.equal(d1, d2)
+    adj, deg = _np(a1), _np(d1)
+    assert np.all(deg >= 1) and np.all(deg <= 32)
+    for i in range(0, 6000, 7):
+        nb = adj[i, :deg[i]]
+        assert i not in nb and len(set(nb.tolist())) == len(nb)
+        assert np.all((nb >= 0) & (nb < 6000)) and np.all(adj[i, deg[i]:] == -1)
+
+
+# ----------------------------------------------------------------------------
+# end to end, graph mode, statistical gates
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("sdt", ["f32", "u8"])
+def test_anns_dpc_mnist_shaped(dev, sdt):
+    X, _ = datagen.config2(n=20_000)
+    P = oracle.Points(X)
+    ref = oracle.exact_dpc(X, k=10, n_c=10)
+    ds = pecann.Dataset(_t(X, dev), "l2", sdt)
+    adj, deg = pecann.build_graph(ds, 64, 128, 1.2, seed=1)
+    idx, dist, rho, key = pecann.knn_density(ds, 10, adj, deg, L_search=64)
+    dep, delta, stats = pecann.dependent_search(ds, key, idx, dist, adj, deg, L_d=64, L_search=64)
+    labels, _ = pecann.cluster(rho, dep, delta, n_c=10)
+    q = np.arange(0, 20_000, 97)
+    rec = metrics.recall_at_k(P, q, _np(idx)[q], ref["knn_dist"][q], 10)
+    a = metrics.ari(_np(labels), ref["labels"])
+    assert rec >= 0.95, rec
+    assert a >= 0.95, a
+    # invariants of the approximate answer
+    g_dep, g_key = _np(dep), _np(key).view(np.uint64)
+    ok = g_dep >= 0
+    assert (g_dep < 0).sum() == 1
+    assert np.all(g_key[g_dep[ok]] < g_key[ok])
+    assert np.all(_np(dist)[:, -1] >= ref["knn_dist"][:, -1] * (1 - 1e-6))  # rho_hat <= rho
