@@ -146,10 +146,16 @@ typedef struct {
   int32_t reserved;     /* must be 0 */
 } pecann_build_params;
 
+/* counters (device, may be NULL): 8 uint64 work tallies accumulated over the
+ * call -- [0] search expansions, [1] neighbour ids read, [2] rows gathered by
+ * the searches, [3] 0, [4] rows gathered by forward prunes, [5] rows gathered by
+ * reverse prunes, [6] targets pruned, [7] targets appended.  The caller zeroes
+ * them; they measure the work that algorithmic-traffic figures are built on. */
 size_t pecann_build_graph_workspace_size(const pecann_dataset *ds, const pecann_build_params *bp);
 pecann_status pecann_build_graph(const pecann_dataset *ds, const pecann_build_params *bp,
                                  const int32_t *perm, uint64_t seed, int32_t *adj,
-                                 int32_t *deg, void *ws, size_t ws_bytes, void *stream);
+                                 int32_t *deg, uint64_t *counters, void *ws, size_t ws_bytes,
+                                 void *stream);
 
 /* ---------------------------------------------------------------------------
  * k nearest neighbours and kth density (Alg. 2, Find-Knn and F_density loops;
@@ -167,15 +173,17 @@ pecann_status pecann_build_graph(const pecann_dataset *ds, const pecann_build_pa
  *
  * Outputs (device): knn_idx[n*k] int32 and knn_dist[n*k] float (distances D,
  * not squared), ascending; rho[n] float (+inf when D_k = 0); rank_key[n]
- * uint64 (see conventions).  Limits: 1 <= k <= min(n-1, 64);
- * k <= L_search <= 1024; k <= rerank <= L_search.
+ * uint64 (see conventions).  counters (device, may be NULL, zeroed by the
+ * caller): 4 uint64 tallies of the graph search -- [0] expansions, [1]
+ * neighbour ids read, [2] rows gathered, [3] float32 rows re-scored.
+ * Limits: 1 <= k <= min(n-1, 64); k <= L_search <= 1024; k <= rerank <= L_search.
  * ------------------------------------------------------------------------- */
 size_t pecann_knn_density_workspace_size(const pecann_dataset *ds, int32_t k, int32_t L_search);
 pecann_status pecann_knn_density(const pecann_dataset *ds, const int32_t *adj,
                                  const int32_t *deg, int32_t R, int32_t k, int32_t L_search,
                                  int32_t rerank, int32_t *knn_idx, float *knn_dist,
-                                 float *rho, uint64_t *rank_key, void *ws, size_t ws_bytes,
-                                 void *stream);
+                                 float *rho, uint64_t *rank_key, uint64_t *counters, void *ws,
+                                 size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Dependent points: ComputeDepPts of Alg. 3 (Def. 1: the closest point of

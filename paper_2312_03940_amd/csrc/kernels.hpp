@@ -64,6 +64,9 @@ struct SearchParams {
   uint64_t *vis;              // [item][vcap] keys of expanded points
   int32_t *vis_count;         // [item] expansions (may exceed vcap)
   int32_t vcap;
+  // optional work counters (nullptr: off): [0] expansions, [1] neighbour ids
+  // read, [2] rows gathered for distances, [3] float32 rows re-scored
+  unsigned long long *counters;
 };
 
 size_t search_lds_bytes(int L, int hbits);
@@ -126,6 +129,9 @@ struct PruneParams {
   int32_t capin;              // max new in-edges merged per target
   int32_t *head;
   int32_t *overflow;          // counts truncations (candidates beyond capacity)
+  // optional work counters (nullptr: off): [0] rows gathered by forward prunes,
+  // [1] rows gathered by reverse prunes, [2] targets pruned, [3] targets appended
+  unsigned long long *counters;
 };
 size_t prune_lds_bytes(int ccap, int R);
 hipError_t launch_prune_forward(int32_t dt, int G, const PruneParams &p, int grid, hipStream_t s);

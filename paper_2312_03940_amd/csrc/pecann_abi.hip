@@ -269,7 +269,8 @@ static uint64_t splitmix64(uint64_t &s) {
 
 extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const pecann_build_params *bp,
                                             const int32_t *perm, uint64_t seed, int32_t *adj,
-                                            int32_t *deg, void *ws, size_t ws_bytes, void *stream) {
+                                            int32_t *deg, uint64_t *counters, void *ws,
+                                            size_t ws_bytes, void *stream) {
   Layout L;
   pecann_status st = check_dataset(ds, &L);
   if (st != PECANN_OK) return st;
@@ -329,6 +330,7 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
   sp.vis = w.vis;
   sp.vis_count = w.vis_count;
   sp.vcap = vcap;
+  sp.counters = (unsigned long long *)counters;
 
   PruneParams pp = {};
   pp.rows = rows;
@@ -349,6 +351,7 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
   pp.rcnt = w.rcnt;
   pp.capin = kCapIn;
   pp.overflow = overflow;
+  pp.counters = counters ? (unsigned long long *)counters + 4 : nullptr;
 
   const int passes = bp->passes == 0 ? 2 : bp->passes;
   for (int pass = 0; pass < passes; ++pass) {
@@ -407,7 +410,8 @@ extern "C" pecann_status pecann_knn_density(const pecann_dataset *ds, const int3
                                             const int32_t *deg, int32_t R, int32_t k,
                                             int32_t L_search, int32_t rerank, int32_t *knn_idx,
                                             float *knn_dist, float *rho, uint64_t *rank_key,
-                                            void *ws, size_t ws_bytes, void *stream) {
+                                            uint64_t *counters, void *ws, size_t ws_bytes,
+                                            void *stream) {
   Layout L;
   pecann_status st = check_dataset(ds, &L);
   if (st != PECANN_OK) return st;
@@ -474,6 +478,7 @@ extern "C" pecann_status pecann_knn_density(const pecann_dataset *ds, const int3
   sp.rank_key = rank_key;
   sp.fb_list = fb;
   sp.fb_count = ctr + 1;
+  sp.counters = (unsigned long long *)counters;
   HIP_TRY(launch_search(dt, G, sp, persistent_grid(n), s));
   // too-few-results fallback: exact search for those queries
   bp.items = fb;

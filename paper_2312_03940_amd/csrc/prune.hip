@@ -49,9 +49,10 @@ __device__ __forceinline__ void rank_sort_dups(const uint64_t *src, uint64_t *ds
 }
 
 // RobustPrune of point pt over s.ids[0..nc); writes Nout(pt) into adj/deg.
+// Returns the number of rows gathered for distances.
 template <int DT, int G>
-__device__ void robust_prune_wave(const PruneParams &p, Engine<DT, G> &eng, PruneLds &s, int32_t pt,
-                                  int nc) {
+__device__ int robust_prune_wave(const PruneParams &p, Engine<DT, G> &eng, PruneLds &s, int32_t pt,
+                                 int nc) {
   constexpr int NPL = Engine<DT, G>::NPL;
   const int l = lane_id();
   const int grp = l / G;
@@ -76,6 +77,7 @@ __device__ void robust_prune_wave(const PruneParams &p, Engine<DT, G> &eng, Prun
 
   int nsel = 0;
   int from = 0;
+  int rows = nc;
   while (nsel < p.R) {
     // first survivor at or after `from`
     int j = -1;
@@ -101,6 +103,7 @@ __device__ void robust_prune_wave(const PruneParams &p, Engine<DT, G> &eng, Prun
     }
     wave_lds_sync();
     if (cnt > 0) {
+      rows += cnt;
       eng.load_query(p.rows, cstar);
       for (int base = 0; base < cnt; base += NPL) {
         const int ci = base + grp;
@@ -116,6 +119,7 @@ __device__ void robust_prune_wave(const PruneParams &p, Engine<DT, G> &eng, Prun
   int32_t *row = p.adj + (int64_t)pt * p.R;
   for (int e = l; e < p.R; e += kWave) row[e] = e < nsel ? s.sel[e] : -1;
   if (l == 0) p.deg[pt] = nsel;
+  return rows;
 }
 
 }  // namespace
@@ -139,7 +143,8 @@ __global__ __launch_bounds__(64) void prune_forward_kernel(PruneParams p) {
     const int32_t *row = p.adj + (int64_t)pt * p.R;
     for (int j = l; j < dp; j += kWave) s.ids[nv + j] = row[j];
     wave_lds_sync();
-    robust_prune_wave<DT, G>(p, eng, s, pt, nv + dp);
+    const int rows = robust_prune_wave<DT, G>(p, eng, s, pt, nv + dp);
+    if (p.counters && l == 0) atomicAdd(p.counters + 0, (unsigned long long)rows);
     wave_lds_sync();
   }
 }
@@ -188,8 +193,13 @@ __global__ __launch_bounds__(64) void prune_reverse_kernel(PruneParams p) {
     if (dq + nnew <= p.R) {
       for (int j = l; j < nnew; j += kWave) row[dq + j] = s.ids[dq + j];
       if (l == 0) p.deg[q] = dq + nnew;
+      if (p.counters && l == 0) atomicAdd(p.counters + 3, 1ull);
     } else {
-      robust_prune_wave<DT, G>(p, eng, s, q, dq + nnew);
+      const int rows = robust_prune_wave<DT, G>(p, eng, s, q, dq + nnew);
+      if (p.counters && l == 0) {
+        atomicAdd(p.counters + 1, (unsigned long long)rows);
+        atomicAdd(p.counters + 2, 1ull);
+      }
     }
     if (l == 0) p.rcnt[q] = 0;
     wave_lds_sync();

@@ -16,6 +16,8 @@ struct Lds {
   SortedList beam;
   IdHash hash;
   int32_t *cid;  // 64 ids awaiting distances
+  // wave-uniform work tallies of the current query
+  unsigned long long n_exp, n_ids, n_rows;
 };
 
 __device__ __forceinline__ Lds carve(uint8_t *smem, int L, int hbits) {
@@ -33,6 +35,7 @@ __device__ __forceinline__ Lds carve(uint8_t *smem, int L, int hbits) {
   s.hash.bits = hbits;
   s.beam.cap = L;
   s.beam.m = 0;
+  s.n_exp = s.n_ids = s.n_rows = 0;
   return s;
 }
 
@@ -45,6 +48,7 @@ __device__ __forceinline__ void score_and_merge(const Engine<DT, G> &eng, const 
   const uint64_t bm = ballot(myid >= 0);
   const int c = __popcll(bm);
   if (c == 0) return;
+  s.n_rows += c;
   if (myid >= 0) s.cid[lanes_below(bm)] = myid;
   wave_lds_sync();
   const int grp = l / G;
@@ -67,6 +71,8 @@ __device__ __forceinline__ void expand(const Engine<DT, G> &eng, const SearchPar
                                        int32_t v) {
   const int dg = min(p.deg[v], p.R);
   const int32_t *row = p.adj + (int64_t)v * p.R;
+  s.n_exp += 1;
+  s.n_ids += dg;
   for (int e0 = 0; e0 < dg; e0 += kWave) {
     const int e = e0 + lane_id();
     int32_t nb = e < dg ? row[e] : -1;
@@ -95,7 +101,7 @@ __device__ __forceinline__ void rerank_beam(const SearchParams &p, Lds &s, int32
 
 }  // namespace
 
-template <int DT, int G>
+template <int DT, int G, int MODE>
 __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
   extern __shared__ __align__(16) uint8_t smem[];
   Lds s = carve(smem, p.L, p.hbits);
@@ -103,7 +109,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
   const int count = p.item_count ? *p.item_count : p.nitems;
   constexpr bool kNeedRerank = (DT == PECANN_BF16 || DT == PECANN_FP8E4M3);
 
-  if (p.mode == MODE_DEP && count <= p.threshold) {
+  if (MODE == MODE_DEP && count <= p.threshold) {
     // Few enough points are left: this round is skipped and the list carried over.
     if (blockIdx.x == 0) {
       for (int u = l; u < count; u += kWave) p.u_out[u] = p.items[u];
@@ -127,7 +133,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
 
     // S = {query} u starts, or S = starts for an insertion.  A query that is
     // itself a start is expanded at once (it never takes a beam slot).
-    bool self_start = (p.mode != MODE_BUILD);
+    bool self_start = (MODE != MODE_BUILD);
     for (int s0 = 0; s0 < p.nstarts && !self_start; s0 += kWave)
       self_start = ballot(s0 + l < p.nstarts && p.starts[s0 + l] == qid) != 0;
     if (self_start) expand<DT, G>(eng, p, s, qid);
@@ -145,7 +151,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
       wave_lds_sync();
       if (l == 0) {
         s.beam.fa[j] = 1;
-        if (p.mode == MODE_BUILD && nv < p.vcap) p.vis[(int64_t)it * p.vcap + nv] = kj;
+        if (MODE == MODE_BUILD && nv < p.vcap) p.vis[(int64_t)it * p.vcap + nv] = kj;
       }
       ++nv;
       wave_lds_sync();
@@ -153,13 +159,15 @@ __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
     }
 
     const int m = s.beam.m;
-    if (p.mode == MODE_BUILD) {
+    unsigned long long n_rerank = 0;
+    if (MODE == MODE_BUILD) {
       if (l == 0) p.vis_count[it] = nv;
-    } else if (p.mode == MODE_KNN) {
+    } else if (MODE == MODE_KNN) {
       int mm = m;
       if (kNeedRerank && m > 0) {
         mm = min(m, p.rerank);
         rerank_beam<G>(p, s, qid, mm);
+        n_rerank = mm;
       }
       if (mm < p.k) {
         if (l == 0) {
@@ -182,7 +190,10 @@ __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
       }
     } else {  // MODE_DEP
       int c = min(m, p.kdep);
-      if (kNeedRerank && c > 0) rerank_beam<G>(p, s, qid, c);
+      if (kNeedRerank && c > 0) {
+        rerank_beam<G>(p, s, qid, c);
+        n_rerank = c;
+      }
       const uint64_t ki = p.key_in[qid];
       uint64_t best = kNoKey;
       for (int t = l; t < c; t += kWave) {
@@ -200,6 +211,13 @@ __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
         }
       }
     }
+    if (p.counters && l == 0) {
+      atomicAdd(p.counters + 0, s.n_exp);
+      atomicAdd(p.counters + 1, s.n_ids);
+      atomicAdd(p.counters + 2, s.n_rows);
+      atomicAdd(p.counters + 3, n_rerank);
+    }
+    s.n_exp = s.n_ids = s.n_rows = 0;
     wave_lds_sync();
   }
 }
@@ -212,7 +230,19 @@ size_t search_lds_bytes(int L, int hbits) {
 template <int DT, int G>
 static hipError_t launch_search_t(const SearchParams &p, int grid, hipStream_t st) {
   const size_t lds = search_lds_bytes(p.L, p.hbits);
-  hipLaunchKernelGGL((search_kernel<DT, G>), dim3(grid), dim3(64), lds, st, p);
+  switch (p.mode) {
+    case MODE_KNN:
+      hipLaunchKernelGGL((search_kernel<DT, G, MODE_KNN>), dim3(grid), dim3(64), lds, st, p);
+      break;
+    case MODE_DEP:
+      hipLaunchKernelGGL((search_kernel<DT, G, MODE_DEP>), dim3(grid), dim3(64), lds, st, p);
+      break;
+    case MODE_BUILD:
+      hipLaunchKernelGGL((search_kernel<DT, G, MODE_BUILD>), dim3(grid), dim3(64), lds, st, p);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

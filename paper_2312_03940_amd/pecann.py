@@ -66,10 +66,10 @@ def load():
         "pecann_prepared_bytes": (sz, [i64, i32, i32, i32]),
         "pecann_prepare_vectors": (ctypes.c_int, [vp, i32, i64, i64, i32, i32, i32, vp, sz, vp]),
         "pecann_build_graph_workspace_size": (sz, [D, B]),
-        "pecann_build_graph": (ctypes.c_int, [D, B, vp, ctypes.c_uint64, vp, vp, vp, sz, vp]),
+        "pecann_build_graph": (ctypes.c_int, [D, B, vp, ctypes.c_uint64, vp, vp, vp, vp, sz, vp]),
         "pecann_knn_density_workspace_size": (sz, [D, i32, i32]),
-        "pecann_knn_density": (ctypes.c_int, [D, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp, sz,
-                                              vp]),
+        "pecann_knn_density": (ctypes.c_int, [D, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp,
+                                              sz, vp]),
         "pecann_dependent_search_workspace_size": (sz, [D, i32, i32]),
         "pecann_dependent_search": (ctypes.c_int, [D, vp, vp, i32, vp, vp, vp, i32, i32, i32, i32,
                                                    i32, vp, vp, vp, vp, sz, vp]),
@@ -133,9 +133,20 @@ class Dataset:
         if nb == 0:
             raise PecannError("invalid (n, d, metric, search dtype)")
         self.prep = torch.empty(nb, dtype=torch.uint8, device=x.device)
-        _check(lib.pecann_prepare_vectors(_ptr(x), xdt, x.stride(0), self.n, self.d, self.metric,
-                                          self.search_dtype, _ptr(self.prep), nb, _stream()))
         self.device = x.device
+        self.prepare(x)
+
+    def prepare(self, x: torch.Tensor):
+        """(Re)write the prepared buffer from rows x of the same shape (no allocation)."""
+        _need_cuda(x)
+        if tuple(x.shape) != (self.n, self.d) or x.stride(1) != 1:
+            raise PecannError("x must match the dataset's (n, d) with unit column stride")
+        xdt = F32 if x.dtype == torch.float32 else U8 if x.dtype == torch.uint8 else None
+        if xdt is None:
+            raise PecannError("x must be float32 or uint8")
+        _check(load().pecann_prepare_vectors(_ptr(x), xdt, x.stride(0), self.n, self.d, self.metric,
+                                             self.search_dtype, _ptr(self.prep), self.prep.numel(),
+                                             _stream()))
 
     @property
     def struct(self):
@@ -144,8 +155,11 @@ class Dataset:
 
 def build_graph(ds: Dataset, R: int, L: int, alpha: float, num_starts: int = 8,
                 max_batch: int = 0, visited_cap: int = 0, perm: torch.Tensor | None = None,
-                seed: int = 0, passes: int = 2, ws: torch.Tensor | None = None):
-    """Batched Vamana construction.  -> (adj int32 [n, R], deg int32 [n])."""
+                seed: int = 0, passes: int = 2, ws: torch.Tensor | None = None, out=None,
+                counters: torch.Tensor | None = None):
+    """Batched Vamana construction.  -> (adj int32 [n, R], deg int32 [n]).
+
+    counters: optional int64 device tensor of 8 entries, accumulated (see pecann.h)."""
     lib = load()
     s = ds.struct
     bp = _BuildParams(R, L, alpha, num_starts, max_batch, visited_cap, passes, 0)
@@ -158,15 +172,17 @@ def build_graph(ds: Dataset, R: int, L: int, alpha: float, num_starts: int = 8,
         _need_cuda(perm)
         if perm.dtype != torch.int32 or perm.numel() != ds.n:
             raise PecannError("perm must be int32 with n entries")
-    adj = torch.empty((ds.n, R), dtype=torch.int32, device=ds.device)
-    deg = torch.empty(ds.n, dtype=torch.int32, device=ds.device)
+    if out is None:
+        out = (torch.empty((ds.n, R), dtype=torch.int32, device=ds.device),
+               torch.empty(ds.n, dtype=torch.int32, device=ds.device))
+    adj, deg = out
     _check(lib.pecann_build_graph(ctypes.byref(s), ctypes.byref(bp), _ptr(perm), seed, _ptr(adj),
-                                  _ptr(deg), _ptr(ws), ws.numel(), _stream()))
+                                  _ptr(deg), _ptr(counters), _ptr(ws), ws.numel(), _stream()))
     return adj, deg
 
 
 def knn_density(ds: Dataset, k: int, adj=None, deg=None, L_search: int = 64, rerank: int | None = None,
-                ws: torch.Tensor | None = None, out=None):
+                ws: torch.Tensor | None = None, out=None, counters: torch.Tensor | None = None):
     """kNN + kth density.  -> (knn_idx int32 [n,k], knn_dist f32 [n,k], rho f32 [n], rank_key int64 [n])."""
     lib = load()
     s = ds.struct
@@ -183,8 +199,8 @@ def knn_density(ds: Dataset, k: int, adj=None, deg=None, L_search: int = 64, rer
                torch.empty(ds.n, dtype=torch.int64, device=ds.device))
     idx, dist, rho, key = out
     _check(lib.pecann_knn_density(ctypes.byref(s), _ptr(adj), _ptr(deg), R, k, L_search, rerank,
-                                  _ptr(idx), _ptr(dist), _ptr(rho), _ptr(key), _ptr(ws), ws.numel(),
-                                  _stream()))
+                                  _ptr(idx), _ptr(dist), _ptr(rho), _ptr(key), _ptr(counters),
+                                  _ptr(ws), ws.numel(), _stream()))
     return idx, dist, rho, key
 
 
@@ -209,6 +225,19 @@ def dependent_search(ds: Dataset, rank_key, knn_idx, knn_dist, adj=None, deg=Non
                                        kdep_cap, _ptr(dep), _ptr(delta), _ptr(stats), _ptr(ws),
                                        ws.numel(), _stream()))
     return dep, delta, stats
+
+
+def workspace_bytes(ds: Dataset, k: int, L_search: int, kdep_cap: int, R: int, L: int,
+                    alpha: float = 1.2, num_starts: int = 8, max_batch: int = 0,
+                    visited_cap: int = 0, passes: int = 2) -> int:
+    """One workspace size that serves every call of a DPC run on ds."""
+    lib = load()
+    s = ds.struct
+    bp = _BuildParams(R, L, alpha, num_starts, max_batch, visited_cap, passes, 0)
+    return max(lib.pecann_build_graph_workspace_size(ctypes.byref(s), ctypes.byref(bp)),
+               lib.pecann_knn_density_workspace_size(ctypes.byref(s), k, L_search),
+               lib.pecann_dependent_search_workspace_size(ctypes.byref(s), kdep_cap, L_search),
+               lib.pecann_cluster_workspace_size(ds.n))
 
 
 def cluster(rho, dep, delta, n_c: int = 1, center_mode: int = CENTER_PRODUCT,

@@ -64,18 +64,19 @@ def test_argument_errors_are_synchronous(lib):
     ds = pecann._Dataset(100, 16, pecann.L2, pecann.F32, 0, None)
     bp = pecann._BuildParams(16, 32, 1.2, 4, 0, 0, 2, 0)
     # NULL prep pointer is rejected before any launch
-    rc = lib.pecann_build_graph(ctypes.byref(ds), ctypes.byref(bp), None, 0, None, None, None, 0, None)
+    rc = lib.pecann_build_graph(ctypes.byref(ds), ctypes.byref(bp), None, 0, None, None, None, None, 0,
+                                None)
     assert rc == 1 and b"prep" in lib.pecann_last_error()
     ds2 = pecann._Dataset(100, 16, pecann.L2, pecann.F32, 0, 256)
     bad = pecann._BuildParams(16, 32, 0.9, 4, 0, 0, 2, 0)
-    rc = lib.pecann_build_graph(ctypes.byref(ds2), ctypes.byref(bad), None, 0, None, None, None, 0,
-                                None)
+    rc = lib.pecann_build_graph(ctypes.byref(ds2), ctypes.byref(bad), None, 0, None, None, None, None,
+                                0, None)
     assert rc == 1 and b"alpha" in lib.pecann_last_error()
     assert lib.pecann_build_graph_workspace_size(ctypes.byref(ds2), ctypes.byref(bad)) == 0
     assert lib.pecann_build_graph_workspace_size(ctypes.byref(ds2), ctypes.byref(bp)) > 0
     # k out of range
     rc = lib.pecann_knn_density(ctypes.byref(ds2), None, None, 0, 100, 64, 64, None, None, None, None,
-                                None, 0, None)
+                                None, None, 0, None)
     assert rc == 1
     # cluster: n_c out of range, bad mode
     rc = lib.pecann_cluster(10, 256, 256, 256, 0, 11, 0.0, 0.0, 256, 256, 256, 1 << 20, None)
