@@ -34,6 +34,20 @@ sys.path.insert(0, ROOT)
 METRIC = "DPC points/s at ARI>=0.95 vs oracle; kNN queries/s at recall@10>=0.95"
 HBM_PEAK_GBS = 8000.0
 REF_PATH = os.path.join(ROOT, "tests", "golden", "c2_reference.npz")
+TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def stored_traffic(key: str):
+    """HBM bytes per launch measured by the FETCH_SIZE/WRITE_SIZE runs, or None when
+    missing or when the search kernel's sources changed since they were taken."""
+    from paper_2312_03940_amd.kernel_hash import search_kernel_hash
+    if not os.path.exists(TRAFFIC_PATH):
+        return None
+    with open(TRAFFIC_PATH) as f:
+        t = json.load(f)
+    if t.get("source_hash") != search_kernel_hash() or key not in t:
+        return None
+    return int(t[key]["traffic_bytes_per_launch"])
 
 
 def parse():
@@ -47,8 +61,13 @@ def parse():
     ap.add_argument("--threshold", type=int, default=300)
     ap.add_argument("--kdep-cap", type=int, default=1024)
     ap.add_argument("--num-starts", type=int, default=8)
-    ap.add_argument("--cpu-sample", type=int, default=4000)
+    ap.add_argument("--max-batch", type=int, default=0,
+                    help="build batch cap (0: the library default, max(n/50, 8192))")
+    ap.add_argument("--cpu-sample", type=int, default=16000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (a reference "
+                         "kernel of known traffic for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -99,7 +118,8 @@ def main():
     ds = pecann.Dataset(x, "l2", args.search)
 
     # every buffer of the step is allocated here, outside the timed region
-    wsb = pecann.workspace_bytes(ds, k, args.L_search, args.kdep_cap, R, L, alpha, args.num_starts)
+    wsb = pecann.workspace_bytes(ds, k, args.L_search, args.kdep_cap, R, L, alpha, args.num_starts,
+                                 args.max_batch)
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     g_out = (torch.empty((n, R), dtype=torch.int32, device=dev),
              torch.empty(n, dtype=torch.int32, device=dev))
@@ -122,7 +142,7 @@ def main():
         if ev:
             ev[1].record()
         adj, deg = pecann.build_graph(ds, R, L, alpha, num_starts=args.num_starts, perm=perm,
-                                      ws=ws, out=g_out, counters=bcnt)
+                                      max_batch=args.max_batch, ws=ws, out=g_out, counters=bcnt)
         if ev:
             ev[2].record()
         idx, dist, rho, key = pecann.knn_density(ds, k, adj, deg, L_search=args.L_search, ws=ws,
@@ -142,14 +162,24 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    if args.copy_probe_mb:
+        src = torch.empty(args.copy_probe_mb << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    pecann.profile_enable(True)  # per-kernel HIP events on the launch stream
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step(evs[i])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    pecann.profile_enable(False)
+    kprof = pecann.profile_report()
 
     ph = {p: [] for p in phases}
     for e in evs:
@@ -158,6 +188,7 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     value = n * args.steps / wall
     knn_ms = float(np.median(ph["knn_density"]))
+
 
     # work counters from one extra (untimed) step
     bcnt = torch.zeros(8, dtype=torch.int64, device=dev)
@@ -194,17 +225,37 @@ def main():
         quality["missing"] = "tests/golden/c2_reference.npz not found"
 
     row_bytes = {"f32": 4 * d, "u8": d}[args.search]
-    # algorithmic bytes of the kNN search launch: per expansion the degree word and the
-    # neighbour ids, per distance the candidate row, per query its own row and its outputs
-    alg_bytes = (4 * (kc[0] + kc[1]) + row_bytes * kc[2] + n * row_bytes
-                 + n * (k * 8 + 4 + 8))
-    achieved = alg_bytes / (knn_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": f"search_kernel<{args.search}, G=16, MODE_KNN>",
+    # algorithmic bytes per step of each gather kernel family, from its own counters:
+    # per expansion the degree word and the neighbour ids, per distance the candidate
+    # row, per search its own row and its outputs
+    nsearch_build = 2 * n - 1
+    alg = {
+        "search_knn": 4 * (kc[0] + kc[1]) + row_bytes * kc[2] + n * row_bytes + n * (k * 8 + 4 + 8),
+        "search_build": (4 * (bc[0] + bc[1]) + row_bytes * bc[2] + nsearch_build * row_bytes
+                         + 8 * bc[0] + 4 * nsearch_build),
+    }
+    fam_ms = {f: v[1] / args.steps for f, v in kprof.items()}
+    fam_launch = {f: v[0] / args.steps for f, v in kprof.items()}
+    dom = max(fam_ms, key=fam_ms.get)
+    rl_fam = dom if dom in alg else max(alg, key=lambda f: fam_ms.get(f, 0.0))
+    avg_launch_ms = fam_ms[rl_fam] / fam_launch[rl_fam]
+    bytes_per_launch = alg[rl_fam] / fam_launch[rl_fam]
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    knl = {"search_build": "MODE_BUILD", "search_knn": "MODE_KNN"}[rl_fam]
+    roofline = {"bound": "hbm", "kernel": f"search_kernel<{args.search}, G=16, {knl}>",
+                "family": rl_fam, "dominant_family": dom,
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "alg_bytes_per_launch": int(alg_bytes),
-                "per_query": {"expansions": kc[0] / n, "ids_read": kc[1] / n,
-                              "rows_gathered": kc[2] / n}}
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": stored_traffic(f"{rl_fam}@{args.search}"),
+                "alg_bytes_per_launch": int(bytes_per_launch),
+                "avg_launch_ms": round(avg_launch_ms, 4), "launches_per_step": fam_launch[rl_fam],
+                "knn_launch": {"ms": round(fam_ms.get("search_knn", 0.0), 3),
+                               "achieved_GBps": round(alg["search_knn"] / (fam_ms["search_knn"] * 1e-3) / 1e9, 1)
+                               if "search_knn" in fam_ms else None,
+                               "per_query": {"expansions": kc[0] / n, "ids_read": kc[1] / n,
+                                             "rows_gathered": kc[2] / n}}}
+    kernels_ms = {f: {"launches_per_step": fam_launch[f], "ms_per_step": round(v, 3)}
+                  for f, v in sorted(fam_ms.items(), key=lambda t: -t[1])}
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "points/s", "n_gpus": 1,
@@ -214,6 +265,7 @@ def main():
         "config": {"workload": "MNIST-shaped 70000x784 uint8 10-Gaussian mixture, L2",
                    "n": n, "d": d, "search_rows": args.search, "R": R, "L_build": L,
                    "alpha": alpha, "build_passes": 2, "num_starts": args.num_starts,
+                   "max_batch": args.max_batch or max(n // 50, 8192),
                    "k": k, "L_search": args.L_search, "L_d": args.L_d,
                    "threshold": args.threshold, "kdep_cap": args.kdep_cap, "n_c": n_c,
                    "parallelism": "single GPU"},
@@ -224,6 +276,7 @@ def main():
                        "forward_prune_rows": int(bc[4]), "reverse_prune_rows": int(bc[5]),
                        "targets_pruned": int(bc[6]), "targets_appended": int(bc[7])},
         "dependent_stats": d_out[2].cpu().numpy()[:8].tolist(),
+        "kernels_ms": kernels_ms,
         "roofline": roofline,
     }
     if not args.no_cpu_baseline and ref is not None:

@@ -78,6 +78,8 @@ typedef enum { PECANN_CENTER_PRODUCT = 0, PECANN_CENTER_THRESHOLD = 1 } pecann_c
  *                every reported distance and every ordering is float32);
  *   row scale    n floats (FP8E4M3 only): row t of the search copy holds
  *                x_t / scale_t with scale_t = max_j |x_tj| / 448;
+ *   row norms    n 32-bit squared norms of the search rows (used when
+ *                candidate-pair distances are formed on the matrix cores);
  *   for PECANN_COSINE every row is divided by its norm first, so that
  *   D = 1 - x.y on the prepared rows (a zero row stays zero: D = 1).
  * Only the sizes matter to the caller: pecann_prepared_bytes() gives the
@@ -114,10 +116,13 @@ pecann_status pecann_prepare_vectors(const void *x, int32_t x_dtype, int64_t x_r
  *
  * Points are inserted in the order perm (device, n distinct int32 indices; NULL
  * means a permutation drawn from `seed` with SplitMix64-driven Fisher-Yates).
- * The first pass starts the graph with perm[0] alone; then (and in the second
- * pass from perm[0] on) batches of 1, 2, 4, ... points capped at max_batch
- * (0 selects floor(n / 50), the paper's 0.02 n).  Every search of a batch sees the graph as it
- * was when the batch began.  The start set S of a batch is the first
+ * The first pass starts the graph with perm[0] alone, then inserts batches of
+ * 1, 2, 4, ... points capped at max_batch; the second pass, with every point
+ * already in the graph, re-inserts perm in batches of max_batch from the start.
+ * max_batch = 0 selects max(floor(n / 50), 8192): the paper's 0.02 n, raised to
+ * the number of concurrent searches that keeps all 256 CUs busy (the cap
+ * leaves the construction's bounds unchanged, Sec. 4.1).  Every search of a
+ * batch sees the graph as it was when the batch began.  The start set S of a batch is the first
  * min(num_starts, points in the graph) points of perm (the random multi-start
  * of Sec. 3.2).  For each point p of the batch: V_p = the points expanded by a
  * greedy beam search (Alg. 1, beam width L) for p from S, p excluded, at most
@@ -140,7 +145,7 @@ typedef struct {
   int32_t L;            /* build beam width */
   float alpha;          /* prune slack, >= 1 */
   int32_t num_starts;   /* random start points */
-  int32_t max_batch;    /* batch size cap in points (0: floor(n / 50)) */
+  int32_t max_batch;    /* batch size cap in points (0: max(n / 50, 8192)) */
   int32_t visited_cap;  /* candidates kept per insertion (0 = 2L) */
   int32_t passes;       /* 2 (default, 0 means 2): alpha = 1 then alpha; 1: alpha only */
   int32_t reserved;     /* must be 0 */
@@ -230,6 +235,27 @@ pecann_status pecann_cluster(int64_t n, const float *rho, const int32_t *dep,
                              const float *delta, int32_t center_mode, int32_t n_c,
                              float delta_min, float rho_min, int32_t *labels,
                              uint8_t *is_center, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Kernel timing (host-side instrumentation, off by default).  While enabled,
+ * every kernel the library launches from this thread is bracketed by a pair of
+ * HIP events recorded on the launch stream, filed under its kernel family
+ * ("search_build", "search_knn", "search_dep", "prune_forward",
+ * "prune_reverse", "reverse_edges", "bf_knn", "bf_dep", "prepare", "cluster",
+ * "other").  pecann_profile_enable(1) clears earlier records; enable(0) stops
+ * recording.  pecann_profile_report synchronises the recorded events and
+ * writes up to max_entries family totals into out; it returns the number
+ * written, or -1 on a HIP error.  Events come from a pool the library keeps
+ * for the life of the process.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+} pecann_profile_entry;
+
+pecann_status pecann_profile_enable(int32_t on);
+int32_t pecann_profile_report(pecann_profile_entry *out, int32_t max_entries);
 
 const char *pecann_status_string(pecann_status s);
 /* Thread-local description of the last error returned on this thread. */

@@ -437,8 +437,9 @@ int32_t oracle_robust_prune(const opoints *P, int64_t p, const int64_t *cand,
 /* given alpha) when passes == 2:                                            */
 /*   points are inserted in the order perm[]; in the first pass perm[0] alone  */
 /*   starts the graph, then batches of size 1, 2, 4, ... capped at max_batch   */
-/*   (0: floor(n / 50), the paper's 0.02 n); a later pass walks the batches   */
-/*   starting with perm[0] itself.  Every search of a batch sees the graph as  */
+/*   (0: floor(n / 50), the paper's 0.02 n); a later pass, every point now in  */
+/*   the graph, re-inserts perm in batches of max_batch from perm[0] on.       */
+/*   Every search of a batch sees the graph as  */
 /*   it was when the batch began; the start set S is the first                */
 /*   min(num_starts, inserted) points of perm;                                */
 /*   for each point p of the batch: V_p = visited set of the greedy search for */
@@ -475,9 +476,10 @@ int oracle_vamana_build(const opoints *P, int32_t R, int32_t L, double alpha,
   int rc = 0;
   for (int32_t pass = 0; pass < passes && rc == 0; ++pass) {
     const double a = (passes > 1 && pass == 0) ? 1.0 : alpha;
-    /* first pass: perm[0] starts the graph unsearched; later passes search it too */
+    /* first pass: perm[0] starts the graph unsearched, batches ramp up from 1;  */
+    /* later passes re-insert every point in full batches                       */
     int64_t inserted = pass == 0 ? 1 : 0;
-    int64_t bsize = 1;
+    int64_t bsize = pass == 0 ? 1 : cap;
     while (inserted < n) {
       int64_t b0 = inserted;
       int64_t nb = bsize < cap ? bsize : cap;

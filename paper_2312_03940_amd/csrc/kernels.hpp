@@ -20,6 +20,10 @@ struct RowsDesc {  // host copy of the row description (mirrors Rows)
   const float *scale;
   const float *xr;
   int64_t xr_stride;
+  // per search row: squared norm of the values the matrix cores multiply --
+  // float for F32/BF16/FP8 (dequantised), int32 bits of sum (x - 128)^2 over
+  // the padded row for U8
+  const uint32_t *sqn;
   int32_t nch;
   int32_t nch_r;
   int32_t d;
@@ -140,7 +144,7 @@ hipError_t launch_prune_reverse(int32_t dt, int G, const PruneParams &p, int gri
 // Plain (non-templated) kernels.
 hipError_t launch_prepare(const void *x, int32_t x_dtype, int64_t x_stride, int64_t n, int32_t d,
                           int32_t metric, int32_t sdt, const RowsDesc &rows, uint8_t *xs,
-                          float *xr, float *scale, hipStream_t s);
+                          float *xr, float *scale, uint32_t *sqn, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 hipError_t launch_identity_perm(int32_t *p, int64_t n, hipStream_t s);

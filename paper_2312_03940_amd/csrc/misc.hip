@@ -28,7 +28,7 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
 __global__ __launch_bounds__(256) void prepare_kernel(const void *x, int32_t x_dtype, int64_t x_stride,
                                                       int64_t n, int32_t d, int32_t metric,
                                                       int32_t sdt, RowsDesc r, uint8_t *xs,
-                                                      float *xr, float *scale) {
+                                                      float *xr, float *scale, uint32_t *sqn) {
   const int l = lane_id();
   const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (row >= n) return;
@@ -61,24 +61,39 @@ __global__ __launch_bounds__(256) void prepare_kernel(const void *x, int32_t x_d
     }
   }
   uint8_t *o = xs + row * r.xs_stride;
+  float nf = 0.f;  // squared norm of the stored values
+  int ni = 0;      // U8: sum of (x - 128)^2 over the padded row
   if (sdt == PECANN_F32) {
     float *of = (float *)o;
     const int64_t cap = r.xs_stride / 4;
     for (int t = 0; t < kMaxPerLane; ++t) {
       const int e = l + 64 * t;
-      if (e < cap) of[e] = e < d ? v[t] : 0.f;
+      if (e < cap) {
+        const float f = e < d ? v[t] : 0.f;
+        of[e] = f;
+        nf = fmaf(f, f, nf);
+      }
     }
   } else if (sdt == PECANN_U8) {
     for (int t = 0; t < kMaxPerLane; ++t) {
       const int e = l + 64 * t;
-      if (e < r.xs_stride) o[e] = e < d ? (uint8_t)v[t] : (uint8_t)0;
+      if (e < r.xs_stride) {
+        const int b = e < d ? (int)v[t] : 0;
+        o[e] = (uint8_t)b;
+        ni += (b - 128) * (b - 128);
+      }
     }
   } else if (sdt == PECANN_BF16) {
     uint16_t *ob = (uint16_t *)o;
     const int64_t cap = r.xs_stride / 2;
     for (int t = 0; t < kMaxPerLane; ++t) {
       const int e = l + 64 * t;
-      if (e < cap) ob[e] = e < d ? f32_to_bf16_rne(v[t]) : (uint16_t)0;
+      if (e < cap) {
+        const uint16_t h = e < d ? f32_to_bf16_rne(v[t]) : (uint16_t)0;
+        ob[e] = h;
+        const float f = __uint_as_float((uint32_t)h << 16);
+        nf = fmaf(f, f, nf);
+      }
     }
   } else {  // FP8 e4m3
 #pragma unroll
@@ -86,24 +101,33 @@ __global__ __launch_bounds__(256) void prepare_kernel(const void *x, int32_t x_d
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
     const float inv = mx > 0.f ? 448.0f / mx : 1.0f;
-    if (l == 0) scale[row] = 1.0f / inv;
+    const float sc = 1.0f / inv;
+    if (l == 0) scale[row] = sc;
     for (int t = 0; t < kMaxPerLane; ++t) {
       const int e = l + 64 * t;
       if (e < r.xs_stride) {
         const float f = e < d ? fminf(448.0f, fmaxf(-448.0f, v[t] * inv)) : 0.f;
         const int w = __builtin_amdgcn_cvt_pk_fp8_f32(f, 0.f, 0, false);
         o[e] = (uint8_t)(w & 0xff);
+        const float back = __builtin_amdgcn_cvt_pk_f32_fp8(w, false)[0] * sc;
+        nf = fmaf(back, back, nf);
       }
     }
   }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    nf += __shfl_xor(nf, m);
+    ni += __shfl_xor(ni, m);
+  }
+  if (l == 0) sqn[row] = sdt == PECANN_U8 ? (uint32_t)ni : __float_as_uint(nf);
 }
 
 hipError_t launch_prepare(const void *x, int32_t x_dtype, int64_t x_stride, int64_t n, int32_t d,
                           int32_t metric, int32_t sdt, const RowsDesc &rows, uint8_t *xs,
-                          float *xr, float *scale, hipStream_t s) {
+                          float *xr, float *scale, uint32_t *sqn, hipStream_t s) {
   const int64_t blocks = (n + 3) / 4;
   hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, x_dtype, x_stride,
-                     n, d, metric, sdt, rows, xs, xr, scale);
+                     n, d, metric, sdt, rows, xs, xr, scale, sqn);
   return hipGetLastError();
 }
 

@@ -46,6 +46,85 @@ extern "C" const char *pecann_status_string(pecann_status s) {
 extern "C" const char *pecann_last_error(void) { return g_err; }
 
 // ---------------------------------------------------------------------------
+// Kernel timing: optional HIP-event brackets around every launch
+// ---------------------------------------------------------------------------
+namespace {
+const char *const kFamilies[] = {"search_build", "search_knn", "search_dep", "prune_forward",
+                                 "prune_reverse", "reverse_edges", "bf_knn", "bf_dep",
+                                 "prepare", "cluster", "other"};
+enum Family { F_SEARCH_BUILD, F_SEARCH_KNN, F_SEARCH_DEP, F_PRUNE_FWD, F_PRUNE_REV, F_REV,
+              F_BF_KNN, F_BF_DEP, F_PREPARE, F_CLUSTER, F_OTHER, F_COUNT };
+struct ProfRec { int fam; hipEvent_t a, b; };
+struct Profiler {
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void recycle() {
+    for (auto &r : recs) { pool.push_back(r.a); pool.push_back(r.b); }
+    recs.clear();
+  }
+};
+thread_local Profiler g_prof;
+
+// Brackets one launch; a no-op unless timing is enabled.
+struct ProfScope {
+  hipStream_t s;
+  int fam;
+  hipEvent_t a = nullptr;
+  ProfScope(int f, hipStream_t st) : s(st), fam(f) {
+    if (!g_prof.on) return;
+    a = g_prof.get();
+    if (a) (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = g_prof.get();
+    if (!b) { g_prof.pool.push_back(a); return; }
+    (void)hipEventRecord(b, s);
+    g_prof.recs.push_back({fam, a, b});
+  }
+};
+}  // namespace
+
+#define PROF_CAT2(a, b) a##b
+#define PROF_CAT(a, b) PROF_CAT2(a, b)
+#define PROF(fam, s) ProfScope PROF_CAT(prof_scope_, __LINE__)(fam, s)
+
+extern "C" pecann_status pecann_profile_enable(int32_t on) {
+  if (on) g_prof.recycle();
+  g_prof.on = on != 0;
+  return PECANN_OK;
+}
+
+extern "C" int32_t pecann_profile_report(pecann_profile_entry *out, int32_t max_entries) {
+  double tot[F_COUNT] = {0};
+  int64_t cnt[F_COUNT] = {0};
+  for (auto &r : g_prof.recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return -1;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return -1;
+    tot[r.fam] += ms;
+    cnt[r.fam] += 1;
+  }
+  int32_t w = 0;
+  for (int f = 0; f < F_COUNT && w < max_entries; ++f) {
+    if (!cnt[f]) continue;
+    memset(out[w].name, 0, sizeof out[w].name);
+    strncpy(out[w].name, kFamilies[f], sizeof out[w].name - 1);
+    out[w].launches = cnt[f];
+    out[w].total_ms = tot[f];
+    ++w;
+  }
+  return w;
+}
+
+// ---------------------------------------------------------------------------
 // Device facts
 // ---------------------------------------------------------------------------
 static int cu_count() {
@@ -95,6 +174,7 @@ struct Layout {
   size_t off_xs, xs_stride;  // bytes
   size_t off_xr, xr_stride;  // bytes offset, floats per row
   size_t off_scale;
+  size_t off_sqn;
   size_t total;
   bool has_xr, has_scale;
 };
@@ -119,6 +199,8 @@ static bool make_layout(int64_t n, int32_t d, int32_t metric, int32_t sdt, Layou
   L->has_scale = (sdt == PECANN_FP8E4M3);
   L->off_scale = off;
   if (L->has_scale) off = up(off + 4 * (size_t)n, 256);
+  L->off_sqn = off;
+  off = up(off + 4 * (size_t)n, 256);
   L->total = off;
   return true;
 }
@@ -131,6 +213,7 @@ static RowsDesc rows_of(const pecann_dataset *ds, const Layout &L) {
   r.scale = L.has_scale ? (const float *)(base + L.off_scale) : nullptr;
   r.xr = L.has_xr ? (const float *)(base + L.off_xr) : nullptr;
   r.xr_stride = (int64_t)L.xr_stride;
+  r.sqn = (const uint32_t *)(base + L.off_sqn);
   r.nch = (int32_t)(L.xs_stride / 16);
   r.nch_r = (int32_t)(L.xr_stride / 4);
   r.d = ds->d;
@@ -171,10 +254,11 @@ extern "C" pecann_status pecann_prepare_vectors(const void *x, int32_t x_dtype, 
   pecann_dataset ds = {n, d, metric, sdt, 0, prep};
   RowsDesc r = rows_of(&ds, L);
   uint8_t *base = (uint8_t *)prep;
+  PROF(F_PREPARE, (hipStream_t)stream);
   HIP_TRY(launch_prepare(x, x_dtype, x_stride, n, d, metric, sdt, r, base + L.off_xs,
                          L.has_xr ? (float *)(base + L.off_xr) : nullptr,
                          L.has_scale ? (float *)(base + L.off_scale) : nullptr,
-                         (hipStream_t)stream));
+                         (uint32_t *)(base + L.off_sqn), (hipStream_t)stream));
   return PECANN_OK;
 }
 
@@ -210,8 +294,12 @@ struct BuildWs {
   uint64_t *vis;
 };
 
+// Batch cap: the paper's 0.02 n, but never below 8192 concurrent searches (a
+// wavefront each), which is what it takes to occupy 256 CUs.
+static constexpr int64_t kMinGpuBatch = 8192;
 static int64_t batch_cap(int64_t n, int32_t max_batch) {
-  const int64_t c = max_batch > 0 ? (int64_t)max_batch : n / 50;
+  int64_t c = max_batch > 0 ? (int64_t)max_batch : std::max<int64_t>(n / 50, kMinGpuBatch);
+  if (c > n) c = n;
   return c < 1 ? 1 : c;
 }
 
@@ -357,8 +445,9 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
   for (int pass = 0; pass < passes; ++pass) {
     // DiskANN's schedule: alpha = 1 first, the given alpha last
     pp.alpha = (passes == 2 && pass == 0) ? 1.0f : bp->alpha;
-    // the first pass starts the graph with perm[0]; later passes re-insert it too
-    int64_t inserted = pass == 0 ? 1 : 0, bsize = 1;
+    // the first pass starts the graph with perm[0] and ramps batches up from 1;
+    // later passes re-insert every point in full batches
+    int64_t inserted = pass == 0 ? 1 : 0, bsize = pass == 0 ? 1 : cap;
     while (inserted < n) {
       int64_t nb = std::min(bsize, cap);
       nb = std::min(nb, n - inserted);
@@ -368,19 +457,31 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
       sp.items = order + b0;
       sp.nitems = (int32_t)nb;
       sp.nstarts = (int32_t)std::min<int64_t>(bp->num_starts, in_graph);
-      HIP_TRY(launch_search(dt, G, sp, persistent_grid(nb), s));
+      {
+        PROF(F_SEARCH_BUILD, s);
+        HIP_TRY(launch_search(dt, G, sp, persistent_grid(nb), s));
+      }
       pp.b0 = b0;
       pp.nb = (int32_t)nb;
       pp.head = head_pf;
-      HIP_TRY(launch_prune_forward(dt, G, pp, persistent_grid(nb), s));
-      HIP_TRY(launch_rev_count(adj, deg, order, b0, (int32_t)nb, R, w.rcnt, ntargets, w.tlist,
-                               w.tidx, w.ticket, s));
-      HIP_TRY(launch_rev_alloc(w.tlist, ntargets, w.rcnt, w.toff, w.tcnt, cursor, (int32_t)(nb * R),
-                               s));
-      HIP_TRY(launch_rev_scatter(adj, deg, order, b0, (int32_t)nb, R, w.tidx, w.toff, w.ticket,
-                                 w.seg, s));
+      {
+        PROF(F_PRUNE_FWD, s);
+        HIP_TRY(launch_prune_forward(dt, G, pp, persistent_grid(nb), s));
+      }
+      {
+        PROF(F_REV, s);
+        HIP_TRY(launch_rev_count(adj, deg, order, b0, (int32_t)nb, R, w.rcnt, ntargets, w.tlist,
+                                 w.tidx, w.ticket, s));
+        HIP_TRY(launch_rev_alloc(w.tlist, ntargets, w.rcnt, w.toff, w.tcnt, cursor,
+                                 (int32_t)(nb * R), s));
+        HIP_TRY(launch_rev_scatter(adj, deg, order, b0, (int32_t)nb, R, w.tidx, w.toff, w.ticket,
+                                   w.seg, s));
+      }
       pp.head = head_pr;
-      HIP_TRY(launch_prune_reverse(dt, G, pp, persistent_grid(nb * R), s));
+      {
+        PROF(F_PRUNE_REV, s);
+        HIP_TRY(launch_prune_reverse(dt, G, pp, persistent_grid(nb * R), s));
+      }
       inserted += nb;
       bsize *= 2;
     }
@@ -452,6 +553,7 @@ extern "C" pecann_status pecann_knn_density(const pecann_dataset *ds, const int3
     bp.item_count = nullptr;
     bp.nitems = (int32_t)n;
     bp.head = ctr + 0;
+    PROF(F_BF_KNN, s);
     HIP_TRY(launch_bf_knn(dt, G, bp, persistent_grid(n), s));
     return PECANN_OK;
   }
@@ -479,12 +581,16 @@ extern "C" pecann_status pecann_knn_density(const pecann_dataset *ds, const int3
   sp.fb_list = fb;
   sp.fb_count = ctr + 1;
   sp.counters = (unsigned long long *)counters;
-  HIP_TRY(launch_search(dt, G, sp, persistent_grid(n), s));
+  {
+    PROF(F_SEARCH_KNN, s);
+    HIP_TRY(launch_search(dt, G, sp, persistent_grid(n), s));
+  }
   // too-few-results fallback: exact search for those queries
   bp.items = fb;
   bp.item_count = ctr + 1;
   bp.nitems = 0;
   bp.head = ctr + 2;
+  PROF(F_BF_KNN, s);
   HIP_TRY(launch_bf_knn(dt, G, bp, cu_count() * 4, s));
   return PECANN_OK;
 }
@@ -596,7 +702,10 @@ extern "C" pecann_status pecann_dependent_search(const pecann_dataset *ds, const
       sp.u_out = nxt;
       sp.u_out_count = w.ucnt + nr + 1;
       sp.threshold = threshold;
-      HIP_TRY(launch_search(dt, G, sp, persistent_grid(n), s));
+      {
+        PROF(F_SEARCH_DEP, s);
+        HIP_TRY(launch_search(dt, G, sp, persistent_grid(n), s));
+      }
       std::swap(cur, nxt);
     }
   }
@@ -612,7 +721,10 @@ extern "C" pecann_status pecann_dependent_search(const pecann_dataset *ds, const
   bd.head = w.ctr + 40;
   bd.key = rank_key;
   bd.best = w.best;
-  HIP_TRY(launch_bf_dep(dt, G, bd, persistent_grid(n * (int64_t)bd.nchunks), s));
+  {
+    PROF(F_BF_DEP, s);
+    HIP_TRY(launch_bf_dep(dt, G, bd, persistent_grid(n * (int64_t)bd.nchunks), s));
+  }
   HIP_TRY(launch_bf_dep_finalize(cur, w.ucnt + nr, w.best, ds->metric, dep, delta, (int32_t)n, s));
   if (stats) {
     hipLaunchKernelGGL(dep_stats_kernel, dim3(1), dim3(64), 0, s, w.ucnt, nr, stats);
@@ -650,6 +762,7 @@ extern "C" pecann_status pecann_cluster(int64_t n, const float *rho, const int32
   int32_t *flag = c.take<int32_t>(64);
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(launch_fill_i32(flag, 0, 1, s));
+  PROF(F_CLUSTER, s);
   HIP_TRY(launch_cluster(n, rho, dep, delta, center_mode, n_c, delta_min, rho_min, labels, is_center,
                          gkey, flag, s));
   return PECANN_OK;

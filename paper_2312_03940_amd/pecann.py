@@ -34,6 +34,11 @@ class _Dataset(ctypes.Structure):
                 ("prep", ctypes.c_void_p)]
 
 
+class _ProfileEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
 class _BuildParams(ctypes.Structure):
     _fields_ = [("R", ctypes.c_int32), ("L", ctypes.c_int32), ("alpha", ctypes.c_float),
                 ("num_starts", ctypes.c_int32), ("max_batch", ctypes.c_int32),
@@ -75,6 +80,8 @@ def load():
                                                    i32, vp, vp, vp, vp, sz, vp]),
         "pecann_cluster_workspace_size": (sz, [i64]),
         "pecann_cluster": (ctypes.c_int, [i64, vp, vp, vp, i32, i32, f32, f32, vp, vp, vp, sz, vp]),
+        "pecann_profile_enable": (ctypes.c_int, [i32]),
+        "pecann_profile_report": (i32, [ctypes.POINTER(_ProfileEntry), i32]),
         "pecann_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "pecann_last_error": (ctypes.c_char_p, []),
     }
@@ -225,6 +232,20 @@ def dependent_search(ds: Dataset, rank_key, knn_idx, knn_dist, adj=None, deg=Non
                                        kdep_cap, _ptr(dep), _ptr(delta), _ptr(stats), _ptr(ws),
                                        ws.numel(), _stream()))
     return dep, delta, stats
+
+
+def profile_enable(on: bool = True):
+    """Start (clearing earlier records) or stop HIP-event timing of every library launch."""
+    _check(load().pecann_profile_enable(1 if on else 0))
+
+
+def profile_report() -> dict:
+    """Synchronise recorded events; -> {family: (launches, total_ms)}."""
+    buf = (_ProfileEntry * 16)()
+    m = load().pecann_profile_report(buf, 16)
+    if m < 0:
+        raise PecannError("pecann_profile_report failed")
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(m)}
 
 
 def workspace_bytes(ds: Dataset, k: int, L_search: int, kdep_cap: int, R: int, L: int,

@@ -44,14 +44,15 @@ def test_prepared_bytes_layout(lib):
         return (v + 255) // 256 * 256
 
     n = 1000
-    assert lib.pecann_prepared_bytes(n, 16, pecann.L2, pecann.F32) == up(64 * n)
-    assert lib.pecann_prepared_bytes(n, 784, pecann.L2, pecann.U8) == up(784 * n)
+    nrm = up(4 * n)  # per-row squared norms
+    assert lib.pecann_prepared_bytes(n, 16, pecann.L2, pecann.F32) == up(64 * n) + nrm
+    assert lib.pecann_prepared_bytes(n, 784, pecann.L2, pecann.U8) == up(784 * n) + nrm
     bf = lib.pecann_prepared_bytes(n, 128, pecann.L2, pecann.BF16)
-    assert bf == up(256 * n) + up(512 * n)
+    assert bf == up(256 * n) + up(512 * n) + nrm
     f8 = lib.pecann_prepared_bytes(n, 1024, pecann.COSINE, pecann.FP8E4M3)
-    assert f8 == up(1024 * n) + up(4096 * n) + up(4 * n)
-    assert lib.pecann_prepared_bytes(n, 5, pecann.L2, pecann.U8) == up(16 * n)
-    assert lib.pecann_prepared_bytes(n, 7, pecann.L2, pecann.F32) == up(32 * n)
+    assert f8 == up(1024 * n) + up(4096 * n) + up(4 * n) + nrm
+    assert lib.pecann_prepared_bytes(n, 5, pecann.L2, pecann.U8) == up(16 * n) + nrm
+    assert lib.pecann_prepared_bytes(n, 7, pecann.L2, pecann.F32) == up(32 * n) + nrm
     # invalid combinations
     assert lib.pecann_prepared_bytes(1, 16, pecann.L2, pecann.F32) == 0
     assert lib.pecann_prepared_bytes(n, 0, pecann.L2, pecann.F32) == 0

@@ -187,10 +187,27 @@ def grid_case():
 def test_build_graph_bit_exact(dev, grid_case, alpha):
     X, P, perm = grid_case["X"], grid_case["P"], grid_case["perm"]
     R, L = 16, 32
-    adj_o, deg_o = oracle.vamana_build(P, R, L, alpha, perm, num_starts=4)
+    adj_o, deg_o = oracle.vamana_build(P, R, L, alpha, perm, num_starts=4, max_batch=60)
     ds = pecann.Dataset(_t(X, dev), "l2", "f32")
     adj, deg = pecann.build_graph(ds, R, L, alpha, num_starts=4, visited_cap=1024,
-                                  perm=_t(perm, dev))
+                                  perm=_t(perm, dev), max_batch=60)
+    assert np.array_equal(_np(deg), deg_o)
+    assert np.array_equal(_np(adj), adj_o)
+
+
+@pytest.mark.parametrize("alpha", [1.0, 2.0])
+def test_build_graph_bit_exact_u8_rows(dev, alpha):
+    # uint8 rows: distances to p by direct differences, candidate pairs on the
+    # integer matrix cores -- both exact, so the graph matches the oracle's
+    n, d = 2500, 64
+    X, _ = datagen.mixture(n, d, 6, seed=3, grid=255)
+    X = X.astype(np.uint8)
+    P = oracle.Points(X)
+    perm = datagen.permutation(n, 9)
+    adj_o, deg_o = oracle.vamana_build(P, 24, 40, alpha, perm, num_starts=4, max_batch=300)
+    ds = pecann.Dataset(_t(X, dev), "l2", "u8")
+    adj, deg = pecann.build_graph(ds, 24, 40, alpha, num_starts=4, visited_cap=1024,
+                                  perm=_t(perm, dev), max_batch=300)
     assert np.array_equal(_np(deg), deg_o)
     assert np.array_equal(_np(adj), adj_o)
 
@@ -200,7 +217,7 @@ def test_search_and_dependent_rounds_bit_exact(dev, grid_case):
     R, L, k = 16, 32, 10
     adj_o, deg_o = oracle.vamana_build(P, R, L, 2.0, perm, num_starts=4)
     ref = oracle.anns_dpc(X, k=k, n_c=8, R=R, L_build=L, alpha=2.0, perm=perm, L_search=24,
-                          L_d=16, threshold=20, num_starts=4, kdep_cap=256)
+                          L_d=16, threshold=20, num_starts=4, kdep_cap=256, max_batch=0)
     assert np.array_equal(ref["adj"], adj_o)
     ds = pecann.Dataset(_t(X, dev), "l2", "f32")
     adj, deg = _t(adj_o, dev), _t(deg_o, dev)
