@@ -78,8 +78,9 @@ typedef enum { PECANN_CENTER_PRODUCT = 0, PECANN_CENTER_THRESHOLD = 1 } pecann_c
  *                every reported distance and every ordering is float32);
  *   row scale    n floats (FP8E4M3 only): row t of the search copy holds
  *                x_t / scale_t with scale_t = max_j |x_tj| / 448;
- *   row norms    n 32-bit squared norms of the search rows (used when
- *                candidate-pair distances are formed on the matrix cores);
+ *   row norms    n 32-bit squared norms of the search rows, and for BF16/FP8
+ *                also of the float32 rerank rows (used when distances are
+ *                formed from matrix-core dot products);
  *   for PECANN_COSINE every row is divided by its norm first, so that
  *   D = 1 - x.y on the prepared rows (a zero row stays zero: D = 1).
  * Only the sizes matter to the caller: pecann_prepared_bytes() gives the
@@ -175,6 +176,11 @@ pecann_status pecann_build_graph(const pecann_dataset *ds, const pecann_build_pa
  * falls back to an exact search for that point (Sec. 4.1).
  * Without a graph (adj == NULL): exact brute force over all other points (the
  * paper's BruteForce index); distances always from float32 (or exact U8) rows.
+ * From n >= 4096 on, the exact search runs as a matrix-core scan (float32 dot
+ * products, or exact int8 ones on U8 rows) that keeps 256 candidates per
+ * point, followed by a direct-difference re-score; a point whose k-th distance
+ * is not separated from the dropped candidates by the scan's rounding bound is
+ * searched again by the direct-difference kernel, so the result is the same.
  *
  * Outputs (device): knn_idx[n*k] int32 and knn_dist[n*k] float (distances D,
  * not squared), ascending; rho[n] float (+inf when D_k = 0); rank_key[n]
@@ -183,7 +189,9 @@ pecann_status pecann_build_graph(const pecann_dataset *ds, const pecann_build_pa
  * neighbour ids read, [2] rows gathered, [3] float32 rows re-scored.
  * Limits: 1 <= k <= min(n-1, 64); k <= L_search <= 1024; k <= rerank <= L_search.
  * ------------------------------------------------------------------------- */
-size_t pecann_knn_density_workspace_size(const pecann_dataset *ds, int32_t k, int32_t L_search);
+/* exact != 0 sizes the workspace of the no-graph (exact) mode. */
+size_t pecann_knn_density_workspace_size(const pecann_dataset *ds, int32_t k, int32_t L_search,
+                                         int32_t exact);
 pecann_status pecann_knn_density(const pecann_dataset *ds, const int32_t *adj,
                                  const int32_t *deg, int32_t R, int32_t k, int32_t L_search,
                                  int32_t rerank, int32_t *knn_idx, float *knn_dist,
@@ -241,8 +249,8 @@ pecann_status pecann_cluster(int64_t n, const float *rho, const int32_t *dep,
  * every kernel the library launches from this thread is bracketed by a pair of
  * HIP events recorded on the launch stream, filed under its kernel family
  * ("search_build", "search_knn", "search_dep", "prune_forward",
- * "prune_reverse", "reverse_edges", "bf_knn", "bf_dep", "prepare", "cluster",
- * "other").  pecann_profile_enable(1) clears earlier records; enable(0) stops
+ * "prune_reverse", "reverse_edges", "bf_knn", "bf_dep", "exact_mfma", "prepare",
+ * "cluster", "other").  pecann_profile_enable(1) clears earlier records; enable(0) stops
  * recording.  pecann_profile_report synchronises the recorded events and
  * writes up to max_entries family totals into out; it returns the number
  * written, or -1 on a HIP error.  Events come from a pool the library keeps

@@ -11,12 +11,6 @@
 
 namespace pecann {
 
-// Engine over exact rows: the search rows themselves when they are float32 or
-// uint8, else the float32 rerank rows.
-template <int DT, int G>
-using ExactEngine = typename std::conditional<(DT == PECANN_F32 || DT == PECANN_U8), Engine<DT, G>,
-                                              Engine32<G>>::type;
-
 template <int DT, int G>
 __global__ __launch_bounds__(64) void bf_knn_kernel(BfKnnParams p) {
   extern __shared__ __align__(16) uint8_t smem[];

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "pecann.h"
 #include "kernels.hpp"
 
@@ -309,5 +311,11 @@ struct Engine32 {
     return acc;
   }
 };
+
+// Engine over exact rows: the search rows themselves when they are float32 or
+// uint8, else the float32 rerank rows.
+template <int DT, int G>
+using ExactEngine = typename std::conditional<(DT == PECANN_F32 || DT == PECANN_U8), Engine<DT, G>,
+                                              Engine32<G>>::type;
 
 }  // namespace pecann

@@ -1,0 +1,325 @@
+// Exact kNN on the matrix cores (the BruteForce index of Sec. 4.1 at scale).
+//
+// scan:   a workgroup of 4 wavefronts takes 64 queries (16 per wavefront) and
+//         streams every point past them in blocks of 64 candidates.  Candidate
+//         rows are staged through LDS four 64-byte steps at a time; each
+//         wavefront forms a 16 x 64 block of dot products on the matrix cores
+//         (f32 16x16x4, or i8 16x16x64 on uint8 rows shifted to x - 128, which
+//         is exact) and turns them into distance measures with the stored row
+//         norms.  Every lane keeps, for each of its 4 query rows, the 16 smallest
+//         (measure, index) pairs of its column stream in registers.
+// rerank: one wavefront per query re-scores the 256 kept candidates by direct
+//         differences -- the same float32 arithmetic as the brute-force kernel
+//         -- and keeps the k best.  A candidate the scan dropped had a
+//         matrix-core measure >= thr (the smallest value any queue dropped), so
+//         its exact measure is >= thr - E, with E a bound on the rounding of
+//         |a|^2 + |b|^2 - 2 a.b; if the k-th re-scored measure is < thr - E the
+//         answer is exact, otherwise the query goes to the brute-force kernel.
+#include "beam.hpp"
+
+namespace pecann {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int kQT = 64;   // queries per workgroup
+constexpr int kCT = 64;   // candidates per block
+constexpr int kKQ = 16;   // queue length per lane and query row
+constexpr int kSPB = 4;   // 64-byte steps staged per barrier
+constexpr int kCand = 16 * kKQ;
+
+struct ScanRows {
+  const uint8_t *rows;
+  int64_t stride;          // bytes
+  int32_t nch;             // 16-byte chunks per row
+  const uint32_t *norms;   // float bits (F32) or int32 (U8)
+};
+
+__device__ __forceinline__ bool kv_less(float a, int ia, float b, int ib) {
+  return a < b || (a == b && ia < ib);
+}
+
+__device__ __forceinline__ uint4 shift_u8(uint4 v) {
+  v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
+  return v;
+}
+
+template <int SDT>
+__global__ __launch_bounds__(256) void exact_scan_kernel(ScanRows sr, int32_t n, int32_t metric,
+                                                         int32_t *cand, float *thr) {
+  __shared__ uint4 bs[kCT][4 * kSPB + 1];
+  __shared__ uint32_t bn[kCT];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, c16 = l & 15;
+  const int q0 = blockIdx.x * kQT + 16 * w;  // this wavefront's first query
+  const int qa = q0 + c16;                    // the query row this lane feeds as A
+  const int steps = (sr.nch + 3) >> 2;
+  const uint8_t *pa = sr.rows + (int64_t)(qa < n ? qa : 0) * sr.stride;
+
+  float qd[4][kKQ];
+  int qi[4][kKQ];
+  float nq[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int q = q0 + 4 * g + r;
+    nq[r] = 0.f;
+    if (q < n) nq[r] = SDT == PECANN_U8 ? (float)(int)sr.norms[q] : __uint_as_float(sr.norms[q]);
+#pragma unroll
+    for (int s = 0; s < kKQ; ++s) { qd[r][s] = __int_as_float(0x7f800000); qi[r][s] = -1; }
+  }
+
+  for (int cb = 0; cb < n; cb += kCT) {
+    if (tid < kCT) bn[tid] = (cb + tid < n) ? sr.norms[cb + tid] : 0u;
+    v4f accf[4];
+    v4i acci[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) { accf[t] = v4f{0.f, 0.f, 0.f, 0.f}; acci[t] = v4i{0, 0, 0, 0}; }
+    const int br = cb + (tid >> 2);  // candidate row this thread stages
+    const uint8_t *pb = sr.rows + (int64_t)(br < n ? br : 0) * sr.stride;
+    for (int s0 = 0; s0 < steps; s0 += kSPB) {
+      uint4 bv[kSPB], av[kSPB];
+#pragma unroll
+      for (int u = 0; u < kSPB; ++u) {
+        const int bq = (tid & 3) + 4 * (s0 + u);
+        bv[u] = make_uint4(0, 0, 0, 0);
+        if (br < n && bq < sr.nch) {
+          bv[u] = *(const uint4 *)(pb + 16 * bq);
+          if (SDT == PECANN_U8) bv[u] = shift_u8(bv[u]);
+        }
+        const int aq = g + 4 * (s0 + u);
+        av[u] = make_uint4(0, 0, 0, 0);
+        if (qa < n && aq < sr.nch) {
+          av[u] = *(const uint4 *)(pa + 16 * aq);
+          if (SDT == PECANN_U8) av[u] = shift_u8(av[u]);
+        }
+      }
+      __syncthreads();  // the previous group's operands have been read
+#pragma unroll
+      for (int u = 0; u < kSPB; ++u) bs[tid >> 2][4 * u + (tid & 3)] = bv[u];
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kSPB; ++u) {
+        if (s0 + u >= steps) break;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const uint4 b = bs[16 * t + c16][4 * u + g];
+          if (SDT == PECANN_U8) {
+            const v4i ai = {(int)av[u].x, (int)av[u].y, (int)av[u].z, (int)av[u].w};
+            const v4i bi = {(int)b.x, (int)b.y, (int)b.z, (int)b.w};
+            acci[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ai, bi, acci[t], 0, 0, 0);
+          } else {
+            accf[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av[u].x), __uint_as_float(b.x), accf[t], 0, 0, 0);
+            accf[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av[u].y), __uint_as_float(b.y), accf[t], 0, 0, 0);
+            accf[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av[u].z), __uint_as_float(b.z), accf[t], 0, 0, 0);
+            accf[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av[u].w), __uint_as_float(b.w), accf[t], 0, 0, 0);
+          }
+        }
+      }
+    }
+    // epilogue: measures of this block into the lane's queues
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int col = cb + 16 * t + c16;
+      const uint32_t nbits = bn[16 * t + c16];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = q0 + 4 * g + r;
+        if (col >= n || q >= n || col == q) continue;
+        float m;
+        if (SDT == PECANN_U8) {
+          const int d2 = (int)nq[r] + (int)nbits - 2 * acci[t][r];
+          m = (float)(d2 < 0 ? 0 : d2);
+        } else if (metric == PECANN_L2) {
+          m = fmaxf(0.f, nq[r] + __uint_as_float(nbits) - 2.0f * accf[t][r]);
+        } else {
+          m = fmaxf(0.f, 1.0f - accf[t][r]);
+        }
+        if (kv_less(m, col, qd[r][kKQ - 1], qi[r][kKQ - 1])) {
+          float cd = m;
+          int ci = col;
+#pragma unroll
+          for (int s = kKQ - 1; s > 0; --s) {
+            const bool shift = kv_less(cd, ci, qd[r][s - 1], qi[r][s - 1]);
+            const bool here = !shift && kv_less(cd, ci, qd[r][s], qi[r][s]);
+            const float od = qd[r][s];
+            const int oi = qi[r][s];
+            qd[r][s] = shift ? qd[r][s - 1] : (here ? cd : od);
+            qi[r][s] = shift ? qi[r][s - 1] : (here ? ci : oi);
+          }
+          if (kv_less(cd, ci, qd[r][0], qi[r][0])) { qd[r][0] = cd; qi[r][0] = ci; }
+        }
+      }
+    }
+    __syncthreads();  // bn is rewritten by the next block
+  }
+
+  // queues out; thr = smallest measure any of the 16 lanes of a row dropped
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int q = q0 + 4 * g + r;
+    float last = qd[r][kKQ - 1];
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) last = fminf(last, __shfl_xor(last, m));
+    if (q < n) {
+      int32_t *o = cand + (int64_t)q * kCand + c16 * kKQ;
+#pragma unroll
+      for (int s = 0; s < kKQ; ++s) o[s] = qi[r][s];
+      if (c16 == 0) thr[q] = last;
+    }
+  }
+}
+
+__global__ __launch_bounds__(1024) void norm_max_kernel(const uint32_t *norms, int32_t n, float *out) {
+  __shared__ float part[16];
+  float m = 0.f;
+  for (int i = threadIdx.x; i < n; i += 1024) m = fmaxf(m, __uint_as_float(norms[i]));
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) m = fmaxf(m, __shfl_xor(m, s));
+  if (lane_id() == 0) part[threadIdx.x / 64] = m;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    float v = threadIdx.x < 16 ? part[threadIdx.x] : 0.f;
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) v = fmaxf(v, __shfl_xor(v, s));
+    if (threadIdx.x == 0) *out = v;
+  }
+}
+
+}  // namespace
+
+// One wavefront per query: exact re-score of the scan's candidates, check, output.
+template <int DT, int G>
+__global__ __launch_bounds__(64) void exact_rerank_kernel(ExactMfmaParams p, float ce, int u8rows) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int k = p.k;
+  const int kp = (k + 15) & ~15;
+  SortedList top;
+  top.a = (uint64_t *)smem;
+  top.b = top.a + kp;
+  top.tmp = top.b + kp;
+  top.fa = (uint8_t *)(top.tmp + 64);
+  top.fb = top.fa + kp;
+  top.cap = k;
+  using E = ExactEngine<DT, G>;
+  constexpr int NPL = E::NPL;
+  E eng;
+  const int l = lane_id();
+  for (;;) {
+    const int q = next_item(p.head);
+    if (q >= p.n) break;
+    eng.load_query(p.rows, q);
+    top.m = 0;
+    wave_lds_sync();
+    const int32_t *c = p.cand + (int64_t)q * kCand;
+    for (int base = 0; base < kCand; base += NPL) {
+      const int32_t row = c[base + l / G];
+      const float m = eng.measure(p.rows, row);
+      const uint64_t key = row >= 0 ? make_key(m, row) : kNoKey;
+      uint64_t kk = shfl_u64(key, (l % NPL) * G);
+      if (l >= NPL) kk = kNoKey;
+      top.merge(kk);
+    }
+    bool ok = top.m == k;
+    if (ok) {
+      // rounding bound of the matrix-core measure against the exact one
+      float nqv;
+      if (u8rows) nqv = 0.f;
+      else nqv = p.rows.xr ? p.rows.sqn_r[q] : __uint_as_float(p.rows.sqn[q]);
+      const float e = u8rows ? ce : ce * (nqv + *p.nmax);
+      const float t = p.thr[q];
+      ok = key_measure(top.a[k - 1]) < t - e;
+    }
+    if (ok) {
+      const int64_t o = (int64_t)q * k;
+      for (int t = l; t < k; t += kWave) {
+        const uint64_t kt = top.a[t];
+        p.knn_idx[o + t] = key_id(kt);
+        p.knn_dist[o + t] = measure_to_dist(key_measure(kt), p.rows.metric);
+      }
+      if (l == 0) {
+        const uint64_t kk = top.a[k - 1];
+        p.rho[q] = 1.0f / measure_to_dist(key_measure(kk), p.rows.metric);
+        p.rank_key[q] = (kk & 0xffffffff00000000ull) | (uint32_t)q;
+      }
+    } else if (l == 0) {
+      p.fb_list[atomicAdd(p.fb_count, 1)] = q;
+    }
+    wave_lds_sync();
+  }
+}
+
+template <int DT, int G>
+static hipError_t launch_rerank_t(const ExactMfmaParams &p, float ce, int u8rows, int grid,
+                                  hipStream_t st) {
+  const size_t kp = (size_t)((p.k + 15) & ~15);
+  hipLaunchKernelGGL((exact_rerank_kernel<DT, G>), dim3(grid), dim3(64), 8 * (2 * kp + 64) + 2 * kp, st,
+                     p, ce, u8rows);
+  return hipGetLastError();
+}
+
+#define PECANN_DISPATCH_G(FN, DT, ...)                      \
+  switch (G) {                                              \
+    case 4: return FN<DT, 4>(__VA_ARGS__);                  \
+    case 8: return FN<DT, 8>(__VA_ARGS__);                  \
+    case 16: return FN<DT, 16>(__VA_ARGS__);                \
+    case 32: return FN<DT, 32>(__VA_ARGS__);                \
+    case 64: return FN<DT, 64>(__VA_ARGS__);                \
+    default: return hipErrorInvalidValue;                   \
+  }
+
+static hipError_t launch_rerank(int32_t dt, int G, const ExactMfmaParams &p, float ce, int u8rows,
+                                int grid, hipStream_t st) {
+  switch (dt) {
+    case PECANN_F32: PECANN_DISPATCH_G(launch_rerank_t, PECANN_F32, p, ce, u8rows, grid, st)
+    case PECANN_U8: PECANN_DISPATCH_G(launch_rerank_t, PECANN_U8, p, ce, u8rows, grid, st)
+    case PECANN_BF16: PECANN_DISPATCH_G(launch_rerank_t, PECANN_BF16, p, ce, u8rows, grid, st)
+    case PECANN_FP8E4M3: PECANN_DISPATCH_G(launch_rerank_t, PECANN_FP8E4M3, p, ce, u8rows, grid, st)
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_exact_mfma(int32_t dt, int G, const ExactMfmaParams &p, hipStream_t st) {
+  const Rows &r = p.rows;
+  ScanRows sr;
+  const bool u8 = dt == PECANN_U8;
+  if (dt == PECANN_F32 || u8) {
+    sr.rows = r.xs;
+    sr.stride = r.xs_stride;
+    sr.nch = r.nch;
+    sr.norms = r.sqn;
+  } else {
+    sr.rows = (const uint8_t *)r.xr;
+    sr.stride = r.xr_stride * 4;
+    sr.nch = r.nch_r;
+    sr.norms = (const uint32_t *)r.sqn_r;
+  }
+  const unsigned blocks = (unsigned)((p.n + kQT - 1) / kQT);
+  if (u8) {
+    hipLaunchKernelGGL(exact_scan_kernel<PECANN_U8>, dim3(blocks), dim3(256), 0, st, sr, p.n, r.metric,
+                       p.cand, p.thr);
+  } else {
+    hipLaunchKernelGGL(norm_max_kernel, dim3(1), dim3(1024), 0, st, sr.norms, p.n, p.nmax);
+    hipLaunchKernelGGL(exact_scan_kernel<PECANN_F32>, dim3(blocks), dim3(256), 0, st, sr, p.n,
+                       r.metric, p.cand, p.thr);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // Rounding bound.  Matrix-core measure |a|^2 + |b|^2 - 2 a.b against the
+  // direct-difference float32 measure: each of the three float32 sums carries
+  // at most gamma_d of its magnitudes, the direct sum gamma_d of D^2 <= 2
+  // (|a|^2 + |b|^2), plus the final additions: E <= 4 (d + 4) u (|a|^2 + |b|^2),
+  // u = 2^-24, and |b|^2 <= the largest row norm.  Cosine rows are unit:
+  // E <= 4 (d + 4) u * 2.  uint8 rows: the matrix-core measure is exact and
+  // only the float32 direct sum rounds, by at most (d + 2) u * d * 255^2.
+  const float u = 5.9604645e-8f;
+  const float dd = (float)r.d;
+  float ce;
+  if (u8) ce = (dd + 2.0f) * u * dd * 65025.0f;
+  else if (r.metric == PECANN_L2) ce = 4.0f * (dd + 4.0f) * u;
+  else ce = 8.0f * (dd + 4.0f) * u;
+  const int grid = (int)std::min<int64_t>((int64_t)p.n, 256 * 32);
+  return launch_rerank(dt, G, p, ce, u8 ? 1 : 0, grid, st);
+}
+
+}  // namespace pecann

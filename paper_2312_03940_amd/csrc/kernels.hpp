@@ -24,6 +24,7 @@ struct RowsDesc {  // host copy of the row description (mirrors Rows)
   // float for F32/BF16/FP8 (dequantised), int32 bits of sum (x - 128)^2 over
   // the padded row for U8
   const uint32_t *sqn;
+  const float *sqn_r;  // squared norms of the float32 rerank rows (BF16/FP8), else nullptr
   int32_t nch;
   int32_t nch_r;
   int32_t d;
@@ -144,7 +145,27 @@ hipError_t launch_prune_reverse(int32_t dt, int G, const PruneParams &p, int gri
 // Plain (non-templated) kernels.
 hipError_t launch_prepare(const void *x, int32_t x_dtype, int64_t x_stride, int64_t n, int32_t d,
                           int32_t metric, int32_t sdt, const RowsDesc &rows, uint8_t *xs,
-                          float *xr, float *scale, uint32_t *sqn, hipStream_t s);
+                          float *xr, float *scale, uint32_t *sqn, float *sqn_r, hipStream_t s);
+
+// Exact kNN on the matrix cores: a scan that keeps, per query, the 16 best
+// candidates of each lane's column stream by matrix-core distance, then an
+// exact (direct-difference) re-score with a rounding-bound check.
+struct ExactMfmaParams {
+  RowsDesc rows;
+  int32_t n;
+  int32_t k;
+  int32_t *cand;               // [n][256] candidate ids of the scan
+  float *thr;                  // [n] smallest measure a scan queue dropped (+inf: none)
+  float *nmax;                 // [1] largest row norm (device)
+  int32_t *head;
+  int32_t *knn_idx;
+  float *knn_dist;
+  float *rho;
+  uint64_t *rank_key;
+  int32_t *fb_list;            // queries whose check failed
+  int32_t *fb_count;
+};
+hipError_t launch_exact_mfma(int32_t dt, int G, const ExactMfmaParams &p, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 hipError_t launch_identity_perm(int32_t *p, int64_t n, hipStream_t s);

@@ -28,7 +28,8 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
 __global__ __launch_bounds__(256) void prepare_kernel(const void *x, int32_t x_dtype, int64_t x_stride,
                                                       int64_t n, int32_t d, int32_t metric,
                                                       int32_t sdt, RowsDesc r, uint8_t *xs,
-                                                      float *xr, float *scale, uint32_t *sqn) {
+                                                      float *xr, float *scale, uint32_t *sqn,
+                                                      float *sqn_r) {
   const int l = lane_id();
   const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (row >= n) return;
@@ -55,10 +56,18 @@ __global__ __launch_bounds__(256) void prepare_kernel(const void *x, int32_t x_d
   }
   if (xr) {
     float *o = xr + row * r.xr_stride;
+    float nr = 0.f;
     for (int t = 0; t < kMaxPerLane; ++t) {
       const int e = l + 64 * t;
-      if (e < r.xr_stride) o[e] = e < d ? v[t] : 0.f;
+      if (e < r.xr_stride) {
+        const float f = e < d ? v[t] : 0.f;
+        o[e] = f;
+        nr = fmaf(f, f, nr);
+      }
     }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) nr += __shfl_xor(nr, m);
+    if (l == 0) sqn_r[row] = nr;
   }
   uint8_t *o = xs + row * r.xs_stride;
   float nf = 0.f;  // squared norm of the stored values
@@ -124,10 +133,10 @@ __global__ __launch_bounds__(256) void prepare_kernel(const void *x, int32_t x_d
 
 hipError_t launch_prepare(const void *x, int32_t x_dtype, int64_t x_stride, int64_t n, int32_t d,
                           int32_t metric, int32_t sdt, const RowsDesc &rows, uint8_t *xs,
-                          float *xr, float *scale, uint32_t *sqn, hipStream_t s) {
+                          float *xr, float *scale, uint32_t *sqn, float *sqn_r, hipStream_t s) {
   const int64_t blocks = (n + 3) / 4;
   hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, x_dtype, x_stride,
-                     n, d, metric, sdt, rows, xs, xr, scale, sqn);
+                     n, d, metric, sdt, rows, xs, xr, scale, sqn, sqn_r);
   return hipGetLastError();
 }
 

@@ -51,9 +51,9 @@ extern "C" const char *pecann_last_error(void) { return g_err; }
 namespace {
 const char *const kFamilies[] = {"search_build", "search_knn", "search_dep", "prune_forward",
                                  "prune_reverse", "reverse_edges", "bf_knn", "bf_dep",
-                                 "prepare", "cluster", "other"};
+                                 "exact_mfma", "prepare", "cluster", "other"};
 enum Family { F_SEARCH_BUILD, F_SEARCH_KNN, F_SEARCH_DEP, F_PRUNE_FWD, F_PRUNE_REV, F_REV,
-              F_BF_KNN, F_BF_DEP, F_PREPARE, F_CLUSTER, F_OTHER, F_COUNT };
+              F_BF_KNN, F_BF_DEP, F_EXACT_MFMA, F_PREPARE, F_CLUSTER, F_OTHER, F_COUNT };
 struct ProfRec { int fam; hipEvent_t a, b; };
 struct Profiler {
   bool on = false;
@@ -175,6 +175,7 @@ struct Layout {
   size_t off_xr, xr_stride;  // bytes offset, floats per row
   size_t off_scale;
   size_t off_sqn;
+  size_t off_sqn_r;
   size_t total;
   bool has_xr, has_scale;
 };
@@ -201,6 +202,8 @@ static bool make_layout(int64_t n, int32_t d, int32_t metric, int32_t sdt, Layou
   if (L->has_scale) off = up(off + 4 * (size_t)n, 256);
   L->off_sqn = off;
   off = up(off + 4 * (size_t)n, 256);
+  L->off_sqn_r = off;
+  if (L->has_xr) off = up(off + 4 * (size_t)n, 256);
   L->total = off;
   return true;
 }
@@ -214,6 +217,7 @@ static RowsDesc rows_of(const pecann_dataset *ds, const Layout &L) {
   r.xr = L.has_xr ? (const float *)(base + L.off_xr) : nullptr;
   r.xr_stride = (int64_t)L.xr_stride;
   r.sqn = (const uint32_t *)(base + L.off_sqn);
+  r.sqn_r = L.has_xr ? (const float *)(base + L.off_sqn_r) : nullptr;
   r.nch = (int32_t)(L.xs_stride / 16);
   r.nch_r = (int32_t)(L.xr_stride / 4);
   r.d = ds->d;
@@ -258,7 +262,8 @@ extern "C" pecann_status pecann_prepare_vectors(const void *x, int32_t x_dtype, 
   HIP_TRY(launch_prepare(x, x_dtype, x_stride, n, d, metric, sdt, r, base + L.off_xs,
                          L.has_xr ? (float *)(base + L.off_xr) : nullptr,
                          L.has_scale ? (float *)(base + L.off_scale) : nullptr,
-                         (uint32_t *)(base + L.off_sqn), (hipStream_t)stream));
+                         (uint32_t *)(base + L.off_sqn),
+                         L.has_xr ? (float *)(base + L.off_sqn_r) : nullptr, (hipStream_t)stream));
   return PECANN_OK;
 }
 
@@ -492,18 +497,29 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
 // ---------------------------------------------------------------------------
 // kNN + density
 // ---------------------------------------------------------------------------
-static void carve_knn(Carver &c, int64_t n, int32_t **ctr, int32_t **fb) {
-  *ctr = c.take<int32_t>(64);
-  *fb = c.take<int32_t>((size_t)n);
+// Exact kNN switches to the matrix-core scan from this many points on.
+static constexpr int64_t kExactMfmaMin = 4096;
+
+struct KnnWs {
+  int32_t *ctr, *fb, *cand;
+  float *thr, *nmax;
+};
+static void carve_knn(Carver &c, int64_t n, bool exact_mfma, KnnWs *w) {
+  w->ctr = c.take<int32_t>(64);
+  w->fb = c.take<int32_t>((size_t)n);
+  w->nmax = c.take<float>(64);
+  w->cand = exact_mfma ? c.take<int32_t>((size_t)n * 256) : nullptr;
+  w->thr = exact_mfma ? c.take<float>((size_t)n) : nullptr;
 }
 
-extern "C" size_t pecann_knn_density_workspace_size(const pecann_dataset *ds, int32_t k, int32_t L_search) {
+extern "C" size_t pecann_knn_density_workspace_size(const pecann_dataset *ds, int32_t k,
+                                                    int32_t L_search, int32_t exact) {
   Layout L;
   if (check_dataset(ds, &L) != PECANN_OK) return 0;
   (void)k; (void)L_search;
   Carver c(nullptr);
-  int32_t *a, *b;
-  carve_knn(c, ds->n, &a, &b);
+  KnnWs w;
+  carve_knn(c, ds->n, exact != 0 && ds->n >= kExactMfmaMin, &w);
   return c.size();
 }
 
@@ -527,13 +543,15 @@ extern "C" pecann_status pecann_knn_density(const pecann_dataset *ds, const int3
     if (lp && (rerank < k || rerank > L_search))
       return fail(PECANN_EINVAL, "rerank must be in [k, L_search]");
   }
+  const bool exact_mfma = !adj && n >= kExactMfmaMin;
   Carver c0(nullptr);
-  int32_t *ctr, *fb;
-  carve_knn(c0, n, &ctr, &fb);
+  KnnWs w;
+  carve_knn(c0, n, exact_mfma, &w);
   if (!ws || ws_bytes < c0.size() || !aligned(ws, 256))
     return fail(PECANN_EWORKSPACE, "workspace needs %zu bytes (256-aligned), got %zu", c0.size(), ws_bytes);
   Carver c(ws);
-  carve_knn(c, n, &ctr, &fb);
+  carve_knn(c, n, exact_mfma, &w);
+  int32_t *ctr = w.ctr, *fb = w.fb;
   hipStream_t s = (hipStream_t)stream;
   const RowsDesc rows = rows_of(ds, L);
   const int dt = ds->search_dtype;
@@ -548,13 +566,40 @@ extern "C" pecann_status pecann_knn_density(const pecann_dataset *ds, const int3
   bp.knn_dist = knn_dist;
   bp.rho = rho;
   bp.rank_key = rank_key;
-  if (!adj) {
+  if (!adj && !exact_mfma) {
     bp.items = nullptr;
     bp.item_count = nullptr;
     bp.nitems = (int32_t)n;
     bp.head = ctr + 0;
     PROF(F_BF_KNN, s);
     HIP_TRY(launch_bf_knn(dt, G, bp, persistent_grid(n), s));
+    return PECANN_OK;
+  }
+  if (exact_mfma) {
+    ExactMfmaParams ep = {};
+    ep.rows = rows;
+    ep.n = (int32_t)n;
+    ep.k = k;
+    ep.cand = w.cand;
+    ep.thr = w.thr;
+    ep.nmax = w.nmax;
+    ep.head = ctr + 0;
+    ep.knn_idx = knn_idx;
+    ep.knn_dist = knn_dist;
+    ep.rho = rho;
+    ep.rank_key = rank_key;
+    ep.fb_list = fb;
+    ep.fb_count = ctr + 1;
+    {
+      PROF(F_EXACT_MFMA, s);
+      HIP_TRY(launch_exact_mfma(dt, G, ep, s));
+    }
+    bp.items = fb;
+    bp.item_count = ctr + 1;
+    bp.nitems = 0;
+    bp.head = ctr + 2;
+    PROF(F_BF_KNN, s);
+    HIP_TRY(launch_bf_knn(dt, G, bp, cu_count() * 4, s));
     return PECANN_OK;
   }
   SearchParams sp = {};

@@ -72,7 +72,7 @@ def load():
         "pecann_prepare_vectors": (ctypes.c_int, [vp, i32, i64, i64, i32, i32, i32, vp, sz, vp]),
         "pecann_build_graph_workspace_size": (sz, [D, B]),
         "pecann_build_graph": (ctypes.c_int, [D, B, vp, ctypes.c_uint64, vp, vp, vp, vp, sz, vp]),
-        "pecann_knn_density_workspace_size": (sz, [D, i32, i32]),
+        "pecann_knn_density_workspace_size": (sz, [D, i32, i32, i32]),
         "pecann_knn_density": (ctypes.c_int, [D, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp,
                                               sz, vp]),
         "pecann_dependent_search_workspace_size": (sz, [D, i32, i32]),
@@ -196,7 +196,7 @@ def knn_density(ds: Dataset, k: int, adj=None, deg=None, L_search: int = 64, rer
     R = 0 if adj is None else adj.shape[1]
     if rerank is None:
         rerank = min(L_search, max(k, 2 * k))
-    need = lib.pecann_knn_density_workspace_size(ctypes.byref(s), k, L_search)
+    need = lib.pecann_knn_density_workspace_size(ctypes.byref(s), k, L_search, 1 if adj is None else 0)
     if ws is None or ws.numel() < need:
         ws = _ws(need, ds.device)
     if out is None:
@@ -256,7 +256,7 @@ def workspace_bytes(ds: Dataset, k: int, L_search: int, kdep_cap: int, R: int, L
     s = ds.struct
     bp = _BuildParams(R, L, alpha, num_starts, max_batch, visited_cap, passes, 0)
     return max(lib.pecann_build_graph_workspace_size(ctypes.byref(s), ctypes.byref(bp)),
-               lib.pecann_knn_density_workspace_size(ctypes.byref(s), k, L_search),
+               lib.pecann_knn_density_workspace_size(ctypes.byref(s), k, L_search, 0),
                lib.pecann_dependent_search_workspace_size(ctypes.byref(s), kdep_cap, L_search),
                lib.pecann_cluster_workspace_size(ds.n))
 

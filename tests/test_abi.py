@@ -48,9 +48,9 @@ def test_prepared_bytes_layout(lib):
     assert lib.pecann_prepared_bytes(n, 16, pecann.L2, pecann.F32) == up(64 * n) + nrm
     assert lib.pecann_prepared_bytes(n, 784, pecann.L2, pecann.U8) == up(784 * n) + nrm
     bf = lib.pecann_prepared_bytes(n, 128, pecann.L2, pecann.BF16)
-    assert bf == up(256 * n) + up(512 * n) + nrm
+    assert bf == up(256 * n) + up(512 * n) + 2 * nrm
     f8 = lib.pecann_prepared_bytes(n, 1024, pecann.COSINE, pecann.FP8E4M3)
-    assert f8 == up(1024 * n) + up(4096 * n) + up(4 * n) + nrm
+    assert f8 == up(1024 * n) + up(4096 * n) + up(4 * n) + 2 * nrm
     assert lib.pecann_prepared_bytes(n, 5, pecann.L2, pecann.U8) == up(16 * n) + nrm
     assert lib.pecann_prepared_bytes(n, 7, pecann.L2, pecann.F32) == up(32 * n) + nrm
     # invalid combinations

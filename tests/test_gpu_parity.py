@@ -153,6 +153,28 @@ def test_exact_integer_grid_bit_exact(dev, n, d, k, nc):
     assert np.array_equal(g["is_center"], ref["is_center"])
 
 
+@pytest.mark.parametrize("n", [4096, 20_000])
+def test_exact_mnist_shaped_u8_rows_bit_exact(dev, n):
+    # exact mode on the integer matrix cores (uint8 rows shifted to int8): exact
+    # integer distances, so indices and labels are bit-exact
+    X, _ = datagen.config2(n=n)
+    ref = oracle.exact_dpc(X, k=10, n_c=10)
+    g = _exact_gpu(X, 10, 10, dev, sdt="u8")
+    assert np.array_equal(g["knn_idx"], ref["knn_idx"])
+    assert np.allclose(g["knn_dist"], ref["knn_dist"], rtol=1e-7)
+    assert np.array_equal(g["dep"], ref["dep"])
+    assert np.array_equal(g["labels"], ref["labels"])
+
+
+def test_exact_bf16_dataset_uses_float32_rows(dev):
+    # a BF16 search dataset's exact mode scans its float32 rerank rows
+    X, _ = datagen.mixture(6000, 48, 6, seed=77, grid=400)
+    ref = oracle.exact_dpc(X, k=8, n_c=6)
+    g = _exact_gpu(X, 8, 6, dev, sdt="bf16")
+    assert np.array_equal(g["knn_idx"], ref["knn_idx"])
+    assert np.array_equal(g["labels"], ref["labels"])
+
+
 def test_exact_c1_float_margin_rule(dev):
     X, _ = datagen.config1()
     k, nc = 10, 10
@@ -297,3 +319,53 @@ def test_anns_dpc_mnist_shaped(dev, sdt):
     assert (g_dep < 0).sum() == 1
     assert np.all(g_key[g_dep[ok]] < g_key[ok])
     assert np.all(_np(dist)[:, -1] >= ref["knn_dist"][:, -1] * (1 - 1e-6))  # rho_hat <= rho
+
+
+# ----------------------------------------------------------------------------
+# reduced-precision search rows (BF16, FP8-e4m3 per-row scaled), float32 rerank
+# ----------------------------------------------------------------------------
+def _anns_gpu(X, metric, sdt, k, n_c, R, L, alpha, L_search, rerank, dev, L_d=None):
+    ds = pecann.Dataset(_t(X, dev), metric, sdt)
+    adj, deg = pecann.build_graph(ds, R, L, alpha, seed=11)
+    idx, dist, rho, key = pecann.knn_density(ds, k, adj, deg, L_search=L_search, rerank=rerank)
+    dep, delta, _ = pecann.dependent_search(ds, key, idx, dist, adj, deg,
+                                            L_d=L_d or max(2 * k, 32), L_search=L_search)
+    labels, _ = pecann.cluster(rho, dep, delta, n_c=n_c)
+    return _np(idx), _np(dist), _np(labels), _np(dep), _np(key).view(np.uint64)
+
+
+@pytest.mark.parametrize("sdt", ["bf16", "f32"])
+def test_c3_shaped_bf16_vs_oracle(dev, sdt):
+    X, _ = datagen.config3(n_clusters=100, per_cluster=200, background=1000)
+    n = X.shape[0]
+    P = oracle.Points(X)
+    ref = oracle.exact_dpc(X, k=16, n_c=100)
+    idx, dist, labels, dep, key = _anns_gpu(X, "l2", sdt, 16, 100, 64, 128, 1.2, 64, 64, dev)
+    q = np.arange(0, n, 37)
+    rec = metrics.recall_at_k(P, q, idx[q], ref["knn_dist"][q], 16)
+    a = metrics.ari(labels, ref["labels"])
+    assert rec >= 0.95, rec
+    assert a >= 0.95, a
+    # re-scored distances are float32 distances of the reported points
+    for i in q[:40]:
+        for t in range(16):
+            assert dist[i, t] == pytest.approx(oracle.distance(P, int(i), int(idx[i, t])), rel=2e-6)
+    ok = dep >= 0
+    assert np.all(key[dep[ok]] < key[ok]) and (~ok).sum() == 1
+
+
+def test_c4_shaped_fp8_cosine_vs_oracle(dev):
+    X, _ = datagen.config4(n_clusters=40, per_cluster=400, d=1024)
+    n = X.shape[0]
+    P = oracle.Points(X, oracle.COSINE)
+    ref = oracle.exact_dpc(X, k=10, n_c=40, metric=oracle.COSINE)
+    idx, dist, labels, dep, key = _anns_gpu(X, "cosine", "fp8", 10, 40, 64, 200, 1.2, 64, 64, dev)
+    q = np.arange(0, n, 41)
+    rec = metrics.recall_at_k(P, q, idx[q], ref["knn_dist"][q], 10)
+    a = metrics.ari(labels, ref["labels"])
+    assert rec >= 0.95, rec
+    assert a >= 0.95, a
+    for i in q[:40]:
+        for t in range(10):
+            assert dist[i, t] == pytest.approx(oracle.distance(P, int(i), int(idx[i, t])),
+                                               rel=1e-4, abs=2e-6)
