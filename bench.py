@@ -1,26 +1,39 @@
 """Benchmark of the DPC hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--config 2|3|4] [--search f32|u8|bf16|fp8] [--mode anns|exact]
 
-Workload (the MNIST-shaped configuration): 70,000 x 784 uint8 points from a seeded
-10-Gaussian mixture scaled into [0, 255], L2 distance, float32 search rows, Vamana
-graph with R = 64, build beam L = 128, alpha = 1.2 (two passes), kth density with
-k = 10, doubling dependent search (L_d = 64, threshold = 300), 10 product centers.
+Default workload (the MNIST-shaped configuration): 70,000 x 784 uint8 points from a
+seeded 10-Gaussian mixture scaled into [0, 255], L2, float32 search rows, Vamana
+graph R = 64, build beam L = 128, alpha = 1.2 (two passes), kth density k = 10,
+doubling dependent search (L_d = 64, threshold = 300), 10 product centers.
 
 One step = the whole hot path on resident data: prepare_vectors -> build_graph ->
-knn_density -> dependent_search -> cluster, all on one HIP stream.  `value` is DPC
-points/s = n * K / (time of K steps).  Quality gates after timing: ARI of the
-labels against the oracle's exact DPC, and recall@10 of the kNN on a 2,000-query
-sample, both from tests/golden/c2_reference.npz (written by the oracle).
+knn_density -> dependent_search -> cluster, all on one HIP stream (exact mode:
+prepare -> exact knn_density -> exact dependent_search -> cluster).  `value` is
+DPC points/s = n * K / (wall time of K steps).  Quality gates after timing: ARI
+of the labels against the oracle's exact DPC and recall@10 on a 2,000-query
+sample (tests/golden/c2_reference.npz, written by the oracle).  The default run
+also reports variants of the same workload: uint8 search rows (bit-identical
+results) and the exact mode (the paper's BruteForce instantiation) on the GPU.
 
-`roofline` reports the kNN search launch (search_kernel<f32, 16, MODE_KNN>, the
-single largest gather-bound launch): algorithmic bytes from the kernel's own work
-counters divided by its HIP-event time; `cpu_baseline` times the CPU oracle's
-exact DPC on a bounded sample.
+--config 3 (1,000,000 x 128, BF16 vs FP32 rows) and --config 4 (1,280,000 x 1024
+unit vectors, cosine, FP8-e4m3 vs FP32 rows) run the larger workloads; their recall
+gate uses the oracle's exact neighbours of a 2,000-point sample
+(tests/golden/c{3,4}_sample.npz) and their ARI gate the GPU exact mode, which the
+GPU tests check bit-exact against the oracle at smaller sizes.
+
+`roofline` reports the dominant gather kernel: algorithmic bytes from the kernel's
+own work counters divided by its average launch time, both measured over the
+timed steps with HIP events on the launch stream; `traffic` is the HBM bytes per
+launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs in profiles/ (null when the
+kernel sources changed since).  `cpu_baseline` times the CPU oracle's exact DPC on
+a bounded sample.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -33,8 +46,49 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DPC points/s at ARI>=0.95 vs oracle; kNN queries/s at recall@10>=0.95"
 HBM_PEAK_GBS = 8000.0
-REF_PATH = os.path.join(ROOT, "tests", "golden", "c2_reference.npz")
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic.json")
+
+WORKLOADS = {
+    2: dict(name="MNIST-shaped 70000x784 uint8 10-Gaussian mixture, L2", metric="l2",
+            R=64, L=128, alpha=1.2, k=10, n_c=10, L_search=64, L_d=64, search="f32"),
+    3: dict(name="1000000x128 float32 mixture of 1000 Gaussians + 5% uniform noise, L2",
+            metric="l2", R=64, L=128, alpha=1.2, k=16, n_c=1000, L_search=64, L_d=64,
+            search="bf16"),
+    4: dict(name="1280000x1024 float32 unit vectors, 1000 clusters (mean cosine 0.7), cosine",
+            metric="cosine", R=64, L=200, alpha=1.2, k=10, n_c=1000, L_search=64, L_d=64,
+            search="fp8"),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4])
+    ap.add_argument("--search", default=None, choices=["f32", "u8", "bf16", "fp8"])
+    ap.add_argument("--mode", default="anns", choices=["anns", "exact"])
+    ap.add_argument("--L-search", type=int, default=None)
+    ap.add_argument("--L-d", type=int, default=None)
+    ap.add_argument("--rerank", type=int, default=None)
+    ap.add_argument("--threshold", type=int, default=300)
+    ap.add_argument("--kdep-cap", type=int, default=1024)
+    ap.add_argument("--num-starts", type=int, default=8)
+    ap.add_argument("--max-batch", type=int, default=0,
+                    help="build batch cap (0: the library default, max(n/50, 8192))")
+    ap.add_argument("--cpu-sample", type=int, default=16000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (a reference "
+                         "kernel of known traffic for hardware byte counters)")
+    return ap.parse_args()
+
+
+def ari(a, b) -> float:
+    from sklearn.metrics import adjusted_rand_score
+    return float(adjusted_rand_score(a, b))
 
 
 def stored_traffic(key: str):
@@ -50,32 +104,6 @@ def stored_traffic(key: str):
     return int(t[key]["traffic_bytes_per_launch"])
 
 
-def parse():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--search", default="f32", choices=["f32", "u8"])
-    ap.add_argument("--L-search", type=int, default=64)
-    ap.add_argument("--L-d", type=int, default=64)
-    ap.add_argument("--threshold", type=int, default=300)
-    ap.add_argument("--kdep-cap", type=int, default=1024)
-    ap.add_argument("--num-starts", type=int, default=8)
-    ap.add_argument("--max-batch", type=int, default=0,
-                    help="build batch cap (0: the library default, max(n/50, 8192))")
-    ap.add_argument("--cpu-sample", type=int, default=16000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-probe-mb", type=int, default=0,
-                    help="also run one device-to-device copy of this many MiB (a reference "
-                         "kernel of known traffic for hardware byte counters)")
-    return ap.parse_args()
-
-
-def ari(a, b) -> float:
-    from sklearn.metrics import adjusted_rand_score
-    return float(adjusted_rand_score(a, b))
-
-
 def cpu_baseline(X, ref, sample_size):
     """The oracle as it stands: exact kNN (k = 10) and exact dependent points of a
     sample of points against all n points, FP64, all host threads."""
@@ -88,11 +116,187 @@ def cpu_baseline(X, ref, sample_size):
     oracle.knn(P, 10, q)
     oracle.dependent_exact(P, rank, q)
     dt = time.perf_counter() - t0
-    return {"value": sample_size / dt, "unit": "points/s", "cores": oracle.num_threads(),
+    return {"value": round(sample_size / dt, 1), "unit": "points/s", "cores": oracle.num_threads(),
             "kind": "oracle", "sample": (f"exact DPC (FP64 brute-force 10-NN + Def. 1 dependent) of "
                                          f"{sample_size} evenly spaced points against all {n}; "
                                          f"density ranks from the stored oracle run"),
-            "seconds": dt}
+            "seconds": round(dt, 2)}
+
+
+def recall_from_sample(idx, dist, sample, ref_dist, k):
+    """Tie-tolerant recall: a returned point counts when its reported float32 distance
+    is within the oracle's k-th distance (duplicates and the query itself never count)."""
+    hits = 0
+    for t, q in enumerate(sample):
+        thr = np.float32(ref_dist[t, k - 1])
+        seen = set()
+        for j, dj in zip(idx[t], dist[t]):
+            j = int(j)
+            if j < 0 or j == q or j in seen:
+                continue
+            seen.add(j)
+            hits += float(dj) <= thr
+    return hits / (k * len(sample))
+
+
+class Pipeline:
+    """Buffers and launch sequence of one DPC step on a resident dataset."""
+
+    def __init__(self, x, wl, search, mode, args, perm):
+        import torch
+        from paper_2312_03940_amd import pecann
+        self.torch, self.pecann = torch, pecann
+        self.x, self.wl, self.mode, self.args, self.perm = x, wl, mode, args, perm
+        dev = x.device
+        self.ds = ds = pecann.Dataset(x, wl["metric"], search)
+        n, k, R = ds.n, wl["k"], wl["R"]
+        self.Ls = args.L_search or wl["L_search"]
+        self.Ld = args.L_d or wl["L_d"]
+        self.rerank = args.rerank or self.Ls
+        ws_anns = pecann.workspace_bytes(ds, k, self.Ls, args.kdep_cap, R, wl["L"], wl["alpha"],
+                                         args.num_starts, args.max_batch)
+        lib = pecann.load()
+        st = ds.struct
+        ws_exact = lib.pecann_knn_density_workspace_size(ctypes.byref(st), k, self.Ls, 1)
+        self.ws = torch.empty(max(ws_anns, ws_exact), dtype=torch.uint8, device=dev)
+        self.g_out = (torch.empty((n, R), dtype=torch.int32, device=dev),
+                      torch.empty(n, dtype=torch.int32, device=dev))
+        self.k_out = (torch.empty((n, k), dtype=torch.int32, device=dev),
+                      torch.empty((n, k), dtype=torch.float32, device=dev),
+                      torch.empty(n, dtype=torch.float32, device=dev),
+                      torch.empty(n, dtype=torch.int64, device=dev))
+        self.d_out = (torch.empty(n, dtype=torch.int32, device=dev),
+                      torch.empty(n, dtype=torch.float32, device=dev),
+                      torch.zeros(32, dtype=torch.int32, device=dev))
+        self.c_out = (torch.empty(n, dtype=torch.int32, device=dev),
+                      torch.empty(n, dtype=torch.uint8, device=dev))
+        self.phases = ["prepare", "build", "knn_density", "dependent", "cluster"]
+
+    def step(self, ev=None, bcnt=None, kcnt=None):
+        p, wl, a = self.pecann, self.wl, self.args
+        if ev:
+            ev[0].record()
+        self.ds.prepare(self.x)
+        if ev:
+            ev[1].record()
+        adj = deg = None
+        if self.mode == "anns":
+            adj, deg = p.build_graph(self.ds, wl["R"], wl["L"], wl["alpha"], num_starts=a.num_starts,
+                                     perm=self.perm, max_batch=a.max_batch, ws=self.ws,
+                                     out=self.g_out, counters=bcnt)
+        if ev:
+            ev[2].record()
+        idx, dist, rho, key = p.knn_density(self.ds, wl["k"], adj, deg, L_search=self.Ls,
+                                            rerank=self.rerank, ws=self.ws, out=self.k_out,
+                                            counters=kcnt)
+        if ev:
+            ev[3].record()
+        dep, delta, _ = p.dependent_search(self.ds, key, idx, dist, adj, deg, L_d=self.Ld,
+                                           L_search=self.Ls, threshold=a.threshold,
+                                           kdep_cap=a.kdep_cap, ws=self.ws, out=self.d_out)
+        if ev:
+            ev[4].record()
+        p.cluster(rho, dep, delta, n_c=wl["n_c"], ws=self.ws, out=self.c_out)
+        if ev:
+            ev[5].record()
+
+    def run(self, steps, warmup):
+        torch, p = self.torch, self.pecann
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
+        p.profile_enable(True)  # per-kernel HIP events on the launch stream
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            self.step(evs[i])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        p.profile_enable(False)
+        kprof = p.profile_report()
+        ph = {q: [] for q in self.phases}
+        for e in evs:
+            for j, q in enumerate(self.phases):
+                ph[q].append(e[j].elapsed_time(e[j + 1]))
+        return wall, {q: float(np.median(v)) for q, v in ph.items()}, kprof
+
+    def counters(self):
+        torch = self.torch
+        dev = self.x.device
+        bcnt = torch.zeros(8, dtype=torch.int64, device=dev)
+        kcnt = torch.zeros(4, dtype=torch.int64, device=dev)
+        self.step(bcnt=bcnt, kcnt=kcnt)
+        torch.cuda.synchronize()
+        return bcnt.cpu().numpy().astype(np.int64), kcnt.cpu().numpy().astype(np.int64)
+
+
+def measure(x, wl, search, mode, args, perm, steps, warmup, ref_labels=None, sample=None):
+    """Time `steps` DPC steps and evaluate the quality gates."""
+    pl = Pipeline(x, wl, search, mode, args, perm)
+    n = pl.ds.n
+    wall, ph, kprof = pl.run(steps, warmup)
+    rec = {"search_rows": search, "mode": mode, "ms_per_step": round(wall * 1e3 / steps, 3),
+           "value": round(n * steps / wall, 1),
+           "knn_queries_per_s": round(n / (ph["knn_density"] * 1e-3), 1),
+           "phases_ms": {q: round(v, 3) for q, v in ph.items()},
+           "kernels_ms": {f: {"launches_per_step": v[0] / steps, "ms_per_step": round(v[1] / steps, 3)}
+                          for f, v in sorted(kprof.items(), key=lambda t: -t[1][1])}}
+    q = {}
+    labels = pl.c_out[0].cpu().numpy()
+    if ref_labels is not None:
+        q["ari_vs_reference"] = ari(labels, ref_labels)
+    if sample is not None:
+        s = sample["sample"]
+        k = wl["k"]
+        q[f"recall_at_{k}"] = recall_from_sample(pl.k_out[0].cpu().numpy()[s],
+                                                 pl.k_out[1].cpu().numpy()[s], s,
+                                                 sample["knn_dist"], k)
+    if q:
+        rk = [v for key, v in q.items() if key.startswith("recall")]
+        q["gates_met"] = bool(q.get("ari_vs_reference", 1.0) >= 0.95 and all(v >= 0.95 for v in rk))
+    rec["quality"] = q
+    rec["dependent_stats"] = pl.d_out[2].cpu().numpy()[:8].tolist()
+    return rec, pl, kprof
+
+
+def roofline(pl, kprof, steps, search, n, d, k):
+    """Roofline of the dominant gather kernel family, from its own work counters."""
+    bc, kc = pl.counters()
+    row_bytes = {"f32": 4 * d, "u8": d, "bf16": 2 * d, "fp8": d}[search]
+    # algorithmic bytes per step: per expansion the degree word and the neighbour ids,
+    # per distance the candidate row, per search its own row (float32 for BF16/FP8
+    # queries) and its outputs, plus the float32 rows re-scored
+    q_bytes = 4 * d if search in ("bf16", "fp8") else row_bytes
+    nsb = 2 * n - 1
+    alg = {
+        "search_knn": (4 * (kc[0] + kc[1]) + row_bytes * kc[2] + n * q_bytes + 4 * d * kc[3]
+                       + n * (k * 8 + 4 + 8)),
+        "search_build": (4 * (bc[0] + bc[1]) + row_bytes * bc[2] + nsb * q_bytes + 8 * bc[0]
+                         + 4 * nsb),
+    }
+    fam_ms = {f: v[1] / steps for f, v in kprof.items()}
+    fam_l = {f: v[0] / steps for f, v in kprof.items()}
+    dom = max(fam_ms, key=fam_ms.get)
+    fam = dom if dom in alg else max(alg, key=lambda f: fam_ms.get(f, 0.0))
+    avg_ms = fam_ms[fam] / fam_l[fam]
+    per_launch = alg[fam] / fam_l[fam]
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    mode = {"search_build": "MODE_BUILD", "search_knn": "MODE_KNN"}[fam]
+    return {"bound": "hbm", "kernel": f"search_kernel<{search}, {mode}>", "family": fam,
+            "dominant_family": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": stored_traffic(f"{fam}@{search}"),
+            "alg_bytes_per_launch": int(per_launch), "avg_launch_ms": round(avg_ms, 4),
+            "launches_per_step": fam_l[fam],
+            "knn_launch": {"ms": round(fam_ms.get("search_knn", 0.0), 3),
+                           "achieved_GBps": round(alg["search_knn"] / (fam_ms["search_knn"] * 1e-3) / 1e9, 1)
+                           if fam_ms.get("search_knn") else None,
+                           "per_query": {"expansions": kc[0] / n, "ids_read": kc[1] / n,
+                                         "rows_gathered": kc[2] / n, "rows_rescored": kc[3] / n}},
+            "build_work": {"search_expansions": int(bc[0]), "search_rows": int(bc[2]),
+                           "forward_prune_rows": int(bc[4]), "reverse_prune_rows": int(bc[5]),
+                           "targets_pruned": int(bc[6]), "targets_appended": int(bc[7])}}
 
 
 def main():
@@ -103,65 +307,17 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2312_03940_amd import datagen, pecann
+    from paper_2312_03940_amd import datagen
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    cfg = datagen.CONFIGS[2]
-    R, L, alpha, k, n_c = cfg["R"], cfg["L"], cfg["alpha"], cfg["k"], cfg["n_c"]
-
-    X, _ = datagen.config2()
+    wl = WORKLOADS[args.config]
+    search = args.search or wl["search"]
+    gen = {2: datagen.config2, 3: datagen.config3, 4: datagen.config4}[args.config]
+    X, _ = gen()
     n, d = X.shape
-    perm_h = datagen.permutation(n, 20231205)
     x = torch.from_numpy(X).to(dev)
-    perm = torch.from_numpy(perm_h).to(dev)
-    ds = pecann.Dataset(x, "l2", args.search)
-
-    # every buffer of the step is allocated here, outside the timed region
-    wsb = pecann.workspace_bytes(ds, k, args.L_search, args.kdep_cap, R, L, alpha, args.num_starts,
-                                 args.max_batch)
-    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
-    g_out = (torch.empty((n, R), dtype=torch.int32, device=dev),
-             torch.empty(n, dtype=torch.int32, device=dev))
-    k_out = (torch.empty((n, k), dtype=torch.int32, device=dev),
-             torch.empty((n, k), dtype=torch.float32, device=dev),
-             torch.empty(n, dtype=torch.float32, device=dev),
-             torch.empty(n, dtype=torch.int64, device=dev))
-    d_out = (torch.empty(n, dtype=torch.int32, device=dev),
-             torch.empty(n, dtype=torch.float32, device=dev),
-             torch.zeros(32, dtype=torch.int32, device=dev))
-    c_out = (torch.empty(n, dtype=torch.int32, device=dev),
-             torch.empty(n, dtype=torch.uint8, device=dev))
-    phases = ["prepare", "build", "knn_density", "dependent", "cluster"]
-
-    def step(events=None, bcnt=None, kcnt=None):
-        ev = events
-        if ev:
-            ev[0].record()
-        ds.prepare(x)
-        if ev:
-            ev[1].record()
-        adj, deg = pecann.build_graph(ds, R, L, alpha, num_starts=args.num_starts, perm=perm,
-                                      max_batch=args.max_batch, ws=ws, out=g_out, counters=bcnt)
-        if ev:
-            ev[2].record()
-        idx, dist, rho, key = pecann.knn_density(ds, k, adj, deg, L_search=args.L_search, ws=ws,
-                                                 out=k_out, counters=kcnt)
-        if ev:
-            ev[3].record()
-        dep, delta, stats = pecann.dependent_search(ds, key, idx, dist, adj, deg, L_d=args.L_d,
-                                                    L_search=args.L_search,
-                                                    threshold=args.threshold,
-                                                    kdep_cap=args.kdep_cap, ws=ws, out=d_out)
-        if ev:
-            ev[4].record()
-        pecann.cluster(rho, dep, delta, n_c=n_c, ws=ws, out=c_out)
-        if ev:
-            ev[5].record()
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+    perm = torch.from_numpy(datagen.permutation(n, 20231205)).to(dev)
     if args.copy_probe_mb:
         src = torch.empty(args.copy_probe_mb << 18, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -170,116 +326,69 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
-    pecann.profile_enable(True)  # per-kernel HIP events on the launch stream
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(evs[i])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    pecann.profile_enable(False)
-    kprof = pecann.profile_report()
-
-    ph = {p: [] for p in phases}
-    for e in evs:
-        for j, p in enumerate(phases):
-            ph[p].append(e[j].elapsed_time(e[j + 1]))
-    ms_per_step = wall * 1e3 / args.steps
-    value = n * args.steps / wall
-    knn_ms = float(np.median(ph["knn_density"]))
-
-
-    # work counters from one extra (untimed) step
-    bcnt = torch.zeros(8, dtype=torch.int64, device=dev)
-    kcnt = torch.zeros(4, dtype=torch.int64, device=dev)
-    step(bcnt=bcnt, kcnt=kcnt)
-    torch.cuda.synchronize()
-    bc = bcnt.cpu().numpy().astype(np.int64)
-    kc = kcnt.cpu().numpy().astype(np.int64)
-
-    # quality gates
-    quality = {}
     ref = None
-    if os.path.exists(REF_PATH):
-        ref = np.load(REF_PATH)
-        labels = c_out[0].cpu().numpy()
-        quality["ari_vs_oracle"] = ari(labels, ref["labels"])
-        s = ref["sample"]
-        gi = k_out[0].cpu().numpy()[s]
-        gd = k_out[1].cpu().numpy()[s]
-        thr = ref["sample_knn_dist"][:, k - 1]
-        # a returned point counts when its distance (exact here: integer rows) is within the
-        # oracle's k-th distance; duplicates and the query itself never count
-        hits = 0
-        for t in range(len(s)):
-            seen = set()
-            for j, dj in zip(gi[t], gd[t]):
-                if j < 0 or j == s[t] or j in seen:
-                    continue
-                seen.add(int(j))
-                hits += float(dj) <= np.float32(thr[t])
-        quality["recall_at_10"] = hits / (k * len(s))
-        quality["gates_met"] = bool(quality["ari_vs_oracle"] >= 0.95 and quality["recall_at_10"] >= 0.95)
-    else:
-        quality["missing"] = "tests/golden/c2_reference.npz not found"
+    ref_labels = sample = None
+    ref_kind = None
+    if args.config == 2 and os.path.exists(os.path.join(GOLDEN, "c2_reference.npz")):
+        ref = np.load(os.path.join(GOLDEN, "c2_reference.npz"))
+        ref_labels = ref["labels"]
+        ref_kind = "oracle exact DPC (tests/golden/c2_reference.npz)"
+        sample = {"sample": ref["sample"], "knn_dist": ref["sample_knn_dist"]}
+    elif args.config in (3, 4):
+        sp = os.path.join(GOLDEN, f"c{args.config}_sample.npz")
+        if os.path.exists(sp):
+            z = np.load(sp)
+            sample = {"sample": z["sample"], "knn_dist": z["knn_dist"]}
+        # ARI reference: the GPU exact mode on float32 rows (bit-exact with the oracle in
+        # the GPU tests), computed once here, outside any timed region
+        rp = Pipeline(x, wl, "f32", "exact", args, perm)
+        rp.step()
+        torch.cuda.synchronize()
+        ref_labels = rp.c_out[0].cpu().numpy()
+        ref_kind = "GPU exact DPC on float32 rows"
+        del rp
+        torch.cuda.empty_cache()
 
-    row_bytes = {"f32": 4 * d, "u8": d}[args.search]
-    # algorithmic bytes per step of each gather kernel family, from its own counters:
-    # per expansion the degree word and the neighbour ids, per distance the candidate
-    # row, per search its own row and its outputs
-    nsearch_build = 2 * n - 1
-    alg = {
-        "search_knn": 4 * (kc[0] + kc[1]) + row_bytes * kc[2] + n * row_bytes + n * (k * 8 + 4 + 8),
-        "search_build": (4 * (bc[0] + bc[1]) + row_bytes * bc[2] + nsearch_build * row_bytes
-                         + 8 * bc[0] + 4 * nsearch_build),
-    }
-    fam_ms = {f: v[1] / args.steps for f, v in kprof.items()}
-    fam_launch = {f: v[0] / args.steps for f, v in kprof.items()}
-    dom = max(fam_ms, key=fam_ms.get)
-    rl_fam = dom if dom in alg else max(alg, key=lambda f: fam_ms.get(f, 0.0))
-    avg_launch_ms = fam_ms[rl_fam] / fam_launch[rl_fam]
-    bytes_per_launch = alg[rl_fam] / fam_launch[rl_fam]
-    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
-    knl = {"search_build": "MODE_BUILD", "search_knn": "MODE_KNN"}[rl_fam]
-    roofline = {"bound": "hbm", "kernel": f"search_kernel<{args.search}, G=16, {knl}>",
-                "family": rl_fam, "dominant_family": dom,
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": stored_traffic(f"{rl_fam}@{args.search}"),
-                "alg_bytes_per_launch": int(bytes_per_launch),
-                "avg_launch_ms": round(avg_launch_ms, 4), "launches_per_step": fam_launch[rl_fam],
-                "knn_launch": {"ms": round(fam_ms.get("search_knn", 0.0), 3),
-                               "achieved_GBps": round(alg["search_knn"] / (fam_ms["search_knn"] * 1e-3) / 1e9, 1)
-                               if "search_knn" in fam_ms else None,
-                               "per_query": {"expansions": kc[0] / n, "ids_read": kc[1] / n,
-                                             "rows_gathered": kc[2] / n}}}
-    kernels_ms = {f: {"launches_per_step": fam_launch[f], "ms_per_step": round(v, 3)}
-                  for f, v in sorted(fam_ms.items(), key=lambda t: -t[1])}
-
+    rec, pl, kprof = measure(x, wl, search, args.mode, args, perm, args.steps, args.warmup,
+                             ref_labels, sample)
+    if ref_kind:
+        rec["quality"]["reference"] = ref_kind
     out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "points/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "metric": METRIC, "value": rec["value"], "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": rec["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.search, "data": "synthetic",
-        "config": {"workload": "MNIST-shaped 70000x784 uint8 10-Gaussian mixture, L2",
-                   "n": n, "d": d, "search_rows": args.search, "R": R, "L_build": L,
-                   "alpha": alpha, "build_passes": 2, "num_starts": args.num_starts,
-                   "max_batch": args.max_batch or max(n // 50, 8192),
-                   "k": k, "L_search": args.L_search, "L_d": args.L_d,
-                   "threshold": args.threshold, "kdep_cap": args.kdep_cap, "n_c": n_c,
+        "dtype": search, "data": "synthetic",
+        "config": {"workload": wl["name"], "n": n, "d": d, "search_rows": search,
+                   "mode": args.mode, "R": wl["R"], "L_build": wl["L"], "alpha": wl["alpha"],
+                   "build_passes": 2, "num_starts": args.num_starts,
+                   "max_batch": args.max_batch or max(n // 50, 8192), "k": wl["k"],
+                   "L_search": pl.Ls, "rerank": pl.rerank, "L_d": pl.Ld,
+                   "threshold": args.threshold, "kdep_cap": args.kdep_cap, "n_c": wl["n_c"],
                    "parallelism": "single GPU"},
-        "knn_queries_per_s": round(n / (knn_ms * 1e-3), 1),
-        "phases_ms": {p: round(float(np.median(v)), 3) for p, v in ph.items()},
-        "quality": quality,
-        "build_work": {"search_expansions": int(bc[0]), "search_rows": int(bc[2]),
-                       "forward_prune_rows": int(bc[4]), "reverse_prune_rows": int(bc[5]),
-                       "targets_pruned": int(bc[6]), "targets_appended": int(bc[7])},
-        "dependent_stats": d_out[2].cpu().numpy()[:8].tolist(),
-        "kernels_ms": kernels_ms,
-        "roofline": roofline,
+        "knn_queries_per_s": rec["knn_queries_per_s"],
+        "phases_ms": rec["phases_ms"],
+        "quality": rec["quality"],
+        "dependent_stats": rec["dependent_stats"],
+        "kernels_ms": rec["kernels_ms"],
     }
-    if not args.no_cpu_baseline and ref is not None:
+    if args.mode == "anns":
+        out["roofline"] = roofline(pl, kprof, args.steps, search, n, d, wl["k"])
+    del pl
+    torch.cuda.empty_cache()
+    if not args.no_variants:
+        variants = {}
+        alt = {2: [("u8", "anns"), ("u8", "exact"), ("f32", "exact")],
+               3: [("f32", "anns")], 4: [("f32", "anns")]}[args.config]
+        for vs, vm in alt:
+            if (vs, vm) == (search, args.mode):
+                continue
+            r, p2, _ = measure(x, wl, vs, vm, args, perm, 3, 1, ref_labels, sample)
+            variants[f"{vs}_{vm}"] = {key: r[key] for key in ("value", "ms_per_step", "phases_ms",
+                                                              "quality", "knn_queries_per_s")}
+            del p2
+            torch.cuda.empty_cache()
+        out["variants"] = variants
+    if args.config == 2 and not args.no_cpu_baseline and ref is not None:
         out["cpu_baseline"] = cpu_baseline(X, ref, args.cpu_sample)
     print(json.dumps(out))
 

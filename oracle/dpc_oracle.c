@@ -548,7 +548,7 @@ int oracle_vamana_build(const opoints *P, int32_t R, int32_t L, double alpha,
         e0 = e1;
       }
       inserted += nb;
-      bsize *= 2;
+      if (bsize < cap) bsize *= 2; /* stop doubling at the cap */
     }
   }
   free(new_out); free(new_deg); free(edges); free(vis); free(tmp);

@@ -33,6 +33,19 @@ static pecann_status fail(pecann_status s, const char *fmt, ...) {
     if (e_ != hipSuccess) return fail(PECANN_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+// Same, naming the build pass and batch.
+#define HIP_TRY_BATCH(expr)                                                                     \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return fail(PECANN_EHIP, "%s: %s (pass %d, batch [%lld, +%lld))", #expr,                 \
+                  hipGetErrorString(e_), pass, (long long)inserted, (long long)nb);             \
+  } while (0)
+
+// A HIP error left pending by earlier, unrelated runtime calls of the process
+// is cleared on entry, so that it is not reported as this call's failure.
+static void clear_stale_error() { (void)hipGetLastError(); }
+
 extern "C" const char *pecann_status_string(pecann_status s) {
   switch (s) {
     case PECANN_OK: return "ok";
@@ -243,6 +256,7 @@ extern "C" size_t pecann_prepared_bytes(int64_t n, int32_t d, int32_t metric, in
 extern "C" pecann_status pecann_prepare_vectors(const void *x, int32_t x_dtype, int64_t x_stride,
                                                 int64_t n, int32_t d, int32_t metric, int32_t sdt,
                                                 void *prep, size_t prep_bytes, void *stream) {
+  clear_stale_error();
   Layout L;
   if (!make_layout(n, d, metric, sdt, &L))
     return fail(PECANN_EINVAL, "invalid (n=%lld, d=%d, metric=%d, search_dtype=%d)", (long long)n, d,
@@ -364,6 +378,7 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
                                             const int32_t *perm, uint64_t seed, int32_t *adj,
                                             int32_t *deg, uint64_t *counters, void *ws,
                                             size_t ws_bytes, void *stream) {
+  clear_stale_error();
   Layout L;
   pecann_status st = check_dataset(ds, &L);
   if (st != PECANN_OK) return st;
@@ -458,37 +473,37 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
       nb = std::min(nb, n - inserted);
       const int b0 = (int)inserted;
       const int64_t in_graph = pass == 0 ? inserted : n;
-      HIP_TRY(launch_fill_i32(w.ctr, 0, 5, s));
+      HIP_TRY_BATCH(launch_fill_i32(w.ctr, 0, 5, s));
       sp.items = order + b0;
       sp.nitems = (int32_t)nb;
       sp.nstarts = (int32_t)std::min<int64_t>(bp->num_starts, in_graph);
       {
         PROF(F_SEARCH_BUILD, s);
-        HIP_TRY(launch_search(dt, G, sp, persistent_grid(nb), s));
+        HIP_TRY_BATCH(launch_search(dt, G, sp, persistent_grid(nb), s));
       }
       pp.b0 = b0;
       pp.nb = (int32_t)nb;
       pp.head = head_pf;
       {
         PROF(F_PRUNE_FWD, s);
-        HIP_TRY(launch_prune_forward(dt, G, pp, persistent_grid(nb), s));
+        HIP_TRY_BATCH(launch_prune_forward(dt, G, pp, persistent_grid(nb), s));
       }
       {
         PROF(F_REV, s);
-        HIP_TRY(launch_rev_count(adj, deg, order, b0, (int32_t)nb, R, w.rcnt, ntargets, w.tlist,
+        HIP_TRY_BATCH(launch_rev_count(adj, deg, order, b0, (int32_t)nb, R, w.rcnt, ntargets, w.tlist,
                                  w.tidx, w.ticket, s));
-        HIP_TRY(launch_rev_alloc(w.tlist, ntargets, w.rcnt, w.toff, w.tcnt, cursor,
+        HIP_TRY_BATCH(launch_rev_alloc(w.tlist, ntargets, w.rcnt, w.toff, w.tcnt, cursor,
                                  (int32_t)(nb * R), s));
-        HIP_TRY(launch_rev_scatter(adj, deg, order, b0, (int32_t)nb, R, w.tidx, w.toff, w.ticket,
+        HIP_TRY_BATCH(launch_rev_scatter(adj, deg, order, b0, (int32_t)nb, R, w.tidx, w.toff, w.ticket,
                                    w.seg, s));
       }
       pp.head = head_pr;
       {
         PROF(F_PRUNE_REV, s);
-        HIP_TRY(launch_prune_reverse(dt, G, pp, persistent_grid(nb * R), s));
+        HIP_TRY_BATCH(launch_prune_reverse(dt, G, pp, persistent_grid(nb * R), s));
       }
       inserted += nb;
-      bsize *= 2;
+      if (bsize < cap) bsize *= 2;  // stop doubling at the cap (no overflow)
     }
   }
   return PECANN_OK;
@@ -529,6 +544,7 @@ extern "C" pecann_status pecann_knn_density(const pecann_dataset *ds, const int3
                                             float *knn_dist, float *rho, uint64_t *rank_key,
                                             uint64_t *counters, void *ws, size_t ws_bytes,
                                             void *stream) {
+  clear_stale_error();
   Layout L;
   pecann_status st = check_dataset(ds, &L);
   if (st != PECANN_OK) return st;
@@ -688,6 +704,7 @@ extern "C" pecann_status pecann_dependent_search(const pecann_dataset *ds, const
                                                  int32_t kdep_cap, int32_t *dep, float *delta,
                                                  int32_t *stats, void *ws, size_t ws_bytes,
                                                  void *stream) {
+  clear_stale_error();
   Layout L;
   pecann_status st = check_dataset(ds, &L);
   if (st != PECANN_OK) return st;
@@ -793,6 +810,7 @@ extern "C" pecann_status pecann_cluster(int64_t n, const float *rho, const int32
                                         const float *delta, int32_t center_mode, int32_t n_c,
                                         float delta_min, float rho_min, int32_t *labels,
                                         uint8_t *is_center, void *ws, size_t ws_bytes, void *stream) {
+  clear_stale_error();
   if (n < 1 || n >= (int64_t)1 << 31) return fail(PECANN_EINVAL, "n out of range");
   if (!rho || !dep || !delta || !labels || !is_center) return fail(PECANN_EINVAL, "pointer is NULL");
   if (center_mode != PECANN_CENTER_PRODUCT && center_mode != PECANN_CENTER_THRESHOLD)

@@ -234,6 +234,16 @@ def test_build_graph_bit_exact_u8_rows(dev, alpha):
     assert np.array_equal(_np(adj), adj_o)
 
 
+def test_build_many_batches_bit_exact(dev, grid_case):
+    # 3000 points in batches of at most 20: > 150 batches per pass
+    X, P, perm = grid_case["X"], grid_case["P"], grid_case["perm"]
+    adj_o, deg_o = oracle.vamana_build(P, 12, 24, 2.0, perm, num_starts=4, max_batch=20)
+    ds = pecann.Dataset(_t(X, dev), "l2", "f32")
+    adj, deg = pecann.build_graph(ds, 12, 24, 2.0, num_starts=4, visited_cap=512,
+                                  perm=_t(perm, dev), max_batch=20)
+    assert np.array_equal(_np(adj), adj_o) and np.array_equal(_np(deg), deg_o)
+
+
 def test_search_and_dependent_rounds_bit_exact(dev, grid_case):
     X, P, perm, n = grid_case["X"], grid_case["P"], grid_case["perm"], grid_case["n"]
     R, L, k = 16, 32, 10

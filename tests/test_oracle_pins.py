@@ -324,6 +324,16 @@ def test_vamana_graph_invariants_and_recall(oracle_lib):
     assert metrics.recall_at_k(P, q, got, ed, 10) >= 0.95
 
 
+def test_many_small_batches(oracle_lib):
+    # more than 64 batches: the doubling batch size must stop at the cap
+    X, _ = datagen.mixture(400, 4, 3, seed=5)
+    P = oracle.Points(X)
+    adj, deg = oracle.vamana_build(P, 8, 16, 1.2, datagen.permutation(400, 2), num_starts=2,
+                                   max_batch=3)
+    assert np.all(deg >= 1) and np.all(deg <= 8)
+    assert len(oracle.batch_schedule(400, 3)) > 64
+
+
 def test_batch_schedule():
     b = oracle.batch_schedule(70_000)
     sizes = [e - s for s, e in b]
