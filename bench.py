@@ -51,13 +51,14 @@ TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic.json")
 
 WORKLOADS = {
     2: dict(name="MNIST-shaped 70000x784 uint8 10-Gaussian mixture, L2", metric="l2",
-            R=64, L=128, alpha=1.2, k=10, n_c=10, L_search=64, L_d=64, search="f32"),
+            R=64, L=128, alpha=1.2, k=10, n_c=10, L_search=64, L_d=64, search="f32",
+            rho_min=0.0),
     3: dict(name="1000000x128 float32 mixture of 1000 Gaussians + 5% uniform noise, L2",
             metric="l2", R=64, L=128, alpha=1.2, k=16, n_c=1000, L_search=64, L_d=64,
-            search="bf16"),
+            search="bf16", rho_min=0.02),
     4: dict(name="1280000x1024 float32 unit vectors, 1000 clusters (mean cosine 0.7), cosine",
             metric="cosine", R=64, L=200, alpha=1.2, k=10, n_c=1000, L_search=64, L_d=64,
-            search="fp8"),
+            search="fp8", rho_min=0.0),
 }
 
 
@@ -80,6 +81,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=16000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--variant-steps", type=int, default=None,
+                    help="timed steps of each variant (default 3; 1 for the 1M-point workloads)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a reference "
                          "kernel of known traffic for hardware byte counters)")
@@ -196,9 +199,17 @@ class Pipeline:
                                            kdep_cap=a.kdep_cap, ws=self.ws, out=self.d_out)
         if ev:
             ev[4].record()
-        p.cluster(rho, dep, delta, n_c=wl["n_c"], ws=self.ws, out=self.c_out)
+        p.cluster(rho, dep, delta, n_c=wl["n_c"], rho_min=wl["rho_min"], ws=self.ws,
+                  out=self.c_out)
         if ev:
             ev[5].record()
+
+    def labels_at(self, rho_min):
+        """Labels of the last step's densities and dependents under another noise cutoff
+        (outside any timed region)."""
+        rho, dep, delta = self.k_out[2], self.d_out[0], self.d_out[1]
+        lab, _ = self.pecann.cluster(rho, dep, delta, n_c=self.wl["n_c"], rho_min=rho_min, ws=self.ws)
+        return lab.cpu().numpy()
 
     def run(self, steps, warmup):
         torch, p = self.torch, self.pecann
@@ -231,8 +242,15 @@ class Pipeline:
         return bcnt.cpu().numpy().astype(np.int64), kcnt.cpu().numpy().astype(np.int64)
 
 
-def measure(x, wl, search, mode, args, perm, steps, warmup, ref_labels=None, sample=None):
-    """Time `steps` DPC steps and evaluate the quality gates."""
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def measure(x, wl, search, mode, args, perm, steps, warmup, ref=None, sample=None):
+    """Time `steps` DPC steps and evaluate the quality gates.  `ref` holds the
+    reference labels under the workload's noise cutoff ("labels"), and optionally
+    under rho_min = 0 ("labels0") with the generator's component ids ("y")."""
+    log(f"measure {search}/{mode}: {warmup} warm-up + {steps} timed steps")
     pl = Pipeline(x, wl, search, mode, args, perm)
     n = pl.ds.n
     wall, ph, kprof = pl.run(steps, warmup)
@@ -244,8 +262,19 @@ def measure(x, wl, search, mode, args, perm, steps, warmup, ref_labels=None, sam
                           for f, v in sorted(kprof.items(), key=lambda t: -t[1][1])}}
     q = {}
     labels = pl.c_out[0].cpu().numpy()
-    if ref_labels is not None:
-        q["ari_vs_reference"] = ari(labels, ref_labels)
+    if ref is not None:
+        q["ari_vs_reference"] = ari(labels, ref["labels"])
+        if wl["rho_min"] > 0:
+            q["rho_min"] = wl["rho_min"]
+            q["noise_points"] = int((labels == np.arange(labels.size)).sum()
+                                    - int(pl.c_out[1].sum().item()))
+        if "labels0" in ref:
+            # diagnostics without the noise function: every background point then joins
+            # some cluster through near-tied distances
+            lab0 = pl.labels_at(0.0)
+            q["ari_rho_min_0"] = ari(lab0, ref["labels0"])
+            fg = ref["y"] >= 0
+            q["ari_rho_min_0_components_only"] = ari(lab0[fg], ref["labels0"][fg])
     if sample is not None:
         s = sample["sample"]
         k = wl["k"]
@@ -314,7 +343,8 @@ def main():
     wl = WORKLOADS[args.config]
     search = args.search or wl["search"]
     gen = {2: datagen.config2, 3: datagen.config3, 4: datagen.config4}[args.config]
-    X, _ = gen()
+    log(f"generating workload {args.config}")
+    X, Y = gen()
     n, d = X.shape
     x = torch.from_numpy(X).to(dev)
     perm = torch.from_numpy(datagen.permutation(n, 20231205)).to(dev)
@@ -327,11 +357,11 @@ def main():
         del src, dst
 
     ref = None
-    ref_labels = sample = None
+    ref_lab = sample = None
     ref_kind = None
     if args.config == 2 and os.path.exists(os.path.join(GOLDEN, "c2_reference.npz")):
         ref = np.load(os.path.join(GOLDEN, "c2_reference.npz"))
-        ref_labels = ref["labels"]
+        ref_lab = {"labels": ref["labels"]}
         ref_kind = "oracle exact DPC (tests/golden/c2_reference.npz)"
         sample = {"sample": ref["sample"], "knn_dist": ref["sample_knn_dist"]}
     elif args.config in (3, 4):
@@ -341,16 +371,22 @@ def main():
             sample = {"sample": z["sample"], "knn_dist": z["knn_dist"]}
         # ARI reference: the GPU exact mode on float32 rows (bit-exact with the oracle in
         # the GPU tests), computed once here, outside any timed region
+        log("reference: GPU exact DPC on float32 rows")
+        t0 = time.perf_counter()
         rp = Pipeline(x, wl, "f32", "exact", args, perm)
         rp.step()
         torch.cuda.synchronize()
-        ref_labels = rp.c_out[0].cpu().numpy()
+        ref_lab = {"labels": rp.c_out[0].cpu().numpy()}
+        if wl["rho_min"] > 0:
+            ref_lab["labels0"] = rp.labels_at(0.0)
+            ref_lab["y"] = Y
         ref_kind = "GPU exact DPC on float32 rows"
+        log(f"reference done in {time.perf_counter() - t0:.1f} s")
         del rp
         torch.cuda.empty_cache()
 
     rec, pl, kprof = measure(x, wl, search, args.mode, args, perm, args.steps, args.warmup,
-                             ref_labels, sample)
+                             ref_lab, sample)
     if ref_kind:
         rec["quality"]["reference"] = ref_kind
     out = {
@@ -364,6 +400,7 @@ def main():
                    "max_batch": args.max_batch or max(n // 50, 8192), "k": wl["k"],
                    "L_search": pl.Ls, "rerank": pl.rerank, "L_d": pl.Ld,
                    "threshold": args.threshold, "kdep_cap": args.kdep_cap, "n_c": wl["n_c"],
+                   "rho_min": wl["rho_min"],
                    "parallelism": "single GPU"},
         "knn_queries_per_s": rec["knn_queries_per_s"],
         "phases_ms": rec["phases_ms"],
@@ -372,6 +409,7 @@ def main():
         "kernels_ms": rec["kernels_ms"],
     }
     if args.mode == "anns":
+        log("work counters for the roofline")
         out["roofline"] = roofline(pl, kprof, args.steps, search, n, d, wl["k"])
     del pl
     torch.cuda.empty_cache()
@@ -382,13 +420,15 @@ def main():
         for vs, vm in alt:
             if (vs, vm) == (search, args.mode):
                 continue
-            r, p2, _ = measure(x, wl, vs, vm, args, perm, 3, 1, ref_labels, sample)
+            vsteps = args.variant_steps or (3 if args.config == 2 else 1)
+            r, p2, _ = measure(x, wl, vs, vm, args, perm, vsteps, 1, ref_lab, sample)
             variants[f"{vs}_{vm}"] = {key: r[key] for key in ("value", "ms_per_step", "phases_ms",
                                                               "quality", "knn_queries_per_s")}
             del p2
             torch.cuda.empty_cache()
         out["variants"] = variants
     if args.config == 2 and not args.no_cpu_baseline and ref is not None:
+        log(f"cpu baseline: oracle on {args.cpu_sample} points")
         out["cpu_baseline"] = cpu_baseline(X, ref, args.cpu_sample)
     print(json.dumps(out))
 

@@ -154,8 +154,9 @@ typedef struct {
 
 /* counters (device, may be NULL): 8 uint64 work tallies accumulated over the
  * call -- [0] search expansions, [1] neighbour ids read, [2] rows gathered by
- * the searches, [3] 0, [4] rows gathered by forward prunes, [5] rows gathered by
- * reverse prunes, [6] targets pruned, [7] targets appended.  The caller zeroes
+ * the searches, [3] 0, [4] row reads of the forward prunes' 16 x 16 distance
+ * tiles (32 per tile), [5] the same for the reverse prunes, [6] targets pruned,
+ * [7] targets appended.  The caller zeroes
  * them; they measure the work that algorithmic-traffic figures are built on. */
 size_t pecann_build_graph_workspace_size(const pecann_dataset *ds, const pecann_build_params *bp);
 pecann_status pecann_build_graph(const pecann_dataset *ds, const pecann_build_params *bp,

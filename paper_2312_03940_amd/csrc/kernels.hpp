@@ -126,21 +126,28 @@ struct PruneParams {
   int32_t vcap;
   // reverse
   const int32_t *tlist;
+  const int32_t *tord;        // work lists (indices into tlist): light from the front,
+                              // heavy from the back
+  const int32_t *nlight;      // length of the light list
+  const int32_t *nheavy;      // length of the heavy list
+  int32_t heavy;              // 0: prune the light list, 1: the heavy list
   const int32_t *ntargets;
   const int32_t *toff;
   const int32_t *tcnt;
   const int32_t *seg;
   int32_t *rcnt;
-  int32_t capin;              // max new in-edges merged per target
+  int32_t capin;              // max new in-edges merged per target (light list: the
+                              // list's bound; heavy list: truncation beyond it)
   int32_t *head;
   int32_t *overflow;          // counts truncations (candidates beyond capacity)
-  // optional work counters (nullptr: off): [0] rows gathered by forward prunes,
-  // [1] rows gathered by reverse prunes, [2] targets pruned, [3] targets appended
+  // optional work counters (nullptr: off): [0] row reads by forward prunes and
+  // [1] by reverse prunes (32 per 16 x 16 tile), [2] targets pruned, [3] targets
+  // appended
   unsigned long long *counters;
 };
 size_t prune_lds_bytes(int ccap, int R);
-hipError_t launch_prune_forward(int32_t dt, int G, const PruneParams &p, int grid, hipStream_t s);
-hipError_t launch_prune_reverse(int32_t dt, int G, const PruneParams &p, int grid, hipStream_t s);
+hipError_t launch_prune_forward(int32_t dt, const PruneParams &p, int grid, hipStream_t s);
+hipError_t launch_prune_reverse(int32_t dt, const PruneParams &p, int grid, hipStream_t s);
 
 // Plain (non-templated) kernels.
 hipError_t launch_prepare(const void *x, int32_t x_dtype, int64_t x_stride, int64_t n, int32_t d,
@@ -173,7 +180,8 @@ hipError_t launch_rev_count(const int32_t *adj, const int32_t *deg, const int32_
                             int32_t nb, int32_t R, int32_t *rcnt, int32_t *ntargets,
                             int32_t *tlist, int32_t *tidx, int32_t *ticket, hipStream_t s);
 hipError_t launch_rev_alloc(const int32_t *tlist, const int32_t *ntargets, const int32_t *rcnt,
-                            int32_t *toff, int32_t *tcnt, int32_t *cursor, int32_t maxt,
+                            int32_t *toff, int32_t *tcnt, int32_t *cursor, int32_t *tord,
+                            int32_t *front, int32_t *back, int32_t light, int32_t maxt,
                             hipStream_t s);
 hipError_t launch_rev_scatter(const int32_t *adj, const int32_t *deg, const int32_t *perm,
                               int32_t b0, int32_t nb, int32_t R, const int32_t *tidx,

@@ -203,13 +203,21 @@ __global__ void rev_count_kernel(const int32_t *adj, const int32_t *deg, const i
     tidx[q] = u;
   }
 }
+// Segment offsets of the targets, and two work lists in tord: targets with at
+// most `light` new sources from the front (tord[0, *front)), the others from the
+// back (tord[nt - *back, nt)).  The two lists are pruned by separate launches
+// whose LDS is sized for their candidate counts.
 __global__ void rev_alloc_kernel(const int32_t *tlist, const int32_t *ntargets, const int32_t *rcnt,
-                                 int32_t *toff, int32_t *tcnt, int32_t *cursor, int32_t maxt) {
+                                 int32_t *toff, int32_t *tcnt, int32_t *cursor, int32_t *tord,
+                                 int32_t *front, int32_t *back, int32_t light, int32_t maxt) {
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= maxt || u >= *ntargets) return;
+  const int nt = *ntargets;
+  if (u >= maxt || u >= nt) return;
   const int c = rcnt[tlist[u]];
   tcnt[u] = c;
   toff[u] = atomicAdd(cursor, c);
+  const int pos = c <= light ? atomicAdd(front, 1) : nt - 1 - atomicAdd(back, 1);
+  tord[pos] = u;
 }
 __global__ void rev_scatter_kernel(const int32_t *adj, const int32_t *deg, const int32_t *perm,
                                    int32_t b0, int32_t nb, int32_t R, const int32_t *tidx,
@@ -231,10 +239,11 @@ hipError_t launch_rev_count(const int32_t *adj, const int32_t *deg, const int32_
   return hipGetLastError();
 }
 hipError_t launch_rev_alloc(const int32_t *tlist, const int32_t *ntargets, const int32_t *rcnt,
-                            int32_t *toff, int32_t *tcnt, int32_t *cursor, int32_t maxt,
+                            int32_t *toff, int32_t *tcnt, int32_t *cursor, int32_t *tord,
+                            int32_t *front, int32_t *back, int32_t light, int32_t maxt,
                             hipStream_t s) {
   hipLaunchKernelGGL(rev_alloc_kernel, dim3((unsigned)((maxt + 255) / 256)), dim3(256), 0, s,
-                     tlist, ntargets, rcnt, toff, tcnt, cursor, maxt);
+                     tlist, ntargets, rcnt, toff, tcnt, cursor, tord, front, back, light, maxt);
   return hipGetLastError();
 }
 hipError_t launch_rev_scatter(const int32_t *adj, const int32_t *deg, const int32_t *perm,

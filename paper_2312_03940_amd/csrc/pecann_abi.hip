@@ -309,13 +309,18 @@ static int hash_bits_for(int L) {
 static constexpr int kCapIn = 1024;  // new in-edges merged per target per batch
 
 struct BuildWs {
-  int32_t *perm, *ctr, *vis_count, *rcnt, *tidx, *tlist, *toff, *tcnt, *ticket, *seg;
+  int32_t *perm, *ctr, *vis_count, *rcnt, *tidx, *tlist, *tord, *toff, *tcnt, *ticket, *seg;
   uint64_t *vis;
 };
 
 // Batch cap: the paper's 0.02 n, but never below 8192 concurrent searches (a
 // wavefront each), which is what it takes to occupy 256 CUs.
 static constexpr int64_t kMinGpuBatch = 8192;
+// Reverse-edge targets with at most this many new sources in a batch (nearly
+// all of them) are pruned by a launch whose LDS fits R + kLightIn candidates;
+// the rest by a second launch sized for R + kCapIn.
+static constexpr int32_t kLightIn = 64;
+static constexpr int kHeavyGridPerCu = 4;
 static int64_t batch_cap(int64_t n, int32_t max_batch) {
   int64_t c = max_batch > 0 ? (int64_t)max_batch : std::max<int64_t>(n / 50, kMinGpuBatch);
   if (c > n) c = n;
@@ -331,6 +336,7 @@ static void carve_build(Carver &c, int64_t n, int R, int64_t cap, int vcap, Buil
   w->tidx = c.take<int32_t>((size_t)n);
   const size_t ce = (size_t)cap * R;
   w->tlist = c.take<int32_t>(ce);
+  w->tord = c.take<int32_t>(ce);
   w->toff = c.take<int32_t>(ce);
   w->tcnt = c.take<int32_t>(ce);
   w->ticket = c.take<int32_t>(ce);
@@ -420,7 +426,8 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
 
   int32_t *head_search = w.ctr + 0, *head_pf = w.ctr + 1, *head_pr = w.ctr + 2;
   int32_t *ntargets = w.ctr + 3, *cursor = w.ctr + 4;
-  int32_t *overflow = w.ctr + 5;
+  int32_t *nlight = w.ctr + 5, *nheavy = w.ctr + 6, *head_ph = w.ctr + 7;
+  int32_t *overflow = w.ctr + 8;
   HIP_TRY(launch_fill_i32(overflow, 0, 1, s));
 
   SearchParams sp = {};
@@ -452,6 +459,9 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
   pp.vis_count = w.vis_count;
   pp.vcap = vcap;
   pp.tlist = w.tlist;
+  pp.tord = w.tord;
+  pp.nlight = nlight;
+  pp.nheavy = nheavy;
   pp.ntargets = ntargets;
   pp.toff = w.toff;
   pp.tcnt = w.tcnt;
@@ -473,7 +483,7 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
       nb = std::min(nb, n - inserted);
       const int b0 = (int)inserted;
       const int64_t in_graph = pass == 0 ? inserted : n;
-      HIP_TRY_BATCH(launch_fill_i32(w.ctr, 0, 5, s));
+      HIP_TRY_BATCH(launch_fill_i32(w.ctr, 0, 8, s));
       sp.items = order + b0;
       sp.nitems = (int32_t)nb;
       sp.nstarts = (int32_t)std::min<int64_t>(bp->num_starts, in_graph);
@@ -486,21 +496,28 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
       pp.head = head_pf;
       {
         PROF(F_PRUNE_FWD, s);
-        HIP_TRY_BATCH(launch_prune_forward(dt, G, pp, persistent_grid(nb), s));
+        HIP_TRY_BATCH(launch_prune_forward(dt, pp, persistent_grid(nb), s));
       }
       {
         PROF(F_REV, s);
         HIP_TRY_BATCH(launch_rev_count(adj, deg, order, b0, (int32_t)nb, R, w.rcnt, ntargets, w.tlist,
                                  w.tidx, w.ticket, s));
-        HIP_TRY_BATCH(launch_rev_alloc(w.tlist, ntargets, w.rcnt, w.toff, w.tcnt, cursor,
-                                 (int32_t)(nb * R), s));
+        HIP_TRY_BATCH(launch_rev_alloc(w.tlist, ntargets, w.rcnt, w.toff, w.tcnt, cursor, w.tord,
+                                       nlight, nheavy, kLightIn, (int32_t)(nb * R), s));
         HIP_TRY_BATCH(launch_rev_scatter(adj, deg, order, b0, (int32_t)nb, R, w.tidx, w.toff, w.ticket,
                                    w.seg, s));
       }
-      pp.head = head_pr;
       {
         PROF(F_PRUNE_REV, s);
-        HIP_TRY_BATCH(launch_prune_reverse(dt, G, pp, persistent_grid(nb * R), s));
+        pp.heavy = 0;
+        pp.head = head_pr;
+        pp.capin = kLightIn;
+        HIP_TRY_BATCH(launch_prune_reverse(dt, pp, persistent_grid(nb * R), s));
+        pp.heavy = 1;
+        pp.head = head_ph;
+        pp.capin = kCapIn;
+        const int heavy_grid = (int)std::min<int64_t>(nb * R, (int64_t)cu_count() * kHeavyGridPerCu);
+        HIP_TRY_BATCH(launch_prune_reverse(dt, pp, heavy_grid, s));
       }
       inserted += nb;
       if (bsize < cap) bsize *= 2;  // stop doubling at the cap (no overflow)

@@ -4,9 +4,12 @@
 //   repeatedly move the closest surviving candidate c* to the output (stop at
 //   R) and drop every surviving c with alpha * D(c*, c) <= D(p, c)
 //   (alpha^2 * D^2 <= D^2 for L2 measures, which are squared distances).
-// Candidate-pair distances are dense 16 x 16 dot-product tiles on the matrix
-// cores (f32, i8, bf16 or fp8 MFMA by row format), turned into distances with
-// the rows' stored norms; distances to p are direct differences.
+// All distances -- to p and between candidates -- come from dense 16 x 16
+// dot-product tiles on the matrix cores (f32, i8, bf16 or fp8 MFMA by row
+// format), turned into distances with the rows' stored norms.  After each
+// block of 16 the surviving candidates are compacted, so every later tile is
+// dense in live candidates; column tiles go four at a time to keep several row
+// loads in flight per lane.
 // prune_forward: Nout(p) = RobustPrune(p, V_p u Nout(p)) for each point of a batch.
 // prune_reverse: for each target q of the batch's reverse edges, append the
 //   new sources not yet present (ascending index) if they fit in R, else
@@ -59,57 +62,77 @@ __device__ __forceinline__ void rank_sort_dups(const uint64_t *src, uint64_t *ds
   wave_lds_sync();
 }
 
-// 16 x 16 tile of dot products between search rows on the matrix cores.  Lane
-// l contributes row (l % 16) of the A tile (arow) and of the B tile (brow);
-// at step s it loads 16-byte chunk (l / 16) + 4 s of each.  The result is the
-// MFMA accumulator layout: register r of lane l holds A-row 4 (l / 16) + r
-// against B-row l % 16.  U8 rows are shifted to signed (x - 128) so that the
-// integer dot is exact.  Missing rows (-1) contribute zeros.
+// NT 16 x 16 tiles of dot products between search rows on the matrix cores,
+// sharing their A rows.  Lane l contributes row (l % 16) of the A tile (arow)
+// and of each B tile (brow[t]); at step s it loads 16-byte chunk (l / 16) + 4 s
+// of each.  The result is the MFMA accumulator layout: register r of lane l
+// holds A-row 4 (l / 16) + r against B-row l % 16.  U8 rows are shifted to
+// signed (x - 128) so that the integer dot is exact (its bits are returned in
+// the float lanes).  Missing rows (-1) contribute zeros.
+__device__ __forceinline__ uint4 load_chunk(const uint8_t *base, int32_t row, int64_t stride, int q,
+                                            bool in, bool u8) {
+  uint4 v = make_uint4(0, 0, 0, 0);
+  if (in && row >= 0) {
+    v = *(const uint4 *)(base + (int64_t)row * stride + 16 * q);
+    if (u8) { v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u; }
+  }
+  return v;
+}
+
 template <int DT>
-__device__ __forceinline__ v4f dot_tile(const Rows &r, int32_t arow, int32_t brow) {
+__device__ __forceinline__ void mfma_chunk(uint4 a, uint4 b, v4f &accf, v4i &acci) {
+  if (DT == PECANN_F32) {
+    accf = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), accf, 0, 0, 0);
+    accf = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), accf, 0, 0, 0);
+    accf = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), accf, 0, 0, 0);
+    accf = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), accf, 0, 0, 0);
+  } else if (DT == PECANN_U8) {
+    const v4i ai = {(int)a.x, (int)a.y, (int)a.z, (int)a.w};
+    const v4i bi = {(int)b.x, (int)b.y, (int)b.z, (int)b.w};
+    acci = __builtin_amdgcn_mfma_i32_16x16x64_i8(ai, bi, acci, 0, 0, 0);
+  } else if (DT == PECANN_BF16) {
+    const v8bf ab = __builtin_bit_cast(v8bf, a);
+    const v8bf bb = __builtin_bit_cast(v8bf, b);
+    accf = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bb, accf, 0, 0, 0);
+  } else {  // FP8 e4m3: two 8-byte halves
+    const long a0 = (long)(((uint64_t)a.y << 32) | a.x), a1 = (long)(((uint64_t)a.w << 32) | a.z);
+    const long b0 = (long)(((uint64_t)b.y << 32) | b.x), b1 = (long)(((uint64_t)b.w << 32) | b.z);
+    accf = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b0, accf, 0, 0, 0);
+    accf = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, accf, 0, 0, 0);
+  }
+}
+
+template <int DT, int NT>
+__device__ __forceinline__ void dot_tiles(const Rows &r, int32_t arow, const int32_t (&brow)[NT],
+                                          v4f (&out)[NT]) {
   const int g = lane_id() >> 4;
-  const uint8_t *pa = r.xs + (int64_t)(arow < 0 ? 0 : arow) * r.xs_stride;
-  const uint8_t *pb = r.xs + (int64_t)(brow < 0 ? 0 : brow) * r.xs_stride;
   const int steps = (r.nch + 3) >> 2;
-  v4f accf = {0.f, 0.f, 0.f, 0.f};
-  v4i acci = {0, 0, 0, 0};
+  constexpr bool u8 = DT == PECANN_U8;
+  v4f accf[NT];
+  v4i acci[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    accf[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    acci[t] = v4i{0, 0, 0, 0};
+  }
   for (int st = 0; st < steps; ++st) {
     const int q = g + 4 * st;
-    uint4 a = make_uint4(0, 0, 0, 0), b = make_uint4(0, 0, 0, 0);
-    if (q < r.nch) {
-      if (arow >= 0) a = *(const uint4 *)(pa + 16 * q);
-      if (brow >= 0) b = *(const uint4 *)(pb + 16 * q);
-      if (DT == PECANN_U8) {
-        if (arow >= 0) { a.x ^= 0x80808080u; a.y ^= 0x80808080u; a.z ^= 0x80808080u; a.w ^= 0x80808080u; }
-        if (brow >= 0) { b.x ^= 0x80808080u; b.y ^= 0x80808080u; b.z ^= 0x80808080u; b.w ^= 0x80808080u; }
-      }
-    }
-    if (DT == PECANN_F32) {
-      accf = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), accf, 0, 0, 0);
-      accf = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), accf, 0, 0, 0);
-      accf = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), accf, 0, 0, 0);
-      accf = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), accf, 0, 0, 0);
-    } else if (DT == PECANN_U8) {
-      const v4i ai = {(int)a.x, (int)a.y, (int)a.z, (int)a.w};
-      const v4i bi = {(int)b.x, (int)b.y, (int)b.z, (int)b.w};
-      acci = __builtin_amdgcn_mfma_i32_16x16x64_i8(ai, bi, acci, 0, 0, 0);
-    } else if (DT == PECANN_BF16) {
-      const v8bf ab = __builtin_bit_cast(v8bf, a);
-      const v8bf bb = __builtin_bit_cast(v8bf, b);
-      accf = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bb, accf, 0, 0, 0);
-    } else {  // FP8 e4m3: two 8-byte halves
-      const long a0 = (long)(((uint64_t)a.y << 32) | a.x), a1 = (long)(((uint64_t)a.w << 32) | a.z);
-      const long b0 = (long)(((uint64_t)b.y << 32) | b.x), b1 = (long)(((uint64_t)b.w << 32) | b.z);
-      accf = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b0, accf, 0, 0, 0);
-      accf = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, accf, 0, 0, 0);
-    }
+    const bool in = q < r.nch;
+    const uint4 a = load_chunk(r.xs, arow, r.xs_stride, q, in, u8);
+    uint4 b[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) b[t] = load_chunk(r.xs, brow[t], r.xs_stride, q, in, u8);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) mfma_chunk<DT>(a, b[t], accf[t], acci[t]);
   }
-  if (DT == PECANN_U8) {
-    // keep the exact integer dot in the float lanes' bits
-    return v4f{__int_as_float(acci[0]), __int_as_float(acci[1]), __int_as_float(acci[2]),
-               __int_as_float(acci[3])};
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (DT == PECANN_U8)
+      out[t] = v4f{__int_as_float(acci[t][0]), __int_as_float(acci[t][1]), __int_as_float(acci[t][2]),
+                   __int_as_float(acci[t][3])};
+    else
+      out[t] = accf[t];
   }
-  return accf;
 }
 
 // Measure (squared L2, or cosine distance) from a dot product and the two rows'
@@ -126,65 +149,116 @@ __device__ __forceinline__ float pair_measure(float dotv, uint32_t na, uint32_t 
   return fmaxf(0.f, 1.0f - dt);
 }
 
-// RobustPrune of point pt over s.ids[0..nc); writes Nout(pt) into adj/deg.
-// Candidates are sorted by (D(pt, c), c) from direct-difference distances.  The
-// greedy pass then walks them in blocks of 16: one matrix-core tile gives the
-// block's own pairwise distances, which settle the block's selections in
-// order; the block's selected points then drop later candidates tile by tile,
-// each lane testing the 4 rows of its accumulator against its column.
-// Returns the number of 16 x 16 tiles formed.
-template <int DT, int G>
-__device__ int robust_prune_tiles(const PruneParams &p, Engine<DT, G> &eng, PruneLds &s, int32_t pt,
-                                  int nc) {
-  constexpr int NPL = Engine<DT, G>::NPL;
+// Compacts the live entries of the sorted list [from, mv) toward `from`, keeping
+// their order; returns the new end.  Entries move only to lower positions and
+// every chunk is read before any lane writes, so the pass works in place.
+__device__ __forceinline__ int compact_live(PruneLds &s, int from, int mv) {
   const int l = lane_id();
-  const int grp = l / G;
-  const bool leader = (l % G) == 0;
+  int out = from;
+  for (int j0 = from; j0 < mv; j0 += kWave) {
+    const int j = j0 + l;
+    const bool live = j < mv && s.alive[j];
+    uint64_t key = 0;
+    uint32_t cn = 0;
+    float cs = 0.f;
+    if (live) { key = s.k1[j]; cn = s.cn[j]; cs = s.cs[j]; }
+    const uint64_t bm = ballot(live);
+    wave_lds_sync();
+    if (live) {
+      const int o = out + lanes_below(bm);
+      s.k1[o] = key;
+      s.cn[o] = cn;
+      s.cs[o] = cs;
+      s.alive[o] = 1;
+    }
+    out += __popcll(bm);
+    wave_lds_sync();
+  }
+  return out;
+}
+
+// RobustPrune of point pt over s.ids[0..nc); writes Nout(pt) into adj/deg.
+// Candidates are sorted by (D(pt, c), c), and empty entries and repeats are
+// dropped.  D(pt, c) comes from tiles whose A rows all hold pt, 64 candidates
+// per round; lanes 0-15 read their column's value in accumulator register 0.  The greedy pass then walks the live
+// list in blocks of 16: one matrix-core tile gives the block's own pairwise
+// distances, which settle the block's selections in order; the block's selected
+// points then drop later candidates tile by tile (each lane testing the 4 rows
+// of its accumulator against its column), and the survivors are compacted.
+// Returns the number of 16 x 16 tiles formed.
+template <int DT>
+__device__ int robust_prune_tiles(const PruneParams &p, PruneLds &s, int32_t pt, int nc) {
+  constexpr int NT = 4;  // tiles in flight
+  const int l = lane_id();
+  const int col = l & 15, g = l >> 4;
   const float a2 = p.rows.metric == PECANN_L2 ? p.alpha * p.alpha : p.alpha;
 
-  eng.load_query(p.rows, pt);
-  for (int base = 0; base < nc; base += NPL) {
-    const int ci = base + grp;
-    int32_t id = ci < nc ? s.ids[ci] : -1;
-    if (id == pt) id = -1;
-    const float m = eng.measure(p.rows, id);
-    if (leader && ci < nc) s.k0[ci] = id >= 0 ? make_key(m, id) : kNoKey;
+  {
+    const uint32_t npt = p.rows.sqn[pt];
+    const float spt = (DT == PECANN_FP8E4M3) ? p.rows.scale[pt] : 1.0f;
+    for (int base = 0; base < nc; base += 16 * NT) {
+      int32_t rj[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int j = base + 16 * t + col;
+        const int32_t id = j < nc ? s.ids[j] : -1;
+        rj[t] = id == pt ? -1 : id;
+      }
+      v4f tt[NT];
+      dot_tiles<DT, NT>(p.rows, pt, rj, tt);
+      if (g == 0) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int j = base + 16 * t + col;
+          if (j < nc) {
+            uint64_t key = kNoKey;
+            if (rj[t] >= 0) {
+              const float sc = (DT == PECANN_FP8E4M3) ? p.rows.scale[rj[t]] : 1.0f;
+              key = make_key(pair_measure<DT>(tt[t][0], npt, p.rows.sqn[rj[t]], spt, sc,
+                                              p.rows.metric), rj[t]);
+            }
+            s.k0[j] = key;
+          }
+        }
+      }
+    }
   }
   wave_lds_sync();
   rank_sort_dups(s.k0, s.k1, nc);
-  int mv = 0;  // valid (non-empty) sorted entries
   for (int j0 = 0; j0 < nc; j0 += kWave) {
     const int j = j0 + l;
-    const uint64_t key = j < nc ? s.k1[j] : kNoKey;
-    const bool valid = key != kNoKey;
     if (j < nc) {
-      s.alive[j] = valid && (j == 0 || s.k1[j - 1] != key);
-      if (valid) {
+      const uint64_t key = s.k1[j];
+      const bool live = key != kNoKey && (j == 0 || s.k1[j - 1] != key);
+      s.alive[j] = live;
+      if (live) {
         const int32_t id = key_id(key);
         s.cn[j] = p.rows.sqn[id];
         s.cs[j] = (DT == PECANN_FP8E4M3) ? p.rows.scale[id] : 1.0f;
       }
     }
-    mv += __popcll(ballot(valid));
   }
   wave_lds_sync();
+  int mv = compact_live(s, 0, nc);
 
-  const int col = l & 15, g = l >> 4;
-  int nsel = 0, tiles = 0;
+  int nsel = 0, tiles = (nc + 15) / 16;
   for (int b = 0; b < mv && nsel < p.R; b += 16) {
-    if (ballot(col + b < mv && l < 16 && s.alive[b + col]) == 0) continue;
-    // (a) the block's own 16 x 16 tile
+    // (a) the block's own 16 x 16 tile (every entry of the block is live)
     const int32_t rb = b + col < mv ? key_id(s.k1[b + col]) : -1;
-    v4f t = dot_tile<DT>(p.rows, rb, rb);
-    ++tiles;
+    {
+      const int32_t br[1] = {rb};
+      v4f t[1];
+      dot_tiles<DT, 1>(p.rows, rb, br, t);
+      ++tiles;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = 4 * g + r;
-      float m = 0.f;
-      if (b + i < mv && b + col < mv)
-        m = pair_measure<DT>(t[r], s.cn[b + i], s.cn[b + col], s.cs[b + i], s.cs[b + col],
-                             p.rows.metric);
-      s.dg[i * 16 + col] = m;
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * g + r;
+        float m = 0.f;
+        if (b + i < mv && b + col < mv)
+          m = pair_measure<DT>(t[0][r], s.cn[b + i], s.cn[b + col], s.cs[b + i], s.cs[b + col],
+                               p.rows.metric);
+        s.dg[i * 16 + col] = m;
+      }
     }
     wave_lds_sync();
     // (b) selections of this block, in order
@@ -202,31 +276,41 @@ __device__ int robust_prune_tiles(const PruneParams &p, Engine<DT, G> &eng, Prun
     }
     wave_lds_sync();
     if (nsel == p.R) break;
-    // (c) the block's selected points drop later candidates
-    const int32_t ra = rb;
-    for (int j0 = b + 16; j0 < mv; j0 += 16) {
-      if (ballot(l < 16 && j0 + l < mv && s.alive[j0 + l]) == 0) continue;
-      const int32_t rj = j0 + col < mv ? key_id(s.k1[j0 + col]) : -1;
-      v4f tt = dot_tile<DT>(p.rows, ra, rj);
-      ++tiles;
-      bool kill = false;
-      if (j0 + col < mv) {
-        const float dpc = key_measure(s.k1[j0 + col]);
+    // (c) the block's selected points drop later candidates, NT tiles at a time
+    for (int j0 = b + 16; j0 < mv; j0 += 16 * NT) {
+      int32_t rj[NT];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = 4 * g + r;
-          if ((selmask >> i) & 1u) {
-            const float m = pair_measure<DT>(tt[r], s.cn[b + i], s.cn[j0 + col], s.cs[b + i],
-                                             s.cs[j0 + col], p.rows.metric);
-            kill |= a2 * m <= dpc;
+      for (int t = 0; t < NT; ++t) {
+        const int j = j0 + 16 * t + col;
+        rj[t] = j < mv ? key_id(s.k1[j]) : -1;
+      }
+      v4f tt[NT];
+      dot_tiles<DT, NT>(p.rows, rb, rj, tt);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int j = j0 + 16 * t + col;
+        bool kill = false;
+        if (j < mv) {
+          const float dpc = key_measure(s.k1[j]);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 4 * g + r;
+            if ((selmask >> i) & 1u) {
+              const float m = pair_measure<DT>(tt[t][r], s.cn[b + i], s.cn[j], s.cs[b + i], s.cs[j],
+                                               p.rows.metric);
+              kill |= a2 * m <= dpc;
+            }
           }
         }
+        const uint64_t km = ballot(kill);
+        const uint32_t k16 = (uint32_t)((km | (km >> 16) | (km >> 32) | (km >> 48)) & 0xffffu);
+        if (l < 16 && ((k16 >> l) & 1u)) s.alive[j0 + 16 * t + l] = 0;
+        tiles += j0 + 16 * t < mv;
       }
-      const uint64_t km = ballot(kill);
-      const uint32_t k16 = (uint32_t)((km | (km >> 16) | (km >> 32) | (km >> 48)) & 0xffffu);
-      if (l < 16 && ((k16 >> l) & 1u)) s.alive[j0 + l] = 0;
       wave_lds_sync();
     }
+    // (d) survivors after this block move up behind it
+    mv = compact_live(s, b + 16, mv);
   }
   int32_t *row = p.adj + (int64_t)pt * p.R;
   for (int e = l; e < p.R; e += kWave) row[e] = e < nsel ? s.sel[e] : -1;
@@ -236,12 +320,11 @@ __device__ int robust_prune_tiles(const PruneParams &p, Engine<DT, G> &eng, Prun
 
 }  // namespace
 
-template <int DT, int G>
+template <int DT>
 __global__ __launch_bounds__(64) void prune_forward_kernel(PruneParams p) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int ccap = p.vcap + p.R;
   PruneLds s = carve_prune(smem, ccap, p.R);
-  Engine<DT, G> eng;
   const int l = lane_id();
   for (;;) {
     const int t = next_item(p.head);
@@ -255,23 +338,24 @@ __global__ __launch_bounds__(64) void prune_forward_kernel(PruneParams p) {
     const int32_t *row = p.adj + (int64_t)pt * p.R;
     for (int j = l; j < dp; j += kWave) s.ids[nv + j] = row[j];
     wave_lds_sync();
-    const int rows = nv + dp + 32 * robust_prune_tiles<DT, G>(p, eng, s, pt, nv + dp);
+    const int rows = 32 * robust_prune_tiles<DT>(p, s, pt, nv + dp);
     if (p.counters && l == 0) atomicAdd(p.counters + 0, (unsigned long long)rows);
     wave_lds_sync();
   }
 }
 
-template <int DT, int G>
+template <int DT>
 __global__ __launch_bounds__(64) void prune_reverse_kernel(PruneParams p) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int ccap = p.R + p.capin;
   PruneLds s = carve_prune(smem, ccap, p.R);
-  Engine<DT, G> eng;
   const int l = lane_id();
   const int nt = *p.ntargets;
+  const int items = p.heavy ? *p.nheavy : *p.nlight;
   for (;;) {
-    const int u = next_item(p.head);
-    if (u >= nt) break;
+    const int it = next_item(p.head);
+    if (it >= items) break;
+    const int u = p.heavy ? p.tord[nt - 1 - it] : p.tord[it];
     const int32_t q = p.tlist[u];
     int cnt = p.tcnt[u];
     if (cnt > p.capin) {
@@ -282,14 +366,18 @@ __global__ __launch_bounds__(64) void prune_reverse_kernel(PruneParams p) {
     const int dq = min(p.deg[q], p.R);
     int32_t *row = p.adj + (int64_t)q * p.R;
     // current out-neighbours, then the new sources in ascending index order,
-    // leaving out sources already among the out-neighbours
+    // leaving out sources already among the out-neighbours (the sources of one
+    // batch are distinct; they are staged in LDS and ranked there)
+    int32_t *stage = (int32_t *)s.k1;
     for (int j = l; j < dq; j += kWave) s.ids[j] = row[j];
+    for (int j = l; j < cnt; j += kWave) stage[j] = src[j];
+    wave_lds_sync();
     for (int j = l; j < cnt; j += kWave) {
-      const int32_t v = src[j];
+      const int32_t v = stage[j];
       int r = 0;
-      for (int t = 0; t < cnt; ++t) r += src[t] < v;
+      for (int t = 0; t < cnt; ++t) r += stage[t] < v;
       bool present = false;
-      for (int t = 0; t < dq; ++t) present |= (row[t] == v);
+      for (int t = 0; t < dq; ++t) present |= (s.ids[t] == v);
       ((int32_t *)s.k0)[r] = present ? -1 : v;
     }
     wave_lds_sync();
@@ -307,7 +395,7 @@ __global__ __launch_bounds__(64) void prune_reverse_kernel(PruneParams p) {
       if (l == 0) p.deg[q] = dq + nnew;
       if (p.counters && l == 0) atomicAdd(p.counters + 3, 1ull);
     } else {
-      const int rows = dq + nnew + 32 * robust_prune_tiles<DT, G>(p, eng, s, q, dq + nnew);
+      const int rows = 32 * robust_prune_tiles<DT>(p, s, q, dq + nnew);
       if (p.counters && l == 0) {
         atomicAdd(p.counters + 1, (unsigned long long)rows);
         atomicAdd(p.counters + 2, 1ull);
@@ -322,44 +410,34 @@ size_t prune_lds_bytes(int ccap, int R) {
   return (size_t)ccap * (8 + 8 + 4 + 4 + 4 + 1) + 4 * 256 + 4 * (size_t)((R + 3) & ~3) + 16;
 }
 
-template <int DT, int G>
+template <int DT>
 static hipError_t launch_pf_t(const PruneParams &p, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((prune_forward_kernel<DT, G>), dim3(grid), dim3(64),
+  hipLaunchKernelGGL((prune_forward_kernel<DT>), dim3(grid), dim3(64),
                      prune_lds_bytes(p.vcap + p.R, p.R), st, p);
   return hipGetLastError();
 }
-template <int DT, int G>
+template <int DT>
 static hipError_t launch_pr_t(const PruneParams &p, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((prune_reverse_kernel<DT, G>), dim3(grid), dim3(64),
+  hipLaunchKernelGGL((prune_reverse_kernel<DT>), dim3(grid), dim3(64),
                      prune_lds_bytes(p.R + p.capin, p.R), st, p);
   return hipGetLastError();
 }
 
-#define PECANN_DISPATCH_G(FN, DT, ...)                      \
-  switch (G) {                                              \
-    case 4: return FN<DT, 4>(__VA_ARGS__);                  \
-    case 8: return FN<DT, 8>(__VA_ARGS__);                  \
-    case 16: return FN<DT, 16>(__VA_ARGS__);                \
-    case 32: return FN<DT, 32>(__VA_ARGS__);                \
-    case 64: return FN<DT, 64>(__VA_ARGS__);                \
-    default: return hipErrorInvalidValue;                   \
-  }
-
-hipError_t launch_prune_forward(int32_t dt, int G, const PruneParams &p, int grid, hipStream_t st) {
+hipError_t launch_prune_forward(int32_t dt, const PruneParams &p, int grid, hipStream_t st) {
   switch (dt) {
-    case PECANN_F32: PECANN_DISPATCH_G(launch_pf_t, PECANN_F32, p, grid, st)
-    case PECANN_U8: PECANN_DISPATCH_G(launch_pf_t, PECANN_U8, p, grid, st)
-    case PECANN_BF16: PECANN_DISPATCH_G(launch_pf_t, PECANN_BF16, p, grid, st)
-    case PECANN_FP8E4M3: PECANN_DISPATCH_G(launch_pf_t, PECANN_FP8E4M3, p, grid, st)
+    case PECANN_F32: return launch_pf_t<PECANN_F32>(p, grid, st);
+    case PECANN_U8: return launch_pf_t<PECANN_U8>(p, grid, st);
+    case PECANN_BF16: return launch_pf_t<PECANN_BF16>(p, grid, st);
+    case PECANN_FP8E4M3: return launch_pf_t<PECANN_FP8E4M3>(p, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
-hipError_t launch_prune_reverse(int32_t dt, int G, const PruneParams &p, int grid, hipStream_t st) {
+hipError_t launch_prune_reverse(int32_t dt, const PruneParams &p, int grid, hipStream_t st) {
   switch (dt) {
-    case PECANN_F32: PECANN_DISPATCH_G(launch_pr_t, PECANN_F32, p, grid, st)
-    case PECANN_U8: PECANN_DISPATCH_G(launch_pr_t, PECANN_U8, p, grid, st)
-    case PECANN_BF16: PECANN_DISPATCH_G(launch_pr_t, PECANN_BF16, p, grid, st)
-    case PECANN_FP8E4M3: PECANN_DISPATCH_G(launch_pr_t, PECANN_FP8E4M3, p, grid, st)
+    case PECANN_F32: return launch_pr_t<PECANN_F32>(p, grid, st);
+    case PECANN_U8: return launch_pr_t<PECANN_U8>(p, grid, st);
+    case PECANN_BF16: return launch_pr_t<PECANN_BF16>(p, grid, st);
+    case PECANN_FP8E4M3: return launch_pr_t<PECANN_FP8E4M3>(p, grid, st);
     default: return hipErrorInvalidValue;
   }
 }

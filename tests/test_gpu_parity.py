@@ -244,6 +244,25 @@ def test_build_many_batches_bit_exact(dev, grid_case):
     assert np.array_equal(_np(adj), adj_o) and np.array_equal(_np(deg), deg_o)
 
 
+def test_build_heavy_target_bit_exact(dev):
+    # a star: every point's nearest neighbour is the hub, so the hub receives
+    # hundreds of reverse edges in one batch (the large-candidate prune path)
+    n, d = 700, 16
+    rng = np.random.default_rng(31)
+    X = np.empty((n, d), np.float32)
+    X[0] = 256
+    mag = rng.integers(40, 100, (n - 1, d))
+    X[1:] = 256 + mag * rng.choice([-1, 1], (n - 1, d))
+    P = oracle.Points(X)
+    perm = datagen.permutation(n, 4)
+    adj_o, deg_o = oracle.vamana_build(P, 16, 32, 1.2, perm, num_starts=4, max_batch=n)
+    assert np.count_nonzero(adj_o == 0) > 300  # the hub is kept by most points
+    ds = pecann.Dataset(_t(X, dev), "l2", "f32")
+    adj, deg = pecann.build_graph(ds, 16, 32, 1.2, num_starts=4, visited_cap=512,
+                                  perm=_t(perm, dev), max_batch=n)
+    assert np.array_equal(_np(adj), adj_o) and np.array_equal(_np(deg), deg_o)
+
+
 def test_search_and_dependent_rounds_bit_exact(dev, grid_case):
     X, P, perm, n = grid_case["X"], grid_case["P"], grid_case["perm"], grid_case["n"]
     R, L, k = 16, 32, 10
