@@ -11,7 +11,7 @@
 
 namespace pecann {
 
-template <int DT, int G>
+template <int DT, int S>
 __global__ __launch_bounds__(64) void bf_knn_kernel(BfKnnParams p) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int k = p.k;
@@ -20,12 +20,11 @@ __global__ __launch_bounds__(64) void bf_knn_kernel(BfKnnParams p) {
   top.a = (uint64_t *)smem;
   top.b = top.a + kp;
   top.tmp = top.b + kp;
-  top.fa = (uint8_t *)(top.tmp + 64);
+  uint64_t *kb = top.tmp + 64;  // keys of the current 64 candidates
+  top.fa = (uint8_t *)(kb + 64);
   top.fb = top.fa + kp;
   top.cap = k;
-  using E = ExactEngine<DT, G>;
-  constexpr int NPL = E::NPL;
-  E eng;
+  ExactEngine<DT, S> eng;
   const int l = lane_id();
   const int count = p.item_count ? *p.item_count : p.nitems;
   for (;;) {
@@ -35,14 +34,13 @@ __global__ __launch_bounds__(64) void bf_knn_kernel(BfKnnParams p) {
     eng.load_query(p.rows, qid);
     top.m = 0;
     wave_lds_sync();
-    for (int base = 0; base < p.n; base += NPL) {
-      int32_t row = base + l / G;
-      if (row >= p.n || row == qid) row = -1;
-      const float m = eng.measure(p.rows, row);
-      const uint64_t key = row >= 0 ? make_key(m, row) : kNoKey;
-      uint64_t kk = shfl_u64(key, (l % NPL) * G);
-      if (l >= NPL) kk = kNoKey;
-      top.merge(kk);
+    for (int base = 0; base < p.n; base += kWave) {
+      const int c = min(kWave, p.n - base);
+      score_keys(eng, p.rows, c, [&](int i) { return base + i == qid ? -1 : base + i; }, kb);
+      wave_lds_sync();
+      const uint64_t key = l < c ? kb[l] : kNoKey;
+      wave_lds_sync();
+      top.merge(key);
     }
     const int64_t o = (int64_t)qid * k;
     for (int t = l; t < k; t += kWave) {
@@ -61,15 +59,14 @@ __global__ __launch_bounds__(64) void bf_knn_kernel(BfKnnParams p) {
 
 size_t bf_knn_lds_bytes(int k) {
   const size_t kp = (size_t)((k + 15) & ~15);
-  return 8 * (2 * kp + 64) + 2 * kp;
+  return 8 * (2 * kp + 128) + 2 * kp;
 }
 
-template <int DT, int G>
+template <int DT, int S>
 __global__ __launch_bounds__(64) void bf_dep_kernel(BfDepParams p) {
   __shared__ int32_t cidx[64];
-  using E = ExactEngine<DT, G>;
-  constexpr int NPL = E::NPL;
-  E eng;
+  __shared__ uint64_t kb[64];
+  ExactEngine<DT, S> eng;
   const int l = lane_id();
   const int count = *p.ucount;
   const int total = count * p.nchunks;
@@ -92,15 +89,9 @@ __global__ __launch_bounds__(64) void bf_dep_kernel(BfDepParams p) {
       const int c = __popcll(bm);
       if (ok) cidx[lanes_below(bm)] = j;
       wave_lds_sync();
-      for (int b2 = 0; b2 < c; b2 += NPL) {
-        const int ci = b2 + l / G;
-        const int32_t row = ci < c ? cidx[ci] : -1;
-        const float m = eng.measure(p.rows, row);
-        if ((l % G) == 0 && row >= 0) {
-          const uint64_t kk = make_key(m, row);
-          best = kk < best ? kk : best;
-        }
-      }
+      score_keys(eng, p.rows, c, [&](int i) { return cidx[i]; }, kb);
+      wave_lds_sync();
+      if (l < c && kb[l] < best) best = kb[l];
       wave_lds_sync();
     }
     best = wave_min_u64(best);
@@ -108,45 +99,31 @@ __global__ __launch_bounds__(64) void bf_dep_kernel(BfDepParams p) {
   }
 }
 
-template <int DT, int G>
+template <int DT, int S>
 static hipError_t launch_bf_knn_t(const BfKnnParams &p, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((bf_knn_kernel<DT, G>), dim3(grid), dim3(64), bf_knn_lds_bytes(p.k), st, p);
-  return hipGetLastError();
+  if constexpr (S > max_shape(DT)) {
+    return hipErrorInvalidValue;
+  } else {
+    hipLaunchKernelGGL((bf_knn_kernel<DT, S>), dim3(grid), dim3(64), bf_knn_lds_bytes(p.k), st, p);
+    return hipGetLastError();
+  }
 }
-template <int DT, int G>
+template <int DT, int S>
 static hipError_t launch_bf_dep_t(const BfDepParams &p, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((bf_dep_kernel<DT, G>), dim3(grid), dim3(64), 0, st, p);
-  return hipGetLastError();
-}
-
-#define PECANN_DISPATCH_G(FN, DT, ...)                      \
-  switch (G) {                                              \
-    case 4: return FN<DT, 4>(__VA_ARGS__);                  \
-    case 8: return FN<DT, 8>(__VA_ARGS__);                  \
-    case 16: return FN<DT, 16>(__VA_ARGS__);                \
-    case 32: return FN<DT, 32>(__VA_ARGS__);                \
-    case 64: return FN<DT, 64>(__VA_ARGS__);                \
-    default: return hipErrorInvalidValue;                   \
-  }
-
-hipError_t launch_bf_knn(int32_t dt, int G, const BfKnnParams &p, int grid, hipStream_t st) {
-  switch (dt) {
-    case PECANN_F32: PECANN_DISPATCH_G(launch_bf_knn_t, PECANN_F32, p, grid, st)
-    case PECANN_U8: PECANN_DISPATCH_G(launch_bf_knn_t, PECANN_U8, p, grid, st)
-    case PECANN_BF16: PECANN_DISPATCH_G(launch_bf_knn_t, PECANN_BF16, p, grid, st)
-    case PECANN_FP8E4M3: PECANN_DISPATCH_G(launch_bf_knn_t, PECANN_FP8E4M3, p, grid, st)
-    default: return hipErrorInvalidValue;
+  if constexpr (S > max_shape(DT)) {
+    return hipErrorInvalidValue;
+  } else {
+    hipLaunchKernelGGL((bf_dep_kernel<DT, S>), dim3(grid), dim3(64), 0, st, p);
+    return hipGetLastError();
   }
 }
 
-hipError_t launch_bf_dep(int32_t dt, int G, const BfDepParams &p, int grid, hipStream_t st) {
-  switch (dt) {
-    case PECANN_F32: PECANN_DISPATCH_G(launch_bf_dep_t, PECANN_F32, p, grid, st)
-    case PECANN_U8: PECANN_DISPATCH_G(launch_bf_dep_t, PECANN_U8, p, grid, st)
-    case PECANN_BF16: PECANN_DISPATCH_G(launch_bf_dep_t, PECANN_BF16, p, grid, st)
-    case PECANN_FP8E4M3: PECANN_DISPATCH_G(launch_bf_dep_t, PECANN_FP8E4M3, p, grid, st)
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_bf_knn(int32_t dt, int S, const BfKnnParams &p, int grid, hipStream_t st) {
+  PECANN_DISPATCH_SHAPE(launch_bf_knn_t, dt, S, p, grid, st)
+}
+
+hipError_t launch_bf_dep(int32_t dt, int S, const BfDepParams &p, int grid, hipStream_t st) {
+  PECANN_DISPATCH_SHAPE(launch_bf_dep_t, dt, S, p, grid, st)
 }
 
 }  // namespace pecann

@@ -162,29 +162,113 @@ __device__ __forceinline__ void unpack_chunk<PECANN_FP8E4M3>(const uint4 &c, flo
 using Rows = RowsDesc;
 
 // ---------------------------------------------------------------------------
-// Gather-distance engine.  A wavefront is split into 64/G groups of G lanes;
-// each group computes the distance from the register-resident query to one
-// candidate row per pass, lane g of a group reading chunks g, g+G, g+2G, ...
-// The query slice is held in float32 (at most 64 floats per lane).
+// Gather-distance engine.  The shape S (a power of two in [4, 1024], at least
+// the row's number of 16-byte chunks) is split into G lanes per candidate and
+// CPL = S / G chunks per lane: as many chunks per lane as a 32-float query
+// slice allows (more only when S > 64 * that), lane g of a group holding chunks
+// g, g + G, ...  A wavefront scores NPL = 64 / G candidates per pass and issues
+// the row loads of U passes (at most LCAP chunks per lane) before reducing any;
+// the U partial sums of a group are then reduced together by recursive halving
+// (each lane ends with the total of one candidate), which costs about one lane
+// exchange per candidate instead of log2(G).
 //   L2:     measure = sum (q - x)^2          (squared distance)
 //   cosine: measure = max(0, 1 - q.x)        (rows are pre-normalised)
-// For FP8 rows the candidate values are x8 * scale_row.
+// FP8 candidate values are x8 * scale_row; U8 rows are summed in int32, so
+// their measures are exact integers (rounded once to float).  XR = true makes
+// a float32 engine over the rerank rows instead of the search rows.
 // ---------------------------------------------------------------------------
-template <int DT, int G>
+constexpr int max_shape(int dt) { return dt == PECANN_F32 ? 1024 : dt == PECANN_BF16 ? 512 : 256; }
+
+// Launch-time dispatch over (row format, shape).  FN<DT, S> is a function
+// template that returns hipErrorInvalidValue for S > max_shape(DT) (under
+// `if constexpr`, so that no kernel is instantiated for those shapes).
+#define PECANN_SHAPES(FN, DT, S, ...)                                            \
+  switch (S) {                                                                   \
+    case 4: return FN<DT, 4>(__VA_ARGS__);                                       \
+    case 8: return FN<DT, 8>(__VA_ARGS__);                                       \
+    case 16: return FN<DT, 16>(__VA_ARGS__);                                     \
+    case 32: return FN<DT, 32>(__VA_ARGS__);                                     \
+    case 64: return FN<DT, 64>(__VA_ARGS__);                                     \
+    case 128: return FN<DT, 128>(__VA_ARGS__);                                   \
+    case 256: return FN<DT, 256>(__VA_ARGS__);                                   \
+    case 512: return FN<DT, 512>(__VA_ARGS__);                                   \
+    case 1024: return FN<DT, 1024>(__VA_ARGS__);                                 \
+    default: return hipErrorInvalidValue;                                        \
+  }
+#define PECANN_DISPATCH_SHAPE(FN, dt, S, ...)                                    \
+  switch (dt) {                                                                  \
+    case PECANN_F32: PECANN_SHAPES(FN, PECANN_F32, S, __VA_ARGS__)               \
+    case PECANN_U8: PECANN_SHAPES(FN, PECANN_U8, S, __VA_ARGS__)                 \
+    case PECANN_BF16: PECANN_SHAPES(FN, PECANN_BF16, S, __VA_ARGS__)             \
+    case PECANN_FP8E4M3: PECANN_SHAPES(FN, PECANN_FP8E4M3, S, __VA_ARGS__)       \
+    default: return hipErrorInvalidValue;                                        \
+  }
+
+// Sums of U values over aligned groups of G lanes (U <= G, both powers of
+// two), scattered: lane l ends with the total of value (l % G) / (G / U) of its
+// group.  INT: the values are int32 bit patterns, added as integers.
+template <int G, int U, bool INT>
+__device__ __forceinline__ float reduce_scatter(float (&v)[U]) {
+  const int l = lane_id();
+#pragma unroll
+  for (int k = 1; k < U; k <<= 1) {
+    const int m = G / (2 * k);
+    const int h = U / (2 * k);  // values kept after this step
+    const bool hi = (l & m) != 0;
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      float lo_v = v[i], hi_v = v[h + i];
+      // pin both values in registers first: a select between two array loads
+      // would otherwise become a load from a selected address (private memory)
+      asm("" : "+v"(lo_v), "+v"(hi_v));
+      const float send = hi ? lo_v : hi_v;
+      const float keep = hi ? hi_v : lo_v;
+      const float got = __shfl_xor(send, m);
+      v[i] = INT ? __int_as_float(__float_as_int(keep) + __float_as_int(got)) : keep + got;
+    }
+  }
+  float r = v[0];
+#pragma unroll
+  for (int m = G / (2 * U); m >= 1; m >>= 1) {
+    const float got = __shfl_xor(r, m);
+    r = INT ? __int_as_float(__float_as_int(r) + __float_as_int(got)) : r + got;
+  }
+  return r;
+}
+
+template <int DT, int S, bool XR = false>
 struct Engine {
+  static_assert(S >= 4 && S <= 1024 && (S & (S - 1)) == 0, "shape must be a power of two in [4, 1024]");
+  static_assert(!XR || DT == PECANN_F32, "the rerank rows are float32");
   static constexpr int EPC = RowFmt<DT>::EPC;
-  static constexpr int CPL = 64 / EPC;  // chunks per lane (max)
-  static constexpr int NPL = kWave / G; // candidates per pass
+  static constexpr int CPL_Q = (32 / EPC) < S ? 32 / EPC : S;  // query budget: 32 floats
+  static constexpr int CPL = (S / kWave) > CPL_Q ? S / kWave : CPL_Q;
+  static constexpr int G = S / CPL;
+  static constexpr int NPL = kWave / G;
+  // chunks per lane in flight: 16 for float32 search rows, 8 for the narrower
+  // formats and the rerank rows (whose kernels need more registers elsewhere;
+  // measured best on MI355X)
+  static constexpr int LCAP = (DT == PECANN_F32 && !XR) ? 16 : 8;
+  static constexpr int U = (LCAP / CPL) < 1 ? 1 : ((LCAP / CPL) < G ? LCAP / CPL : G);
+  static constexpr bool INT = DT == PECANN_U8 && !XR;
   float q[CPL * EPC];
 
-  __device__ __forceinline__ int grp() const { return lane_id() / G; }
-  __device__ __forceinline__ int gl() const { return lane_id() % G; }
+  __device__ __forceinline__ static int gl() { return lane_id() % G; }
+  __device__ __forceinline__ static int chunks(const Rows &r) { return XR ? r.nch_r : r.nch; }
+  __device__ __forceinline__ static const uint8_t *row_ptr(const Rows &r, int32_t row) {
+    return XR ? (const uint8_t *)(r.xr + (int64_t)row * r.xr_stride) : r.xs + (int64_t)row * r.xs_stride;
+  }
+  // Index (in [0, U)) of the candidate whose total this lane holds after a
+  // measure_batch, and whether it is the lane that reports it.
+  __device__ __forceinline__ static int owned() { return gl() / (G / U); }
+  __device__ __forceinline__ static bool reporter() { return gl() % (G / U) == 0; }
 
   // Query from the float32 rows when present, else from the search rows.
   __device__ __forceinline__ void load_query(const Rows &r, int32_t row) {
     const int g = gl();
-    if (r.xr) {
+    if (XR || r.xr) {
       const float *base = r.xr + (int64_t)row * r.xr_stride;
+      const int lim = r.nch_r * 4;  // floats held by a rerank row
 #pragma unroll
       for (int t = 0; t < CPL; ++t) {
         const int c = g + G * t;
@@ -192,7 +276,7 @@ struct Engine {
         for (int e = 0; e < EPC; e += 4) {
           float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
           const int el = c * EPC + e;  // first element of this float4
-          if (c < r.nch && el < r.nch_r * 4) v = *(const float4 *)(base + el);
+          if (el < lim) v = *(const float4 *)(base + el);
           q[t * EPC + e + 0] = v.x; q[t * EPC + e + 1] = v.y;
           q[t * EPC + e + 2] = v.z; q[t * EPC + e + 3] = v.w;
         }
@@ -214,20 +298,25 @@ struct Engine {
     }
   }
 
-  // Partial measure of this lane against search row `row` (row < 0: returns 0).
-  __device__ __forceinline__ float partial(const Rows &r, int32_t row) const {
-    const int g = gl();
-    uint4 v[CPL];
-    const uint8_t *base = r.xs + (int64_t)(row < 0 ? 0 : row) * r.xs_stride;
+  // This lane's partial measure against the chunks v of one candidate (scale s);
+  // int32 bits for U8 rows.
+  __device__ __forceinline__ float partial(const uint4 (&v)[CPL], float s, int metric) const {
+    if (INT) {
+      int acc = 0;
 #pragma unroll
-    for (int t = 0; t < CPL; ++t) {
-      const int c = g + G * t;
-      v[t] = make_uint4(0, 0, 0, 0);
-      if (row >= 0 && c < r.nch) v[t] = *(const uint4 *)(base + 16 * c);
+      for (int t = 0; t < CPL; ++t) {
+        float x[EPC];
+        unpack_chunk<DT>(v[t], x);
+#pragma unroll
+        for (int e = 0; e < EPC; ++e) {
+          const int df = (int)q[t * EPC + e] - (int)x[e];
+          acc += df * df;
+        }
+      }
+      return __int_as_float(acc);
     }
     float acc = 0.f;
-    if (r.metric == PECANN_L2) {
-      const float s = (DT == PECANN_FP8E4M3 && row >= 0) ? r.scale[row] : 1.0f;
+    if (metric == PECANN_L2) {
 #pragma unroll
       for (int t = 0; t < CPL; ++t) {
         float x[EPC];
@@ -240,82 +329,105 @@ struct Engine {
         }
       }
     } else {
-      float dot = 0.f;
 #pragma unroll
       for (int t = 0; t < CPL; ++t) {
         float x[EPC];
         unpack_chunk<DT>(v[t], x);
 #pragma unroll
-        for (int e = 0; e < EPC; ++e) dot = fmaf(q[t * EPC + e], x[e], dot);
+        for (int e = 0; e < EPC; ++e) acc = fmaf(q[t * EPC + e], x[e], acc);
       }
-      if (DT == PECANN_FP8E4M3 && row >= 0) dot *= r.scale[row];
-      acc = dot;
+      if (DT == PECANN_FP8E4M3) acc *= s;
     }
     return acc;
   }
 
-  // Full measure for the candidate of this lane's group; valid in every lane.
+  // Measure from a group total.
+  __device__ __forceinline__ static float finish(float tot, int metric) {
+    if (INT) return (float)__float_as_int(tot);
+    return metric == PECANN_L2 ? tot : fmaxf(0.f, 1.0f - tot);
+  }
+
+  // Measures of the U candidates row[0..U) of this lane's group; the lane gets
+  // the measure of row[owned()] (unspecified when that row is < 0).
+  __device__ __forceinline__ float measure_batch(const Rows &r, const int32_t (&row)[U]) const {
+    const int g = gl();
+    const int nch = chunks(r);
+    uint4 v[U][CPL];
+    float sc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint8_t *base = row_ptr(r, row[u] < 0 ? 0 : row[u]);
+      sc[u] = (DT == PECANN_FP8E4M3 && !XR && row[u] >= 0) ? r.scale[row[u]] : 1.0f;
+#pragma unroll
+      for (int t = 0; t < CPL; ++t) {
+        const int c = g + G * t;
+        v[u][t] = make_uint4(0, 0, 0, 0);
+        if (row[u] >= 0 && c < nch) v[u][t] = *(const uint4 *)(base + 16 * c);
+      }
+    }
+    float part[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) part[u] = partial(v[u], sc[u], r.metric);
+    return finish(reduce_scatter<G, U, INT>(part), r.metric);
+  }
+
+  // Measure of one candidate per lane group, valid in every lane of the group.
   __device__ __forceinline__ float measure(const Rows &r, int32_t row) const {
-    float s = group_sum<G>(partial(r, row));
-    if (r.metric != PECANN_L2) s = fmaxf(0.f, 1.0f - s);
-    return s;
+    const int g = gl();
+    const int nch = chunks(r);
+    const uint8_t *base = row_ptr(r, row < 0 ? 0 : row);
+    uint4 v[CPL];
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) {
+      const int c = g + G * t;
+      v[t] = make_uint4(0, 0, 0, 0);
+      if (row >= 0 && c < nch) v[t] = *(const uint4 *)(base + 16 * c);
+    }
+    const float s = (DT == PECANN_FP8E4M3 && !XR && row >= 0) ? r.scale[row] : 1.0f;
+    float part[1] = {partial(v, s, r.metric)};
+    return finish(reduce_scatter<G, 1, INT>(part), r.metric);
   }
 };
 
-// Float32 engine over the rerank rows (same lane layout: G lanes, 16-byte
-// chunks, 64 floats per lane at most).
-template <int G>
-struct Engine32 {
-  static constexpr int CPL = 16;
-  static constexpr int NPL = kWave / G;
-  float q[CPL * 4];
-  __device__ __forceinline__ int gl() const { return lane_id() % G; }
-  __device__ __forceinline__ void load_query(const Rows &r, int32_t row) {
-    const float *base = r.xr + (int64_t)row * r.xr_stride;
-    const int g = gl();
-#pragma unroll
-    for (int t = 0; t < CPL; ++t) {
-      const int c = g + G * t;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (c < r.nch_r) v = *(const float4 *)(base + 4 * c);
-      q[4 * t] = v.x; q[4 * t + 1] = v.y; q[4 * t + 2] = v.z; q[4 * t + 3] = v.w;
-    }
-  }
-  __device__ __forceinline__ float measure(const Rows &r, int32_t row) const {
-    const int g = gl();
-    const float *base = r.xr + (int64_t)(row < 0 ? 0 : row) * r.xr_stride;
-    float4 v[CPL];
-#pragma unroll
-    for (int t = 0; t < CPL; ++t) {
-      const int c = g + G * t;
-      v[t] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (row >= 0 && c < r.nch_r) v[t] = *(const float4 *)(base + 4 * c);
-    }
-    float acc = 0.f;
-    if (r.metric == PECANN_L2) {
-#pragma unroll
-      for (int t = 0; t < CPL; ++t) {
-        float a = q[4 * t] - v[t].x, b = q[4 * t + 1] - v[t].y;
-        float c = q[4 * t + 2] - v[t].z, d = q[4 * t + 3] - v[t].w;
-        acc = fmaf(a, a, acc); acc = fmaf(b, b, acc); acc = fmaf(c, c, acc); acc = fmaf(d, d, acc);
-      }
-      acc = group_sum<G>(acc);
-    } else {
-#pragma unroll
-      for (int t = 0; t < CPL; ++t) {
-        acc = fmaf(q[4 * t], v[t].x, acc); acc = fmaf(q[4 * t + 1], v[t].y, acc);
-        acc = fmaf(q[4 * t + 2], v[t].z, acc); acc = fmaf(q[4 * t + 3], v[t].w, acc);
-      }
-      acc = fmaxf(0.f, 1.0f - group_sum<G>(acc));
-    }
-    return acc;
-  }
+// Float32 engine over the rerank rows.
+template <int S>
+using Engine32 = Engine<PECANN_F32, S, true>;
+
+// Shape of the rerank-row engine that goes with search-row shape S: a
+// BF16 (FP8) chunk holds 8 (16) values, a float32 chunk 4.
+template <int DT, int S>
+struct RerankShape {
+  static constexpr int v = (S * RowFmt<DT>::EPC / 4) < 4 ? 4 : (S * RowFmt<DT>::EPC / 4);
 };
 
 // Engine over exact rows: the search rows themselves when they are float32 or
 // uint8, else the float32 rerank rows.
-template <int DT, int G>
-using ExactEngine = typename std::conditional<(DT == PECANN_F32 || DT == PECANN_U8), Engine<DT, G>,
-                                              Engine32<G>>::type;
+template <int DT, int S>
+using ExactEngine = typename std::conditional<(DT == PECANN_F32 || DT == PECANN_U8), Engine<DT, S>,
+                                              Engine32<RerankShape<DT, S>::v>>::type;
+
+// Keys (measure, id) of the candidates id_of(i), i in [0, c), into out[0, c)
+// (LDS); ids < 0 give kNoKey.  Visible to the wavefront after a wave_lds_sync.
+template <class E, class IdFn>
+__device__ __forceinline__ void score_keys(const E &eng, const Rows &r, int c, IdFn id_of,
+                                           uint64_t *out) {
+  constexpr int NPL = E::NPL, U = E::U, G = E::G;
+  const int grp = lane_id() / G;
+  const int mine = E::owned();
+  const bool rep = E::reporter();
+  for (int base = 0; base < c; base += NPL * U) {
+    int32_t row[U];
+    int32_t myrow = -1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int ci = base + u * NPL + grp;
+      row[u] = ci < c ? id_of(ci) : -1;
+      if (u == mine) myrow = row[u];
+    }
+    const float m = eng.measure_batch(r, row);
+    const int ci = base + mine * NPL + grp;
+    if (rep && ci < c) out[ci] = myrow >= 0 ? make_key(m, myrow) : kNoKey;
+  }
+}
 
 }  // namespace pecann

@@ -189,7 +189,7 @@ __global__ __launch_bounds__(1024) void norm_max_kernel(const uint32_t *norms, i
 }  // namespace
 
 // One wavefront per query: exact re-score of the scan's candidates, check, output.
-template <int DT, int G>
+template <int DT, int S>
 __global__ __launch_bounds__(64) void exact_rerank_kernel(ExactMfmaParams p, float ce, int u8rows) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int k = p.k;
@@ -198,12 +198,11 @@ __global__ __launch_bounds__(64) void exact_rerank_kernel(ExactMfmaParams p, flo
   top.a = (uint64_t *)smem;
   top.b = top.a + kp;
   top.tmp = top.b + kp;
-  top.fa = (uint8_t *)(top.tmp + 64);
+  uint64_t *kb = top.tmp + 64;  // keys of the current 64 candidates
+  top.fa = (uint8_t *)(kb + 64);
   top.fb = top.fa + kp;
   top.cap = k;
-  using E = ExactEngine<DT, G>;
-  constexpr int NPL = E::NPL;
-  E eng;
+  ExactEngine<DT, S> eng;
   const int l = lane_id();
   for (;;) {
     const int q = next_item(p.head);
@@ -212,13 +211,12 @@ __global__ __launch_bounds__(64) void exact_rerank_kernel(ExactMfmaParams p, flo
     top.m = 0;
     wave_lds_sync();
     const int32_t *c = p.cand + (int64_t)q * kCand;
-    for (int base = 0; base < kCand; base += NPL) {
-      const int32_t row = c[base + l / G];
-      const float m = eng.measure(p.rows, row);
-      const uint64_t key = row >= 0 ? make_key(m, row) : kNoKey;
-      uint64_t kk = shfl_u64(key, (l % NPL) * G);
-      if (l >= NPL) kk = kNoKey;
-      top.merge(kk);
+    for (int base = 0; base < kCand; base += kWave) {
+      score_keys(eng, p.rows, kWave, [&](int i) { return c[base + i]; }, kb);
+      wave_lds_sync();
+      const uint64_t key = kb[l];
+      wave_lds_sync();
+      top.merge(key);
     }
     bool ok = top.m == k;
     if (ok) {
@@ -249,37 +247,25 @@ __global__ __launch_bounds__(64) void exact_rerank_kernel(ExactMfmaParams p, flo
   }
 }
 
-template <int DT, int G>
+template <int DT, int S>
 static hipError_t launch_rerank_t(const ExactMfmaParams &p, float ce, int u8rows, int grid,
                                   hipStream_t st) {
-  const size_t kp = (size_t)((p.k + 15) & ~15);
-  hipLaunchKernelGGL((exact_rerank_kernel<DT, G>), dim3(grid), dim3(64), 8 * (2 * kp + 64) + 2 * kp, st,
-                     p, ce, u8rows);
-  return hipGetLastError();
+  if constexpr (S > max_shape(DT)) {
+    return hipErrorInvalidValue;
+  } else {
+    const size_t kp = (size_t)((p.k + 15) & ~15);
+    hipLaunchKernelGGL((exact_rerank_kernel<DT, S>), dim3(grid), dim3(64), 8 * (2 * kp + 128) + 2 * kp,
+                       st, p, ce, u8rows);
+    return hipGetLastError();
+  }
 }
 
-#define PECANN_DISPATCH_G(FN, DT, ...)                      \
-  switch (G) {                                              \
-    case 4: return FN<DT, 4>(__VA_ARGS__);                  \
-    case 8: return FN<DT, 8>(__VA_ARGS__);                  \
-    case 16: return FN<DT, 16>(__VA_ARGS__);                \
-    case 32: return FN<DT, 32>(__VA_ARGS__);                \
-    case 64: return FN<DT, 64>(__VA_ARGS__);                \
-    default: return hipErrorInvalidValue;                   \
-  }
-
-static hipError_t launch_rerank(int32_t dt, int G, const ExactMfmaParams &p, float ce, int u8rows,
+static hipError_t launch_rerank(int32_t dt, int S, const ExactMfmaParams &p, float ce, int u8rows,
                                 int grid, hipStream_t st) {
-  switch (dt) {
-    case PECANN_F32: PECANN_DISPATCH_G(launch_rerank_t, PECANN_F32, p, ce, u8rows, grid, st)
-    case PECANN_U8: PECANN_DISPATCH_G(launch_rerank_t, PECANN_U8, p, ce, u8rows, grid, st)
-    case PECANN_BF16: PECANN_DISPATCH_G(launch_rerank_t, PECANN_BF16, p, ce, u8rows, grid, st)
-    case PECANN_FP8E4M3: PECANN_DISPATCH_G(launch_rerank_t, PECANN_FP8E4M3, p, ce, u8rows, grid, st)
-    default: return hipErrorInvalidValue;
-  }
+  PECANN_DISPATCH_SHAPE(launch_rerank_t, dt, S, p, ce, u8rows, grid, st)
 }
 
-hipError_t launch_exact_mfma(int32_t dt, int G, const ExactMfmaParams &p, hipStream_t st) {
+hipError_t launch_exact_mfma(int32_t dt, int S, const ExactMfmaParams &p, hipStream_t st) {
   const Rows &r = p.rows;
   ScanRows sr;
   const bool u8 = dt == PECANN_U8;
@@ -310,16 +296,16 @@ hipError_t launch_exact_mfma(int32_t dt, int G, const ExactMfmaParams &p, hipStr
   // at most gamma_d of its magnitudes, the direct sum gamma_d of D^2 <= 2
   // (|a|^2 + |b|^2), plus the final additions: E <= 4 (d + 4) u (|a|^2 + |b|^2),
   // u = 2^-24, and |b|^2 <= the largest row norm.  Cosine rows are unit:
-  // E <= 4 (d + 4) u * 2.  uint8 rows: the matrix-core measure is exact and
-  // only the float32 direct sum rounds, by at most (d + 2) u * d * 255^2.
+  // E <= 4 (d + 4) u * 2.  uint8 rows: both measures are exact integers,
+  // each rounded once to float32, so E <= 2 u * d * 255^2.
   const float u = 5.9604645e-8f;
   const float dd = (float)r.d;
   float ce;
-  if (u8) ce = (dd + 2.0f) * u * dd * 65025.0f;
+  if (u8) ce = 2.0f * u * dd * 65025.0f;
   else if (r.metric == PECANN_L2) ce = 4.0f * (dd + 4.0f) * u;
   else ce = 8.0f * (dd + 4.0f) * u;
   const int grid = (int)std::min<int64_t>((int64_t)p.n, 256 * 32);
-  return launch_rerank(dt, G, p, ce, u8 ? 1 : 0, grid, st);
+  return launch_rerank(dt, S, p, ce, u8 ? 1 : 0, grid, st);
 }
 
 }  // namespace pecann

@@ -10,9 +10,10 @@
 
 namespace pecann {
 
-// Lane-group width G of the gather-distance engine for a row format: the
-// smallest power of two >= 4 that leaves at most 64 floats of query per lane.
-int engine_group(int32_t search_dtype, int32_t d);
+// Shape S of the gather-distance engine for a row format: the smallest power
+// of two >= 4 and >= the row's number of 16-byte chunks (lanes x chunks per
+// lane of one candidate).
+int engine_shape(int32_t search_dtype, int32_t d);
 
 struct RowsDesc {  // host copy of the row description (mirrors Rows)
   const uint8_t *xs;
@@ -75,7 +76,7 @@ struct SearchParams {
 };
 
 size_t search_lds_bytes(int L, int hbits);
-hipError_t launch_search(int32_t dt, int G, const SearchParams &p, int grid, hipStream_t s);
+hipError_t launch_search(int32_t dt, int S, const SearchParams &p, int grid, hipStream_t s);
 
 // Exact (brute-force) kNN over all points for a list of queries.
 struct BfKnnParams {
@@ -92,7 +93,7 @@ struct BfKnnParams {
   uint64_t *rank_key;
 };
 size_t bf_knn_lds_bytes(int k);
-hipError_t launch_bf_knn(int32_t dt, int G, const BfKnnParams &p, int grid, hipStream_t s);
+hipError_t launch_bf_knn(int32_t dt, int S, const BfKnnParams &p, int grid, hipStream_t s);
 
 // Exact dependent point for a list of unfinished points: chunked argmin over
 // the points of strictly smaller rank key.
@@ -107,7 +108,7 @@ struct BfDepParams {
   const uint64_t *key;
   unsigned long long *best;  // [u] packed (measure, index), ~0 at launch
 };
-hipError_t launch_bf_dep(int32_t dt, int G, const BfDepParams &p, int grid, hipStream_t s);
+hipError_t launch_bf_dep(int32_t dt, int S, const BfDepParams &p, int grid, hipStream_t s);
 
 // RobustPrune for a batch of new points (forward) and the reverse-edge merge.
 struct PruneParams {
@@ -172,7 +173,7 @@ struct ExactMfmaParams {
   int32_t *fb_list;            // queries whose check failed
   int32_t *fb_count;
 };
-hipError_t launch_exact_mfma(int32_t dt, int G, const ExactMfmaParams &p, hipStream_t s);
+hipError_t launch_exact_mfma(int32_t dt, int S, const ExactMfmaParams &p, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 hipError_t launch_identity_perm(int32_t *p, int64_t n, hipStream_t s);

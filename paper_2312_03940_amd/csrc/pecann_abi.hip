@@ -165,18 +165,12 @@ static int persistent_grid(int64_t items) {
 static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 namespace pecann {
-int engine_group(int32_t sdt, int32_t d) {
-  int bytes = sdt == PECANN_F32 ? 4 : sdt == PECANN_BF16 ? 2 : 1;
-  int epc = 16 / bytes;
-  int nch = (d * bytes + 15) / 16;
-  int cpl = 64 / epc;
-  int G = 4;
-  while (G * cpl < nch) G *= 2;
-  if (sdt == PECANN_BF16 || sdt == PECANN_FP8E4M3) {
-    int nch_r = (d + 3) / 4;
-    while (G * 16 < nch_r) G *= 2;
-  }
-  return G;
+int engine_shape(int32_t sdt, int32_t d) {
+  const int bytes = sdt == PECANN_F32 ? 4 : sdt == PECANN_BF16 ? 2 : 1;
+  const int nch = (d * bytes + 15) / 16;
+  int S = 4;
+  while (S < nch) S *= 2;
+  return S;
 }
 }  // namespace pecann
 
@@ -297,9 +291,13 @@ struct Carver {
   size_t size() const { return up(off, 256); }
 };
 
+// Visited-hash size of a search with beam L: about 20 L slots (a search
+// visits some 15 L distinct points), between 2^10 and 2^13.  The hash may
+// forget (results do not change, only repeated distance evaluations), and a
+// larger table costs occupancy: 4096 slots measured best at L = 128 and 200.
 static int hash_bits_for(int L) {
   int b = 10;
-  while (b < 13 && (1 << b) < 32 * L) ++b;
+  while (b < 13 && (1 << b) < 20 * L) ++b;
   return b;
 }
 
@@ -404,7 +402,7 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
   hipStream_t s = (hipStream_t)stream;
   const RowsDesc rows = rows_of(ds, L);
   const int dt = ds->search_dtype;
-  const int G = engine_group(dt, ds->d);
+  const int S = engine_shape(dt, ds->d);
 
   const int32_t *order = perm;
   if (!order) {
@@ -489,7 +487,7 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
       sp.nstarts = (int32_t)std::min<int64_t>(bp->num_starts, in_graph);
       {
         PROF(F_SEARCH_BUILD, s);
-        HIP_TRY_BATCH(launch_search(dt, G, sp, persistent_grid(nb), s));
+        HIP_TRY_BATCH(launch_search(dt, S, sp, persistent_grid(nb), s));
       }
       pp.b0 = b0;
       pp.nb = (int32_t)nb;
@@ -588,7 +586,7 @@ extern "C" pecann_status pecann_knn_density(const pecann_dataset *ds, const int3
   hipStream_t s = (hipStream_t)stream;
   const RowsDesc rows = rows_of(ds, L);
   const int dt = ds->search_dtype;
-  const int G = engine_group(dt, ds->d);
+  const int S = engine_shape(dt, ds->d);
   HIP_TRY(launch_fill_i32(ctr, 0, 4, s));
 
   BfKnnParams bp = {};
@@ -605,7 +603,7 @@ extern "C" pecann_status pecann_knn_density(const pecann_dataset *ds, const int3
     bp.nitems = (int32_t)n;
     bp.head = ctr + 0;
     PROF(F_BF_KNN, s);
-    HIP_TRY(launch_bf_knn(dt, G, bp, persistent_grid(n), s));
+    HIP_TRY(launch_bf_knn(dt, S, bp, persistent_grid(n), s));
     return PECANN_OK;
   }
   if (exact_mfma) {
@@ -625,14 +623,14 @@ extern "C" pecann_status pecann_knn_density(const pecann_dataset *ds, const int3
     ep.fb_count = ctr + 1;
     {
       PROF(F_EXACT_MFMA, s);
-      HIP_TRY(launch_exact_mfma(dt, G, ep, s));
+      HIP_TRY(launch_exact_mfma(dt, S, ep, s));
     }
     bp.items = fb;
     bp.item_count = ctr + 1;
     bp.nitems = 0;
     bp.head = ctr + 2;
     PROF(F_BF_KNN, s);
-    HIP_TRY(launch_bf_knn(dt, G, bp, cu_count() * 4, s));
+    HIP_TRY(launch_bf_knn(dt, S, bp, cu_count() * 4, s));
     return PECANN_OK;
   }
   SearchParams sp = {};
@@ -661,7 +659,7 @@ extern "C" pecann_status pecann_knn_density(const pecann_dataset *ds, const int3
   sp.counters = (unsigned long long *)counters;
   {
     PROF(F_SEARCH_KNN, s);
-    HIP_TRY(launch_search(dt, G, sp, persistent_grid(n), s));
+    HIP_TRY(launch_search(dt, S, sp, persistent_grid(n), s));
   }
   // too-few-results fallback: exact search for those queries
   bp.items = fb;
@@ -669,7 +667,7 @@ extern "C" pecann_status pecann_knn_density(const pecann_dataset *ds, const int3
   bp.nitems = 0;
   bp.head = ctr + 2;
   PROF(F_BF_KNN, s);
-  HIP_TRY(launch_bf_knn(dt, G, bp, cu_count() * 4, s));
+  HIP_TRY(launch_bf_knn(dt, S, bp, cu_count() * 4, s));
   return PECANN_OK;
 }
 
@@ -746,7 +744,7 @@ extern "C" pecann_status pecann_dependent_search(const pecann_dataset *ds, const
   hipStream_t s = (hipStream_t)stream;
   const RowsDesc rows = rows_of(ds, L);
   const int dt = ds->search_dtype;
-  const int G = engine_group(dt, ds->d);
+  const int S = engine_shape(dt, ds->d);
 
   HIP_TRY(launch_fill_i32(w.ctr, 0, 64, s));
   HIP_TRY(launch_fill_i32(w.ucnt, 0, 64, s));
@@ -783,7 +781,7 @@ extern "C" pecann_status pecann_dependent_search(const pecann_dataset *ds, const
       sp.threshold = threshold;
       {
         PROF(F_SEARCH_DEP, s);
-        HIP_TRY(launch_search(dt, G, sp, persistent_grid(n), s));
+        HIP_TRY(launch_search(dt, S, sp, persistent_grid(n), s));
       }
       std::swap(cur, nxt);
     }
@@ -802,7 +800,7 @@ extern "C" pecann_status pecann_dependent_search(const pecann_dataset *ds, const
   bd.best = w.best;
   {
     PROF(F_BF_DEP, s);
-    HIP_TRY(launch_bf_dep(dt, G, bd, persistent_grid(n * (int64_t)bd.nchunks), s));
+    HIP_TRY(launch_bf_dep(dt, S, bd, persistent_grid(n * (int64_t)bd.nchunks), s));
   }
   HIP_TRY(launch_bf_dep_finalize(cur, w.ucnt + nr, w.best, ds->metric, dep, delta, (int32_t)n, s));
   if (stats) {

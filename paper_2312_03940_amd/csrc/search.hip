@@ -40,10 +40,8 @@ __device__ __forceinline__ Lds carve(uint8_t *smem, int L, int hbits) {
 }
 
 // Distances for the ids given one per lane (-1 = none), then merge into the beam.
-template <int DT, int G>
-__device__ __forceinline__ void score_and_merge(const Engine<DT, G> &eng, const Rows &rows, Lds &s,
-                                                int32_t myid) {
-  constexpr int NPL = Engine<DT, G>::NPL;
+template <class E>
+__device__ __forceinline__ void score_and_merge(const E &eng, const Rows &rows, Lds &s, int32_t myid) {
   const int l = lane_id();
   const uint64_t bm = ballot(myid >= 0);
   const int c = __popcll(bm);
@@ -51,14 +49,7 @@ __device__ __forceinline__ void score_and_merge(const Engine<DT, G> &eng, const 
   s.n_rows += c;
   if (myid >= 0) s.cid[lanes_below(bm)] = myid;
   wave_lds_sync();
-  const int grp = l / G;
-  const bool leader = (l % G) == 0;
-  for (int base = 0; base < c; base += NPL) {
-    const int ci = base + grp;
-    const int32_t row = ci < c ? s.cid[ci] : -1;
-    const float m = eng.measure(rows, row);
-    if (leader && ci < c) s.beam.tmp[ci] = make_key(m, row);
-  }
+  score_keys(eng, rows, c, [&](int i) { return s.cid[i]; }, s.beam.tmp);
   wave_lds_sync();
   const uint64_t key = l < c ? s.beam.tmp[l] : kNoKey;
   wave_lds_sync();
@@ -66,42 +57,39 @@ __device__ __forceinline__ void score_and_merge(const Engine<DT, G> &eng, const 
 }
 
 // Add the out-neighbours of point v to the beam (ids seen before are skipped).
-template <int DT, int G>
-__device__ __forceinline__ void expand(const Engine<DT, G> &eng, const SearchParams &p, Lds &s,
-                                       int32_t v) {
-  const int dg = min(p.deg[v], p.R);
+template <class E>
+__device__ __forceinline__ void expand(const E &eng, const SearchParams &p, Lds &s, int32_t v) {
   const int32_t *row = p.adj + (int64_t)v * p.R;
+  // the degree and the first 64 entries of the row are loaded together (the
+  // row always has R entries), so the expansion costs one memory round trip
+  const int e_first = lane_id();
+  const int32_t nb_first = e_first < p.R ? row[e_first] : -1;
+  const int dg = min(p.deg[v], p.R);
   s.n_exp += 1;
   s.n_ids += dg;
   for (int e0 = 0; e0 < dg; e0 += kWave) {
     const int e = e0 + lane_id();
-    int32_t nb = e < dg ? row[e] : -1;
+    int32_t nb = e < dg ? (e0 == 0 ? nb_first : row[e]) : -1;
     if (nb >= p.n) nb = -1;  // ids outside the point set are ignored
     if (nb >= 0 && !s.hash.insert(nb)) nb = -1;
-    score_and_merge<DT, G>(eng, p.rows, s, nb);
+    score_and_merge(eng, p.rows, s, nb);
   }
 }
 
 // Re-score the first r beam entries from float32 rows and sort them (into beam.a).
-template <int G>
+template <int SR>
 __device__ __forceinline__ void rerank_beam(const SearchParams &p, Lds &s, int32_t qid, int r) {
-  constexpr int NPL = Engine32<G>::NPL;
-  Engine32<G> e32;
+  Engine32<SR> e32;
   e32.load_query(p.rows, qid);
-  const int l = lane_id();
-  for (int base = 0; base < r; base += NPL) {
-    const int ci = base + l / G;
-    const int32_t row = ci < r ? key_id(s.beam.a[ci]) : -1;
-    const float m = e32.measure(p.rows, row);
-    if ((l % G) == 0 && ci < r) s.beam.b[ci] = make_key(m, row);
-  }
+  const uint64_t *a = s.beam.a;
+  score_keys(e32, p.rows, r, [&](int i) { return key_id(a[i]); }, s.beam.b);
   wave_lds_sync();
   lds_rank_sort(s.beam.b, s.beam.a, r);
 }
 
 }  // namespace
 
-template <int DT, int G, int MODE>
+template <int DT, int S, int MODE>
 __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
   extern __shared__ __align__(16) uint8_t smem[];
   Lds s = carve(smem, p.L, p.hbits);
@@ -118,7 +106,8 @@ __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
     return;
   }
 
-  Engine<DT, G> eng;
+  Engine<DT, S> eng;
+  constexpr int SR = RerankShape<DT, S>::v;
   for (;;) {
     const int it = next_item(p.head);
     if (it >= count) break;
@@ -136,11 +125,11 @@ __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
     bool self_start = (MODE != MODE_BUILD);
     for (int s0 = 0; s0 < p.nstarts && !self_start; s0 += kWave)
       self_start = ballot(s0 + l < p.nstarts && p.starts[s0 + l] == qid) != 0;
-    if (self_start) expand<DT, G>(eng, p, s, qid);
+    if (self_start) expand(eng, p, s, qid);
     for (int s0 = 0; s0 < p.nstarts; s0 += kWave) {
       int32_t id = s0 + l < p.nstarts ? p.starts[s0 + l] : -1;
       if (id >= 0 && !s.hash.insert(id)) id = -1;
-      score_and_merge<DT, G>(eng, p.rows, s, id);
+      score_and_merge(eng, p.rows, s, id);
     }
 
     int nv = 0;
@@ -155,7 +144,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
       }
       ++nv;
       wave_lds_sync();
-      expand<DT, G>(eng, p, s, key_id(kj));
+      expand(eng, p, s, key_id(kj));
     }
 
     const int m = s.beam.m;
@@ -166,7 +155,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
       int mm = m;
       if (kNeedRerank && m > 0) {
         mm = min(m, p.rerank);
-        rerank_beam<G>(p, s, qid, mm);
+        rerank_beam<SR>(p, s, qid, mm);
         n_rerank = mm;
       }
       if (mm < p.k) {
@@ -191,7 +180,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
     } else {  // MODE_DEP
       int c = min(m, p.kdep);
       if (kNeedRerank && c > 0) {
-        rerank_beam<G>(p, s, qid, c);
+        rerank_beam<SR>(p, s, qid, c);
         n_rerank = c;
       }
       const uint64_t ki = p.key_in[qid];
@@ -227,43 +216,31 @@ size_t search_lds_bytes(int L, int hbits) {
   return 8 * (2 * (size_t)L + 64) + 4 * 64 + 2 * Lp + 4 * ((size_t)1 << hbits);
 }
 
-template <int DT, int G>
+template <int DT, int S>
 static hipError_t launch_search_t(const SearchParams &p, int grid, hipStream_t st) {
+  if constexpr (S > max_shape(DT)) {
+    return hipErrorInvalidValue;
+  } else {
   const size_t lds = search_lds_bytes(p.L, p.hbits);
   switch (p.mode) {
     case MODE_KNN:
-      hipLaunchKernelGGL((search_kernel<DT, G, MODE_KNN>), dim3(grid), dim3(64), lds, st, p);
+      hipLaunchKernelGGL((search_kernel<DT, S, MODE_KNN>), dim3(grid), dim3(64), lds, st, p);
       break;
     case MODE_DEP:
-      hipLaunchKernelGGL((search_kernel<DT, G, MODE_DEP>), dim3(grid), dim3(64), lds, st, p);
+      hipLaunchKernelGGL((search_kernel<DT, S, MODE_DEP>), dim3(grid), dim3(64), lds, st, p);
       break;
     case MODE_BUILD:
-      hipLaunchKernelGGL((search_kernel<DT, G, MODE_BUILD>), dim3(grid), dim3(64), lds, st, p);
+      hipLaunchKernelGGL((search_kernel<DT, S, MODE_BUILD>), dim3(grid), dim3(64), lds, st, p);
       break;
     default:
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+  }
 }
 
-#define PECANN_DISPATCH_G(FN, DT, ...)                      \
-  switch (G) {                                              \
-    case 4: return FN<DT, 4>(__VA_ARGS__);                  \
-    case 8: return FN<DT, 8>(__VA_ARGS__);                  \
-    case 16: return FN<DT, 16>(__VA_ARGS__);                \
-    case 32: return FN<DT, 32>(__VA_ARGS__);                \
-    case 64: return FN<DT, 64>(__VA_ARGS__);                \
-    default: return hipErrorInvalidValue;                   \
-  }
-
-hipError_t launch_search(int32_t dt, int G, const SearchParams &p, int grid, hipStream_t st) {
-  switch (dt) {
-    case PECANN_F32: PECANN_DISPATCH_G(launch_search_t, PECANN_F32, p, grid, st)
-    case PECANN_U8: PECANN_DISPATCH_G(launch_search_t, PECANN_U8, p, grid, st)
-    case PECANN_BF16: PECANN_DISPATCH_G(launch_search_t, PECANN_BF16, p, grid, st)
-    case PECANN_FP8E4M3: PECANN_DISPATCH_G(launch_search_t, PECANN_FP8E4M3, p, grid, st)
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_search(int32_t dt, int S, const SearchParams &p, int grid, hipStream_t st) {
+  PECANN_DISPATCH_SHAPE(launch_search_t, dt, S, p, grid, st)
 }
 
 }  // namespace pecann
