@@ -59,6 +59,10 @@ WORKLOADS = {
     4: dict(name="1280000x1024 float32 unit vectors, 1000 clusters (mean cosine 0.7), cosine",
             metric="cosine", R=64, L=200, alpha=1.2, k=10, n_c=1000, L_search=64, L_d=64,
             search="fp8", rho_min=0.0),
+    5: dict(name="64 independent instances, n_i log-uniform in [2000, 200000], 384-d Gaussian "
+                 "mixtures of 5-200 clusters, k_i in {5, 10, 20}, L2, one batched call per step",
+            metric="l2", R=64, L=128, alpha=1.2, k=20, n_c=None, L_search=64, L_d=64,
+            search="bf16", rho_min=0.0),
 }
 
 
@@ -67,7 +71,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4])
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5])
     ap.add_argument("--search", default=None, choices=["f32", "u8", "bf16", "fp8"])
     ap.add_argument("--mode", default="anns", choices=["anns", "exact"])
     ap.add_argument("--L-search", type=int, default=None)
@@ -128,39 +132,50 @@ def cpu_baseline(X, ref, sample_size):
 
 def recall_from_sample(idx, dist, sample, ref_dist, k):
     """Tie-tolerant recall: a returned point counts when its reported float32 distance
-    is within the oracle's k-th distance (duplicates and the query itself never count)."""
+    is within the oracle's k-th distance (duplicates and the query itself never count).
+    k may be one value or one per sample row."""
     hits = 0
+    ks = np.broadcast_to(np.asarray(k), (len(sample),))
     for t, q in enumerate(sample):
-        thr = np.float32(ref_dist[t, k - 1])
+        kt = int(ks[t])
+        thr = np.float32(ref_dist[t, kt - 1])
         seen = set()
-        for j, dj in zip(idx[t], dist[t]):
+        for j, dj in zip(idx[t][:kt], dist[t][:kt]):
             j = int(j)
             if j < 0 or j == q or j in seen:
                 continue
             seen.add(j)
             hits += float(dj) <= thr
-    return hits / (k * len(sample))
+    return hits / float(ks.sum())
 
 
 class Pipeline:
     """Buffers and launch sequence of one DPC step on a resident dataset."""
 
-    def __init__(self, x, wl, search, mode, args, perm):
+    def __init__(self, x, wl, search, mode, args, perm, inst=None):
         import torch
         from paper_2312_03940_amd import pecann
         self.torch, self.pecann = torch, pecann
         self.x, self.wl, self.mode, self.args, self.perm = x, wl, mode, args, perm
+        self.inst = inst  # pecann.Instances: one batched call per step covers them all
         dev = x.device
         self.ds = ds = pecann.Dataset(x, wl["metric"], search)
         n, k, R = ds.n, wl["k"], wl["R"]
         self.Ls = args.L_search or wl["L_search"]
         self.Ld = args.L_d or wl["L_d"]
         self.rerank = args.rerank or self.Ls
-        ws_anns = pecann.workspace_bytes(ds, k, self.Ls, args.kdep_cap, R, wl["L"], wl["alpha"],
-                                         args.num_starts, args.max_batch)
-        lib = pecann.load()
-        st = ds.struct
-        ws_exact = lib.pecann_knn_density_workspace_size(ctypes.byref(st), k, self.Ls, 1)
+        if inst is None:
+            ws_anns = pecann.workspace_bytes(ds, k, self.Ls, args.kdep_cap, R, wl["L"], wl["alpha"],
+                                             args.num_starts, args.max_batch)
+            lib = pecann.load()
+            st = ds.struct
+            ws_exact = lib.pecann_knn_density_workspace_size(ctypes.byref(st), k, self.Ls, 1)
+        else:
+            ws_anns = pecann.workspace_bytes_batched(ds, inst, k, self.Ls, args.kdep_cap, R, wl["L"],
+                                                     wl["alpha"], args.num_starts, args.max_batch)
+            ws_exact = pecann.workspace_bytes_batched(ds, inst, k, self.Ls, args.kdep_cap, R, wl["L"],
+                                                      wl["alpha"], args.num_starts, args.max_batch,
+                                                      exact=True)
         self.ws = torch.empty(max(ws_anns, ws_exact), dtype=torch.uint8, device=dev)
         self.g_out = (torch.empty((n, R), dtype=torch.int32, device=dev),
                       torch.empty(n, dtype=torch.int32, device=dev))
@@ -176,7 +191,7 @@ class Pipeline:
         self.phases = ["prepare", "build", "knn_density", "dependent", "cluster"]
 
     def step(self, ev=None, bcnt=None, kcnt=None):
-        p, wl, a = self.pecann, self.wl, self.args
+        p, wl, a, inst = self.pecann, self.wl, self.args, self.inst
         if ev:
             ev[0].record()
         self.ds.prepare(self.x)
@@ -184,31 +199,58 @@ class Pipeline:
             ev[1].record()
         adj = deg = None
         if self.mode == "anns":
-            adj, deg = p.build_graph(self.ds, wl["R"], wl["L"], wl["alpha"], num_starts=a.num_starts,
-                                     perm=self.perm, max_batch=a.max_batch, ws=self.ws,
-                                     out=self.g_out, counters=bcnt)
+            if inst is None:
+                adj, deg = p.build_graph(self.ds, wl["R"], wl["L"], wl["alpha"],
+                                         num_starts=a.num_starts, perm=self.perm,
+                                         max_batch=a.max_batch, ws=self.ws, out=self.g_out,
+                                         counters=bcnt)
+            else:
+                adj, deg = p.build_graph_batched(self.ds, inst, wl["R"], wl["L"], wl["alpha"],
+                                                 num_starts=a.num_starts, perm=self.perm,
+                                                 max_batch=a.max_batch, ws=self.ws, out=self.g_out,
+                                                 counters=bcnt)
         if ev:
             ev[2].record()
-        idx, dist, rho, key = p.knn_density(self.ds, wl["k"], adj, deg, L_search=self.Ls,
-                                            rerank=self.rerank, ws=self.ws, out=self.k_out,
-                                            counters=kcnt)
+        if inst is None:
+            idx, dist, rho, key = p.knn_density(self.ds, wl["k"], adj, deg, L_search=self.Ls,
+                                                rerank=self.rerank, ws=self.ws, out=self.k_out,
+                                                counters=kcnt)
+        else:
+            idx, dist, rho, key = p.knn_density_batched(self.ds, inst, wl["k"], adj, deg,
+                                                        L_search=self.Ls, rerank=self.rerank,
+                                                        ws=self.ws, out=self.k_out, counters=kcnt)
         if ev:
             ev[3].record()
-        dep, delta, _ = p.dependent_search(self.ds, key, idx, dist, adj, deg, L_d=self.Ld,
-                                           L_search=self.Ls, threshold=a.threshold,
-                                           kdep_cap=a.kdep_cap, ws=self.ws, out=self.d_out)
+        if inst is None:
+            dep, delta, _ = p.dependent_search(self.ds, key, idx, dist, adj, deg, L_d=self.Ld,
+                                               L_search=self.Ls, threshold=a.threshold,
+                                               kdep_cap=a.kdep_cap, ws=self.ws, out=self.d_out)
+        else:
+            dep, delta, _ = p.dependent_search_batched(self.ds, inst, key, idx, dist, adj, deg,
+                                                       L_d=self.Ld, L_search=self.Ls,
+                                                       threshold=a.threshold, kdep_cap=a.kdep_cap,
+                                                       ws=self.ws, out=self.d_out)
         if ev:
             ev[4].record()
-        p.cluster(rho, dep, delta, n_c=wl["n_c"], rho_min=wl["rho_min"], ws=self.ws,
-                  out=self.c_out)
+        self._cluster(wl["rho_min"])
         if ev:
             ev[5].record()
+
+    def _cluster(self, rho_min, out=None):
+        p, rho, dep, delta = self.pecann, self.k_out[2], self.d_out[0], self.d_out[1]
+        out = self.c_out if out is None else out
+        if self.inst is None:
+            return p.cluster(rho, dep, delta, n_c=self.wl["n_c"], rho_min=rho_min, ws=self.ws, out=out)
+        return p.cluster_batched(self.inst, rho, dep, delta, rho_min=rho_min, ws=self.ws, out=out)
 
     def labels_at(self, rho_min):
         """Labels of the last step's densities and dependents under another noise cutoff
         (outside any timed region)."""
-        rho, dep, delta = self.k_out[2], self.d_out[0], self.d_out[1]
-        lab, _ = self.pecann.cluster(rho, dep, delta, n_c=self.wl["n_c"], rho_min=rho_min, ws=self.ws)
+        torch = self.torch
+        n = self.ds.n
+        out = (torch.empty(n, dtype=torch.int32, device=self.x.device),
+               torch.empty(n, dtype=torch.uint8, device=self.x.device))
+        lab, _ = self._cluster(rho_min, out)
         return lab.cpu().numpy()
 
     def run(self, steps, warmup):
@@ -246,12 +288,16 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def measure(x, wl, search, mode, args, perm, steps, warmup, ref=None, sample=None):
+def ari_per_instance(a, b, off):
+    return [ari(a[off[t]:off[t + 1]], b[off[t]:off[t + 1]]) for t in range(len(off) - 1)]
+
+
+def measure(x, wl, search, mode, args, perm, steps, warmup, ref=None, sample=None, inst=None):
     """Time `steps` DPC steps and evaluate the quality gates.  `ref` holds the
     reference labels under the workload's noise cutoff ("labels"), and optionally
     under rho_min = 0 ("labels0") with the generator's component ids ("y")."""
     log(f"measure {search}/{mode}: {warmup} warm-up + {steps} timed steps")
-    pl = Pipeline(x, wl, search, mode, args, perm)
+    pl = Pipeline(x, wl, search, mode, args, perm, inst)
     n = pl.ds.n
     wall, ph, kprof = pl.run(steps, warmup)
     rec = {"search_rows": search, "mode": mode, "ms_per_step": round(wall * 1e3 / steps, 3),
@@ -262,7 +308,12 @@ def measure(x, wl, search, mode, args, perm, steps, warmup, ref=None, sample=Non
                           for f, v in sorted(kprof.items(), key=lambda t: -t[1][1])}}
     q = {}
     labels = pl.c_out[0].cpu().numpy()
-    if ref is not None:
+    if ref is not None and inst is not None:
+        per = ari_per_instance(labels, ref["labels"], inst.offsets)
+        q["ari_vs_reference"] = float(min(per))  # the gate: every instance
+        q["ari_mean"] = float(np.mean(per))
+        q["instances_below_0.95"] = int(sum(v < 0.95 for v in per))
+    elif ref is not None:
         q["ari_vs_reference"] = ari(labels, ref["labels"])
         if wl["rho_min"] > 0:
             q["rho_min"] = wl["rho_min"]
@@ -278,9 +329,9 @@ def measure(x, wl, search, mode, args, perm, steps, warmup, ref=None, sample=Non
     if sample is not None:
         s = sample["sample"]
         k = wl["k"]
-        q[f"recall_at_{k}"] = recall_from_sample(pl.k_out[0].cpu().numpy()[s],
-                                                 pl.k_out[1].cpu().numpy()[s], s,
-                                                 sample["knn_dist"], k)
+        name = f"recall_at_{k}" if inst is None else "recall_at_k_i"
+        q[name] = recall_from_sample(pl.k_out[0].cpu().numpy()[s], pl.k_out[1].cpu().numpy()[s], s,
+                                     sample["knn_dist"], sample.get("k", k))
     if q:
         rk = [v for key, v in q.items() if key.startswith("recall")]
         q["gates_met"] = bool(q.get("ari_vs_reference", 1.0) >= 0.95 and all(v >= 0.95 for v in rk))
@@ -342,12 +393,22 @@ def main():
     dev = torch.device("cuda:0")
     wl = WORKLOADS[args.config]
     search = args.search or wl["search"]
-    gen = {2: datagen.config2, 3: datagen.config3, 4: datagen.config4}[args.config]
     log(f"generating workload {args.config}")
-    X, Y = gen()
+    inst = None
+    if args.config == 5:
+        from paper_2312_03940_amd import pecann
+        X, Y, off, ks, ncs = datagen.config5()
+        inst = pecann.Instances(off, k=ks, n_c=ncs)
+        # each instance's own insertion order, in its own index range
+        perm_np = np.concatenate([datagen.permutation(int(off[t + 1] - off[t]), 20231205 + t) + off[t]
+                                  for t in range(len(off) - 1)]).astype(np.int32)
+    else:
+        gen = {2: datagen.config2, 3: datagen.config3, 4: datagen.config4}[args.config]
+        X, Y = gen()
+        perm_np = datagen.permutation(X.shape[0], 20231205)
     n, d = X.shape
     x = torch.from_numpy(X).to(dev)
-    perm = torch.from_numpy(datagen.permutation(n, 20231205)).to(dev)
+    perm = torch.from_numpy(perm_np).to(dev)
     if args.copy_probe_mb:
         src = torch.empty(args.copy_probe_mb << 18, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -364,16 +425,18 @@ def main():
         ref_lab = {"labels": ref["labels"]}
         ref_kind = "oracle exact DPC (tests/golden/c2_reference.npz)"
         sample = {"sample": ref["sample"], "knn_dist": ref["sample_knn_dist"]}
-    elif args.config in (3, 4):
+    elif args.config in (3, 4, 5):
         sp = os.path.join(GOLDEN, f"c{args.config}_sample.npz")
         if os.path.exists(sp):
             z = np.load(sp)
             sample = {"sample": z["sample"], "knn_dist": z["knn_dist"]}
+            if args.config == 5:
+                sample["k"] = z["k"]
         # ARI reference: the GPU exact mode on float32 rows (bit-exact with the oracle in
         # the GPU tests), computed once here, outside any timed region
         log("reference: GPU exact DPC on float32 rows")
         t0 = time.perf_counter()
-        rp = Pipeline(x, wl, "f32", "exact", args, perm)
+        rp = Pipeline(x, wl, "f32", "exact", args, perm, inst)
         rp.step()
         torch.cuda.synchronize()
         ref_lab = {"labels": rp.c_out[0].cpu().numpy()}
@@ -386,7 +449,7 @@ def main():
         torch.cuda.empty_cache()
 
     rec, pl, kprof = measure(x, wl, search, args.mode, args, perm, args.steps, args.warmup,
-                             ref_lab, sample)
+                             ref_lab, sample, inst)
     if ref_kind:
         rec["quality"]["reference"] = ref_kind
     out = {
@@ -397,11 +460,17 @@ def main():
         "config": {"workload": wl["name"], "n": n, "d": d, "search_rows": search,
                    "mode": args.mode, "R": wl["R"], "L_build": wl["L"], "alpha": wl["alpha"],
                    "build_passes": 2, "num_starts": args.num_starts,
-                   "max_batch": args.max_batch or max(n // 50, 8192), "k": wl["k"],
+                   "max_batch": args.max_batch or (max(n // 50, 8192) if inst is None
+                                                   else "per instance: max(n_i / 50, 8192)"),
+                   "k": wl["k"] if inst is None else "per instance (max 20)",
                    "L_search": pl.Ls, "rerank": pl.rerank, "L_d": pl.Ld,
-                   "threshold": args.threshold, "kdep_cap": args.kdep_cap, "n_c": wl["n_c"],
+                   "threshold": args.threshold, "kdep_cap": args.kdep_cap,
+                   "n_c": wl["n_c"] if inst is None else "per instance (its cluster count)",
                    "rho_min": wl["rho_min"],
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   **({} if inst is None else {"instances": inst.count,
+                                               "instance_sizes": [int(inst.offsets[t + 1] - inst.offsets[t])
+                                                                  for t in range(inst.count)]})},
         "knn_queries_per_s": rec["knn_queries_per_s"],
         "phases_ms": rec["phases_ms"],
         "quality": rec["quality"],
@@ -416,12 +485,12 @@ def main():
     if not args.no_variants:
         variants = {}
         alt = {2: [("u8", "anns"), ("u8", "exact"), ("f32", "exact")],
-               3: [("f32", "anns")], 4: [("f32", "anns")]}[args.config]
+               3: [("f32", "anns")], 4: [("f32", "anns")], 5: [("f32", "anns")]}[args.config]
         for vs, vm in alt:
             if (vs, vm) == (search, args.mode):
                 continue
             vsteps = args.variant_steps or (3 if args.config == 2 else 1)
-            r, p2, _ = measure(x, wl, vs, vm, args, perm, vsteps, 1, ref_lab, sample)
+            r, p2, _ = measure(x, wl, vs, vm, args, perm, vsteps, 1, ref_lab, sample, inst)
             variants[f"{vs}_{vm}"] = {key: r[key] for key in ("value", "ms_per_step", "phases_ms",
                                                               "quality", "knn_queries_per_s")}
             del p2

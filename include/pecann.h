@@ -246,6 +246,91 @@ pecann_status pecann_cluster(int64_t n, const float *rho, const int32_t *dep,
                              uint8_t *is_center, void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Batches of independent instances (many clustering problems per call).
+ *
+ * A prepared point set may hold several independent instances: instance t
+ * owns the points [offsets[t], offsets[t+1]).  The *_batched calls run each
+ * step on every instance at once (one launch per step covers all of them)
+ * and nothing crosses instances: graph edges, neighbours, dependent points,
+ * centers and labels stay inside each instance, with global indices.  Each
+ * instance's results equal those of the single-instance call applied to that
+ * instance alone (its rows, its insertion order, its k and n_c).
+ *   num_instances  1 <= num_instances <= 4096
+ *   offsets        host, num_instances + 1 values: offsets[0] = 0, ascending,
+ *                  offsets[num_instances] = n, every instance >= 2 points
+ *   k              host, k of each instance (NULL: the call's k for all);
+ *                  1 <= k[t] <= min(n_t - 1, k_max)
+ *   n_c            host, center count of each instance in product mode (NULL:
+ *                  the call's n_c for all); 1 <= n_c[t] <= n_t
+ * The host arrays are read during the call only.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t num_instances;
+  int32_t reserved;        /* must be 0 */
+  const int64_t *offsets;
+  const int32_t *k;
+  const int32_t *n_c;
+} pecann_instances;
+
+/* pecann_build_graph for every instance.  perm (device, n int32, may be NULL):
+ * perm[offsets[t] .. offsets[t+1]) is instance t's insertion order (global
+ * indices of its own points); NULL: a seeded shuffle of each instance (seed
+ * + t for instance t).  Each instance keeps its own batch schedule and cap
+ * (max_batch, or max(n_t / 50, 8192)); a launch covers the next batch of every
+ * instance, so the workspace grows with the sum of the caps. */
+size_t pecann_build_graph_batched_workspace_size(const pecann_dataset *ds,
+                                                 const pecann_build_params *bp,
+                                                 const pecann_instances *inst);
+pecann_status pecann_build_graph_batched(const pecann_dataset *ds, const pecann_build_params *bp,
+                                         const pecann_instances *inst, const int32_t *perm,
+                                         uint64_t seed, int32_t *adj, int32_t *deg,
+                                         uint64_t *counters, void *ws, size_t ws_bytes,
+                                         void *stream);
+
+/* pecann_knn_density for every instance.  Rows of knn_idx / knn_dist have
+ * stride k_max: row i holds point i's k[t] neighbours, then -1 / +inf.
+ * L_search >= k_max, rerank in [k_max, L_search].  Without a graph each
+ * instance is searched exactly (the matrix-core scan for instances of 4096
+ * points or more). */
+size_t pecann_knn_density_batched_workspace_size(const pecann_dataset *ds,
+                                                 const pecann_instances *inst, int32_t k_max,
+                                                 int32_t L_search, int32_t exact);
+pecann_status pecann_knn_density_batched(const pecann_dataset *ds, const pecann_instances *inst,
+                                         const int32_t *adj, const int32_t *deg, int32_t R,
+                                         int32_t k_max, int32_t L_search, int32_t rerank,
+                                         int32_t *knn_idx, float *knn_dist, float *rho,
+                                         uint64_t *rank_key, uint64_t *counters, void *ws,
+                                         size_t ws_bytes, void *stream);
+
+/* pecann_dependent_search for every instance (kNN rows of stride k_max as
+ * written by pecann_knn_density_batched).  The densest point of each instance
+ * has dep = -1; an instance stops doubling on its own once at most
+ * `threshold` of its points are unfinished or k_dep exceeds
+ * min(kdep_cap, n_t - 1); the final brute force scans the point's instance.
+ * stats counts points over all instances. */
+size_t pecann_dependent_search_batched_workspace_size(const pecann_dataset *ds,
+                                                      const pecann_instances *inst,
+                                                      int32_t kdep_cap, int32_t L_search);
+pecann_status pecann_dependent_search_batched(const pecann_dataset *ds,
+                                              const pecann_instances *inst, const int32_t *adj,
+                                              const int32_t *deg, int32_t R,
+                                              const uint64_t *rank_key, const int32_t *knn_idx,
+                                              const float *knn_dist, int32_t k_max, int32_t L_d,
+                                              int32_t L_search, int32_t threshold,
+                                              int32_t kdep_cap, int32_t *dep, float *delta,
+                                              int32_t *stats, void *ws, size_t ws_bytes,
+                                              void *stream);
+
+/* pecann_cluster for every instance: the n_c[t] largest gamma of instance t
+ * become its centers. */
+size_t pecann_cluster_batched_workspace_size(int64_t n, const pecann_instances *inst);
+pecann_status pecann_cluster_batched(int64_t n, const pecann_instances *inst, const float *rho,
+                                     const int32_t *dep, const float *delta,
+                                     int32_t center_mode, int32_t n_c, float delta_min,
+                                     float rho_min, int32_t *labels, uint8_t *is_center,
+                                     void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing (host-side instrumentation, off by default).  While enabled,
  * every kernel the library launches from this thread is bracketed by a pair of
  * HIP events recorded on the launch stream, filed under its kernel family

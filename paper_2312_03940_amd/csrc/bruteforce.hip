@@ -1,7 +1,7 @@
 // Exact (brute-force) kernels, float32 (or exact uint8) distances:
 //   K1 bf_knn  -- exact k nearest neighbours of a list of queries over all points
-//                 (the paper's BruteForce index, Sec. 4.1; also the fallback when
-//                 a graph search returns fewer than k points);
+//                 of their instance (the paper's BruteForce index, Sec. 4.1; also
+//                 the fallback when a graph search returns fewer than k points);
 //   K7 bf_dep  -- DPBruteForce(x_i, P) of Alg. 3 for the unfinished points: the
 //                 closest point of strictly smaller rank key, split into chunks
 //                 of candidates whose partial argmins meet in a 64-bit atomic min.
@@ -14,8 +14,7 @@ namespace pecann {
 template <int DT, int S>
 __global__ __launch_bounds__(64) void bf_knn_kernel(BfKnnParams p) {
   extern __shared__ __align__(16) uint8_t smem[];
-  const int k = p.k;
-  const int kp = (k + 15) & ~15;
+  const int kp = (p.k + 15) & ~15;  // p.k: the largest k of any instance
   SortedList top;
   top.a = (uint64_t *)smem;
   top.b = top.a + kp;
@@ -23,7 +22,6 @@ __global__ __launch_bounds__(64) void bf_knn_kernel(BfKnnParams p) {
   uint64_t *kb = top.tmp + 64;  // keys of the current 64 candidates
   top.fa = (uint8_t *)(kb + 64);
   top.fb = top.fa + kp;
-  top.cap = k;
   ExactEngine<DT, S> eng;
   const int l = lane_id();
   const int count = p.item_count ? *p.item_count : p.nitems;
@@ -31,22 +29,28 @@ __global__ __launch_bounds__(64) void bf_knn_kernel(BfKnnParams p) {
     const int it = next_item(p.head);
     if (it >= count) break;
     const int32_t qid = p.items ? p.items[it] : it;
+    const int ti = find_instance(p.inst, qid);
+    const int32_t lo = (int32_t)p.inst.off[ti], hi = (int32_t)p.inst.off[ti + 1];
+    if (hi - lo >= p.skip_from) continue;  // searched by another path
+    const int k = p.inst.k[ti];
+    top.cap = k;
     eng.load_query(p.rows, qid);
     top.m = 0;
     wave_lds_sync();
-    for (int base = 0; base < p.n; base += kWave) {
-      const int c = min(kWave, p.n - base);
+    for (int base = lo; base < hi; base += kWave) {
+      const int c = min(kWave, hi - base);
       score_keys(eng, p.rows, c, [&](int i) { return base + i == qid ? -1 : base + i; }, kb);
       wave_lds_sync();
       const uint64_t key = l < c ? kb[l] : kNoKey;
       wave_lds_sync();
       top.merge(key);
     }
-    const int64_t o = (int64_t)qid * k;
-    for (int t = l; t < k; t += kWave) {
-      const uint64_t kt = top.a[t];
-      p.knn_idx[o + t] = key_id(kt);
-      p.knn_dist[o + t] = measure_to_dist(key_measure(kt), p.rows.metric);
+    const int64_t o = (int64_t)qid * p.kstride;
+    for (int t = l; t < p.kstride; t += kWave) {
+      const uint64_t kt = t < k ? top.a[t] : kNoKey;
+      p.knn_idx[o + t] = t < k ? key_id(kt) : -1;
+      p.knn_dist[o + t] = t < k ? measure_to_dist(key_measure(kt), p.rows.metric)
+                                : __int_as_float(0x7f800000);
     }
     if (l == 0) {
       const uint64_t kk = top.a[k - 1];
@@ -76,10 +80,13 @@ __global__ __launch_bounds__(64) void bf_dep_kernel(BfDepParams p) {
     const int u = it / p.nchunks;
     const int ch = it - u * p.nchunks;
     const int32_t qid = p.ulist[u];
+    const int ti = find_instance(p.inst, qid);
+    const int32_t lo = (int32_t)p.inst.off[ti], hi = (int32_t)p.inst.off[ti + 1];
+    const int j0 = lo + ch * p.chunk;
+    if (j0 >= hi) continue;  // beyond this instance
+    const int j1 = min(hi, j0 + p.chunk);
     const uint64_t ki = p.key[qid];
     eng.load_query(p.rows, qid);
-    const int j0 = ch * p.chunk;
-    const int j1 = min(p.n, j0 + p.chunk);
     uint64_t best = kNoKey;
     for (int base = j0; base < j1; base += kWave) {
       const int j = base + l;

@@ -109,6 +109,18 @@ __device__ __forceinline__ int next_item(int32_t *head) {
   return __shfl(v, 0);
 }
 
+// Instance of point i: the t with off[t] <= i < off[t+1] (0 for a single
+// instance or no table).
+__device__ __forceinline__ int find_instance(const InstTable &it, int64_t i) {
+  if (it.count <= 1) return 0;
+  int lo = 0, hi = it.count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (it.off[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 // ---------------------------------------------------------------------------
 // Row formats.  Rows are read in 16-byte chunks; EPC = elements per chunk.
 // ---------------------------------------------------------------------------

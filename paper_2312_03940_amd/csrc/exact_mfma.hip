@@ -229,19 +229,22 @@ __global__ __launch_bounds__(64) void exact_rerank_kernel(ExactMfmaParams p, flo
       ok = key_measure(top.a[k - 1]) < t - e;
     }
     if (ok) {
-      const int64_t o = (int64_t)q * k;
-      for (int t = l; t < k; t += kWave) {
-        const uint64_t kt = top.a[t];
-        p.knn_idx[o + t] = key_id(kt);
-        p.knn_dist[o + t] = measure_to_dist(key_measure(kt), p.rows.metric);
+      // rows, outputs and ids of this call are the instance's: global index =
+      // base + local index
+      const int64_t o = (int64_t)q * p.kstride;
+      for (int t = l; t < p.kstride; t += kWave) {
+        const uint64_t kt = t < k ? top.a[t] : kNoKey;
+        p.knn_idx[o + t] = t < k ? key_id(kt) + p.base : -1;
+        p.knn_dist[o + t] = t < k ? measure_to_dist(key_measure(kt), p.rows.metric)
+                                  : __int_as_float(0x7f800000);
       }
       if (l == 0) {
         const uint64_t kk = top.a[k - 1];
         p.rho[q] = 1.0f / measure_to_dist(key_measure(kk), p.rows.metric);
-        p.rank_key[q] = (kk & 0xffffffff00000000ull) | (uint32_t)q;
+        p.rank_key[q] = (kk & 0xffffffff00000000ull) | (uint32_t)(q + p.base);
       }
     } else if (l == 0) {
-      p.fb_list[atomicAdd(p.fb_count, 1)] = q;
+      p.fb_list[atomicAdd(p.fb_count, 1)] = q + p.base;
     }
     wave_lds_sync();
   }

@@ -34,6 +34,15 @@ struct RowsDesc {  // host copy of the row description (mirrors Rows)
 
 enum SearchMode { MODE_KNN = 0, MODE_DEP = 1, MODE_BUILD = 2 };
 
+// Independent instances over one point set (device tables): instance t owns
+// points [off[t], off[t+1]); k[t] and nc[t] are its kNN size and center count.
+struct InstTable {
+  const int64_t *off;  // [count + 1]
+  const int32_t *k;    // [count]
+  const int32_t *nc;   // [count]
+  int32_t count;
+};
+
 struct SearchParams {
   RowsDesc rows;
   const int32_t *adj;
@@ -46,12 +55,17 @@ struct SearchParams {
   int32_t *head;              // device work-queue head, 0 at launch
   const int32_t *starts;      // start points besides the query itself
   int32_t nstarts;
+  const int32_t *item_sbase;  // per item: its start points are starts[item_sbase[it] ..]
+  const int32_t *item_ns;     // per item: ... and there are item_ns[it] of them
+                              // (both nullptr: starts[0 .. nstarts) for every item)
+  InstTable inst;             // instance of each query (k per instance, round limits)
   int32_t L;                  // beam width
   int32_t hbits;              // log2 of visited-hash slots
   int32_t mode;
   int32_t rerank;             // entries re-scored in float32 (0: none)
-  // MODE_KNN
+  // MODE_KNN (k: the instance's, kstride: row stride of knn_idx / knn_dist)
   int32_t k;
+  int32_t kstride;
   int32_t *knn_idx;
   float *knn_dist;
   float *rho;
@@ -66,6 +80,9 @@ struct SearchParams {
   int32_t *u_out;
   int32_t *u_out_count;
   int32_t threshold;
+  int32_t kdep_cap;           // per-instance limit min(kdep_cap, n_t - 1) on kdep
+  const int32_t *ucnt_in;     // [instance] unfinished points entering this round
+  int32_t *ucnt_out;          // [instance] unfinished points leaving it
   // MODE_BUILD
   uint64_t *vis;              // [item][vcap] keys of expanded points
   int32_t *vis_count;         // [item] expansions (may exceed vcap)
@@ -78,11 +95,14 @@ struct SearchParams {
 size_t search_lds_bytes(int L, int hbits);
 hipError_t launch_search(int32_t dt, int S, const SearchParams &p, int grid, hipStream_t s);
 
-// Exact (brute-force) kNN over all points for a list of queries.
+// Exact (brute-force) kNN over the query's instance for a list of queries.
 struct BfKnnParams {
   RowsDesc rows;
   int32_t n;
-  int32_t k;
+  int32_t k;                  // k of every query without an instance table
+  int32_t kstride;            // row stride of knn_idx / knn_dist
+  InstTable inst;
+  int32_t skip_from;          // queries of instances with >= skip_from points are skipped
   const int32_t *items;       // nullptr: all points
   const int32_t *item_count;  // nullptr: nitems
   int32_t nitems;
@@ -105,6 +125,7 @@ struct BfDepParams {
   int32_t chunk;
   int32_t nchunks;
   int32_t *head;
+  InstTable inst;             // candidates come from the query's instance
   const uint64_t *key;
   unsigned long long *best;  // [u] packed (measure, index), ~0 at launch
 };
@@ -119,8 +140,7 @@ struct PruneParams {
   int32_t *adj;
   int32_t *deg;
   // forward
-  const int32_t *perm;        // batch point of item t is perm[b0 + t]
-  int32_t b0;
+  const int32_t *items;       // batch point of item t
   int32_t nb;
   const uint64_t *vis;
   const int32_t *vis_count;
@@ -159,9 +179,11 @@ hipError_t launch_prepare(const void *x, int32_t x_dtype, int64_t x_stride, int6
 // candidates of each lane's column stream by matrix-core distance, then an
 // exact (direct-difference) re-score with a rounding-bound check.
 struct ExactMfmaParams {
-  RowsDesc rows;
+  RowsDesc rows;              // one instance's rows (row 0 = global index base)
   int32_t n;
   int32_t k;
+  int32_t kstride;            // row stride of knn_idx / knn_dist
+  int32_t base;               // global index of row 0
   int32_t *cand;               // [n][256] candidate ids of the scan
   float *thr;                  // [n] smallest measure a scan queue dropped (+inf: none)
   float *nmax;                 // [1] largest row norm (device)
@@ -177,28 +199,50 @@ hipError_t launch_exact_mfma(int32_t dt, int S, const ExactMfmaParams &p, hipStr
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 hipError_t launch_identity_perm(int32_t *p, int64_t n, hipStream_t s);
-hipError_t launch_rev_count(const int32_t *adj, const int32_t *deg, const int32_t *perm, int32_t b0,
+hipError_t launch_rev_count(const int32_t *adj, const int32_t *deg, const int32_t *items,
                             int32_t nb, int32_t R, int32_t *rcnt, int32_t *ntargets,
                             int32_t *tlist, int32_t *tidx, int32_t *ticket, hipStream_t s);
 hipError_t launch_rev_alloc(const int32_t *tlist, const int32_t *ntargets, const int32_t *rcnt,
                             int32_t *toff, int32_t *tcnt, int32_t *cursor, int32_t *tord,
                             int32_t *front, int32_t *back, int32_t light, int32_t maxt,
                             hipStream_t s);
-hipError_t launch_rev_scatter(const int32_t *adj, const int32_t *deg, const int32_t *perm,
-                              int32_t b0, int32_t nb, int32_t R, const int32_t *tidx,
+hipError_t launch_rev_scatter(const int32_t *adj, const int32_t *deg, const int32_t *items,
+                              int32_t nb, int32_t R, const int32_t *tidx,
                               const int32_t *toff, const int32_t *ticket, int32_t *seg,
                               hipStream_t s);
-hipError_t launch_min_key(const uint64_t *key, int64_t n, uint64_t *out, hipStream_t s);
-hipError_t launch_dep_in_knn(int64_t n, int32_t k, const uint64_t *key, const uint64_t *minkey,
-                             const int32_t *knn_idx, const float *knn_dist, int32_t *dep,
-                             float *delta, int32_t *ulist, int32_t *ucount, hipStream_t s);
+// Smallest rank key of each instance (one workgroup per instance).
+hipError_t launch_min_key(const uint64_t *key, const InstTable &inst, uint64_t *out, hipStream_t s);
+hipError_t launch_dep_in_knn(int64_t n, const InstTable &inst, int32_t kstride, const uint64_t *key,
+                             const uint64_t *minkey, const int32_t *knn_idx, const float *knn_dist,
+                             int32_t *dep, float *delta, int32_t *ulist, int32_t *ucount,
+                             int32_t *ucnt_inst, hipStream_t s);
 hipError_t launch_bf_dep_finalize(const int32_t *ulist, const int32_t *ucount,
                                   const unsigned long long *best, int32_t metric, int32_t *dep,
                                   float *delta, int32_t maxu, hipStream_t s);
 hipError_t launch_copy_count(const int32_t *src, int32_t *dst, int32_t nmax, hipStream_t s);
-hipError_t launch_cluster(int64_t n, const float *rho, const int32_t *dep, const float *delta,
-                          int32_t center_mode, int32_t n_c, float delta_min, float rho_min,
+hipError_t launch_cluster(int64_t n, const InstTable &inst, const float *rho, const int32_t *dep,
+                          const float *delta, int32_t center_mode, float delta_min, float rho_min,
                           int32_t *labels, uint8_t *is_center, uint64_t *gkey, int32_t *flag,
                           hipStream_t s);
+
+// Host tables to device memory through kernel arguments (no host copy, no
+// synchronisation): dst[first + j] = v[j] for j < count <= 64.
+struct I64Chunk { int64_t v[64]; };
+struct I32Chunk { int32_t v[64]; };
+hipError_t launch_put_i64(const I64Chunk &c, int32_t count, int64_t *dst, hipStream_t s);
+hipError_t launch_put_i32(const I32Chunk &c, int32_t count, int32_t *dst, hipStream_t s);
+
+// One build round's work items from ranges of the insertion order: range j
+// puts perm[pbeg[j] ..+ cnt[j]) at items[obeg[j] ..), every one with start
+// points perm[sbase[j] ..+ ns[j]).
+struct RangeChunk {
+  int32_t pbeg[32], cnt[32], obeg[32], sbase[32], ns[32];
+};
+hipError_t launch_gather_items(const RangeChunk &c, int32_t nranges, int32_t maxcnt,
+                               const int32_t *perm, int32_t *items, int32_t *item_sbase,
+                               int32_t *item_ns, hipStream_t s);
+// Appends to list every point whose instance has fewer than `below` points.
+hipError_t launch_small_instance_points(int64_t n, const InstTable &inst, int32_t below,
+                                        int32_t *list, int32_t *count, hipStream_t s);
 
 }  // namespace pecann

@@ -185,14 +185,14 @@ hipError_t launch_identity_perm(int32_t *p, int64_t n, hipStream_t s) {
 //   scatter: source p goes to slot (segment of q) + ticket.
 // Arrival order is not deterministic; the merge sorts each segment by index.
 // ---------------------------------------------------------------------------
-__global__ void rev_count_kernel(const int32_t *adj, const int32_t *deg, const int32_t *perm,
-                                 int32_t b0, int32_t nb, int32_t R, int32_t *rcnt,
+__global__ void rev_count_kernel(const int32_t *adj, const int32_t *deg, const int32_t *items,
+                                 int32_t nb, int32_t R, int32_t *rcnt,
                                  int32_t *ntargets, int32_t *tlist, int32_t *tidx,
                                  int32_t *ticket) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)nb * R) return;
   const int t = (int)(i / R), e = (int)(i % R);
-  const int32_t p = perm[b0 + t];
+  const int32_t p = items[t];
   if (e >= deg[p]) return;
   const int32_t q = adj[(int64_t)p * R + e];
   const int slot = atomicAdd(&rcnt[q], 1);
@@ -219,23 +219,23 @@ __global__ void rev_alloc_kernel(const int32_t *tlist, const int32_t *ntargets, 
   const int pos = c <= light ? atomicAdd(front, 1) : nt - 1 - atomicAdd(back, 1);
   tord[pos] = u;
 }
-__global__ void rev_scatter_kernel(const int32_t *adj, const int32_t *deg, const int32_t *perm,
-                                   int32_t b0, int32_t nb, int32_t R, const int32_t *tidx,
+__global__ void rev_scatter_kernel(const int32_t *adj, const int32_t *deg, const int32_t *items,
+                                   int32_t nb, int32_t R, const int32_t *tidx,
                                    const int32_t *toff, const int32_t *ticket, int32_t *seg) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)nb * R) return;
   const int t = (int)(i / R), e = (int)(i % R);
-  const int32_t p = perm[b0 + t];
+  const int32_t p = items[t];
   if (e >= deg[p]) return;
   const int32_t q = adj[(int64_t)p * R + e];
   seg[toff[tidx[q]] + ticket[i]] = p;
 }
-hipError_t launch_rev_count(const int32_t *adj, const int32_t *deg, const int32_t *perm, int32_t b0,
+hipError_t launch_rev_count(const int32_t *adj, const int32_t *deg, const int32_t *items,
                             int32_t nb, int32_t R, int32_t *rcnt, int32_t *ntargets,
                             int32_t *tlist, int32_t *tidx, int32_t *ticket, hipStream_t s) {
   const int64_t tot = (int64_t)nb * R;
   hipLaunchKernelGGL(rev_count_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, adj,
-                     deg, perm, b0, nb, R, rcnt, ntargets, tlist, tidx, ticket);
+                     deg, items, nb, R, rcnt, ntargets, tlist, tidx, ticket);
   return hipGetLastError();
 }
 hipError_t launch_rev_alloc(const int32_t *tlist, const int32_t *ntargets, const int32_t *rcnt,
@@ -246,23 +246,25 @@ hipError_t launch_rev_alloc(const int32_t *tlist, const int32_t *ntargets, const
                      tlist, ntargets, rcnt, toff, tcnt, cursor, tord, front, back, light, maxt);
   return hipGetLastError();
 }
-hipError_t launch_rev_scatter(const int32_t *adj, const int32_t *deg, const int32_t *perm,
-                              int32_t b0, int32_t nb, int32_t R, const int32_t *tidx,
+hipError_t launch_rev_scatter(const int32_t *adj, const int32_t *deg, const int32_t *items,
+                              int32_t nb, int32_t R, const int32_t *tidx,
                               const int32_t *toff, const int32_t *ticket, int32_t *seg,
                               hipStream_t s) {
   const int64_t tot = (int64_t)nb * R;
   hipLaunchKernelGGL(rev_scatter_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, adj,
-                     deg, perm, b0, nb, R, tidx, toff, ticket, seg);
+                     deg, items, nb, R, tidx, toff, ticket, seg);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Smallest rank key (the densest point), one workgroup.
+// Smallest rank key (the densest point) of each instance, one workgroup each.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void min_key_kernel(const uint64_t *key, int64_t n, uint64_t *out) {
+__global__ __launch_bounds__(1024) void min_key_kernel(const uint64_t *key, InstTable inst, uint64_t *out_all) {
   __shared__ uint64_t part[16];
+  const int64_t lo = inst.off[blockIdx.x], hi = inst.off[blockIdx.x + 1];
+  uint64_t *out = out_all + blockIdx.x;
   uint64_t m = kNoKey;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) m = key[i] < m ? key[i] : m;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 1024) m = key[i] < m ? key[i] : m;
   m = wave_min_u64(m);
   if (lane_id() == 0) part[threadIdx.x / 64] = m;
   __syncthreads();
@@ -272,8 +274,8 @@ __global__ __launch_bounds__(1024) void min_key_kernel(const uint64_t *key, int6
     if (threadIdx.x == 0) *out = v;
   }
 }
-hipError_t launch_min_key(const uint64_t *key, int64_t n, uint64_t *out, hipStream_t s) {
-  hipLaunchKernelGGL(min_key_kernel, dim3(1), dim3(1024), 0, s, key, n, out);
+hipError_t launch_min_key(const uint64_t *key, const InstTable &inst, uint64_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(min_key_kernel, dim3((unsigned)inst.count), dim3(1024), 0, s, key, inst, out);
   return hipGetLastError();
 }
 
@@ -282,34 +284,39 @@ hipError_t launch_min_key(const uint64_t *key, int64_t n, uint64_t *out, hipStre
 // so the first entry of strictly smaller rank key is the argmin.  The densest
 // point gets no dependent; the others left without one join the unfinished list.
 // ---------------------------------------------------------------------------
-__global__ void dep_in_knn_kernel(int64_t n, int32_t k, const uint64_t *key, const uint64_t *minkey,
-                                  const int32_t *knn_idx, const float *knn_dist, int32_t *dep,
-                                  float *delta, int32_t *ulist, int32_t *ucount) {
+__global__ void dep_in_knn_kernel(int64_t n, InstTable inst, int32_t kstride, const uint64_t *key,
+                                  const uint64_t *minkey, const int32_t *knn_idx,
+                                  const float *knn_dist, int32_t *dep, float *delta,
+                                  int32_t *ulist, int32_t *ucount, int32_t *ucnt_inst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const int ti = find_instance(inst, i);
+  const int k = inst.k[ti];
   const uint64_t ki = key[i];
-  if (ki == *minkey) {
+  if (ki == minkey[ti]) {
     dep[i] = -1;
     delta[i] = __int_as_float(0x7f800000);
     return;
   }
   for (int t = 0; t < k; ++t) {
-    const int32_t j = knn_idx[i * k + t];
+    const int32_t j = knn_idx[i * kstride + t];
     if (j >= 0 && key[j] < ki) {
       dep[i] = j;
-      delta[i] = knn_dist[i * k + t];
+      delta[i] = knn_dist[i * kstride + t];
       return;
     }
   }
   dep[i] = -1;
   delta[i] = __int_as_float(0x7f800000);
   ulist[atomicAdd(ucount, 1)] = (int32_t)i;
+  atomicAdd(ucnt_inst + ti, 1);
 }
-hipError_t launch_dep_in_knn(int64_t n, int32_t k, const uint64_t *key, const uint64_t *minkey,
-                             const int32_t *knn_idx, const float *knn_dist, int32_t *dep,
-                             float *delta, int32_t *ulist, int32_t *ucount, hipStream_t s) {
-  hipLaunchKernelGGL(dep_in_knn_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, k,
-                     key, minkey, knn_idx, knn_dist, dep, delta, ulist, ucount);
+hipError_t launch_dep_in_knn(int64_t n, const InstTable &inst, int32_t kstride, const uint64_t *key,
+                             const uint64_t *minkey, const int32_t *knn_idx, const float *knn_dist,
+                             int32_t *dep, float *delta, int32_t *ulist, int32_t *ucount,
+                             int32_t *ucnt_inst, hipStream_t s) {
+  hipLaunchKernelGGL(dep_in_knn_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, inst,
+                     kstride, key, minkey, knn_idx, knn_dist, dep, delta, ulist, ucount, ucnt_inst);
   return hipGetLastError();
 }
 
@@ -361,18 +368,21 @@ __global__ void gamma_kernel(int64_t n, const float *rho, const float *delta, in
   }
 }
 
-// Radix select (8 passes of 8 bits) of the n_c-th largest key; marks centers.
-__global__ __launch_bounds__(1024) void select_kernel(int64_t n, int32_t n_c, const uint64_t *gkey,
+// Radix select (8 passes of 8 bits) of the n_c-th largest key of each
+// instance (one workgroup each); marks centers.
+__global__ __launch_bounds__(1024) void select_kernel(InstTable inst, const uint64_t *gkey,
                                                        uint8_t *is_center) {
   __shared__ int32_t hist[256];
   __shared__ uint64_t s_prefix;
   __shared__ int32_t s_need;
   __shared__ int32_t s_nonnoise;
+  const int64_t lo = inst.off[blockIdx.x], hi = inst.off[blockIdx.x + 1];
+  const int32_t n_c = inst.nc[blockIdx.x];
   if (threadIdx.x == 0) { s_prefix = 0; s_need = n_c; s_nonnoise = 0; }
   __syncthreads();
   {
     int c = 0;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) c += gkey[i] != 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 1024) c += gkey[i] != 0;
     c = wave_sum_i32(c);
     if (lane_id() == 0) atomicAdd(&s_nonnoise, c);
   }
@@ -386,7 +396,7 @@ __global__ __launch_bounds__(1024) void select_kernel(int64_t n, int32_t n_c, co
       __syncthreads();
       const uint64_t prefix = s_prefix;
       const uint64_t hmask = shift == 56 ? 0ull : (~0ull << (shift + 8));
-      for (int64_t i = threadIdx.x; i < n; i += 1024) {
+      for (int64_t i = lo + threadIdx.x; i < hi; i += 1024) {
         const uint64_t k = gkey[i];
         if ((k & hmask) == prefix) atomicAdd(&hist[(k >> shift) & 0xff], 1);
       }
@@ -405,7 +415,7 @@ __global__ __launch_bounds__(1024) void select_kernel(int64_t n, int32_t n_c, co
     }
     thr = s_prefix;
   }
-  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 1024) {
     const uint64_t k = gkey[i];
     is_center[i] = (k != 0 && k >= thr) ? 1 : 0;
   }
@@ -441,18 +451,73 @@ __global__ void jump_kernel(int64_t n, int32_t *labels, int32_t *flag) {
   atomicAdd(flag, 1);
 }
 
-hipError_t launch_cluster(int64_t n, const float *rho, const int32_t *dep, const float *delta,
-                          int32_t center_mode, int32_t n_c, float delta_min, float rho_min,
+hipError_t launch_cluster(int64_t n, const InstTable &inst, const float *rho, const int32_t *dep,
+                          const float *delta, int32_t center_mode, float delta_min, float rho_min,
                           int32_t *labels, uint8_t *is_center, uint64_t *gkey, int32_t *flag,
                           hipStream_t s) {
   const unsigned b = (unsigned)((n + 255) / 256);
   hipLaunchKernelGGL(gamma_kernel, dim3(b), dim3(256), 0, s, n, rho, delta, center_mode, delta_min,
                      rho_min, gkey, is_center);
   if (center_mode == PECANN_CENTER_PRODUCT)
-    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(1024), 0, s, n, n_c, gkey, is_center);
+    hipLaunchKernelGGL(select_kernel, dim3((unsigned)inst.count), dim3(1024), 0, s, inst, gkey,
+                       is_center);
   hipLaunchKernelGGL(parent_kernel, dim3(b), dim3(256), 0, s, n, dep, is_center, gkey, rho, rho_min,
                      labels);
   hipLaunchKernelGGL(jump_kernel, dim3(b), dim3(256), 0, s, n, labels, flag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Instance tables and build-round work lists.
+// ---------------------------------------------------------------------------
+__global__ void put_i64_kernel(I64Chunk c, int32_t count, int64_t *dst) {
+  const int j = threadIdx.x;
+  if (j < count) dst[j] = c.v[j];
+}
+__global__ void put_i32_kernel(I32Chunk c, int32_t count, int32_t *dst) {
+  const int j = threadIdx.x;
+  if (j < count) dst[j] = c.v[j];
+}
+hipError_t launch_put_i64(const I64Chunk &c, int32_t count, int64_t *dst, hipStream_t s) {
+  hipLaunchKernelGGL(put_i64_kernel, dim3(1), dim3(64), 0, s, c, count, dst);
+  return hipGetLastError();
+}
+hipError_t launch_put_i32(const I32Chunk &c, int32_t count, int32_t *dst, hipStream_t s) {
+  hipLaunchKernelGGL(put_i32_kernel, dim3(1), dim3(64), 0, s, c, count, dst);
+  return hipGetLastError();
+}
+
+// blockIdx.y = range, blockIdx.x * 256 + threadIdx.x = position in it.
+__global__ void gather_items_kernel(RangeChunk c, const int32_t *perm, int32_t *items,
+                                    int32_t *item_sbase, int32_t *item_ns) {
+  const int j = blockIdx.y;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= c.cnt[j]) return;
+  const int o = c.obeg[j] + x;
+  items[o] = perm[c.pbeg[j] + x];
+  item_sbase[o] = c.sbase[j];
+  item_ns[o] = c.ns[j];
+}
+hipError_t launch_gather_items(const RangeChunk &c, int32_t nranges, int32_t maxcnt,
+                               const int32_t *perm, int32_t *items, int32_t *item_sbase,
+                               int32_t *item_ns, hipStream_t s) {
+  if (nranges <= 0 || maxcnt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_items_kernel, dim3((unsigned)((maxcnt + 255) / 256), (unsigned)nranges),
+                     dim3(256), 0, s, c, perm, items, item_sbase, item_ns);
+  return hipGetLastError();
+}
+
+__global__ void small_instance_points_kernel(int64_t n, InstTable inst, int32_t below, int32_t *list,
+                                             int32_t *count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int t = find_instance(inst, i);
+  if (inst.off[t + 1] - inst.off[t] < below) list[atomicAdd(count, 1)] = (int32_t)i;
+}
+hipError_t launch_small_instance_points(int64_t n, const InstTable &inst, int32_t below,
+                                        int32_t *list, int32_t *count, hipStream_t s) {
+  hipLaunchKernelGGL(small_instance_points_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     n, inst, below, list, count);
   return hipGetLastError();
 }
 

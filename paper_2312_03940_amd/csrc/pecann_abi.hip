@@ -302,14 +302,104 @@ static int hash_bits_for(int L) {
 }
 
 // ---------------------------------------------------------------------------
+// Instances: host spec, validation, device table
+// ---------------------------------------------------------------------------
+static constexpr int kMaxInstances = 4096;
+
+struct InstSpec {
+  std::vector<int64_t> off;  // count + 1
+  std::vector<int32_t> k, nc;
+  int count() const { return (int)k.size(); }
+  int64_t size(int t) const { return off[t + 1] - off[t]; }
+  int64_t max_size() const {
+    int64_t m = 0;
+    for (int t = 0; t < count(); ++t) m = std::max(m, size(t));
+    return m;
+  }
+};
+
+// One instance over all n points.
+static InstSpec single_spec(int64_t n, int32_t k, int32_t nc) {
+  InstSpec sp;
+  sp.off = {0, n};
+  sp.k = {k};
+  sp.nc = {nc};
+  return sp;
+}
+
+// Validates the caller's instance table against n points.  k_default /
+// nc_default fill tables the caller leaves NULL.
+static pecann_status make_spec(int64_t n, const pecann_instances *pi, int32_t k_default,
+                               int32_t nc_default, InstSpec *sp) {
+  if (!pi) return fail(PECANN_EINVAL, "instances are NULL");
+  if (pi->reserved != 0) return fail(PECANN_EINVAL, "instances.reserved must be 0");
+  const int I = pi->num_instances;
+  if (I < 1 || I > kMaxInstances) return fail(PECANN_EINVAL, "num_instances must be in [1, %d]", kMaxInstances);
+  if (!pi->offsets) return fail(PECANN_EINVAL, "instances.offsets is NULL");
+  if (pi->offsets[0] != 0 || pi->offsets[I] != n)
+    return fail(PECANN_EINVAL, "offsets must start at 0 and end at n = %lld", (long long)n);
+  sp->off.assign(pi->offsets, pi->offsets + I + 1);
+  sp->k.assign(I, k_default);
+  sp->nc.assign(I, nc_default);
+  for (int t = 0; t < I; ++t) {
+    if (sp->off[t + 1] - sp->off[t] < 2) return fail(PECANN_EINVAL, "instance %d has fewer than 2 points", t);
+    if (pi->k) sp->k[t] = pi->k[t];
+    if (pi->n_c) sp->nc[t] = pi->n_c[t];
+  }
+  return PECANN_OK;
+}
+
+// k of every instance in [1, min(n_t - 1, kmax)], kmax <= 64.
+static pecann_status check_inst_k(const InstSpec &sp, int32_t kmax) {
+  if (kmax < 1 || kmax > 64) return fail(PECANN_EINVAL, "k must be in [1, 64]");
+  for (int t = 0; t < sp.count(); ++t)
+    if (sp.k[t] < 1 || sp.k[t] > kmax || sp.k[t] > sp.size(t) - 1)
+      return fail(PECANN_EINVAL, "k of instance %d must be in [1, min(n_t - 1, %d)]", t, kmax);
+  return PECANN_OK;
+}
+
+struct InstDev {
+  int64_t *off;
+  int32_t *k, *nc;
+};
+static void carve_inst(Carver &c, int count, InstDev *d) {
+  d->off = c.take<int64_t>((size_t)count + 1);
+  d->k = c.take<int32_t>((size_t)count);
+  d->nc = c.take<int32_t>((size_t)count);
+}
+// Device copy of the table through kernel arguments (no host buffer to keep).
+static hipError_t upload_inst(const InstSpec &sp, const InstDev &d, hipStream_t s) {
+  const int I = sp.count();
+  for (int b = 0; b <= I; b += 64) {
+    I64Chunk c;
+    const int cnt = std::min(64, I + 1 - b);
+    for (int j = 0; j < cnt; ++j) c.v[j] = sp.off[b + j];
+    hipError_t e = launch_put_i64(c, cnt, d.off + b, s);
+    if (e != hipSuccess) return e;
+  }
+  for (int b = 0; b < I; b += 64) {
+    I32Chunk ck, cn;
+    const int cnt = std::min(64, I - b);
+    for (int j = 0; j < cnt; ++j) { ck.v[j] = sp.k[b + j]; cn.v[j] = sp.nc[b + j]; }
+    hipError_t e = launch_put_i32(ck, cnt, d.k + b, s);
+    if (e == hipSuccess) e = launch_put_i32(cn, cnt, d.nc + b, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+static InstTable table_of(const InstDev &d, int count) {
+  InstTable t;
+  t.off = d.off;
+  t.k = d.k;
+  t.nc = d.nc;
+  t.count = count;
+  return t;
+}
+
+// ---------------------------------------------------------------------------
 // Graph build
 // ---------------------------------------------------------------------------
 static constexpr int kCapIn = 1024;  // new in-edges merged per target per batch
-
-struct BuildWs {
-  int32_t *perm, *ctr, *vis_count, *rcnt, *tidx, *tlist, *tord, *toff, *tcnt, *ticket, *seg;
-  uint64_t *vis;
-};
 
 // Batch cap: the paper's 0.02 n, but never below 8192 concurrent searches (a
 // wavefront each), which is what it takes to occupy 256 CUs.
@@ -325,11 +415,74 @@ static int64_t batch_cap(int64_t n, int32_t max_batch) {
   return c < 1 ? 1 : c;
 }
 
+// One build round: the next batch of every instance that has one.  An
+// instance's batches follow the single-instance schedule (DiskANN's two
+// passes: the first starts the graph with the instance's first point and
+// doubles its batch from 1 up to the cap, the second re-inserts every point in
+// full batches).
+struct BuildRange { int32_t pbeg, cnt, sbase, ns; };
+struct BuildRound {
+  int pass;
+  std::vector<BuildRange> ranges;
+  int64_t total = 0;
+  int32_t maxcnt = 0;
+};
+static std::vector<BuildRound> build_schedule(const InstSpec &sp, const pecann_build_params *bp,
+                                              int passes) {
+  std::vector<BuildRound> rounds;
+  const int I = sp.count();
+  std::vector<int64_t> ins(I), bs(I), cap(I);
+  for (int t = 0; t < I; ++t) cap[t] = batch_cap(sp.size(t), bp->max_batch);
+  for (int pass = 0; pass < passes; ++pass) {
+    for (int t = 0; t < I; ++t) {
+      ins[t] = pass == 0 ? 1 : 0;
+      bs[t] = pass == 0 ? 1 : cap[t];
+    }
+    for (;;) {
+      BuildRound r;
+      r.pass = pass;
+      for (int t = 0; t < I; ++t) {
+        const int64_t nt = sp.size(t);
+        if (ins[t] >= nt) continue;
+        const int64_t nb = std::min(std::min(bs[t], cap[t]), nt - ins[t]);
+        const int64_t in_graph = pass == 0 ? ins[t] : nt;
+        BuildRange g;
+        g.pbeg = (int32_t)(sp.off[t] + ins[t]);
+        g.cnt = (int32_t)nb;
+        g.sbase = (int32_t)sp.off[t];
+        g.ns = (int32_t)std::min<int64_t>(bp->num_starts, in_graph);
+        r.ranges.push_back(g);
+        r.total += nb;
+        r.maxcnt = std::max(r.maxcnt, g.cnt);
+        ins[t] += nb;
+        if (bs[t] < cap[t]) bs[t] *= 2;  // stop doubling at the cap (no overflow)
+      }
+      if (r.ranges.empty()) break;
+      rounds.push_back(std::move(r));
+    }
+  }
+  return rounds;
+}
+static int64_t round_capacity(const InstSpec &sp, int32_t max_batch) {
+  int64_t c = 0;
+  for (int t = 0; t < sp.count(); ++t) c += batch_cap(sp.size(t), max_batch);
+  return c;
+}
+
+struct BuildWs {
+  int32_t *perm, *ctr, *vis_count, *rcnt, *tidx, *tlist, *tord, *toff, *tcnt, *ticket, *seg;
+  int32_t *items, *item_sbase, *item_ns;
+  uint64_t *vis;
+};
+
 static void carve_build(Carver &c, int64_t n, int R, int64_t cap, int vcap, BuildWs *w) {
   w->perm = c.take<int32_t>((size_t)n);
   w->ctr = c.take<int32_t>(64);
   w->vis = c.take<uint64_t>((size_t)cap * vcap);
   w->vis_count = c.take<int32_t>((size_t)cap);
+  w->items = c.take<int32_t>((size_t)cap);
+  w->item_sbase = c.take<int32_t>((size_t)cap);
+  w->item_ns = c.take<int32_t>((size_t)cap);
   w->rcnt = c.take<int32_t>((size_t)n);
   w->tidx = c.take<int32_t>((size_t)n);
   const size_t ce = (size_t)cap * R;
@@ -360,13 +513,27 @@ static pecann_status check_build(const pecann_dataset *ds, const pecann_build_pa
   return PECANN_OK;
 }
 
+static size_t build_ws_size(const pecann_dataset *ds, const pecann_build_params *bp, const InstSpec &sp) {
+  Carver c(nullptr);
+  BuildWs w;
+  carve_build(c, ds->n, bp->R, round_capacity(sp, bp->max_batch), effective_vcap(bp), &w);
+  return c.size();
+}
+
 extern "C" size_t pecann_build_graph_workspace_size(const pecann_dataset *ds, const pecann_build_params *bp) {
   Layout L;
   if (check_dataset(ds, &L) != PECANN_OK || check_build(ds, bp) != PECANN_OK) return 0;
-  Carver c(nullptr);
-  BuildWs w;
-  carve_build(c, ds->n, bp->R, batch_cap(ds->n, bp->max_batch), effective_vcap(bp), &w);
-  return c.size();
+  return build_ws_size(ds, bp, single_spec(ds->n, 1, 1));
+}
+
+extern "C" size_t pecann_build_graph_batched_workspace_size(const pecann_dataset *ds,
+                                                           const pecann_build_params *bp,
+                                                           const pecann_instances *inst) {
+  Layout L;
+  InstSpec sp;
+  if (check_dataset(ds, &L) != PECANN_OK || check_build(ds, bp) != PECANN_OK) return 0;
+  if (make_spec(ds->n, inst, 1, 1, &sp) != PECANN_OK) return 0;
+  return build_ws_size(ds, bp, sp);
 }
 
 // SplitMix64 (Steele, Lea, Flood, "Fast splittable pseudorandom number
@@ -378,11 +545,18 @@ static uint64_t splitmix64(uint64_t &s) {
   return z ^ (z >> 31);
 }
 
-extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const pecann_build_params *bp,
-                                            const int32_t *perm, uint64_t seed, int32_t *adj,
-                                            int32_t *deg, uint64_t *counters, void *ws,
-                                            size_t ws_bytes, void *stream) {
-  clear_stale_error();
+#define HIP_TRY_ROUND(expr)                                                                     \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return fail(PECANN_EHIP, "%s: %s (pass %d, round %d, %lld items)", #expr,                \
+                  hipGetErrorString(e_), rd.pass, ri, (long long)rd.total);                     \
+  } while (0)
+
+static pecann_status build_impl(const pecann_dataset *ds, const pecann_build_params *bp,
+                                const InstSpec &spec, const int32_t *perm, uint64_t seed,
+                                int32_t *adj, int32_t *deg, uint64_t *counters, void *ws,
+                                size_t ws_bytes, void *stream) {
   Layout L;
   pecann_status st = check_dataset(ds, &L);
   if (st != PECANN_OK) return st;
@@ -391,7 +565,8 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
   const int64_t n = ds->n;
   const int R = bp->R;
   const int vcap = effective_vcap(bp);
-  const int64_t cap = batch_cap(n, bp->max_batch);
+  const int64_t cap = round_capacity(spec, bp->max_batch);
+  const int I = spec.count();
   Carver c0(nullptr);
   BuildWs w;
   carve_build(c0, n, R, cap, vcap, &w);
@@ -403,15 +578,21 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
   const RowsDesc rows = rows_of(ds, L);
   const int dt = ds->search_dtype;
   const int S = engine_shape(dt, ds->d);
+  const int passes = bp->passes == 0 ? 2 : bp->passes;
+  const std::vector<BuildRound> sched = build_schedule(spec, bp, passes);
 
   const int32_t *order = perm;
   if (!order) {
+    // instance t: its own seeded shuffle (seed + t) of its points
     std::vector<int32_t> h((size_t)n);
-    for (int64_t i = 0; i < n; ++i) h[i] = (int32_t)i;
-    uint64_t sm = seed;
-    for (int64_t i = n - 1; i > 0; --i) {
-      const int64_t j = (int64_t)(splitmix64(sm) % (uint64_t)(i + 1));
-      std::swap(h[i], h[j]);
+    for (int t = 0; t < I; ++t) {
+      const int64_t lo = spec.off[t], nt = spec.size(t);
+      for (int64_t i = 0; i < nt; ++i) h[lo + i] = (int32_t)(lo + i);
+      uint64_t sm = seed + (uint64_t)t;
+      for (int64_t i = nt - 1; i > 0; --i) {
+        const int64_t j = (int64_t)(splitmix64(sm) % (uint64_t)(i + 1));
+        std::swap(h[lo + i], h[lo + j]);
+      }
     }
     HIP_TRY(hipMemcpyAsync(w.perm, h.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));  // h is pageable and about to go away
@@ -437,6 +618,9 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
   sp.item_count = nullptr;
   sp.head = head_search;
   sp.starts = order;
+  sp.item_sbase = w.item_sbase;
+  sp.item_ns = w.item_ns;
+  sp.items = w.items;
   sp.L = bp->L;
   sp.hbits = hash_bits_for(bp->L);
   sp.mode = MODE_BUILD;
@@ -449,10 +633,9 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
   pp.rows = rows;
   pp.n = (int32_t)n;
   pp.R = R;
-  pp.alpha = bp->alpha;
   pp.adj = adj;
   pp.deg = deg;
-  pp.perm = order;
+  pp.items = w.items;
   pp.vis = w.vis;
   pp.vis_count = w.vis_count;
   pp.vcap = vcap;
@@ -465,81 +648,115 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
   pp.tcnt = w.tcnt;
   pp.seg = w.seg;
   pp.rcnt = w.rcnt;
-  pp.capin = kCapIn;
   pp.overflow = overflow;
   pp.counters = counters ? (unsigned long long *)counters + 4 : nullptr;
 
-  const int passes = bp->passes == 0 ? 2 : bp->passes;
-  for (int pass = 0; pass < passes; ++pass) {
+  for (int ri = 0; ri < (int)sched.size(); ++ri) {
+    const BuildRound &rd = sched[ri];
     // DiskANN's schedule: alpha = 1 first, the given alpha last
-    pp.alpha = (passes == 2 && pass == 0) ? 1.0f : bp->alpha;
-    // the first pass starts the graph with perm[0] and ramps batches up from 1;
-    // later passes re-insert every point in full batches
-    int64_t inserted = pass == 0 ? 1 : 0, bsize = pass == 0 ? 1 : cap;
-    while (inserted < n) {
-      int64_t nb = std::min(bsize, cap);
-      nb = std::min(nb, n - inserted);
-      const int b0 = (int)inserted;
-      const int64_t in_graph = pass == 0 ? inserted : n;
-      HIP_TRY_BATCH(launch_fill_i32(w.ctr, 0, 8, s));
-      sp.items = order + b0;
-      sp.nitems = (int32_t)nb;
-      sp.nstarts = (int32_t)std::min<int64_t>(bp->num_starts, in_graph);
-      {
-        PROF(F_SEARCH_BUILD, s);
-        HIP_TRY_BATCH(launch_search(dt, S, sp, persistent_grid(nb), s));
+    pp.alpha = (passes == 2 && rd.pass == 0) ? 1.0f : bp->alpha;
+    const int32_t nb = (int32_t)rd.total;
+    for (size_t r0 = 0; r0 < rd.ranges.size(); r0 += 32) {
+      RangeChunk ch;
+      int cnt = 0;
+      int32_t obeg = 0;
+      for (size_t j = 0; j < r0; ++j) obeg += rd.ranges[j].cnt;
+      for (; cnt < 32 && r0 + cnt < rd.ranges.size(); ++cnt) {
+        const BuildRange &g = rd.ranges[r0 + cnt];
+        ch.pbeg[cnt] = g.pbeg;
+        ch.cnt[cnt] = g.cnt;
+        ch.obeg[cnt] = obeg;
+        ch.sbase[cnt] = g.sbase;
+        ch.ns[cnt] = g.ns;
+        obeg += g.cnt;
       }
-      pp.b0 = b0;
-      pp.nb = (int32_t)nb;
-      pp.head = head_pf;
-      {
-        PROF(F_PRUNE_FWD, s);
-        HIP_TRY_BATCH(launch_prune_forward(dt, pp, persistent_grid(nb), s));
-      }
-      {
-        PROF(F_REV, s);
-        HIP_TRY_BATCH(launch_rev_count(adj, deg, order, b0, (int32_t)nb, R, w.rcnt, ntargets, w.tlist,
-                                 w.tidx, w.ticket, s));
-        HIP_TRY_BATCH(launch_rev_alloc(w.tlist, ntargets, w.rcnt, w.toff, w.tcnt, cursor, w.tord,
-                                       nlight, nheavy, kLightIn, (int32_t)(nb * R), s));
-        HIP_TRY_BATCH(launch_rev_scatter(adj, deg, order, b0, (int32_t)nb, R, w.tidx, w.toff, w.ticket,
-                                   w.seg, s));
-      }
-      {
-        PROF(F_PRUNE_REV, s);
-        pp.heavy = 0;
-        pp.head = head_pr;
-        pp.capin = kLightIn;
-        HIP_TRY_BATCH(launch_prune_reverse(dt, pp, persistent_grid(nb * R), s));
-        pp.heavy = 1;
-        pp.head = head_ph;
-        pp.capin = kCapIn;
-        const int heavy_grid = (int)std::min<int64_t>(nb * R, (int64_t)cu_count() * kHeavyGridPerCu);
-        HIP_TRY_BATCH(launch_prune_reverse(dt, pp, heavy_grid, s));
-      }
-      inserted += nb;
-      if (bsize < cap) bsize *= 2;  // stop doubling at the cap (no overflow)
+      HIP_TRY_ROUND(launch_gather_items(ch, cnt, rd.maxcnt, order, w.items, w.item_sbase, w.item_ns, s));
+    }
+    HIP_TRY_ROUND(launch_fill_i32(w.ctr, 0, 8, s));
+    sp.nitems = nb;
+    {
+      PROF(F_SEARCH_BUILD, s);
+      HIP_TRY_ROUND(launch_search(dt, S, sp, persistent_grid(nb), s));
+    }
+    pp.nb = nb;
+    pp.head = head_pf;
+    {
+      PROF(F_PRUNE_FWD, s);
+      HIP_TRY_ROUND(launch_prune_forward(dt, pp, persistent_grid(nb), s));
+    }
+    {
+      PROF(F_REV, s);
+      HIP_TRY_ROUND(launch_rev_count(adj, deg, w.items, nb, R, w.rcnt, ntargets, w.tlist, w.tidx,
+                                     w.ticket, s));
+      HIP_TRY_ROUND(launch_rev_alloc(w.tlist, ntargets, w.rcnt, w.toff, w.tcnt, cursor, w.tord,
+                                     nlight, nheavy, kLightIn, (int32_t)((int64_t)nb * R), s));
+      HIP_TRY_ROUND(launch_rev_scatter(adj, deg, w.items, nb, R, w.tidx, w.toff, w.ticket, w.seg, s));
+    }
+    {
+      PROF(F_PRUNE_REV, s);
+      pp.heavy = 0;
+      pp.head = head_pr;
+      pp.capin = kLightIn;
+      HIP_TRY_ROUND(launch_prune_reverse(dt, pp, persistent_grid((int64_t)nb * R), s));
+      pp.heavy = 1;
+      pp.head = head_ph;
+      pp.capin = kCapIn;
+      const int heavy_grid = (int)std::min<int64_t>((int64_t)nb * R, (int64_t)cu_count() * kHeavyGridPerCu);
+      HIP_TRY_ROUND(launch_prune_reverse(dt, pp, heavy_grid, s));
     }
   }
   return PECANN_OK;
 }
 
+extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const pecann_build_params *bp,
+                                            const int32_t *perm, uint64_t seed, int32_t *adj,
+                                            int32_t *deg, uint64_t *counters, void *ws,
+                                            size_t ws_bytes, void *stream) {
+  clear_stale_error();
+  if (!ds) return fail(PECANN_EINVAL, "dataset is NULL");
+  return build_impl(ds, bp, single_spec(ds->n, 1, 1), perm, seed, adj, deg, counters, ws, ws_bytes,
+                    stream);
+}
+
+extern "C" pecann_status pecann_build_graph_batched(const pecann_dataset *ds,
+                                                    const pecann_build_params *bp,
+                                                    const pecann_instances *inst,
+                                                    const int32_t *perm, uint64_t seed,
+                                                    int32_t *adj, int32_t *deg,
+                                                    uint64_t *counters, void *ws, size_t ws_bytes,
+                                                    void *stream) {
+  clear_stale_error();
+  if (!ds) return fail(PECANN_EINVAL, "dataset is NULL");
+  InstSpec sp;
+  pecann_status st = make_spec(ds->n, inst, 1, 1, &sp);
+  if (st != PECANN_OK) return st;
+  return build_impl(ds, bp, sp, perm, seed, adj, deg, counters, ws, ws_bytes, stream);
+}
+
 // ---------------------------------------------------------------------------
 // kNN + density
 // ---------------------------------------------------------------------------
-// Exact kNN switches to the matrix-core scan from this many points on.
+// Exact kNN switches to the matrix-core scan from this many points on (per
+// instance).
 static constexpr int64_t kExactMfmaMin = 4096;
 
 struct KnnWs {
   int32_t *ctr, *fb, *cand;
   float *thr, *nmax;
+  InstDev inst;
 };
-static void carve_knn(Carver &c, int64_t n, bool exact_mfma, KnnWs *w) {
+static bool any_large(const InstSpec &sp) {
+  for (int t = 0; t < sp.count(); ++t)
+    if (sp.size(t) >= kExactMfmaMin) return true;
+  return false;
+}
+static void carve_knn(Carver &c, int64_t n, bool exact_mfma, int ninst, KnnWs *w) {
   w->ctr = c.take<int32_t>(64);
   w->fb = c.take<int32_t>((size_t)n);
   w->nmax = c.take<float>(64);
   w->cand = exact_mfma ? c.take<int32_t>((size_t)n * 256) : nullptr;
   w->thr = exact_mfma ? c.take<float>((size_t)n) : nullptr;
+  carve_inst(c, ninst, &w->inst);
 }
 
 extern "C" size_t pecann_knn_density_workspace_size(const pecann_dataset *ds, int32_t k,
@@ -549,22 +766,44 @@ extern "C" size_t pecann_knn_density_workspace_size(const pecann_dataset *ds, in
   (void)k; (void)L_search;
   Carver c(nullptr);
   KnnWs w;
-  carve_knn(c, ds->n, exact != 0 && ds->n >= kExactMfmaMin, &w);
+  carve_knn(c, ds->n, exact != 0 && ds->n >= kExactMfmaMin, 1, &w);
   return c.size();
 }
 
-extern "C" pecann_status pecann_knn_density(const pecann_dataset *ds, const int32_t *adj,
-                                            const int32_t *deg, int32_t R, int32_t k,
-                                            int32_t L_search, int32_t rerank, int32_t *knn_idx,
-                                            float *knn_dist, float *rho, uint64_t *rank_key,
-                                            uint64_t *counters, void *ws, size_t ws_bytes,
-                                            void *stream) {
-  clear_stale_error();
+extern "C" size_t pecann_knn_density_batched_workspace_size(const pecann_dataset *ds,
+                                                            const pecann_instances *inst,
+                                                            int32_t k_max, int32_t L_search,
+                                                            int32_t exact) {
+  Layout L;
+  InstSpec sp;
+  if (check_dataset(ds, &L) != PECANN_OK || make_spec(ds->n, inst, k_max, 1, &sp) != PECANN_OK) return 0;
+  (void)L_search;
+  Carver c(nullptr);
+  KnnWs w;
+  carve_knn(c, ds->n, exact != 0 && any_large(sp), sp.count(), &w);
+  return c.size();
+}
+
+// Rows of one instance: row 0 of the view is global row lo.
+static RowsDesc shift_rows(RowsDesc r, int64_t lo) {
+  r.xs += lo * r.xs_stride;
+  if (r.xr) r.xr += lo * r.xr_stride;
+  if (r.scale) r.scale += lo;
+  r.sqn += lo;
+  if (r.sqn_r) r.sqn_r += lo;
+  return r;
+}
+
+static pecann_status knn_impl(const pecann_dataset *ds, const InstSpec &spec, const int32_t *adj,
+                              const int32_t *deg, int32_t R, int32_t k, int32_t L_search,
+                              int32_t rerank, int32_t *knn_idx, float *knn_dist, float *rho,
+                              uint64_t *rank_key, uint64_t *counters, void *ws, size_t ws_bytes,
+                              void *stream) {
   Layout L;
   pecann_status st = check_dataset(ds, &L);
   if (st != PECANN_OK) return st;
   const int64_t n = ds->n;
-  if (k < 1 || k > 64 || k > n - 1) return fail(PECANN_EINVAL, "k must be in [1, min(n-1, 64)]");
+  if ((st = check_inst_k(spec, k)) != PECANN_OK) return st;
   if (!knn_idx || !knn_dist || !rho || !rank_key) return fail(PECANN_EINVAL, "output pointer is NULL");
   if (adj) {
     if (!deg) return fail(PECANN_EINVAL, "deg is NULL");
@@ -574,63 +813,70 @@ extern "C" pecann_status pecann_knn_density(const pecann_dataset *ds, const int3
     if (lp && (rerank < k || rerank > L_search))
       return fail(PECANN_EINVAL, "rerank must be in [k, L_search]");
   }
-  const bool exact_mfma = !adj && n >= kExactMfmaMin;
+  const int I = spec.count();
+  const bool exact_mfma = !adj && any_large(spec);
   Carver c0(nullptr);
   KnnWs w;
-  carve_knn(c0, n, exact_mfma, &w);
+  carve_knn(c0, n, exact_mfma, I, &w);
   if (!ws || ws_bytes < c0.size() || !aligned(ws, 256))
     return fail(PECANN_EWORKSPACE, "workspace needs %zu bytes (256-aligned), got %zu", c0.size(), ws_bytes);
   Carver c(ws);
-  carve_knn(c, n, exact_mfma, &w);
+  carve_knn(c, n, exact_mfma, I, &w);
   int32_t *ctr = w.ctr, *fb = w.fb;
   hipStream_t s = (hipStream_t)stream;
   const RowsDesc rows = rows_of(ds, L);
   const int dt = ds->search_dtype;
   const int S = engine_shape(dt, ds->d);
   HIP_TRY(launch_fill_i32(ctr, 0, 4, s));
+  HIP_TRY(upload_inst(spec, w.inst, s));
+  const InstTable itab = table_of(w.inst, I);
 
+  // exact searches of a list of queries (fb, ctr[1] entries) over their instance
   BfKnnParams bp = {};
   bp.rows = rows;
   bp.n = (int32_t)n;
   bp.k = k;
+  bp.kstride = k;
+  bp.inst = itab;
+  bp.skip_from = INT32_MAX;
   bp.knn_idx = knn_idx;
   bp.knn_dist = knn_dist;
   bp.rho = rho;
   bp.rank_key = rank_key;
-  if (!adj && !exact_mfma) {
-    bp.items = nullptr;
-    bp.item_count = nullptr;
-    bp.nitems = (int32_t)n;
-    bp.head = ctr + 0;
-    PROF(F_BF_KNN, s);
-    HIP_TRY(launch_bf_knn(dt, S, bp, persistent_grid(n), s));
-    return PECANN_OK;
-  }
-  if (exact_mfma) {
-    ExactMfmaParams ep = {};
-    ep.rows = rows;
-    ep.n = (int32_t)n;
-    ep.k = k;
-    ep.cand = w.cand;
-    ep.thr = w.thr;
-    ep.nmax = w.nmax;
-    ep.head = ctr + 0;
-    ep.knn_idx = knn_idx;
-    ep.knn_dist = knn_dist;
-    ep.rho = rho;
-    ep.rank_key = rank_key;
-    ep.fb_list = fb;
-    ep.fb_count = ctr + 1;
-    {
+  bp.items = fb;
+  bp.item_count = ctr + 1;
+  bp.nitems = 0;
+  bp.head = ctr + 2;
+
+  if (!adj) {
+    // large instances: matrix-core scan, then exact re-score; queries whose
+    // check fails, and every query of a small instance, go to the list
+    for (int t = 0; t < I; ++t) {
+      const int64_t lo = spec.off[t], nt = spec.size(t);
+      if (nt < kExactMfmaMin) continue;
+      ExactMfmaParams ep = {};
+      ep.rows = shift_rows(rows, lo);
+      ep.n = (int32_t)nt;
+      ep.k = spec.k[t];
+      ep.kstride = k;
+      ep.base = (int32_t)lo;
+      ep.cand = w.cand + lo * 256;
+      ep.thr = w.thr + lo;
+      ep.nmax = w.nmax;
+      ep.head = ctr + 0;
+      ep.knn_idx = knn_idx + lo * k;
+      ep.knn_dist = knn_dist + lo * k;
+      ep.rho = rho + lo;
+      ep.rank_key = rank_key + lo;
+      ep.fb_list = fb;
+      ep.fb_count = ctr + 1;
+      HIP_TRY(launch_fill_i32(ctr, 0, 1, s));
       PROF(F_EXACT_MFMA, s);
       HIP_TRY(launch_exact_mfma(dt, S, ep, s));
     }
-    bp.items = fb;
-    bp.item_count = ctr + 1;
-    bp.nitems = 0;
-    bp.head = ctr + 2;
+    HIP_TRY(launch_small_instance_points(n, itab, (int32_t)kExactMfmaMin, fb, ctr + 1, s));
     PROF(F_BF_KNN, s);
-    HIP_TRY(launch_bf_knn(dt, S, bp, cu_count() * 4, s));
+    HIP_TRY(launch_bf_knn(dt, S, bp, persistent_grid(n), s));
     return PECANN_OK;
   }
   SearchParams sp = {};
@@ -645,11 +891,13 @@ extern "C" pecann_status pecann_knn_density(const pecann_dataset *ds, const int3
   sp.head = ctr + 0;
   sp.starts = nullptr;
   sp.nstarts = 0;
+  sp.inst = itab;
   sp.L = L_search;
   sp.hbits = hash_bits_for(L_search);
   sp.mode = MODE_KNN;
   sp.rerank = rerank;
   sp.k = k;
+  sp.kstride = k;
   sp.knn_idx = knn_idx;
   sp.knn_dist = knn_dist;
   sp.rho = rho;
@@ -662,31 +910,61 @@ extern "C" pecann_status pecann_knn_density(const pecann_dataset *ds, const int3
     HIP_TRY(launch_search(dt, S, sp, persistent_grid(n), s));
   }
   // too-few-results fallback: exact search for those queries
-  bp.items = fb;
-  bp.item_count = ctr + 1;
-  bp.nitems = 0;
-  bp.head = ctr + 2;
   PROF(F_BF_KNN, s);
   HIP_TRY(launch_bf_knn(dt, S, bp, cu_count() * 4, s));
   return PECANN_OK;
 }
 
+extern "C" pecann_status pecann_knn_density(const pecann_dataset *ds, const int32_t *adj,
+                                            const int32_t *deg, int32_t R, int32_t k,
+                                            int32_t L_search, int32_t rerank, int32_t *knn_idx,
+                                            float *knn_dist, float *rho, uint64_t *rank_key,
+                                            uint64_t *counters, void *ws, size_t ws_bytes,
+                                            void *stream) {
+  clear_stale_error();
+  if (!ds) return fail(PECANN_EINVAL, "dataset is NULL");
+  if (k < 1 || k > 64 || k > ds->n - 1) return fail(PECANN_EINVAL, "k must be in [1, min(n-1, 64)]");
+  return knn_impl(ds, single_spec(ds->n, k, 1), adj, deg, R, k, L_search, rerank, knn_idx, knn_dist,
+                  rho, rank_key, counters, ws, ws_bytes, stream);
+}
+
+extern "C" pecann_status pecann_knn_density_batched(const pecann_dataset *ds,
+                                                    const pecann_instances *inst,
+                                                    const int32_t *adj, const int32_t *deg,
+                                                    int32_t R, int32_t k_max, int32_t L_search,
+                                                    int32_t rerank, int32_t *knn_idx,
+                                                    float *knn_dist, float *rho,
+                                                    uint64_t *rank_key, uint64_t *counters,
+                                                    void *ws, size_t ws_bytes, void *stream) {
+  clear_stale_error();
+  if (!ds) return fail(PECANN_EINVAL, "dataset is NULL");
+  InstSpec sp;
+  pecann_status st = make_spec(ds->n, inst, k_max, 1, &sp);
+  if (st != PECANN_OK) return st;
+  return knn_impl(ds, sp, adj, deg, R, k_max, L_search, rerank, knn_idx, knn_dist, rho, rank_key,
+                  counters, ws, ws_bytes, stream);
+}
+
 // ---------------------------------------------------------------------------
 // Dependent points
 // ---------------------------------------------------------------------------
+static constexpr int kMaxRounds = 30;
+
 struct DepWs {
-  int32_t *ctr, *ucnt, *ua, *ub, *stats_tmp;
+  int32_t *ctr, *ucnt, *ua, *ub, *ucnt_inst;
   uint64_t *minkey;
   unsigned long long *best;
+  InstDev inst;
 };
-static void carve_dep(Carver &c, int64_t n, DepWs *w) {
+static void carve_dep(Carver &c, int64_t n, int ninst, DepWs *w) {
   w->ctr = c.take<int32_t>(64);
   w->ucnt = c.take<int32_t>(64);
-  w->minkey = c.take<uint64_t>(1);
+  w->minkey = c.take<uint64_t>((size_t)ninst);
   w->ua = c.take<int32_t>((size_t)n);
   w->ub = c.take<int32_t>((size_t)n);
   w->best = c.take<unsigned long long>((size_t)n);
-  w->stats_tmp = nullptr;
+  w->ucnt_inst = c.take<int32_t>((size_t)(kMaxRounds + 1) * ninst);
+  carve_inst(c, ninst, &w->inst);
 }
 
 extern "C" size_t pecann_dependent_search_workspace_size(const pecann_dataset *ds, int32_t kdep_cap,
@@ -696,7 +974,20 @@ extern "C" size_t pecann_dependent_search_workspace_size(const pecann_dataset *d
   (void)kdep_cap; (void)L_search;
   Carver c(nullptr);
   DepWs w;
-  carve_dep(c, ds->n, &w);
+  carve_dep(c, ds->n, 1, &w);
+  return c.size();
+}
+
+extern "C" size_t pecann_dependent_search_batched_workspace_size(const pecann_dataset *ds,
+                                                                 const pecann_instances *inst,
+                                                                 int32_t kdep_cap, int32_t L_search) {
+  Layout L;
+  InstSpec sp;
+  if (check_dataset(ds, &L) != PECANN_OK || make_spec(ds->n, inst, 1, 1, &sp) != PECANN_OK) return 0;
+  (void)kdep_cap; (void)L_search;
+  Carver c(nullptr);
+  DepWs w;
+  carve_dep(c, ds->n, sp.count(), &w);
   return c.size();
 }
 
@@ -711,20 +1002,16 @@ __global__ void dep_stats_kernel(const int32_t *ucnt, int nr, int32_t *stats) {
   }
 }
 
-extern "C" pecann_status pecann_dependent_search(const pecann_dataset *ds, const int32_t *adj,
-                                                 const int32_t *deg, int32_t R,
-                                                 const uint64_t *rank_key, const int32_t *knn_idx,
-                                                 const float *knn_dist, int32_t k, int32_t L_d,
-                                                 int32_t L_search, int32_t threshold,
-                                                 int32_t kdep_cap, int32_t *dep, float *delta,
-                                                 int32_t *stats, void *ws, size_t ws_bytes,
-                                                 void *stream) {
-  clear_stale_error();
+static pecann_status dep_impl(const pecann_dataset *ds, const InstSpec &spec, const int32_t *adj,
+                              const int32_t *deg, int32_t R, const uint64_t *rank_key,
+                              const int32_t *knn_idx, const float *knn_dist, int32_t k, int32_t L_d,
+                              int32_t L_search, int32_t threshold, int32_t kdep_cap, int32_t *dep,
+                              float *delta, int32_t *stats, void *ws, size_t ws_bytes, void *stream) {
   Layout L;
   pecann_status st = check_dataset(ds, &L);
   if (st != PECANN_OK) return st;
   const int64_t n = ds->n;
-  if (k < 1 || k > 64 || k > n - 1) return fail(PECANN_EINVAL, "k must be in [1, min(n-1, 64)]");
+  if ((st = check_inst_k(spec, k)) != PECANN_OK) return st;
   if (!rank_key || !knn_idx || !knn_dist || !dep || !delta) return fail(PECANN_EINVAL, "pointer is NULL");
   if (threshold < 0) return fail(PECANN_EINVAL, "threshold must be >= 0");
   if (adj) {
@@ -734,13 +1021,14 @@ extern "C" pecann_status pecann_dependent_search(const pecann_dataset *ds, const
     if (kdep_cap < L_d || kdep_cap > 1024) return fail(PECANN_EINVAL, "kdep_cap must be in [L_d, 1024]");
     if (L_search < 1 || L_search > 1024) return fail(PECANN_EINVAL, "L_search must be in [1, 1024]");
   }
+  const int I = spec.count();
   Carver c0(nullptr);
   DepWs w;
-  carve_dep(c0, n, &w);
+  carve_dep(c0, n, I, &w);
   if (!ws || ws_bytes < c0.size() || !aligned(ws, 256))
     return fail(PECANN_EWORKSPACE, "workspace needs %zu bytes (256-aligned), got %zu", c0.size(), ws_bytes);
   Carver c(ws);
-  carve_dep(c, n, &w);
+  carve_dep(c, n, I, &w);
   hipStream_t s = (hipStream_t)stream;
   const RowsDesc rows = rows_of(ds, L);
   const int dt = ds->search_dtype;
@@ -748,14 +1036,19 @@ extern "C" pecann_status pecann_dependent_search(const pecann_dataset *ds, const
 
   HIP_TRY(launch_fill_i32(w.ctr, 0, 64, s));
   HIP_TRY(launch_fill_i32(w.ucnt, 0, 64, s));
-  HIP_TRY(launch_min_key(rank_key, n, w.minkey, s));
-  HIP_TRY(launch_dep_in_knn(n, k, rank_key, w.minkey, knn_idx, knn_dist, dep, delta, w.ua, w.ucnt, s));
+  HIP_TRY(launch_fill_i32(w.ucnt_inst, 0, (int64_t)(kMaxRounds + 1) * I, s));
+  HIP_TRY(upload_inst(spec, w.inst, s));
+  const InstTable itab = table_of(w.inst, I);
+  HIP_TRY(launch_min_key(rank_key, itab, w.minkey, s));
+  HIP_TRY(launch_dep_in_knn(n, itab, k, rank_key, w.minkey, knn_idx, knn_dist, dep, delta, w.ua,
+                            w.ucnt, w.ucnt_inst, s));
 
   int32_t *cur = w.ua, *nxt = w.ub;
   int nr = 0;
   if (adj) {
-    const int64_t lim = std::min<int64_t>(kdep_cap, n - 1);
-    for (int64_t kd = L_d; kd <= lim && nr < 30; kd *= 2, ++nr) {
+    // rounds while some instance may still double: k_dep <= min(kdep_cap, n_t - 1)
+    const int64_t lim = std::min<int64_t>(kdep_cap, spec.max_size() - 1);
+    for (int64_t kd = L_d; kd <= lim && nr < kMaxRounds; kd *= 2, ++nr) {
       SearchParams sp = {};
       sp.rows = rows;
       sp.adj = adj;
@@ -768,16 +1061,20 @@ extern "C" pecann_status pecann_dependent_search(const pecann_dataset *ds, const
       sp.head = w.ctr + nr;
       sp.starts = nullptr;
       sp.nstarts = 0;
+      sp.inst = itab;
       sp.L = (int32_t)std::max<int64_t>(kd, L_search);
       sp.hbits = hash_bits_for(sp.L);
       sp.mode = MODE_DEP;
       sp.rerank = (int32_t)kd;
       sp.kdep = (int32_t)kd;
+      sp.kdep_cap = kdep_cap;
       sp.key_in = rank_key;
       sp.dep = dep;
       sp.delta = delta;
       sp.u_out = nxt;
       sp.u_out_count = w.ucnt + nr + 1;
+      sp.ucnt_in = w.ucnt_inst + (int64_t)nr * I;
+      sp.ucnt_out = w.ucnt_inst + (int64_t)(nr + 1) * I;
       sp.threshold = threshold;
       {
         PROF(F_SEARCH_DEP, s);
@@ -786,7 +1083,7 @@ extern "C" pecann_status pecann_dependent_search(const pecann_dataset *ds, const
       std::swap(cur, nxt);
     }
   }
-  // final brute force over all of P for the points still unfinished
+  // final brute force over the instance for the points still unfinished
   HIP_TRY(launch_fill_u64((uint64_t *)w.best, ~0ull, n, s));
   BfDepParams bd = {};
   bd.rows = rows;
@@ -794,8 +1091,9 @@ extern "C" pecann_status pecann_dependent_search(const pecann_dataset *ds, const
   bd.ulist = cur;
   bd.ucount = w.ucnt + nr;
   bd.chunk = 4096;
-  bd.nchunks = (int32_t)((n + bd.chunk - 1) / bd.chunk);
+  bd.nchunks = (int32_t)((spec.max_size() + bd.chunk - 1) / bd.chunk);
   bd.head = w.ctr + 40;
+  bd.inst = itab;
   bd.key = rank_key;
   bd.best = w.best;
   {
@@ -810,15 +1108,90 @@ extern "C" pecann_status pecann_dependent_search(const pecann_dataset *ds, const
   return PECANN_OK;
 }
 
+extern "C" pecann_status pecann_dependent_search(const pecann_dataset *ds, const int32_t *adj,
+                                                 const int32_t *deg, int32_t R,
+                                                 const uint64_t *rank_key, const int32_t *knn_idx,
+                                                 const float *knn_dist, int32_t k, int32_t L_d,
+                                                 int32_t L_search, int32_t threshold,
+                                                 int32_t kdep_cap, int32_t *dep, float *delta,
+                                                 int32_t *stats, void *ws, size_t ws_bytes,
+                                                 void *stream) {
+  clear_stale_error();
+  if (!ds) return fail(PECANN_EINVAL, "dataset is NULL");
+  if (k < 1 || k > 64 || k > ds->n - 1) return fail(PECANN_EINVAL, "k must be in [1, min(n-1, 64)]");
+  return dep_impl(ds, single_spec(ds->n, k, 1), adj, deg, R, rank_key, knn_idx, knn_dist, k, L_d,
+                  L_search, threshold, kdep_cap, dep, delta, stats, ws, ws_bytes, stream);
+}
+
+extern "C" pecann_status pecann_dependent_search_batched(const pecann_dataset *ds,
+                                                         const pecann_instances *inst,
+                                                         const int32_t *adj, const int32_t *deg,
+                                                         int32_t R, const uint64_t *rank_key,
+                                                         const int32_t *knn_idx,
+                                                         const float *knn_dist, int32_t k_max,
+                                                         int32_t L_d, int32_t L_search,
+                                                         int32_t threshold, int32_t kdep_cap,
+                                                         int32_t *dep, float *delta, int32_t *stats,
+                                                         void *ws, size_t ws_bytes, void *stream) {
+  clear_stale_error();
+  if (!ds) return fail(PECANN_EINVAL, "dataset is NULL");
+  InstSpec sp;
+  pecann_status st = make_spec(ds->n, inst, k_max, 1, &sp);
+  if (st != PECANN_OK) return st;
+  return dep_impl(ds, sp, adj, deg, R, rank_key, knn_idx, knn_dist, k_max, L_d, L_search, threshold,
+                  kdep_cap, dep, delta, stats, ws, ws_bytes, stream);
+}
+
 // ---------------------------------------------------------------------------
 // Cluster
 // ---------------------------------------------------------------------------
-extern "C" size_t pecann_cluster_workspace_size(int64_t n) {
-  if (n < 1) return 0;
+static size_t cluster_ws_size(int64_t n, int ninst) {
   Carver c(nullptr);
   c.take<uint64_t>((size_t)n);
   c.take<int32_t>(64);
+  InstDev d;
+  carve_inst(c, ninst, &d);
   return c.size();
+}
+
+extern "C" size_t pecann_cluster_workspace_size(int64_t n) {
+  if (n < 1) return 0;
+  return cluster_ws_size(n, 1);
+}
+
+extern "C" size_t pecann_cluster_batched_workspace_size(int64_t n, const pecann_instances *inst) {
+  InstSpec sp;
+  if (n < 2 || make_spec(n, inst, 1, 1, &sp) != PECANN_OK) return 0;
+  return cluster_ws_size(n, sp.count());
+}
+
+static pecann_status cluster_impl(int64_t n, const InstSpec &spec, const float *rho, const int32_t *dep,
+                                  const float *delta, int32_t center_mode, float delta_min,
+                                  float rho_min, int32_t *labels, uint8_t *is_center, void *ws,
+                                  size_t ws_bytes, void *stream) {
+  if (n < 1 || n >= (int64_t)1 << 31) return fail(PECANN_EINVAL, "n out of range");
+  if (!rho || !dep || !delta || !labels || !is_center) return fail(PECANN_EINVAL, "pointer is NULL");
+  if (center_mode != PECANN_CENTER_PRODUCT && center_mode != PECANN_CENTER_THRESHOLD)
+    return fail(PECANN_EINVAL, "center_mode");
+  if (center_mode == PECANN_CENTER_PRODUCT)
+    for (int t = 0; t < spec.count(); ++t)
+      if (spec.nc[t] < 1 || spec.nc[t] > spec.size(t))
+        return fail(PECANN_EINVAL, "n_c of instance %d must be in [1, n_t]", t);
+  const size_t need = cluster_ws_size(n, spec.count());
+  if (!ws || ws_bytes < need || !aligned(ws, 256))
+    return fail(PECANN_EWORKSPACE, "workspace needs %zu bytes (256-aligned), got %zu", need, ws_bytes);
+  Carver c(ws);
+  uint64_t *gkey = c.take<uint64_t>((size_t)n);
+  int32_t *flag = c.take<int32_t>(64);
+  InstDev d;
+  carve_inst(c, spec.count(), &d);
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_fill_i32(flag, 0, 1, s));
+  HIP_TRY(upload_inst(spec, d, s));
+  PROF(F_CLUSTER, s);
+  HIP_TRY(launch_cluster(n, table_of(d, spec.count()), rho, dep, delta, center_mode, delta_min,
+                         rho_min, labels, is_center, gkey, flag, s));
+  return PECANN_OK;
 }
 
 extern "C" pecann_status pecann_cluster(int64_t n, const float *rho, const int32_t *dep,
@@ -827,21 +1200,23 @@ extern "C" pecann_status pecann_cluster(int64_t n, const float *rho, const int32
                                         uint8_t *is_center, void *ws, size_t ws_bytes, void *stream) {
   clear_stale_error();
   if (n < 1 || n >= (int64_t)1 << 31) return fail(PECANN_EINVAL, "n out of range");
-  if (!rho || !dep || !delta || !labels || !is_center) return fail(PECANN_EINVAL, "pointer is NULL");
-  if (center_mode != PECANN_CENTER_PRODUCT && center_mode != PECANN_CENTER_THRESHOLD)
-    return fail(PECANN_EINVAL, "center_mode");
   if (center_mode == PECANN_CENTER_PRODUCT && (n_c < 1 || n_c > n))
     return fail(PECANN_EINVAL, "n_c must be in [1, n]");
-  const size_t need = pecann_cluster_workspace_size(n);
-  if (!ws || ws_bytes < need || !aligned(ws, 256))
-    return fail(PECANN_EWORKSPACE, "workspace needs %zu bytes (256-aligned), got %zu", need, ws_bytes);
-  Carver c(ws);
-  uint64_t *gkey = c.take<uint64_t>((size_t)n);
-  int32_t *flag = c.take<int32_t>(64);
-  hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(launch_fill_i32(flag, 0, 1, s));
-  PROF(F_CLUSTER, s);
-  HIP_TRY(launch_cluster(n, rho, dep, delta, center_mode, n_c, delta_min, rho_min, labels, is_center,
-                         gkey, flag, s));
-  return PECANN_OK;
+  return cluster_impl(n, single_spec(n, 1, n_c), rho, dep, delta, center_mode, delta_min, rho_min,
+                      labels, is_center, ws, ws_bytes, stream);
+}
+
+extern "C" pecann_status pecann_cluster_batched(int64_t n, const pecann_instances *inst,
+                                                const float *rho, const int32_t *dep,
+                                                const float *delta, int32_t center_mode,
+                                                int32_t n_c, float delta_min, float rho_min,
+                                                int32_t *labels, uint8_t *is_center, void *ws,
+                                                size_t ws_bytes, void *stream) {
+  clear_stale_error();
+  if (n < 2 || n >= (int64_t)1 << 31) return fail(PECANN_EINVAL, "n out of range");
+  InstSpec sp;
+  pecann_status st = make_spec(n, inst, 1, n_c, &sp);
+  if (st != PECANN_OK) return st;
+  return cluster_impl(n, sp, rho, dep, delta, center_mode, delta_min, rho_min, labels, is_center, ws,
+                      ws_bytes, stream);
 }

@@ -329,7 +329,7 @@ __global__ __launch_bounds__(64) void prune_forward_kernel(PruneParams p) {
   for (;;) {
     const int t = next_item(p.head);
     if (t >= p.nb) break;
-    const int32_t pt = p.perm[p.b0 + t];
+    const int32_t pt = p.items[t];
     // candidates: the visited set V_p, then the current out-neighbours Nout(p)
     const int nv = min(p.vis_count[t], p.vcap);
     const uint64_t *v = p.vis + (int64_t)t * p.vcap;

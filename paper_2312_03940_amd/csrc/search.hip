@@ -97,14 +97,6 @@ __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
   const int count = p.item_count ? *p.item_count : p.nitems;
   constexpr bool kNeedRerank = (DT == PECANN_BF16 || DT == PECANN_FP8E4M3);
 
-  if (MODE == MODE_DEP && count <= p.threshold) {
-    // Few enough points are left: this round is skipped and the list carried over.
-    if (blockIdx.x == 0) {
-      for (int u = l; u < count; u += kWave) p.u_out[u] = p.items[u];
-      if (l == 0) *p.u_out_count = count;
-    }
-    return;
-  }
 
   Engine<DT, S> eng;
   constexpr int SR = RerankShape<DT, S>::v;
@@ -112,6 +104,21 @@ __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
     const int it = next_item(p.head);
     if (it >= count) break;
     const int32_t qid = p.items ? p.items[it] : it;
+    int ti = 0;  // the query's instance
+    if (MODE != MODE_BUILD) ti = find_instance(p.inst, qid);
+    if (MODE == MODE_DEP) {
+      // this instance's doubling has ended (few enough points left, or k_dep
+      // beyond its limit): carry the point over to the next list unchanged
+      const int64_t nt = p.inst.off[ti + 1] - p.inst.off[ti];
+      const int64_t lim = min((int64_t)p.kdep_cap, nt - 1);
+      if (p.ucnt_in[ti] <= p.threshold || p.kdep > lim) {
+        if (l == 0) {
+          p.u_out[atomicAdd(p.u_out_count, 1)] = qid;
+          atomicAdd(p.ucnt_out + ti, 1);
+        }
+        continue;
+      }
+    }
 
     s.hash.clear();
     s.beam.m = 0;
@@ -122,12 +129,14 @@ __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
 
     // S = {query} u starts, or S = starts for an insertion.  A query that is
     // itself a start is expanded at once (it never takes a beam slot).
+    const int32_t *starts = p.item_sbase ? p.starts + p.item_sbase[it] : p.starts;
+    const int nstarts = p.item_ns ? p.item_ns[it] : p.nstarts;
     bool self_start = (MODE != MODE_BUILD);
-    for (int s0 = 0; s0 < p.nstarts && !self_start; s0 += kWave)
-      self_start = ballot(s0 + l < p.nstarts && p.starts[s0 + l] == qid) != 0;
+    for (int s0 = 0; s0 < nstarts && !self_start; s0 += kWave)
+      self_start = ballot(s0 + l < nstarts && starts[s0 + l] == qid) != 0;
     if (self_start) expand(eng, p, s, qid);
-    for (int s0 = 0; s0 < p.nstarts; s0 += kWave) {
-      int32_t id = s0 + l < p.nstarts ? p.starts[s0 + l] : -1;
+    for (int s0 = 0; s0 < nstarts; s0 += kWave) {
+      int32_t id = s0 + l < nstarts ? starts[s0 + l] : -1;
       if (id >= 0 && !s.hash.insert(id)) id = -1;
       score_and_merge(eng, p.rows, s, id);
     }
@@ -152,26 +161,28 @@ __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
     if (MODE == MODE_BUILD) {
       if (l == 0) p.vis_count[it] = nv;
     } else if (MODE == MODE_KNN) {
+      const int k = p.inst.k[ti];
       int mm = m;
       if (kNeedRerank && m > 0) {
         mm = min(m, p.rerank);
         rerank_beam<SR>(p, s, qid, mm);
         n_rerank = mm;
       }
-      if (mm < p.k) {
+      if (mm < k) {
         if (l == 0) {
           const int slot = atomicAdd(p.fb_count, 1);
           p.fb_list[slot] = qid;
         }
       } else {
-        const int64_t o = (int64_t)qid * p.k;
-        for (int t = l; t < p.k; t += kWave) {
-          const uint64_t kt = s.beam.a[t];
-          p.knn_idx[o + t] = key_id(kt);
-          p.knn_dist[o + t] = measure_to_dist(key_measure(kt), p.rows.metric);
+        const int64_t o = (int64_t)qid * p.kstride;
+        for (int t = l; t < p.kstride; t += kWave) {
+          const uint64_t kt = t < k ? s.beam.a[t] : kNoKey;
+          p.knn_idx[o + t] = t < k ? key_id(kt) : -1;
+          p.knn_dist[o + t] = t < k ? measure_to_dist(key_measure(kt), p.rows.metric)
+                                    : __int_as_float(0x7f800000);
         }
         if (l == 0) {
-          const uint64_t kk = s.beam.a[p.k - 1];
+          const uint64_t kk = s.beam.a[k - 1];
           const float dk = measure_to_dist(key_measure(kk), p.rows.metric);
           p.rho[qid] = 1.0f / dk;
           p.rank_key[qid] = (kk & 0xffffffff00000000ull) | (uint32_t)qid;
@@ -197,6 +208,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
         } else {
           const int slot = atomicAdd(p.u_out_count, 1);
           p.u_out[slot] = qid;
+          atomicAdd(p.ucnt_out + ti, 1);
         }
       }
     }

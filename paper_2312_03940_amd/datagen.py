@@ -146,6 +146,27 @@ def config5_instance(spec: dict, d: int = 384):
     return mixture(spec["n"], d, spec["n_clusters"], spec["seed"])
 
 
+def config5(count: int = 64, d: int = 384):
+    """Every instance of the batched workload, stacked in instance order.
+
+    -> (X float32 [N, d], y int64 [N] (component ids, distinct across instances),
+        offsets int64 [count + 1], k int32 [count], n_clusters int32 [count])."""
+    specs = config5_instances(count)
+    sizes = np.array([sp["n"] for sp in specs], dtype=np.int64)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    X = np.empty((int(off[-1]), d), dtype=np.float32)
+    y = np.empty(int(off[-1]), dtype=np.int64)
+    base = 0
+    for t, sp in enumerate(specs):
+        Xt, yt = config5_instance(sp, d)
+        X[off[t]:off[t + 1]] = Xt
+        y[off[t]:off[t + 1]] = yt + base
+        base += sp["n_clusters"]
+    k = np.array([sp["k"] for sp in specs], dtype=np.int32)
+    ncl = np.array([sp["n_clusters"] for sp in specs], dtype=np.int32)
+    return X, y, off, k, ncl
+
+
 def permutation(n: int, seed: int) -> np.ndarray:
     """Insertion order for the batched graph build (int32)."""
     return np.random.default_rng(seed).permutation(n).astype(np.int32)

@@ -46,6 +46,38 @@ class _BuildParams(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class _Instances(ctypes.Structure):
+    _fields_ = [("num_instances", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("offsets", ctypes.POINTER(ctypes.c_int64)), ("k", ctypes.POINTER(ctypes.c_int32)),
+                ("n_c", ctypes.POINTER(ctypes.c_int32))]
+
+
+class Instances:
+    """Independent instances over one point set: instance t owns rows
+    [offsets[t], offsets[t+1]); optional per-instance k and n_c (host arrays)."""
+
+    def __init__(self, offsets, k=None, n_c=None):
+        import numpy as np
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.count = len(self.offsets) - 1
+        self.k = None if k is None else np.ascontiguousarray(k, dtype=np.int32)
+        self.n_c = None if n_c is None else np.ascontiguousarray(n_c, dtype=np.int32)
+        if self.count < 1 or (self.k is not None and len(self.k) != self.count) or \
+                (self.n_c is not None and len(self.n_c) != self.count):
+            raise PecannError("instance tables have inconsistent lengths")
+
+    @property
+    def k_max(self) -> int:
+        return int(self.k.max()) if self.k is not None else 0
+
+    @property
+    def struct(self):
+        def p(a, t):
+            return None if a is None else a.ctypes.data_as(ctypes.POINTER(t))
+        return _Instances(self.count, 0, p(self.offsets, ctypes.c_int64), p(self.k, ctypes.c_int32),
+                          p(self.n_c, ctypes.c_int32))
+
+
 _lib = None
 
 
@@ -67,6 +99,7 @@ def load():
     vp, i32, i64, f32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
     D = ctypes.POINTER(_Dataset)
     B = ctypes.POINTER(_BuildParams)
+    N = ctypes.POINTER(_Instances)
     sig = {
         "pecann_prepared_bytes": (sz, [i64, i32, i32, i32]),
         "pecann_prepare_vectors": (ctypes.c_int, [vp, i32, i64, i64, i32, i32, i32, vp, sz, vp]),
@@ -82,6 +115,18 @@ def load():
         "pecann_cluster": (ctypes.c_int, [i64, vp, vp, vp, i32, i32, f32, f32, vp, vp, vp, sz, vp]),
         "pecann_profile_enable": (ctypes.c_int, [i32]),
         "pecann_profile_report": (i32, [ctypes.POINTER(_ProfileEntry), i32]),
+        "pecann_build_graph_batched_workspace_size": (sz, [D, B, N]),
+        "pecann_build_graph_batched": (ctypes.c_int, [D, B, N, vp, ctypes.c_uint64, vp, vp, vp, vp, sz,
+                                                      vp]),
+        "pecann_knn_density_batched_workspace_size": (sz, [D, N, i32, i32, i32]),
+        "pecann_knn_density_batched": (ctypes.c_int, [D, N, vp, vp, i32, i32, i32, i32, vp, vp, vp, vp,
+                                                      vp, vp, sz, vp]),
+        "pecann_dependent_search_batched_workspace_size": (sz, [D, N, i32, i32]),
+        "pecann_dependent_search_batched": (ctypes.c_int, [D, N, vp, vp, i32, vp, vp, vp, i32, i32, i32,
+                                                           i32, i32, vp, vp, vp, vp, sz, vp]),
+        "pecann_cluster_batched_workspace_size": (sz, [i64, N]),
+        "pecann_cluster_batched": (ctypes.c_int, [i64, N, vp, vp, vp, i32, i32, f32, f32, vp, vp, vp, sz,
+                                                  vp]),
         "pecann_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "pecann_last_error": (ctypes.c_char_p, []),
     }
@@ -276,3 +321,130 @@ def cluster(rho, dep, delta, n_c: int = 1, center_mode: int = CENTER_PRODUCT,
     _check(lib.pecann_cluster(n, _ptr(rho), _ptr(dep), _ptr(delta), center_mode, n_c, delta_min,
                               rho_min, _ptr(labels), _ptr(isc), _ptr(ws), ws.numel(), _stream()))
     return labels, isc
+
+
+# ---------------------------------------------------------------------------
+# Batches of independent instances (pecann_*_batched)
+# ---------------------------------------------------------------------------
+def build_graph_batched(ds: Dataset, inst: Instances, R: int, L: int, alpha: float,
+                        num_starts: int = 8, max_batch: int = 0, visited_cap: int = 0,
+                        perm: torch.Tensor | None = None, seed: int = 0, passes: int = 2,
+                        ws: torch.Tensor | None = None, out=None,
+                        counters: torch.Tensor | None = None):
+    """Vamana construction of every instance.  -> (adj int32 [n, R], deg int32 [n])."""
+    lib = load()
+    s, ni = ds.struct, inst.struct
+    bp = _BuildParams(R, L, alpha, num_starts, max_batch, visited_cap, passes, 0)
+    need = lib.pecann_build_graph_batched_workspace_size(ctypes.byref(s), ctypes.byref(bp),
+                                                         ctypes.byref(ni))
+    if need == 0:
+        raise PecannError(f"invalid build parameters or instances: {lib.pecann_last_error().decode()}")
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, ds.device)
+    if perm is not None:
+        _need_cuda(perm)
+        if perm.dtype != torch.int32 or perm.numel() != ds.n:
+            raise PecannError("perm must be int32 with n entries")
+    if out is None:
+        out = (torch.empty((ds.n, R), dtype=torch.int32, device=ds.device),
+               torch.empty(ds.n, dtype=torch.int32, device=ds.device))
+    adj, deg = out
+    _check(lib.pecann_build_graph_batched(ctypes.byref(s), ctypes.byref(bp), ctypes.byref(ni),
+                                          _ptr(perm), seed, _ptr(adj), _ptr(deg), _ptr(counters),
+                                          _ptr(ws), ws.numel(), _stream()))
+    return adj, deg
+
+
+def knn_density_batched(ds: Dataset, inst: Instances, k_max: int, adj=None, deg=None,
+                        L_search: int = 64, rerank: int | None = None,
+                        ws: torch.Tensor | None = None, out=None,
+                        counters: torch.Tensor | None = None):
+    """kNN + kth density of every instance; rows of stride k_max.
+    -> (knn_idx int32 [n,k_max], knn_dist f32 [n,k_max], rho f32 [n], rank_key int64 [n])."""
+    lib = load()
+    s, ni = ds.struct, inst.struct
+    R = 0 if adj is None else adj.shape[1]
+    if rerank is None:
+        rerank = min(L_search, 2 * k_max)
+    need = lib.pecann_knn_density_batched_workspace_size(ctypes.byref(s), ctypes.byref(ni), k_max,
+                                                         L_search, 1 if adj is None else 0)
+    if need == 0:
+        raise PecannError(f"invalid instances: {lib.pecann_last_error().decode()}")
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, ds.device)
+    if out is None:
+        out = (torch.empty((ds.n, k_max), dtype=torch.int32, device=ds.device),
+               torch.empty((ds.n, k_max), dtype=torch.float32, device=ds.device),
+               torch.empty(ds.n, dtype=torch.float32, device=ds.device),
+               torch.empty(ds.n, dtype=torch.int64, device=ds.device))
+    idx, dist, rho, key = out
+    _check(lib.pecann_knn_density_batched(ctypes.byref(s), ctypes.byref(ni), _ptr(adj), _ptr(deg), R,
+                                          k_max, L_search, rerank, _ptr(idx), _ptr(dist), _ptr(rho),
+                                          _ptr(key), _ptr(counters), _ptr(ws), ws.numel(), _stream()))
+    return idx, dist, rho, key
+
+
+def dependent_search_batched(ds: Dataset, inst: Instances, rank_key, knn_idx, knn_dist, adj=None,
+                             deg=None, L_d: int = 32, L_search: int = 64, threshold: int = 300,
+                             kdep_cap: int = 1024, ws: torch.Tensor | None = None, out=None):
+    """Alg. 3 on every instance.  -> (dep int32 [n], delta f32 [n], stats int32 [32])."""
+    lib = load()
+    s, ni = ds.struct, inst.struct
+    k_max = knn_idx.shape[1]
+    R = 0 if adj is None else adj.shape[1]
+    need = lib.pecann_dependent_search_batched_workspace_size(ctypes.byref(s), ctypes.byref(ni),
+                                                              kdep_cap, L_search)
+    if need == 0:
+        raise PecannError(f"invalid instances: {lib.pecann_last_error().decode()}")
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, ds.device)
+    if out is None:
+        out = (torch.empty(ds.n, dtype=torch.int32, device=ds.device),
+               torch.empty(ds.n, dtype=torch.float32, device=ds.device),
+               torch.zeros(32, dtype=torch.int32, device=ds.device))
+    dep, delta, stats = out
+    _check(lib.pecann_dependent_search_batched(ctypes.byref(s), ctypes.byref(ni), _ptr(adj), _ptr(deg),
+                                               R, _ptr(rank_key), _ptr(knn_idx), _ptr(knn_dist), k_max,
+                                               L_d, L_search, threshold, kdep_cap, _ptr(dep),
+                                               _ptr(delta), _ptr(stats), _ptr(ws), ws.numel(),
+                                               _stream()))
+    return dep, delta, stats
+
+
+def cluster_batched(inst: Instances, rho, dep, delta, n_c: int = 1,
+                    center_mode: int = CENTER_PRODUCT, delta_min: float = 0.0,
+                    rho_min: float = 0.0, ws: torch.Tensor | None = None, out=None):
+    """Noise, centers, labels of every instance.  -> (labels int32 [n], is_center uint8 [n])."""
+    lib = load()
+    n = rho.numel()
+    ni = inst.struct
+    need = lib.pecann_cluster_batched_workspace_size(n, ctypes.byref(ni))
+    if need == 0:
+        raise PecannError(f"invalid instances: {lib.pecann_last_error().decode()}")
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, rho.device)
+    if out is None:
+        out = (torch.empty(n, dtype=torch.int32, device=rho.device),
+               torch.empty(n, dtype=torch.uint8, device=rho.device))
+    labels, isc = out
+    _check(lib.pecann_cluster_batched(n, ctypes.byref(ni), _ptr(rho), _ptr(dep), _ptr(delta),
+                                      center_mode, n_c, delta_min, rho_min, _ptr(labels), _ptr(isc),
+                                      _ptr(ws), ws.numel(), _stream()))
+    return labels, isc
+
+
+def workspace_bytes_batched(ds: Dataset, inst: Instances, k_max: int, L_search: int, kdep_cap: int,
+                            R: int, L: int, alpha: float = 1.2, num_starts: int = 8,
+                            max_batch: int = 0, visited_cap: int = 0, passes: int = 2,
+                            exact: bool = False) -> int:
+    """One workspace size that serves every batched call of a DPC run on ds."""
+    lib = load()
+    s, ni = ds.struct, inst.struct
+    bp = _BuildParams(R, L, alpha, num_starts, max_batch, visited_cap, passes, 0)
+    return max(lib.pecann_build_graph_batched_workspace_size(ctypes.byref(s), ctypes.byref(bp),
+                                                             ctypes.byref(ni)),
+               lib.pecann_knn_density_batched_workspace_size(ctypes.byref(s), ctypes.byref(ni), k_max,
+                                                             L_search, 1 if exact else 0),
+               lib.pecann_dependent_search_batched_workspace_size(ctypes.byref(s), ctypes.byref(ni),
+                                                                  kdep_cap, L_search),
+               lib.pecann_cluster_batched_workspace_size(ds.n, ctypes.byref(ni)))

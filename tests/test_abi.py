@@ -88,3 +88,39 @@ def test_argument_errors_are_synchronous(lib):
     rc = lib.pecann_cluster(10, 256, 256, 256, 0, 1, 0.0, 0.0, 256, 256, 256, 8, None)
     assert rc == 2
     assert lib.pecann_status_string(2) == b"workspace too small"
+
+
+def test_batched_instance_tables_are_validated(lib):
+    # offsets must cover [0, n) with instances of at least 2 points; per-instance
+    # k within [1, min(n_t - 1, k_max)] and n_c within [1, n_t]
+    ds = pecann._Dataset(100, 16, pecann.L2, pecann.F32, 0, 256)  # fake aligned prep address
+    bp = pecann._BuildParams(16, 32, 1.2, 4, 0, 0, 2, 0)
+
+    def ws_build(off, **kw):
+        inst = pecann.Instances(off, **kw)
+        return lib.pecann_build_graph_batched_workspace_size(ctypes.byref(ds), ctypes.byref(bp),
+                                                             ctypes.byref(inst.struct))
+
+    assert ws_build([0, 40, 100]) > 0
+    assert ws_build([0, 100]) == lib.pecann_build_graph_workspace_size(ctypes.byref(ds), ctypes.byref(bp))
+    assert ws_build([0, 40, 99]) == 0    # does not end at n
+    assert ws_build([1, 40, 100]) == 0   # does not start at 0
+    assert ws_build([0, 99, 100]) == 0   # a 1-point instance
+    assert ws_build([0, 60, 40, 100]) == 0
+    # the workspace grows with the instances' batch caps
+    big = pecann._Dataset(200_000, 16, pecann.L2, pecann.F32, 0, 256)
+    one = lib.pecann_build_graph_workspace_size(ctypes.byref(big), ctypes.byref(bp))
+    two = lib.pecann_build_graph_batched_workspace_size(
+        ctypes.byref(big), ctypes.byref(bp), ctypes.byref(pecann.Instances([0, 100_000, 200_000]).struct))
+    assert two > one
+
+    inst = pecann.Instances([0, 40, 100], k=[5, 50], n_c=[2, 3])
+    # k of instance 1 (50) exceeds k_max = 10
+    rc = lib.pecann_knn_density_batched(ctypes.byref(ds), ctypes.byref(inst.struct), None, None, 0, 10, 64,
+                                        10, None, None, None, None, None, None, 0, None)
+    assert rc == 1 and b"k of instance 1" in lib.pecann_last_error()
+    bad_nc = pecann.Instances([0, 40, 100], n_c=[2, 61])
+    rc = lib.pecann_cluster_batched(100, ctypes.byref(bad_nc.struct), ctypes.c_void_p(256),
+                                    ctypes.c_void_p(256), ctypes.c_void_p(256), 0, 1, 0.0, 0.0,
+                                    ctypes.c_void_p(256), ctypes.c_void_p(256), None, 0, None)
+    assert rc == 1 and b"n_c of instance 1" in lib.pecann_last_error()
