@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=16000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-quality", action="store_true",
+                    help="skip the reference clustering and the quality gates (profiling runs)")
     ap.add_argument("--variant-steps", type=int, default=None,
                     help="timed steps of each variant (default 3; 1 for the 1M-point workloads)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -420,7 +422,9 @@ def main():
     ref = None
     ref_lab = sample = None
     ref_kind = None
-    if args.config == 2 and os.path.exists(os.path.join(GOLDEN, "c2_reference.npz")):
+    if args.no_quality:
+        pass
+    elif args.config == 2 and os.path.exists(os.path.join(GOLDEN, "c2_reference.npz")):
         ref = np.load(os.path.join(GOLDEN, "c2_reference.npz"))
         ref_lab = {"labels": ref["labels"]}
         ref_kind = "oracle exact DPC (tests/golden/c2_reference.npz)"
