@@ -25,6 +25,9 @@ struct SortedList {
   uint64_t *tmp;    // 64 keys of scratch
   int cap;
   int m;            // entries held
+  int hint;         // every entry before index `hint` is flagged
+
+  __device__ __forceinline__ void reset() { m = 0; hint = 0; }
 
   __device__ __forceinline__ void swap_bufs() {
     uint64_t *t = a; a = b; b = t;
@@ -32,12 +35,57 @@ struct SortedList {
   }
 
   // Merge one candidate key per lane (kNoKey = none) into the list, keeping the
-  // `cap` smallest.  Keys already present are ignored.  Returns the number of
-  // keys that entered the list.
+  // `cap` smallest.  Keys already present are ignored; the keys of one call are
+  // distinct.  Returns the number of keys that entered the list.
   __device__ int merge(uint64_t mykey) {
-    const int l = lane_id();
     if (m == cap && mykey != kNoKey && mykey >= a[cap - 1]) mykey = kNoKey;
-    if (ballot(mykey != kNoKey) == 0) return 0;
+    const uint64_t cm = ballot(mykey != kNoKey);
+    if (cm == 0) return 0;
+    return __popcll(cm) <= 16 ? merge_few(mykey) : merge_sorted(mykey);
+  }
+
+  // Few candidates: each finds its place in the list by binary search and its
+  // rank among the others by direct comparison (no sort).
+  __device__ int merge_few(uint64_t mykey) {
+    const int l = lane_id();
+    bool valid = mykey != kNoKey;
+    int pos = 0;
+    if (valid) {
+      pos = lower_bound_u64(a, m, mykey);
+      if (pos < m && a[pos] == mykey) valid = false;
+    }
+    const uint64_t vb = ballot(valid);
+    const int nc = __popcll(vb);
+    if (nc == 0) return 0;
+    const int slot = lanes_below(vb);
+    if (valid) tmp[slot] = mykey;
+    wave_lds_sync();
+    int r = 0;
+    if (valid) {
+      for (int t = 0; t < nc; ++t) r += tmp[t] < mykey;
+      const int np = pos + r;
+      if (np < cap) { b[np] = mykey; fb[np] = 0; }
+    }
+    for (int j = l; j < m; j += kWave) {
+      const uint64_t k = a[j];
+      int rj = 0;
+      for (int t = 0; t < nc; ++t) rj += tmp[t] < k;
+      const int np = j + rj;
+      if (np < cap) { b[np] = k; fb[np] = fa[j]; }
+    }
+    // the smallest new key lands at its own lower bound
+    const uint64_t lead = ballot(valid && r == 0);
+    const int first_new = __shfl(pos, __builtin_ctzll(lead));
+    wave_lds_sync();
+    swap_bufs();
+    m = min(cap, m + nc);
+    hint = min(min(hint, first_new), m);
+    return nc;
+  }
+
+  // Many candidates: bitonic sort across the wave, then merge by ranks.
+  __device__ int merge_sorted(uint64_t mykey) {
+    const int l = lane_id();
     uint64_t s = wave_sort_u64(mykey);
     bool valid = (s != kNoKey);
     uint64_t prev = shfl_u64(s, l > 0 ? l - 1 : 0);
@@ -62,20 +110,26 @@ struct SortedList {
       const int np = j + lower_bound_u64(tmp, nc, k);
       if (np < cap) { b[np] = k; fb[np] = fa[j]; }
     }
+    const int first_new = __shfl(pos, __builtin_ctzll(vb));
     wave_lds_sync();
     swap_bufs();
     m = min(cap, m + nc);
+    hint = min(min(hint, first_new), m);
     return nc;
   }
 
-  // Index of the first entry whose flag is 0, or -1.
-  __device__ __forceinline__ int first_unflagged() const {
+  // Index of the first entry whose flag is 0, or -1 (scans from `hint`).
+  __device__ __forceinline__ int first_unflagged() {
     const int l = lane_id();
-    for (int base = 0; base < m; base += kWave) {
+    for (int base = hint; base < m; base += kWave) {
       const int j = base + l;
       const uint64_t bm = ballot(j < m && fa[j] == 0);
-      if (bm) return base + __builtin_ctzll(bm);
+      if (bm) {
+        hint = base + __builtin_ctzll(bm);
+        return hint;
+      }
     }
+    hint = m;
     return -1;
   }
 };

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(64) void bf_knn_kernel(BfKnnParams p) {
     const int k = p.inst.k[ti];
     top.cap = k;
     eng.load_query(p.rows, qid);
-    top.m = 0;
+    top.reset();
     wave_lds_sync();
     for (int base = lo; base < hi; base += kWave) {
       const int c = min(kWave, hi - base);

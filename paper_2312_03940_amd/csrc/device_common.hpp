@@ -253,7 +253,10 @@ struct Engine {
   static_assert(S >= 4 && S <= 1024 && (S & (S - 1)) == 0, "shape must be a power of two in [4, 1024]");
   static_assert(!XR || DT == PECANN_F32, "the rerank rows are float32");
   static constexpr int EPC = RowFmt<DT>::EPC;
-  static constexpr int CPL_Q = (32 / EPC) < S ? 32 / EPC : S;  // query budget: 32 floats
+  // query budget: 32 floats per lane (16 for the rerank rows, whose engine is
+  // live next to the search engine's state)
+  static constexpr int QCAP = XR ? 16 : 32;
+  static constexpr int CPL_Q = (QCAP / EPC) < S ? QCAP / EPC : S;
   static constexpr int CPL = (S / kWave) > CPL_Q ? S / kWave : CPL_Q;
   static constexpr int G = S / CPL;
   static constexpr int NPL = kWave / G;

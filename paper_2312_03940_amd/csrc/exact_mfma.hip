@@ -208,7 +208,7 @@ __global__ __launch_bounds__(64) void exact_rerank_kernel(ExactMfmaParams p, flo
     const int q = next_item(p.head);
     if (q >= p.n) break;
     eng.load_query(p.rows, q);
-    top.m = 0;
+    top.reset();
     wave_lds_sync();
     const int32_t *c = p.cand + (int64_t)q * kCand;
     for (int base = 0; base < kCand; base += kWave) {

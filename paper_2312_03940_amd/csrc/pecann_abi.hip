@@ -292,12 +292,18 @@ struct Carver {
 };
 
 // Visited-hash size of a search with beam L: about 20 L slots (a search
-// visits some 15 L distinct points), between 2^10 and 2^13.  The hash may
-// forget (results do not change, only repeated distance evaluations), and a
-// larger table costs occupancy: 4096 slots measured best at L = 128 and 200.
-static int hash_bits_for(int L) {
+// visits some 15 L distinct points), or 10 L for build searches over search
+// rows under 512 bytes, between 2^10 and 2^13.  The hash may forget (results
+// do not change, only repeated distance evaluations) and a larger table costs
+// occupancy; a forgotten point costs a row gather, so short rows favour the
+// smaller table.  Measured (build searches): 784-d float32 rows, L = 128:
+// 4096 slots 196 ms, 2048 223 ms; 128-d BF16 rows, L = 128: 4096 496 ms, 2048
+// 453 ms; 1024-d FP8, L = 200: 4096 and 2048 within 2 %.  The kNN search of
+// the 128-d BF16 rows (L = 64) was faster with 2048 slots than with 1024.
+static int hash_bits_for(int L, size_t row_bytes, bool build) {
+  const int mult = (build && row_bytes < 512) ? 10 : 20;
   int b = 10;
-  while (b < 13 && (1 << b) < 20 * L) ++b;
+  while (b < 13 && (1 << b) < mult * L) ++b;
   return b;
 }
 
@@ -622,7 +628,7 @@ static pecann_status build_impl(const pecann_dataset *ds, const pecann_build_par
   sp.item_ns = w.item_ns;
   sp.items = w.items;
   sp.L = bp->L;
-  sp.hbits = hash_bits_for(bp->L);
+  sp.hbits = hash_bits_for(bp->L, L.xs_stride, true);
   sp.mode = MODE_BUILD;
   sp.vis = w.vis;
   sp.vis_count = w.vis_count;
@@ -893,7 +899,7 @@ static pecann_status knn_impl(const pecann_dataset *ds, const InstSpec &spec, co
   sp.nstarts = 0;
   sp.inst = itab;
   sp.L = L_search;
-  sp.hbits = hash_bits_for(L_search);
+  sp.hbits = hash_bits_for(L_search, L.xs_stride, false);
   sp.mode = MODE_KNN;
   sp.rerank = rerank;
   sp.k = k;
@@ -1063,7 +1069,7 @@ static pecann_status dep_impl(const pecann_dataset *ds, const InstSpec &spec, co
       sp.nstarts = 0;
       sp.inst = itab;
       sp.L = (int32_t)std::max<int64_t>(kd, L_search);
-      sp.hbits = hash_bits_for(sp.L);
+      sp.hbits = hash_bits_for(sp.L, L.xs_stride, false);
       sp.mode = MODE_DEP;
       sp.rerank = (int32_t)kd;
       sp.kdep = (int32_t)kd;

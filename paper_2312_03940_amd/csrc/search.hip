@@ -34,7 +34,7 @@ __device__ __forceinline__ Lds carve(uint8_t *smem, int L, int hbits) {
   s.hash.slot = (int32_t *)(f + 2 * Lp);
   s.hash.bits = hbits;
   s.beam.cap = L;
-  s.beam.m = 0;
+  s.beam.reset();
   s.n_exp = s.n_ids = s.n_rows = 0;
   return s;
 }
@@ -90,7 +90,7 @@ __device__ __forceinline__ void rerank_beam(const SearchParams &p, Lds &s, int32
 }  // namespace
 
 template <int DT, int S, int MODE>
-__global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
+__device__ __forceinline__ void search_body(const SearchParams &p) {
   extern __shared__ __align__(16) uint8_t smem[];
   Lds s = carve(smem, p.L, p.hbits);
   const int l = lane_id();
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
     }
 
     s.hash.clear();
-    s.beam.m = 0;
+    s.beam.reset();
     wave_lds_sync();
     eng.load_query(p.rows, qid);
     if (l == 0) s.hash.insert(qid);  // the query never takes a beam slot
@@ -223,6 +223,18 @@ __global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
   }
 }
 
+template <int DT, int S, int MODE>
+__global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
+  search_body<DT, S, MODE>(p);
+}
+// The kNN search with a register budget for three waves per SIMD (168 VGPRs):
+// there the extra wave hides more gather latency than the few spilled
+// registers cost (measured); the build and doubling searches gained nothing.
+template <int DT, int S>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void search_knn_kernel(SearchParams p) {
+  search_body<DT, S, MODE_KNN>(p);
+}
+
 size_t search_lds_bytes(int L, int hbits) {
   const size_t Lp = (size_t)((L + 15) & ~15);
   return 8 * (2 * (size_t)L + 64) + 4 * 64 + 2 * Lp + 4 * ((size_t)1 << hbits);
@@ -236,7 +248,7 @@ static hipError_t launch_search_t(const SearchParams &p, int grid, hipStream_t s
   const size_t lds = search_lds_bytes(p.L, p.hbits);
   switch (p.mode) {
     case MODE_KNN:
-      hipLaunchKernelGGL((search_kernel<DT, S, MODE_KNN>), dim3(grid), dim3(64), lds, st, p);
+      hipLaunchKernelGGL((search_knn_kernel<DT, S>), dim3(grid), dim3(64), lds, st, p);
       break;
     case MODE_DEP:
       hipLaunchKernelGGL((search_kernel<DT, S, MODE_DEP>), dim3(grid), dim3(64), lds, st, p);
