@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=16000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the variant that replays the step from a captured HIP graph")
     ap.add_argument("--no-quality", action="store_true",
                     help="skip the reference clustering and the quality gates (profiling runs)")
     ap.add_argument("--variant-steps", type=int, default=None,
@@ -342,6 +344,35 @@ def measure(x, wl, search, mode, args, perm, steps, warmup, ref=None, sample=Non
     return rec, pl, kprof
 
 
+def measure_graph(x, wl, search, args, perm, steps, inst=None):
+    """The whole step captured into one HIP graph, timed by replays.  Labels of
+    the last replay must equal those of an eager step."""
+    import torch
+    pl = Pipeline(x, wl, search, "anns", args, perm, inst)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        pl.step()  # warm-up on a side stream before capture
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    eager = pl.c_out[0].cpu().numpy().copy()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pl.step()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    same = bool(np.array_equal(pl.c_out[0].cpu().numpy(), eager))
+    n = pl.ds.n
+    del g, pl
+    return {"value": round(n * steps / wall, 1), "ms_per_step": round(wall * 1e3 / steps, 3),
+            "steps": steps, "labels_equal_eager": same}
+
+
 def roofline(pl, kprof, steps, search, n, d, k):
     """Roofline of the dominant gather kernel family, from its own work counters."""
     bc, kc = pl.counters()
@@ -498,6 +529,11 @@ def main():
             variants[f"{vs}_{vm}"] = {key: r[key] for key in ("value", "ms_per_step", "phases_ms",
                                                               "quality", "knn_queries_per_s")}
             del p2
+            torch.cuda.empty_cache()
+        if not args.no_graph and args.mode == "anns":
+            log("graph replay variant")
+            vsteps = args.variant_steps or (3 if args.config == 2 else 1)
+            variants[f"{search}_anns_graph_replay"] = measure_graph(x, wl, search, args, perm, vsteps, inst)
             torch.cuda.empty_cache()
         out["variants"] = variants
     if args.config == 2 and not args.no_cpu_baseline and ref is not None:
