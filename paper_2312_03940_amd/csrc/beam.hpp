@@ -45,7 +45,9 @@ struct SortedList {
   }
 
   // Few candidates: each finds its place in the list by binary search and its
-  // rank among the others by direct comparison (no sort).
+  // rank among the others by direct comparison (no sort); the list is updated
+  // in place, moving only the entries behind the first insertion point (in
+  // 64-entry chunks from the top, each read before any of it is written).
   __device__ int merge_few(uint64_t mykey) {
     const int l = lane_id();
     bool valid = mykey != kNoKey;
@@ -61,23 +63,31 @@ struct SortedList {
     if (valid) tmp[slot] = mykey;
     wave_lds_sync();
     int r = 0;
-    if (valid) {
+    if (valid)
       for (int t = 0; t < nc; ++t) r += tmp[t] < mykey;
-      const int np = pos + r;
-      if (np < cap) { b[np] = mykey; fb[np] = 0; }
-    }
-    for (int j = l; j < m; j += kWave) {
-      const uint64_t k = a[j];
-      int rj = 0;
-      for (int t = 0; t < nc; ++t) rj += tmp[t] < k;
-      const int np = j + rj;
-      if (np < cap) { b[np] = k; fb[np] = fa[j]; }
-    }
-    // the smallest new key lands at its own lower bound
+    // the smallest new key lands at its own lower bound; entries before it stay
     const uint64_t lead = ballot(valid && r == 0);
     const int first_new = __shfl(pos, __builtin_ctzll(lead));
+    for (int top = m; top > first_new;) {
+      const int c0 = max(first_new, top - kWave);
+      const int j = c0 + l;
+      uint64_t k = 0;
+      uint8_t f = 0;
+      int np = cap;
+      if (j < top) {
+        k = a[j];
+        f = fa[j];
+        int rj = 0;
+        for (int t = 0; t < nc; ++t) rj += tmp[t] < k;
+        np = j + rj;
+      }
+      wave_lds_sync();
+      if (np < cap) { a[np] = k; fa[np] = f; }
+      wave_lds_sync();
+      top = c0;
+    }
+    if (valid && pos + r < cap) { a[pos + r] = mykey; fa[pos + r] = 0; }
     wave_lds_sync();
-    swap_bufs();
     m = min(cap, m + nc);
     hint = min(min(hint, first_new), m);
     return nc;
@@ -134,26 +144,38 @@ struct SortedList {
   }
 };
 
-// Open-addressing set of int32 ids in LDS (slots hold -1 when empty).  It may
-// forget: when a probe sequence is exhausted the id is reported as new, which
-// only costs a repeated distance evaluation -- the sorted list drops the
-// duplicate key, because a point's key is a deterministic function of it.
+// Open-addressing set of int32 ids in LDS (slots hold -1 when empty), in
+// buckets of four slots (16 bytes, read at once).  A lookup reads a bucket,
+// and claims an empty slot with a compare-and-swap only when the id is absent;
+// it visits at most four buckets.  The set may forget: when they are full the
+// id is reported as new, which only costs a repeated distance evaluation --
+// the sorted list drops the duplicate key, because a point's key is a
+// deterministic function of it.  The ids inserted by one call are distinct.
 struct IdHash {
-  int32_t *slot;
-  int bits;
+  int32_t *slot;  // 16-byte aligned
+  int bits;       // log2 of the slot count (>= 3)
   __device__ __forceinline__ void clear() {
     const int H = 1 << bits;
     for (int s = lane_id(); s < H; s += kWave) slot[s] = -1;
   }
   // true if id was not in the set (and is now, if there was room)
   __device__ __forceinline__ bool insert(int32_t id) {
-    const uint32_t mask = (1u << bits) - 1u;
-    uint32_t s = ((uint32_t)id * 2654435761u) >> (32 - bits);
-    for (int probe = 0; probe < 16; ++probe) {
-      const int old = atomicCAS(&slot[s], -1, id);
-      if (old == -1) return true;
-      if (old == id) return false;
-      s = (s + 1) & mask;
+    const int bb = bits - 2;
+    const uint32_t mask = (1u << bb) - 1u;
+    uint32_t b = ((uint32_t)id * 2654435761u) >> (32 - bb);
+    for (int probe = 0; probe < 4; ++probe) {
+      int32_t *bucket = slot + 4 * b;
+      const int4 v = *(const int4 *)bucket;
+      if (v.x == id || v.y == id || v.z == id || v.w == id) return false;
+      const int e4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (e4[e] != -1) continue;
+        const int old = atomicCAS(&bucket[e], -1, id);
+        if (old == -1) return true;
+        if (old == id) return false;
+      }
+      b = (b + 1) & mask;
     }
     return true;
   }
