@@ -91,6 +91,12 @@ def load():
         lib.oracle_dependent_alg3.argtypes = [P, vp, vp, i32, vp, vp, i32, i32, i64, i32,
                                               i32, vp, vp, vp, i32]
         lib.oracle_dependent_alg3.restype = i32
+        lib.oracle_density.argtypes = [i64, i32, i32, vp, vp, vp]
+        lib.oracle_density.restype = ctypes.c_int
+        lib.oracle_rank_density.argtypes = [i64, vp, vp, vp]
+        lib.oracle_rank_density.restype = None
+        lib.oracle_local_centers.argtypes = [i64, i32, vp, vp, vp, f64, vp]
+        lib.oracle_local_centers.restype = None
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -161,14 +167,55 @@ def dependent_exact(P: Points, rank: np.ndarray, queries=None):
     return dep, delta
 
 
-def cluster(rho, dep, delta, n_c=1, center_mode=0, delta_min=0.0, rho_min=0.0):
-    """Noise, centers and root labels (Alg. 2).  -> (labels int64, is_center bool)."""
+DENSITY_FNS = {"kth": 0, "normalized": 1, "exp-sum": 2, "sum-exp": 3, "sum": 4}
+CENTER_PRODUCT, CENTER_THRESHOLD, CENTER_GIVEN = 0, 1, 2
+
+
+def density(knn_idx, knn_dist, fn="kth"):
+    """Density of every point from its k nearest neighbours (Sec. 4.2; App. A).
+    -> rho float64 [n]."""
+    idx = np.ascontiguousarray(knn_idx, dtype=np.int64)
+    dist = np.ascontiguousarray(knn_dist, dtype=np.float64)
+    n, k = idx.shape
+    rho = np.empty(n, dtype=np.float64)
+    if load().oracle_density(n, k, DENSITY_FNS[fn], _ptr(idx), _ptr(dist), _ptr(rho)) != 0:
+        raise ValueError(fn)
+    return rho
+
+
+def rank_from_rho(rho):
+    """Density order of any density function: rho descending, ties to the lower index.
+    -> (order, rank)."""
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    n = len(rho)
+    order = np.empty(n, dtype=np.int64)
+    rank = np.empty(n, dtype=np.int64)
+    load().oracle_rank_density(n, _ptr(rho), _ptr(order), _ptr(rank))
+    return order, rank
+
+
+def local_centers(knn_idx, rank, rho, rho_min=0.0):
+    """Non-noise points ranked above all their k nearest neighbours (App. A). -> bool [n]."""
+    idx = np.ascontiguousarray(knn_idx, dtype=np.int64)
+    rank = np.ascontiguousarray(rank, dtype=np.int64)
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    n, k = idx.shape
+    isc = np.zeros(n, dtype=np.uint8)
+    load().oracle_local_centers(n, k, _ptr(idx), _ptr(rank), _ptr(rho), ctypes.c_double(rho_min),
+                                _ptr(isc))
+    return isc.astype(bool)
+
+
+def cluster(rho, dep, delta, n_c=1, center_mode=0, delta_min=0.0, rho_min=0.0, centers=None):
+    """Noise, centers and root labels (Alg. 2).  center_mode 2 takes the given centers.
+    -> (labels int64, is_center bool)."""
     rho = np.ascontiguousarray(rho, dtype=np.float64)
     dep = np.ascontiguousarray(dep, dtype=np.int64)
     delta = np.ascontiguousarray(delta, dtype=np.float64)
     n = len(rho)
     labels = np.empty(n, dtype=np.int64)
-    isc = np.zeros(n, dtype=np.uint8)
+    isc = np.zeros(n, dtype=np.uint8) if centers is None else \
+        np.ascontiguousarray(centers, dtype=np.uint8).copy()
     rc = load().oracle_cluster(n, _ptr(rho), _ptr(dep), _ptr(delta), center_mode, n_c,
                                delta_min, rho_min, _ptr(labels), _ptr(isc))
     if rc != 0:

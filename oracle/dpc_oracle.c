@@ -181,6 +181,76 @@ void oracle_rank(int64_t n, const double *dk, int64_t *order, int64_t *rank) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Density functions from each point's k nearest neighbours N_i (ids and     */
+/* distances D, row i of knn_idx / knn_dist):                                 */
+/*   fn 0 kth (Sec. 4.2):        rho_i = 1 / D(x_i, k-th neighbour)          */
+/*   fn 1 normalized (Sec. 4.2): rho_i * k / sum_{j in N_i} rho_j, with the  */
+/*                               kth densities                               */
+/*   fn 2 exp-sum (App. A):      exp(-sum_{j in N_i} D(x_i, x_j)^2 / k)      */
+/*   fn 3 sum-exp (App. A):      sum_{j in N_i} exp(-D(x_i, x_j)^2) / k      */
+/*   fn 4 sum (App. A):          -sum_{j in N_i} D(x_i, x_j)                 */
+/* Returns 0, or -1 for an unknown function.                                 */
+/* ------------------------------------------------------------------------ */
+int oracle_density(int64_t n, int32_t k, int32_t fn, const int64_t *knn_idx,
+                   const double *knn_dist, double *rho) {
+  if (fn < 0 || fn > 4) return -1;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t *ids = knn_idx + i * k;
+    const double *ds = knn_dist + i * k;
+    double v = 0.0;
+    if (fn == 0) {
+      v = 1.0 / ds[k - 1];
+    } else if (fn == 1) {
+      double s = 0.0;
+      for (int32_t t = 0; t < k; ++t) s += 1.0 / knn_dist[ids[t] * k + (k - 1)];
+      v = (1.0 / ds[k - 1]) * k / s;
+    } else if (fn == 2) {
+      double s = 0.0;
+      for (int32_t t = 0; t < k; ++t) s += ds[t] * ds[t];
+      v = exp(-s / k);
+    } else if (fn == 3) {
+      double s = 0.0;
+      for (int32_t t = 0; t < k; ++t) s += exp(-ds[t] * ds[t]);
+      v = s / k;
+    } else {
+      double s = 0.0;
+      for (int32_t t = 0; t < k; ++t) s += ds[t];
+      v = -s;
+    }
+    rho[i] = v;
+  }
+  return 0;
+}
+
+/* Density order of any density function: rho descending, ties to the lower */
+/* index (the kth density gives the same order as oracle_rank on D_k).       */
+static int cmp_rho_desc_then_id(const void *a, const void *b) {
+  int64_t i = *(const int64_t *)a, j = *(const int64_t *)b;
+  double ri = g_sort_key[i], rj = g_sort_key[j];
+  if (ri > rj) return -1;
+  if (ri < rj) return 1;
+  return (i > j) - (i < j);
+}
+void oracle_rank_density(int64_t n, const double *rho, int64_t *order, int64_t *rank) {
+  for (int64_t i = 0; i < n; ++i) order[i] = i;
+  g_sort_key = rho;
+  qsort(order, (size_t)n, sizeof(int64_t), cmp_rho_desc_then_id);
+  g_sort_key = NULL;
+  for (int64_t r = 0; r < n; ++r) rank[order[r]] = r;
+}
+
+/* Local centers (App. A, Local Center): the non-noise points ranked above  */
+/* every one of their k nearest neighbours.                                  */
+void oracle_local_centers(int64_t n, int32_t k, const int64_t *knn_idx, const int64_t *rank,
+                          const double *rho, double rho_min, uint8_t *is_center) {
+  for (int64_t i = 0; i < n; ++i) {
+    int c = !(rho[i] < rho_min);
+    for (int32_t t = 0; t < k && c; ++t) c = rank[i] < rank[knn_idx[i * k + t]];
+    is_center[i] = (uint8_t)c;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Exact dependent point (Def. 1): lambda_i = argmin over points ranked      */
 /* strictly above i of (D(i,j), j); delta_i = D(i, lambda_i).  The top-ranked */
 /* point has lambda = -1 and delta = +inf.                                   */
@@ -214,6 +284,8 @@ void oracle_dependent_exact(const opoints *P, const int64_t *rank,
 /*            gamma_i = rho_i * delta_i, ties to the lower index; a product   */
 /*            that is not a number (inf * 0) counts as 0;                    */
 /*   center_mode 1 (threshold): non-noise points with delta_i >= delta_min;  */
+/*   center_mode 2 (given): is_center is an input (e.g. local centers);      */
+/*            noise points are never centers;                                */
 /*   labels:  non-noise, non-center points are joined with their dependent;  */
 /*            every point is labelled with the index of the root it reaches  */
 /*            (a center, a noise point, or the point with no dependent).     */
@@ -236,9 +308,12 @@ int oracle_cluster(int64_t n, const double *rho, const int64_t *dep,
   if (!noise) return -1;
   for (int64_t i = 0; i < n; ++i) {
     noise[i] = rho[i] < rho_min;
-    is_center[i] = 0;
+    if (center_mode == 2) is_center[i] = is_center[i] && !noise[i];
+    else is_center[i] = 0;
   }
-  if (center_mode == 0) {
+  if (center_mode == 2) {
+    /* the caller's centers */
+  } else if (center_mode == 0) {
     double *gamma = (double *)malloc(sizeof(double) * (size_t)n);
     int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     if (!gamma || !cand) { free(noise); free(gamma); free(cand); return -1; }

@@ -377,3 +377,87 @@ def test_u8_distance_exact(oracle_lib):
     Xi = X.astype(np.int64)
     for i, j in itertools.combinations(range(0, 50, 7), 2):
         assert oracle.distance(P, i, j) == math.sqrt(float(((Xi[i] - Xi[j]) ** 2).sum()))
+
+
+# ----------------------------------------------------------------------------
+# Density functions (Sec. 4.2 kth / normalized; App. A exp-sum, sum-exp, sum)
+# and the local center function (App. A).
+# ----------------------------------------------------------------------------
+def test_density_functions_closed_forms_on_a_lattice(oracle_lib):
+    # points 0, 1, ..., 9 on a line, k = 2.  Interior point: neighbours at 1, 1.
+    # End point 0: neighbours at 1 and 2.  Point 1: neighbours 0 and 2 (kth 1 and
+    # 1/2 for its end neighbour).
+    X = np.arange(10, dtype=np.float32).reshape(-1, 1)
+    idx, dist = oracle.knn(oracle.Points(X), 2)
+    e = math.exp
+    kth = oracle.density(idx, dist, "kth")
+    assert kth[0] == 0.5 and np.all(kth[1:9] == 1.0)
+    es = oracle.density(idx, dist, "exp-sum")
+    assert math.isclose(es[0], e(-(1 + 4) / 2), rel_tol=1e-15)
+    assert np.allclose(es[1:9], e(-1.0), rtol=1e-15)
+    se = oracle.density(idx, dist, "sum-exp")
+    assert math.isclose(se[0], (e(-1) + e(-4)) / 2, rel_tol=1e-15)
+    assert np.allclose(se[1:9], e(-1.0), rtol=1e-15)
+    sm = oracle.density(idx, dist, "sum")
+    assert sm[0] == -3.0 and np.all(sm[1:9] == -2.0)
+    nz = oracle.density(idx, dist, "normalized")
+    assert math.isclose(nz[1], 1.0 * 2 / (0.5 + 1.0), rel_tol=1e-15)  # next to an end
+    assert np.all(nz[2:8] == 1.0)  # all neighbours equally dense
+
+
+def test_density_functions_under_scaling(oracle_lib):
+    # scaling X by 4 (exact in binary floating point): kth -> /4, sum -> *4,
+    # normalized unchanged (it is a ratio of densities), the order by kth unchanged
+    X, _ = datagen.mixture(400, 3, 4, seed=8)
+    idx, dist = oracle.knn(oracle.Points(X), 7)
+    idx4, dist4 = oracle.knn(oracle.Points(X * 4), 7)
+    assert np.array_equal(idx, idx4)
+    assert np.allclose(oracle.density(idx4, dist4, "kth") * 4, oracle.density(idx, dist, "kth"), rtol=1e-15)
+    assert np.allclose(oracle.density(idx4, dist4, "sum"), 4 * oracle.density(idx, dist, "sum"), rtol=1e-15)
+    assert np.allclose(oracle.density(idx4, dist4, "normalized"), oracle.density(idx, dist, "normalized"),
+                       rtol=1e-13)
+    # the kth order of rank_from_rho equals rank_from_dk (Sec. 3 step 3)
+    _, r1 = oracle.rank_from_dk(dist[:, -1])
+    _, r2 = oracle.rank_from_rho(oracle.density(idx, dist, "kth"))
+    assert np.array_equal(r1, r2)
+
+
+def test_rank_from_rho_breaks_ties_by_index(oracle_lib):
+    order, rank = oracle.rank_from_rho(np.array([1.0, 3.0, 3.0, -2.0, 1.0]))
+    assert list(order) == [1, 2, 0, 4, 3] and list(rank) == [2, 0, 1, 4, 3]
+
+
+def test_local_centers_are_the_peaks(oracle_lib):
+    # two 1-D groups whose gaps grow strictly away from a peak point (at 10 and at
+    # 100): with k = 2 the peaks, and only they, rank above both neighbours
+    cum = np.cumsum([1, 2, 3, 4, 5]).astype(np.float64)       # 1, 3, 6, 10, 15
+    left = np.concatenate([10 - cum[::-1], [10.0], 10 + cum])   # peak at index 5
+    right = np.concatenate([100 - 1.5 * cum[::-1], [100.0], 100 + 1.5 * cum])  # index 16
+    X = np.concatenate([left, right]).astype(np.float32).reshape(-1, 1)
+    idx, dist = oracle.knn(oracle.Points(X), 2)
+    rho = oracle.density(idx, dist, "kth")
+    _, rank = oracle.rank_from_rho(rho)
+    isc = oracle.local_centers(idx, rank, rho)
+    assert set(np.nonzero(isc)[0]) == {5, 16}
+    # the densest point is always a local center; noise points never are
+    assert isc[np.argmin(rank)]
+    assert not oracle.local_centers(idx, rank, rho, rho_min=10.0).any()
+
+
+def test_cluster_with_given_centers(oracle_lib):
+    # given centers cut the dependent forest at those points; noise is never a center
+    X, _ = datagen.mixture(300, 2, 3, seed=12)
+    ref = oracle.exact_dpc(X, k=6, n_c=3)
+    isc = np.zeros(300, bool)
+    isc[np.argsort(ref["rank"])[:3]] = True  # the three densest points
+    labels, isc2 = oracle.cluster(ref["rho"], ref["dep"], ref["delta"], center_mode=oracle.CENTER_GIVEN,
+                                  centers=isc)
+    assert np.array_equal(isc2, isc)
+    roots = set(labels.tolist())
+    assert roots <= set(np.nonzero(isc)[0].tolist()) | {int(np.argmin(ref["rank"]))}
+    assert len(np.unique(labels)) == 3
+    rho_min = np.sort(ref["rho"])[10]
+    labels3, isc3 = oracle.cluster(ref["rho"], ref["dep"], ref["delta"], center_mode=oracle.CENTER_GIVEN,
+                                   centers=isc, rho_min=rho_min)
+    noise = ref["rho"] < rho_min
+    assert not (isc3 & noise).any() and np.array_equal(labels3[noise], np.nonzero(noise)[0])
