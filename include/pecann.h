@@ -64,7 +64,20 @@ typedef enum {
   PECANN_COSINE = 1  /* 1 - x.y / (|x| |y|) */
 } pecann_metric;
 
-typedef enum { PECANN_CENTER_PRODUCT = 0, PECANN_CENTER_THRESHOLD = 1 } pecann_center_mode;
+typedef enum {
+  PECANN_CENTER_PRODUCT = 0,    /* the n_c largest rho * delta (Sec. 4.2) */
+  PECANN_CENTER_THRESHOLD = 1,  /* delta >= delta_min (Sec. 4.2) */
+  PECANN_CENTER_GIVEN = 2       /* is_center is an input, e.g. from pecann_local_centers */
+} pecann_center_mode;
+
+/* Density functions (Sec. 4.2; appendix A). */
+typedef enum {
+  PECANN_DENSITY_KTH = 0,         /* 1 / D(x_i, k-th neighbour) */
+  PECANN_DENSITY_NORMALIZED = 1,  /* rho_i k / sum_{j in N_i} rho_j, kth densities */
+  PECANN_DENSITY_EXP_SUM = 2,     /* exp(-sum_{j in N_i} D(x_i, x_j)^2 / k) */
+  PECANN_DENSITY_SUM_EXP = 3,     /* sum_{j in N_i} exp(-D(x_i, x_j)^2) / k */
+  PECANN_DENSITY_SUM = 4          /* -sum_{j in N_i} D(x_i, x_j) */
+} pecann_density_fn;
 
 /* ---------------------------------------------------------------------------
  * Prepared point set.
@@ -232,12 +245,15 @@ pecann_status pecann_dependent_search(const pecann_dataset *ds, const int32_t *a
  *   centers: PECANN_CENTER_PRODUCT -- the n_c non-noise points with the
  *            largest gamma_i = rho_i * delta_i (float32 product; inf*0 counts
  *            as 0), ties to the lower index; PECANN_CENTER_THRESHOLD -- the
- *            non-noise points with delta_i >= delta_min;
+ *            non-noise points with delta_i >= delta_min; PECANN_CENTER_GIVEN --
+ *            is_center is an input (e.g. pecann_local_centers), noise points
+ *            are never centers;
  *   labels:  every non-noise, non-center point joins its dependent's cluster;
  *            labels[i] = index of the root reached along dep (a center, a
  *            noise point, or the point with dep = -1).
  * Inputs rho, dep, delta (device, n).  Outputs labels[n] int32, is_center[n]
- * uint8 (device).  Limits: 1 <= n_c <= n in product mode.
+ * uint8 (device; an input as well with PECANN_CENTER_GIVEN).  Limits:
+ * 1 <= n_c <= n in product mode.
  * ------------------------------------------------------------------------- */
 size_t pecann_cluster_workspace_size(int64_t n);
 pecann_status pecann_cluster(int64_t n, const float *rho, const int32_t *dep,
@@ -329,6 +345,37 @@ pecann_status pecann_cluster_batched(int64_t n, const pecann_instances *inst, co
                                      int32_t center_mode, int32_t n_c, float delta_min,
                                      float rho_min, int32_t *labels, uint8_t *is_center,
                                      void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Other density functions (Sec. 4.2: normalized; appendix A: exp-sum, sum-exp,
+ * sum; see pecann_density_fn) and the local center function (appendix A).
+ *
+ * pecann_density replaces rho and rank_key with those of another density
+ * function, computed in float32 from the kNN lists that pecann_knn_density(_batched)
+ * wrote (row stride k; rows of instance t hold k[t] neighbours when inst is
+ * given, inst NULL: one instance with this k).  Rank key: (~ordered(rho) << 32)
+ * | index, where ordered() maps a float to an unsigned integer of the same
+ * order, so a smaller key is a strictly higher density with ties to the lower
+ * index, as for the kth keys.  rho and rank_key may be the arrays written by
+ * pecann_knn_density (no element is read after it is written).  Densities of
+ * duplicate points (D = 0) are +inf (kth, normalized numerators) and the
+ * normalized density is then undefined.
+ *
+ * pecann_local_centers marks is_center[i] = 1 for the non-noise points
+ * (rho_i >= rho_min) whose rank key is smaller than that of each of their k
+ * nearest neighbours; pecann_cluster(_batched) with PECANN_CENTER_GIVEN then
+ * labels the dependent forest from those centers.
+ * ------------------------------------------------------------------------- */
+size_t pecann_density_workspace_size(int64_t n, const pecann_instances *inst);
+pecann_status pecann_density(int64_t n, const pecann_instances *inst, int32_t k,
+                             int32_t density_fn, const int32_t *knn_idx, const float *knn_dist,
+                             float *rho, uint64_t *rank_key, void *ws, size_t ws_bytes,
+                             void *stream);
+size_t pecann_local_centers_workspace_size(int64_t n, const pecann_instances *inst);
+pecann_status pecann_local_centers(int64_t n, const pecann_instances *inst, int32_t k,
+                                   const int32_t *knn_idx, const uint64_t *rank_key,
+                                   const float *rho, float rho_min, uint8_t *is_center, void *ws,
+                                   size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Kernel timing (host-side instrumentation, off by default).  While enabled,

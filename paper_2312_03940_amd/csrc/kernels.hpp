@@ -225,6 +225,13 @@ hipError_t launch_cluster(int64_t n, const InstTable &inst, const float *rho, co
                           int32_t *labels, uint8_t *is_center, uint64_t *gkey, int32_t *flag,
                           hipStream_t s);
 
+hipError_t launch_density(int64_t n, const InstTable &inst, int32_t kstride, int32_t fn,
+                          const int32_t *knn_idx, const float *knn_dist, float *rho,
+                          uint64_t *rank_key, hipStream_t s);
+hipError_t launch_local_centers(int64_t n, const InstTable &inst, int32_t kstride,
+                                const int32_t *knn_idx, const uint64_t *rank_key, const float *rho,
+                                float rho_min, uint8_t *is_center, hipStream_t s);
+
 // Host tables to device memory through kernel arguments (no host copy, no
 // synchronisation): dst[first + j] = v[j] for j < count <= 64.
 struct I64Chunk { int64_t v[64]; };

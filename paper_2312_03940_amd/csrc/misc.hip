@@ -347,10 +347,85 @@ hipError_t launch_copy_count(const int32_t *src, int32_t *dst, int32_t, hipStrea
   return hipGetLastError();
 }
 
+// Unsigned key with the order of the float (negative values included).
+__device__ __forceinline__ uint32_t ordered_bits(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// ---------------------------------------------------------------------------
+// Density functions from the kNN lists (Sec. 4.2 kth and normalized; the
+// appendix's exp-sum, sum-exp and sum), in float32 from the reported
+// distances.  Rank key: (~ordered_bits(rho) << 32) | index, so a smaller key
+// is a strictly higher density with ties to the lower index.
+// ---------------------------------------------------------------------------
+__global__ void density_kernel(int64_t n, InstTable inst, int32_t kstride, int32_t fn,
+                               const int32_t *knn_idx, const float *knn_dist, float *rho,
+                               uint64_t *rank_key) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int k = inst.k[find_instance(inst, i)];
+  const float *ds = knn_dist + i * kstride;
+  float v;
+  if (fn == PECANN_DENSITY_KTH) {
+    v = 1.0f / ds[k - 1];
+  } else if (fn == PECANN_DENSITY_NORMALIZED) {
+    float s = 0.f;
+    for (int t = 0; t < k; ++t) s += 1.0f / knn_dist[(int64_t)knn_idx[i * kstride + t] * kstride + (k - 1)];
+    v = (1.0f / ds[k - 1]) * (float)k / s;
+  } else if (fn == PECANN_DENSITY_EXP_SUM) {
+    float s = 0.f;
+    for (int t = 0; t < k; ++t) s = fmaf(ds[t], ds[t], s);
+    v = expf(-s / (float)k);
+  } else if (fn == PECANN_DENSITY_SUM_EXP) {
+    float s = 0.f;
+    for (int t = 0; t < k; ++t) s += expf(-ds[t] * ds[t]);
+    v = s / (float)k;
+  } else {
+    float s = 0.f;
+    for (int t = 0; t < k; ++t) s += ds[t];
+    v = -s;
+  }
+  rho[i] = v;
+  rank_key[i] = ((uint64_t)(~ordered_bits(v)) << 32) | (uint32_t)i;
+}
+hipError_t launch_density(int64_t n, const InstTable &inst, int32_t kstride, int32_t fn,
+                          const int32_t *knn_idx, const float *knn_dist, float *rho,
+                          uint64_t *rank_key, hipStream_t s) {
+  hipLaunchKernelGGL(density_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, inst,
+                     kstride, fn, knn_idx, knn_dist, rho, rank_key);
+  return hipGetLastError();
+}
+
+// Local centers (appendix, Local Center): non-noise points whose rank key is
+// smaller than that of every one of their k nearest neighbours.
+__global__ void local_centers_kernel(int64_t n, InstTable inst, int32_t kstride,
+                                     const int32_t *knn_idx, const uint64_t *rank_key,
+                                     const float *rho, float rho_min, uint8_t *is_center) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int k = inst.k[find_instance(inst, i)];
+  bool c = !(rho[i] < rho_min);
+  const uint64_t ki = rank_key[i];
+  for (int t = 0; t < k && c; ++t) {
+    const int32_t j = knn_idx[i * kstride + t];
+    c = j >= 0 && ki < rank_key[j];
+  }
+  is_center[i] = c ? 1 : 0;
+}
+hipError_t launch_local_centers(int64_t n, const InstTable &inst, int32_t kstride,
+                                const int32_t *knn_idx, const uint64_t *rank_key, const float *rho,
+                                float rho_min, uint8_t *is_center, hipStream_t s) {
+  hipLaunchKernelGGL(local_centers_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, inst,
+                     kstride, knn_idx, rank_key, rho, rho_min, is_center);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // K10 + K11: noise, centers, labels.
-// gkey[i] = 0 for noise; else (bits(gamma_i) << 32) | (0xffffffff - i), so the
-// n_c largest keys are the n_c largest gamma with ties to the lower index.
+// gkey[i] = 0 for noise; else (ordered_bits(gamma_i) << 32) | (0xffffffff - i),
+// so the n_c largest keys are the n_c largest gamma with ties to the lower
+// index (gamma may be negative for the `sum` density).
 // ---------------------------------------------------------------------------
 __global__ void gamma_kernel(int64_t n, const float *rho, const float *delta, int32_t center_mode,
                              float delta_min, float rho_min, uint64_t *gkey, uint8_t *is_center) {
@@ -360,11 +435,14 @@ __global__ void gamma_kernel(int64_t n, const float *rho, const float *delta, in
   if (center_mode == PECANN_CENTER_PRODUCT) {
     float g = rho[i] * delta[i];
     if (g != g) g = 0.f;  // inf * 0
-    gkey[i] = noise ? 0ull : (((uint64_t)__float_as_uint(g) << 32) | (uint32_t)(0xffffffffu - (uint32_t)i));
+    gkey[i] = noise ? 0ull : (((uint64_t)ordered_bits(g) << 32) | (uint32_t)(0xffffffffu - (uint32_t)i));
     is_center[i] = 0;
-  } else {
-    gkey[i] = noise ? 1ull : 0ull;  // noise flag for the label step
+  } else if (center_mode == PECANN_CENTER_THRESHOLD) {
+    gkey[i] = noise ? 1ull : 0ull;
     is_center[i] = (!noise && delta[i] >= delta_min) ? 1 : 0;
+  } else {  // given centers; noise points are never centers
+    gkey[i] = noise ? 1ull : 0ull;
+    is_center[i] = (!noise && is_center[i]) ? 1 : 0;
   }
 }
 

@@ -1177,7 +1177,8 @@ static pecann_status cluster_impl(int64_t n, const InstSpec &spec, const float *
                                   size_t ws_bytes, void *stream) {
   if (n < 1 || n >= (int64_t)1 << 31) return fail(PECANN_EINVAL, "n out of range");
   if (!rho || !dep || !delta || !labels || !is_center) return fail(PECANN_EINVAL, "pointer is NULL");
-  if (center_mode != PECANN_CENTER_PRODUCT && center_mode != PECANN_CENTER_THRESHOLD)
+  if (center_mode != PECANN_CENTER_PRODUCT && center_mode != PECANN_CENTER_THRESHOLD &&
+      center_mode != PECANN_CENTER_GIVEN)
     return fail(PECANN_EINVAL, "center_mode");
   if (center_mode == PECANN_CENTER_PRODUCT)
     for (int t = 0; t < spec.count(); ++t)
@@ -1225,4 +1226,83 @@ extern "C" pecann_status pecann_cluster_batched(int64_t n, const pecann_instance
   if (st != PECANN_OK) return st;
   return cluster_impl(n, sp, rho, dep, delta, center_mode, delta_min, rho_min, labels, is_center, ws,
                       ws_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Other density functions and local centers (epilogues over the kNN lists)
+// ---------------------------------------------------------------------------
+static size_t table_ws_size(int ninst) {
+  Carver c(nullptr);
+  InstDev d;
+  carve_inst(c, ninst, &d);
+  return c.size();
+}
+
+// inst NULL: one instance of n points with the call's k.
+static pecann_status spec_or_single(int64_t n, const pecann_instances *inst, int32_t k, InstSpec *sp) {
+  if (n < 2 || n >= (int64_t)1 << 31) return fail(PECANN_EINVAL, "n out of range");
+  if (!inst) {
+    *sp = single_spec(n, k, 1);
+    return PECANN_OK;
+  }
+  return make_spec(n, inst, k, 1, sp);
+}
+
+extern "C" size_t pecann_density_workspace_size(int64_t n, const pecann_instances *inst) {
+  InstSpec sp;
+  if (spec_or_single(n, inst, 1, &sp) != PECANN_OK) return 0;
+  return table_ws_size(sp.count());
+}
+
+extern "C" pecann_status pecann_density(int64_t n, const pecann_instances *inst, int32_t k,
+                                        int32_t density_fn, const int32_t *knn_idx,
+                                        const float *knn_dist, float *rho, uint64_t *rank_key,
+                                        void *ws, size_t ws_bytes, void *stream) {
+  clear_stale_error();
+  InstSpec sp;
+  pecann_status st = spec_or_single(n, inst, k, &sp);
+  if (st != PECANN_OK) return st;
+  if ((st = check_inst_k(sp, k)) != PECANN_OK) return st;
+  if (density_fn < PECANN_DENSITY_KTH || density_fn > PECANN_DENSITY_SUM)
+    return fail(PECANN_EINVAL, "density_fn");
+  if (!knn_idx || !knn_dist || !rho || !rank_key) return fail(PECANN_EINVAL, "pointer is NULL");
+  const size_t need = table_ws_size(sp.count());
+  if (!ws || ws_bytes < need || !aligned(ws, 256))
+    return fail(PECANN_EWORKSPACE, "workspace needs %zu bytes (256-aligned), got %zu", need, ws_bytes);
+  Carver c(ws);
+  InstDev d;
+  carve_inst(c, sp.count(), &d);
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(upload_inst(sp, d, s));
+  PROF(F_OTHER, s);
+  HIP_TRY(launch_density(n, table_of(d, sp.count()), k, density_fn, knn_idx, knn_dist, rho, rank_key, s));
+  return PECANN_OK;
+}
+
+extern "C" size_t pecann_local_centers_workspace_size(int64_t n, const pecann_instances *inst) {
+  return pecann_density_workspace_size(n, inst);
+}
+
+extern "C" pecann_status pecann_local_centers(int64_t n, const pecann_instances *inst, int32_t k,
+                                              const int32_t *knn_idx, const uint64_t *rank_key,
+                                              const float *rho, float rho_min, uint8_t *is_center,
+                                              void *ws, size_t ws_bytes, void *stream) {
+  clear_stale_error();
+  InstSpec sp;
+  pecann_status st = spec_or_single(n, inst, k, &sp);
+  if (st != PECANN_OK) return st;
+  if ((st = check_inst_k(sp, k)) != PECANN_OK) return st;
+  if (!knn_idx || !rank_key || !rho || !is_center) return fail(PECANN_EINVAL, "pointer is NULL");
+  const size_t need = table_ws_size(sp.count());
+  if (!ws || ws_bytes < need || !aligned(ws, 256))
+    return fail(PECANN_EWORKSPACE, "workspace needs %zu bytes (256-aligned), got %zu", need, ws_bytes);
+  Carver c(ws);
+  InstDev d;
+  carve_inst(c, sp.count(), &d);
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(upload_inst(sp, d, s));
+  PROF(F_CLUSTER, s);
+  HIP_TRY(launch_local_centers(n, table_of(d, sp.count()), k, knn_idx, rank_key, rho, rho_min,
+                               is_center, s));
+  return PECANN_OK;
 }

@@ -19,7 +19,8 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "pecann.h")
 
 F32, U8, BF16, FP8E4M3 = 0, 1, 2, 3
 L2, COSINE = 0, 1
-CENTER_PRODUCT, CENTER_THRESHOLD = 0, 1
+CENTER_PRODUCT, CENTER_THRESHOLD, CENTER_GIVEN = 0, 1, 2
+DENSITY_FNS = {"kth": 0, "normalized": 1, "exp-sum": 2, "sum-exp": 3, "sum": 4}
 DTYPES = {"f32": F32, "u8": U8, "bf16": BF16, "fp8": FP8E4M3}
 METRICS = {"l2": L2, "cosine": COSINE}
 
@@ -127,6 +128,10 @@ def load():
         "pecann_cluster_batched_workspace_size": (sz, [i64, N]),
         "pecann_cluster_batched": (ctypes.c_int, [i64, N, vp, vp, vp, i32, i32, f32, f32, vp, vp, vp, sz,
                                                   vp]),
+        "pecann_density_workspace_size": (sz, [i64, N]),
+        "pecann_density": (ctypes.c_int, [i64, N, i32, i32, vp, vp, vp, vp, vp, sz, vp]),
+        "pecann_local_centers_workspace_size": (sz, [i64, N]),
+        "pecann_local_centers": (ctypes.c_int, [i64, N, i32, vp, vp, vp, f32, vp, vp, sz, vp]),
         "pecann_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "pecann_last_error": (ctypes.c_char_p, []),
     }
@@ -448,3 +453,44 @@ def workspace_bytes_batched(ds: Dataset, inst: Instances, k_max: int, L_search: 
                lib.pecann_dependent_search_batched_workspace_size(ctypes.byref(s), ctypes.byref(ni),
                                                                   kdep_cap, L_search),
                lib.pecann_cluster_batched_workspace_size(ds.n, ctypes.byref(ni)))
+
+
+# ---------------------------------------------------------------------------
+# Other density functions and local centers
+# ---------------------------------------------------------------------------
+def density(knn_idx, knn_dist, fn: str = "normalized", inst: Instances | None = None,
+            out=None, ws: torch.Tensor | None = None):
+    """Density of another function from the kNN lists (rows of stride knn_idx.shape[1]).
+    -> (rho f32 [n], rank_key int64 [n]); out may be knn_density's (rho, rank_key)."""
+    lib = load()
+    n, k = knn_idx.shape
+    ni = None if inst is None else ctypes.byref(inst.struct)
+    need = lib.pecann_density_workspace_size(n, ni)
+    if need == 0:
+        raise PecannError(f"invalid arguments: {lib.pecann_last_error().decode()}")
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, knn_idx.device)
+    if out is None:
+        out = (torch.empty(n, dtype=torch.float32, device=knn_idx.device),
+               torch.empty(n, dtype=torch.int64, device=knn_idx.device))
+    rho, key = out
+    _check(lib.pecann_density(n, ni, k, DENSITY_FNS[fn], _ptr(knn_idx), _ptr(knn_dist), _ptr(rho),
+                              _ptr(key), _ptr(ws), ws.numel(), _stream()))
+    return rho, key
+
+
+def local_centers(knn_idx, rank_key, rho, rho_min: float = 0.0, inst: Instances | None = None,
+                  out: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+    """Non-noise points ranked above all their k nearest neighbours. -> is_center uint8 [n]."""
+    lib = load()
+    n, k = knn_idx.shape
+    ni = None if inst is None else ctypes.byref(inst.struct)
+    need = lib.pecann_local_centers_workspace_size(n, ni)
+    if need == 0:
+        raise PecannError(f"invalid arguments: {lib.pecann_last_error().decode()}")
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, knn_idx.device)
+    isc = torch.empty(n, dtype=torch.uint8, device=knn_idx.device) if out is None else out
+    _check(lib.pecann_local_centers(n, ni, k, _ptr(knn_idx), _ptr(rank_key), _ptr(rho), rho_min,
+                                    _ptr(isc), _ptr(ws), ws.numel(), _stream()))
+    return isc
