@@ -512,6 +512,18 @@ def main():
         "dependent_stats": rec["dependent_stats"],
         "kernels_ms": rec["kernels_ms"],
     }
+    # dendrogram re-cut (Sec. 1): densities and dependents stay, each cut is one
+    # cluster call; time a sweep of n_c on the last step's forest
+    if inst is None and wl["n_c"]:
+        cuts = [max(1, wl["n_c"] // 2), wl["n_c"], 2 * wl["n_c"], 4 * wl["n_c"]]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for nc in cuts:
+            pl.pecann.cluster(pl.k_out[2], pl.d_out[0], pl.d_out[1], n_c=nc, rho_min=wl["rho_min"],
+                              ws=pl.ws)
+        torch.cuda.synchronize()
+        out["recut"] = {"n_c": cuts, "ms_per_cut": round((time.perf_counter() - t0) * 1e3 / len(cuts), 3),
+                        "full_step_ms": rec["ms_per_step"]}
     if args.mode == "anns":
         log("work counters for the roofline")
         out["roofline"] = roofline(pl, kprof, args.steps, search, n, d, wl["k"])
