@@ -115,15 +115,24 @@ __device__ __forceinline__ void dot_tiles(const Rows &r, int32_t arow, const int
     accf[t] = v4f{0.f, 0.f, 0.f, 0.f};
     acci[t] = v4i{0, 0, 0, 0};
   }
-  for (int st = 0; st < steps; ++st) {
-    const int q = g + 4 * st;
-    const bool in = q < r.nch;
-    const uint4 a = load_chunk(r.xs, arow, r.xs_stride, q, in, u8);
-    uint4 b[NT];
+  // the loads of SG steps go out before any of their products (one memory
+  // round trip per SG steps instead of one per step)
+  constexpr int SG = 4;
+  for (int st0 = 0; st0 < steps; st0 += SG) {
+    uint4 a[SG], b[SG][NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) b[t] = load_chunk(r.xs, brow[t], r.xs_stride, q, in, u8);
+    for (int u = 0; u < SG; ++u) {
+      const int q = g + 4 * (st0 + u);
+      const bool in = st0 + u < steps && q < r.nch;
+      a[u] = load_chunk(r.xs, arow, r.xs_stride, q, in, u8);
 #pragma unroll
-    for (int t = 0; t < NT; ++t) mfma_chunk<DT>(a, b[t], accf[t], acci[t]);
+      for (int t = 0; t < NT; ++t) b[u][t] = load_chunk(r.xs, brow[t], r.xs_stride, q, in, u8);
+    }
+#pragma unroll
+    for (int u = 0; u < SG; ++u) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) mfma_chunk<DT>(a[u], b[u][t], accf[t], acci[t]);
+    }
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -175,6 +184,77 @@ __device__ __forceinline__ int compact_live(PruneLds &s, int from, int mv) {
     wave_lds_sync();
   }
   return out;
+}
+
+// Short lists (at most kSmallBlocks blocks of 16 live candidates): block B's
+// tiles against itself and every later block are formed in one round (rows
+// already dropped are not loaded), then the block's selections and kills are
+// settled from them -- one memory round trip per block instead of two or three.
+constexpr int kSmallBlocks = 5;
+
+template <int DT, int B>
+__device__ __forceinline__ void short_block(const PruneParams &p, PruneLds &s, int mv, float a2,
+                                            int &nsel) {
+  if (16 * B >= mv || nsel >= p.R) return;
+  constexpr int NT = kSmallBlocks - B;
+  const int l = lane_id();
+  const int col = l & 15, g = l >> 4;
+  const int o = 16 * B;
+  int32_t br[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int j = o + 16 * t + col;
+    br[t] = (j < mv && s.alive[j]) ? key_id(s.k1[j]) : -1;
+  }
+  v4f tt[NT];
+  dot_tiles<DT, NT>(p.rows, br[0], br, tt);
+  // (a) the block's own tile -> its selections, in order
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = 4 * g + r;
+    float m = 0.f;
+    if (o + i < mv && o + col < mv)
+      m = pair_measure<DT>(tt[0][r], s.cn[o + i], s.cn[o + col], s.cs[o + i], s.cs[o + col],
+                           p.rows.metric);
+    s.dg[i * 16 + col] = m;
+  }
+  wave_lds_sync();
+  uint32_t selmask = 0;
+  for (int i = 0; i < 16 && o + i < mv; ++i) {
+    if (!s.alive[o + i]) continue;
+    if (l == 0) { s.sel[nsel] = key_id(s.k1[o + i]); s.alive[o + i] = 0; }
+    selmask |= 1u << i;
+    ++nsel;
+    if (nsel == p.R) break;
+    if (l > i && l < 16 && o + l < mv && s.alive[o + l] &&
+        a2 * s.dg[i * 16 + l] <= key_measure(s.k1[o + l]))
+      s.alive[o + l] = 0;
+    wave_lds_sync();
+  }
+  wave_lds_sync();
+  if (nsel == p.R) return;
+  // (b) the block's selected points drop later candidates
+#pragma unroll
+  for (int t = 1; t < NT; ++t) {
+    const int j = o + 16 * t + col;
+    bool kill = false;
+    if (j < mv) {
+      const float dpc = key_measure(s.k1[j]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * g + r;
+        if ((selmask >> i) & 1u) {
+          const float m = pair_measure<DT>(tt[t][r], s.cn[o + i], s.cn[j], s.cs[o + i], s.cs[j],
+                                           p.rows.metric);
+          kill |= a2 * m <= dpc;
+        }
+      }
+    }
+    const uint64_t km = ballot(kill);
+    const uint32_t k16 = (uint32_t)((km | (km >> 16) | (km >> 32) | (km >> 48)) & 0xffffu);
+    if (l < 16 && ((k16 >> l) & 1u)) s.alive[o + 16 * t + l] = 0;
+  }
+  wave_lds_sync();
 }
 
 // RobustPrune of point pt over s.ids[0..nc); writes Nout(pt) into adj/deg.
@@ -242,6 +322,19 @@ __device__ int robust_prune_tiles(const PruneParams &p, PruneLds &s, int32_t pt,
   int mv = compact_live(s, 0, nc);
 
   int nsel = 0, tiles = (nc + 15) / 16;
+  if (mv <= 16 * kSmallBlocks) {
+    const int nb = (mv + 15) / 16;
+    short_block<DT, 0>(p, s, mv, a2, nsel);
+    short_block<DT, 1>(p, s, mv, a2, nsel);
+    short_block<DT, 2>(p, s, mv, a2, nsel);
+    short_block<DT, 3>(p, s, mv, a2, nsel);
+    short_block<DT, 4>(p, s, mv, a2, nsel);
+    tiles += nb * kSmallBlocks - nb * (nb - 1) / 2;
+    int32_t *row = p.adj + (int64_t)pt * p.R;
+    for (int e = l; e < p.R; e += kWave) row[e] = e < nsel ? s.sel[e] : -1;
+    if (l == 0) p.deg[pt] = nsel;
+    return tiles;
+  }
   for (int b = 0; b < mv && nsel < p.R; b += 16) {
     // (a) the block's own 16 x 16 tile (every entry of the block is live)
     const int32_t rb = b + col < mv ? key_id(s.k1[b + col]) : -1;
@@ -352,10 +445,21 @@ __global__ __launch_bounds__(64) void prune_reverse_kernel(PruneParams p) {
   const int l = lane_id();
   const int nt = *p.ntargets;
   const int items = p.heavy ? *p.nheavy : *p.nlight;
+  // light targets are many and short: a wave takes kLightChunk of them per
+  // queue atomic so that the queue head is not the serialising point
+  constexpr int kLightChunk = 8;
+  const int chunk = p.heavy ? 1 : kLightChunk;
+  int it = 0, end = 0;
   for (;;) {
-    const int it = next_item(p.head);
-    if (it >= items) break;
+    if (it >= end) {
+      int v = 0;
+      if (l == 0) v = atomicAdd(p.head, chunk);
+      it = __shfl(v, 0);
+      if (it >= items) break;
+      end = min(items, it + chunk);
+    }
     const int u = p.heavy ? p.tord[nt - 1 - it] : p.tord[it];
+    ++it;
     const int32_t q = p.tlist[u];
     int cnt = p.tcnt[u];
     if (cnt > p.capin) {
