@@ -26,8 +26,9 @@ struct SortedList {
   int cap;
   int m;            // entries held
   int hint;         // every entry before index `hint` is flagged
+  uint64_t tail;    // key of the last entry (kNoKey while empty)
 
-  __device__ __forceinline__ void reset() { m = 0; hint = 0; }
+  __device__ __forceinline__ void reset() { m = 0; hint = 0; tail = kNoKey; }
 
   __device__ __forceinline__ void swap_bufs() {
     uint64_t *t = a; a = b; b = t;
@@ -38,7 +39,7 @@ struct SortedList {
   // `cap` smallest.  Keys already present are ignored; the keys of one call are
   // distinct.  Returns the number of keys that entered the list.
   __device__ int merge(uint64_t mykey) {
-    if (m == cap && mykey != kNoKey && mykey >= a[cap - 1]) mykey = kNoKey;
+    if (m == cap && mykey >= tail) mykey = kNoKey;
     const uint64_t cm = ballot(mykey != kNoKey);
     if (cm == 0) return 0;
     return __popcll(cm) <= 16 ? merge_few(mykey) : merge_sorted(mykey);
@@ -90,6 +91,7 @@ struct SortedList {
     wave_lds_sync();
     m = min(cap, m + nc);
     hint = min(min(hint, first_new), m);
+    tail = a[m - 1];
     return nc;
   }
 
@@ -125,17 +127,24 @@ struct SortedList {
     swap_bufs();
     m = min(cap, m + nc);
     hint = min(min(hint, first_new), m);
+    tail = a[m - 1];
     return nc;
   }
 
-  // Index of the first entry whose flag is 0, or -1 (scans from `hint`).
-  __device__ __forceinline__ int first_unflagged() {
+  // Index of the first entry whose flag is 0, or -1 (scans from `hint`); its
+  // key is read in the same pass.
+  __device__ __forceinline__ int first_unflagged(uint64_t &key) {
     const int l = lane_id();
     for (int base = hint; base < m; base += kWave) {
       const int j = base + l;
-      const uint64_t bm = ballot(j < m && fa[j] == 0);
+      uint8_t fl = 1;
+      uint64_t k = kNoKey;
+      if (j < m) { fl = fa[j]; k = a[j]; }
+      const uint64_t bm = ballot(fl == 0);
       if (bm) {
-        hint = base + __builtin_ctzll(bm);
+        const int t = __builtin_ctzll(bm);
+        hint = base + t;
+        key = readlane_u64(k, t);
         return hint;
       }
     }

@@ -51,6 +51,13 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
   hi = (uint32_t)__shfl_xor((int)hi, m);
   return ((uint64_t)hi << 32) | lo;
 }
+// value of v in lane `src` (src wave-uniform)
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int src) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
   uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
   lo = (uint32_t)__shfl((int)lo, src);

@@ -143,10 +143,9 @@ __device__ __forceinline__ void search_body(const SearchParams &p) {
 
     int nv = 0;
     for (;;) {
-      const int j = s.beam.first_unflagged();
+      uint64_t kj = kNoKey;
+      const int j = s.beam.first_unflagged(kj);
       if (j < 0) break;
-      const uint64_t kj = s.beam.a[j];
-      wave_lds_sync();
       if (l == 0) {
         s.beam.fa[j] = 1;
         if (MODE == MODE_BUILD && nv < p.vcap) p.vis[(int64_t)it * p.vcap + nv] = kj;
