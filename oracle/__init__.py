@@ -91,6 +91,8 @@ def load():
         lib.oracle_dependent_alg3.argtypes = [P, vp, vp, i32, vp, vp, i32, i32, i64, i32,
                                               i32, vp, vp, vp, i32]
         lib.oracle_dependent_alg3.restype = i32
+        lib.oracle_nndescent.argtypes = [P, i32, i32, f64, i32, f64, i32, vp, vp, vp, vp, vp, vp]
+        lib.oracle_nndescent.restype = ctypes.c_int
         lib.oracle_density.argtypes = [i64, i32, i32, vp, vp, vp]
         lib.oracle_density.restype = ctypes.c_int
         lib.oracle_rank_density.argtypes = [i64, vp, vp, vp]
@@ -280,6 +282,27 @@ def vamana_build(P: Points, R: int, L: int, alpha: float, perm, num_starts: int 
                                   passes, _ptr(adj), _ptr(deg)) != 0:
         raise MemoryError("oracle_vamana_build")
     return adj, deg
+
+
+def nndescent(P: Points, init, K: int, R: int, alpha: float, max_iters: int, delta: float = 0.0):
+    """NN-descent lists in synchronous rounds, then RobustPrune(list u reverse list).
+    init: [num_repeats, n, K] (or [n, K]) distinct ids other than the row's own.
+    -> (adj int32 [n, R], deg int32 [n], list_idx int64 [n, K], list_dist float64 [n, K],
+        rounds int32 [num_repeats])."""
+    init = np.ascontiguousarray(init, dtype=np.int64)
+    if init.ndim == 2:
+        init = init[None]
+    reps = init.shape[0]
+    assert init.shape[1:] == (P.n, K)
+    adj = np.empty((P.n, R), dtype=np.int32)
+    deg = np.empty(P.n, dtype=np.int32)
+    li = np.empty((P.n, K), dtype=np.int64)
+    ld = np.empty((P.n, K), dtype=np.float64)
+    rounds = np.zeros(reps, dtype=np.int32)
+    if load().oracle_nndescent(P.ref, K, R, alpha, max_iters, delta, reps, _ptr(init), _ptr(adj),
+                               _ptr(deg), _ptr(li), _ptr(ld), _ptr(rounds)) != 0:
+        raise ValueError("oracle_nndescent: bad init or allocation failure")
+    return adj, deg, li, ld, rounds
 
 
 def dependent_alg3(P: Points, adj, deg, rank, knn_idx, L_d: int, threshold: int,

@@ -631,6 +631,198 @@ int oracle_vamana_build(const opoints *P, int32_t R, int32_t L, double alpha,
 }
 
 /* ------------------------------------------------------------------------ */
+/* NN-descent graph: the PyNNDescent index the framework offers beside        */
+/* Vamana (Sec. 4.1; the graph comparison of Sec. 6 prunes both with alpha). */
+/* The paper does not print the construction; this is Dong, Charikar and     */
+/* Li's NN-descent in synchronous rounds:                                    */
+/*   every point i keeps a list of K neighbours ordered by (D, index), each  */
+/*   flagged new or old; the first list holds init[i][0..K) (K distinct ids  */
+/*   other than i, drawn by the caller), all new.                            */
+/*   A round: new_i / old_i are the new / old entries of list i (all count   */
+/*   as old afterwards); rnew_i is the K smallest (D(i,j), j) over the j     */
+/*   whose list holds i flagged new, rold_i the same over old entries;       */
+/*   U_i = new_i u rnew_i, W_i = (old_i u rold_i) minus U_i.  The local join */
+/*   of i proposes v to u and u to v for every pair of distinct u, v in U_i  */
+/*   and for every u in U_i with v in W_i.  The next list of u is the K      */
+/*   smallest (D, index) of its list and its proposals, ids distinct; an     */
+/*   entry whose id was not in the list before the round is flagged new.     */
+/*   Rounds stop after max_iters, or after the first round whose lists end   */
+/*   with at most floor(delta * n * K) new entries.                          */
+/* num_repeats runs start from init[r]; their final lists are merged (the K  */
+/* smallest of the union).  Graph: Nout(i) = RobustPrune(i, list_i u rev_i,  */
+/* alpha, R) with rev_i the K smallest (D(i,j), j) over j whose list holds i. */
+/* Outputs adj/deg, the final lists (ids, distances) and the rounds run by   */
+/* each repeat.  Returns 0, or -1 (bad init or allocation failure).          */
+/* ------------------------------------------------------------------------ */
+
+/* Offer (d, id) to the sorted list l[0..*m) of capacity K: ignored if the id */
+/* is present or the list is full of smaller entries; else inserted in order  */
+/* (the largest entry of a full list leaves).  Returns 1 if inserted.         */
+static int nnd_offer(cand_t *l, uint8_t *fl, int32_t *m, int32_t K, double d, int64_t id,
+                     uint8_t flag) {
+  for (int32_t t = 0; t < *m; ++t)
+    if (l[t].id == id) return 0;
+  if (*m == K && !before(d, id, l[K - 1].d, l[K - 1].id)) return 0;
+  int32_t pos = *m < K ? *m : K - 1;
+  while (pos > 0 && before(d, id, l[pos - 1].d, l[pos - 1].id)) {
+    l[pos] = l[pos - 1];
+    if (fl) fl[pos] = fl[pos - 1];
+    --pos;
+  }
+  l[pos].d = d;
+  l[pos].id = id;
+  if (fl) fl[pos] = flag;
+  if (*m < K) ++*m;
+  return 1;
+}
+
+static int nnd_contains(const int64_t *a, int32_t m, int64_t id) {
+  for (int32_t t = 0; t < m; ++t)
+    if (a[t] == id) return 1;
+  return 0;
+}
+
+/* One repeat: lists (n*K entries, counts cnt) from init; returns rounds run. */
+static int32_t nnd_descend(const opoints *P, int32_t K, int32_t max_iters, double delta,
+                           const int64_t *init, cand_t *list, uint8_t *flag, int32_t *cnt,
+                           cand_t *nxt, uint8_t *nflag, int32_t *ncnt, cand_t *rnew,
+                           int32_t *rnew_m, cand_t *rold, int32_t *rold_m, int64_t *U,
+                           int64_t *W) {
+  const int64_t n = P->n;
+  for (int64_t i = 0; i < n; ++i) {
+    cnt[i] = 0;
+    for (int32_t t = 0; t < K; ++t) {
+      int64_t j = init[i * K + t];
+      nnd_offer(list + i * K, flag + i * K, cnt + i, K, D(P, i, j), j, 1);
+    }
+  }
+  const double thr = floor(delta * (double)n * (double)K);
+  int32_t rounds = 0;
+  for (int32_t it = 0; it < max_iters; ++it) {
+    /* reverse lists of the new and of the old entries */
+    for (int64_t i = 0; i < n; ++i) rnew_m[i] = rold_m[i] = 0;
+    for (int64_t j = 0; j < n; ++j)
+      for (int32_t t = 0; t < cnt[j]; ++t) {
+        const int64_t i = list[j * K + t].id;
+        if (flag[j * K + t])
+          nnd_offer(rnew + i * K, NULL, rnew_m + i, K, list[j * K + t].d, j, 0);
+        else
+          nnd_offer(rold + i * K, NULL, rold_m + i, K, list[j * K + t].d, j, 0);
+      }
+    /* next lists start as the current ones, every entry old */
+    for (int64_t i = 0; i < n; ++i) {
+      ncnt[i] = cnt[i];
+      for (int32_t t = 0; t < cnt[i]; ++t) {
+        nxt[i * K + t] = list[i * K + t];
+        nflag[i * K + t] = 0;
+      }
+    }
+    /* local joins */
+    for (int64_t i = 0; i < n; ++i) {
+      int32_t nu = 0, nw = 0;
+      for (int32_t t = 0; t < cnt[i]; ++t)
+        if (flag[i * K + t] && !nnd_contains(U, nu, list[i * K + t].id)) U[nu++] = list[i * K + t].id;
+      for (int32_t t = 0; t < rnew_m[i]; ++t)
+        if (!nnd_contains(U, nu, rnew[i * K + t].id)) U[nu++] = rnew[i * K + t].id;
+      for (int32_t t = 0; t < cnt[i]; ++t) {
+        const int64_t v = list[i * K + t].id;
+        if (!flag[i * K + t] && !nnd_contains(U, nu, v) && !nnd_contains(W, nw, v)) W[nw++] = v;
+      }
+      for (int32_t t = 0; t < rold_m[i]; ++t) {
+        const int64_t v = rold[i * K + t].id;
+        if (!nnd_contains(U, nu, v) && !nnd_contains(W, nw, v)) W[nw++] = v;
+      }
+      for (int32_t a = 0; a < nu; ++a) {
+        const int64_t u = U[a];
+        for (int32_t b = a + 1; b < nu + nw; ++b) {
+          const int64_t v = b < nu ? U[b] : W[b - nu];
+          const double d = D(P, u, v);
+          /* an id already in the list is present in the next list (or was */
+          /* pushed out of it by closer ones), so whatever enters is new    */
+          nnd_offer(nxt + u * K, nflag + u * K, ncnt + u, K, d, v, 1);
+          nnd_offer(nxt + v * K, nflag + v * K, ncnt + v, K, d, u, 1);
+        }
+      }
+    }
+    int64_t updates = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      cnt[i] = ncnt[i];
+      for (int32_t t = 0; t < ncnt[i]; ++t) {
+        list[i * K + t] = nxt[i * K + t];
+        flag[i * K + t] = nflag[i * K + t];
+        updates += nflag[i * K + t];
+      }
+    }
+    ++rounds;
+    if ((double)updates <= thr) break;
+  }
+  return rounds;
+}
+
+int oracle_nndescent(const opoints *P, int32_t K, int32_t R, double alpha, int32_t max_iters,
+                     double delta, int32_t num_repeats, const int64_t *init, int32_t *adj,
+                     int32_t *deg, int64_t *list_idx, double *list_dist, int32_t *rounds) {
+  const int64_t n = P->n;
+  if (K < 1 || K > n - 1 || R < 1 || num_repeats < 1) return -1;
+  for (int32_t r = 0; r < num_repeats; ++r)
+    for (int64_t i = 0; i < n; ++i)
+      for (int32_t t = 0; t < K; ++t) {
+        const int64_t j = init[((int64_t)r * n + i) * K + t];
+        if (j < 0 || j >= n || j == i) return -1;
+        for (int32_t u = 0; u < t; ++u)
+          if (init[((int64_t)r * n + i) * K + u] == j) return -1;
+      }
+  const size_t nk = (size_t)(n * K);
+  cand_t *list = malloc(sizeof(cand_t) * nk), *nxt = malloc(sizeof(cand_t) * nk);
+  cand_t *rnew = malloc(sizeof(cand_t) * nk), *rold = malloc(sizeof(cand_t) * nk);
+  cand_t *acc = malloc(sizeof(cand_t) * nk);
+  uint8_t *flag = malloc(nk), *nflag = malloc(nk);
+  int32_t *cnt = malloc(sizeof(int32_t) * (size_t)n), *ncnt = malloc(sizeof(int32_t) * (size_t)n);
+  int32_t *rnew_m = malloc(sizeof(int32_t) * (size_t)n), *rold_m = malloc(sizeof(int32_t) * (size_t)n);
+  int32_t *acc_m = malloc(sizeof(int32_t) * (size_t)n);
+  int64_t *U = malloc(sizeof(int64_t) * (size_t)(4 * K + 2)), *W = malloc(sizeof(int64_t) * (size_t)(4 * K + 2));
+  int64_t *cand = malloc(sizeof(int64_t) * (size_t)(2 * K + 1)), *out = malloc(sizeof(int64_t) * (size_t)(R + 1));
+  int rc = 0;
+  if (!list || !nxt || !rnew || !rold || !acc || !flag || !nflag || !cnt || !ncnt || !rnew_m ||
+      !rold_m || !acc_m || !U || !W || !cand || !out) {
+    rc = -1;
+  } else {
+    for (int64_t i = 0; i < n; ++i) acc_m[i] = 0;
+    for (int32_t r = 0; r < num_repeats; ++r) {
+      rounds[r] = nnd_descend(P, K, max_iters, delta, init + (int64_t)r * n * K, list, flag, cnt,
+                              nxt, nflag, ncnt, rnew, rnew_m, rold, rold_m, U, W);
+      for (int64_t i = 0; i < n; ++i)
+        for (int32_t t = 0; t < cnt[i]; ++t)
+          nnd_offer(acc + i * K, NULL, acc_m + i, K, list[i * K + t].d, list[i * K + t].id, 0);
+    }
+    /* reverse lists of the final lists, then the pruned graph */
+    for (int64_t i = 0; i < n; ++i) rnew_m[i] = 0;
+    for (int64_t j = 0; j < n; ++j)
+      for (int32_t t = 0; t < acc_m[j]; ++t) {
+        const int64_t i = acc[j * K + t].id;
+        nnd_offer(rnew + i * K, NULL, rnew_m + i, K, acc[j * K + t].d, j, 0);
+      }
+    for (int64_t i = 0; i < n && rc == 0; ++i) {
+      int32_t nc = 0;
+      for (int32_t t = 0; t < acc_m[i]; ++t) cand[nc++] = acc[i * K + t].id;
+      for (int32_t t = 0; t < rnew_m[i]; ++t) cand[nc++] = rnew[i * K + t].id;
+      const int32_t no = oracle_robust_prune(P, i, cand, nc, alpha, R, out);
+      if (no < 0) { rc = -1; break; }
+      for (int32_t e = 0; e < R; ++e) adj[i * R + e] = e < no ? (int32_t)out[e] : -1;
+      deg[i] = no;
+      for (int32_t t = 0; t < K; ++t) {
+        list_idx[i * K + t] = t < acc_m[i] ? acc[i * K + t].id : -1;
+        list_dist[i * K + t] = t < acc_m[i] ? acc[i * K + t].d : INFINITY;
+      }
+    }
+  }
+  free(list); free(nxt); free(rnew); free(rold); free(acc); free(flag); free(nflag);
+  free(cnt); free(ncnt); free(rnew_m); free(rold_m); free(acc_m); free(U); free(W);
+  free(cand); free(out);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* ComputeDepPts (Alg. 3) over a graph index.                                */
 /*   1. DPBruteForce over each point's kNN list N_i (the list's distances    */
 /*      are recomputed here);                                               */

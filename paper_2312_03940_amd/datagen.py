@@ -170,3 +170,23 @@ def config5(count: int = 64, d: int = 384):
 def permutation(n: int, seed: int) -> np.ndarray:
     """Insertion order for the batched graph build (int32)."""
     return np.random.default_rng(seed).permutation(n).astype(np.int32)
+
+
+def random_neighbour_lists(n: int, K: int, seed: int, repeats: int = 1) -> np.ndarray:
+    """Random starting lists for an NN-descent construction: for each repeat and
+    each point i, K distinct ids drawn uniformly from the other n - 1 points
+    (Floyd's sampling, vectorised over points).  -> int32 [repeats, n, K]."""
+    if not 1 <= K <= n - 1:
+        raise ValueError("need 1 <= K <= n - 1")
+    rng = np.random.default_rng(seed)
+    out = np.empty((repeats, n, K), dtype=np.int32)
+    rows = np.arange(n, dtype=np.int64)
+    N = n - 1
+    for r in range(repeats):
+        S = np.empty((n, K), dtype=np.int64)
+        for c, j in enumerate(range(N - K, N)):
+            t = rng.integers(0, j + 1, size=n, dtype=np.int64)
+            taken = (S[:, :c] == t[:, None]).any(axis=1) if c else np.zeros(n, bool)
+            S[:, c] = np.where(taken, j, t)
+        out[r] = (S + (S >= rows[:, None])).astype(np.int32)  # skip the row's own index
+    return out

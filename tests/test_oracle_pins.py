@@ -461,3 +461,129 @@ def test_cluster_with_given_centers(oracle_lib):
                                    centers=isc, rho_min=rho_min)
     noise = ref["rho"] < rho_min
     assert not (isc3 & noise).any() and np.array_equal(labels3[noise], np.nonzero(noise)[0])
+
+
+# --------------------------------------------------------------------------
+# NN-descent (the second graph index; pins are written from the definition of
+# a synchronous NN-descent round as a candidate set, not from the oracle's
+# local-join loops)
+# --------------------------------------------------------------------------
+
+def _dmat(X):
+    """Exact pairwise Euclidean distances of integer-valued rows (exact sums)."""
+    Xi = X.astype(np.int64)
+    d2 = ((Xi[:, None, :] - Xi[None, :, :]) ** 2).sum(-1)
+    return np.sqrt(d2.astype(np.float64))
+
+
+def _topk(Dm, i, ids, K):
+    ids = sorted(set(int(v) for v in ids if v != i), key=lambda v: (Dm[i, v], v))
+    return ids[:K]
+
+
+def _round_by_candidate_sets(Dm, lists, flags, K):
+    """One synchronous round written as: the next list of u is the K best of its
+    list and of every v that shares a join neighbourhood with u in which at
+    least one of the two is 'new'."""
+    n = len(lists)
+    rnew = [[] for _ in range(n)]
+    rold = [[] for _ in range(n)]
+    for j in range(n):
+        for v, f in zip(lists[j], flags[j]):
+            (rnew if f else rold)[v].append(j)
+    rnew = [_topk(Dm, i, rnew[i], K) for i in range(n)]
+    rold = [_topk(Dm, i, rold[i], K) for i in range(n)]
+    cand = [set() for _ in range(n)]
+    for i in range(n):
+        Ui = {v for v, f in zip(lists[i], flags[i]) if f} | set(rnew[i])
+        Wi = ({v for v, f in zip(lists[i], flags[i]) if not f} | set(rold[i])) - Ui
+        for u in Ui:
+            cand[u] |= (Ui | Wi) - {u}
+        for w in Wi:
+            cand[w] |= Ui
+    nxt, nfl = [], []
+    for u in range(n):
+        new_list = _topk(Dm, u, set(lists[u]) | cand[u], K)
+        nxt.append(new_list)
+        nfl.append([v not in set(lists[u]) for v in new_list])
+    return nxt, nfl
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_nndescent_rounds_match_candidate_set_definition(oracle_lib, seed):
+    X, _ = datagen.mixture(60, 3, 4, seed=seed, grid=31)
+    n, K = len(X), 5
+    Dm = _dmat(X)
+    init = datagen.random_neighbour_lists(n, K, seed=seed + 10)[0]
+    lists = [_topk(Dm, i, init[i], K) for i in range(n)]
+    flags = [[True] * K for _ in range(n)]
+    for rounds in (1, 2, 3):
+        lists, flags = _round_by_candidate_sets(Dm, lists, flags, K)
+        _, _, li, ld, r = oracle.nndescent(oracle.Points(X), init, K, 8, 1.2, rounds, delta=-1.0)
+        assert r[0] == rounds
+        assert [list(row) for row in li] == lists, rounds
+        assert np.array_equal(ld, Dm[np.arange(n)[:, None], li])
+
+
+def test_nndescent_complete_start_is_exact_knn(oracle_lib):
+    # K = n - 1: the first list already holds every other point, so it is the
+    # exact neighbour order, no round changes it, and the graph is RobustPrune
+    # over all other points
+    X, _ = datagen.mixture(40, 4, 3, seed=5, grid=63)
+    n = len(X)
+    K = n - 1
+    P = oracle.Points(X)
+    init = datagen.random_neighbour_lists(n, K, seed=1)
+    adj, deg, li, ld, r = oracle.nndescent(P, init, K, 6, 1.2, 10, delta=0.0)
+    ref_idx, ref_dist = oracle.knn(P, K)
+    assert np.array_equal(li, ref_idx) and np.allclose(ld, ref_dist, rtol=0, atol=0)
+    assert r[0] == 1  # the first round inserts nothing
+    for i in range(n):
+        assert list(adj[i, :deg[i]]) == list(oracle.robust_prune(P, i, np.delete(np.arange(n), i), 1.2, 6))
+
+
+def test_nndescent_lists_improve_and_stay_valid(oracle_lib):
+    X, _ = datagen.mixture(400, 8, 6, seed=9)
+    n, K = len(X), 8
+    P = oracle.Points(X)
+    init = datagen.random_neighbour_lists(n, K, seed=4)
+    prev = None
+    for rounds in range(0, 5):
+        _, _, li, ld, _ = oracle.nndescent(P, init, K, 12, 1.2, rounds, delta=-1.0)
+        assert np.all(li >= 0) and np.all(li != np.arange(n)[:, None])
+        assert all(len(set(row)) == K for row in li)
+        assert np.all(np.diff(ld, axis=1) >= 0)
+        if prev is not None:
+            assert np.all(ld[:, -1] <= prev[:, -1])  # the K-th distance never grows
+            assert np.all(ld.sum(1) <= prev.sum(1) + 1e-9)
+        prev = ld
+
+
+def test_nndescent_converges_to_high_recall(oracle_lib):
+    X, _ = datagen.mixture(1500, 8, 10, seed=2)
+    P = oracle.Points(X)
+    n, K = len(X), 12
+    init = datagen.random_neighbour_lists(n, K, seed=7)
+    adj, deg, li, ld, r = oracle.nndescent(P, init, K, 16, 1.2, 30, delta=0.0)
+    ref, _ = oracle.knn(P, 10)
+    rec = np.mean([len(set(li[i, :10]) & set(ref[i])) / 10 for i in range(n)])
+    assert rec >= 0.95, rec
+    assert r[0] < 30  # stopped because a round changed nothing
+    assert np.all(deg >= 1) and np.all(deg <= 16)
+
+
+def test_nndescent_repeats_merge_and_delta_stop(oracle_lib):
+    X, _ = datagen.mixture(300, 6, 5, seed=3, grid=63)
+    P = oracle.Points(X)
+    n, K = len(X), 6
+    init = datagen.random_neighbour_lists(n, K, seed=2, repeats=2)
+    Dm = _dmat(X)
+    _, _, l0, _, _ = oracle.nndescent(P, init[0], K, 8, 1.2, 2, delta=-1.0)
+    _, _, l1, _, _ = oracle.nndescent(P, init[1], K, 8, 1.2, 2, delta=-1.0)
+    _, _, lm, _, r = oracle.nndescent(P, init, K, 8, 1.2, 2, delta=-1.0)
+    assert list(r) == [2, 2]
+    for i in range(n):
+        assert list(lm[i]) == _topk(Dm, i, set(l0[i]) | set(l1[i]), K)
+    # delta = 1: the first round ends with at most n * K new entries, so it stops
+    _, _, _, _, r = oracle.nndescent(P, init[0], K, 8, 1.2, 10, delta=1.0)
+    assert r[0] == 1
