@@ -178,6 +178,64 @@ pecann_status pecann_build_graph(const pecann_dataset *ds, const pecann_build_pa
                                  void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Second graph index: NN-descent (the PyNNDescent index that the paper's
+ * framework offers beside Vamana, Sec. 4.1; the graph comparison of Sec. 6
+ * prunes both with alpha).  The paper does not print the construction; this
+ * is Dong, Charikar and Li's NN-descent in synchronous rounds:
+ *   every point keeps K neighbours in (distance, index) order, each flagged
+ *   new or old; point i's first list holds init[i][0..K), all new.
+ *   A round: U_i = i's new entries and the K closest points whose list holds
+ *   i as new; W_i = i's old entries and the K closest points holding i as
+ *   old, minus U_i.  Every pair of U_i x U_i and U_i x W_i is proposed both
+ *   ways; a point's next list is the K smallest of its list and its proposals
+ *   (distinct ids) and an entry that was not in its list is new.  Rounds end
+ *   after max_iters, or after the first round that leaves at most
+ *   floor(delta * n * K) new entries.
+ *   num_repeats runs (run r from init + r*n*K) are merged: the K smallest of
+ *   the union of their final lists.
+ *   Graph: Nout(i) = RobustPrune(i, list_i u rev_i, alpha, R) (the rule of
+ *   pecann_build_graph) with rev_i the K closest points whose list holds i.
+ * Distances come from matrix-core dot-product tiles of the search rows and
+ * the stored norms; a pair gets the same measure bit for bit wherever it is
+ * formed, so a point's list never holds an id twice.
+ *
+ *   init      device, num_repeats * n * K int32: K distinct ids other than the
+ *             point, per repeat and point.  An id outside [0, n) or equal to
+ *             the point is an empty entry; repeated ids give unspecified
+ *             (memory-safe) results.
+ *   adj, deg  device outputs laid out as for pecann_build_graph
+ *   knn_idx   device n*K int32 or NULL: the final lists (-1 = empty entry)
+ *   knn_dist  device n*K float or NULL: their distances (+inf = empty)
+ *   rounds    device num_repeats int32 or NULL: rounds run by each repeat
+ *   counters  device 4 uint64 or NULL (caller zeroes): [0] proposals written,
+ *             [1] 16 x 16 join tiles, [2] proposal merges (targets), [3] row
+ *             reads of the final prune's tiles (32 per tile)
+ * Local joins run in chunks of `chunk` points (0: as many as fit 1.5 GiB of
+ * proposal buffers at the worst case of 12 K^2 proposals per join); the
+ * result does not depend on the chunking.  The workspace grows with it.
+ * Limits: 1 <= K <= 64, K <= n - 1, 1 <= R <= 128, alpha >= 1,
+ * 0 <= max_iters <= 1000, delta >= 0, 1 <= num_repeats <= 16, chunk >= 0.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t K;            /* list length */
+  int32_t R;            /* degree bound of the graph */
+  float alpha;          /* prune slack, >= 1 */
+  int32_t max_iters;    /* rounds per repeat */
+  float delta;          /* stop level as a fraction of n * K */
+  int32_t num_repeats;  /* independent runs merged */
+  int32_t chunk;        /* local joins per proposal batch (0: automatic) */
+  int32_t reserved;     /* must be 0 */
+} pecann_nnd_params;
+
+size_t pecann_build_graph_nndescent_workspace_size(const pecann_dataset *ds,
+                                                   const pecann_nnd_params *np);
+pecann_status pecann_build_graph_nndescent(const pecann_dataset *ds, const pecann_nnd_params *np,
+                                           const int32_t *init, int32_t *adj, int32_t *deg,
+                                           int32_t *knn_idx, float *knn_dist, int32_t *rounds,
+                                           uint64_t *counters, void *ws, size_t ws_bytes,
+                                           void *stream);
+
+/* ---------------------------------------------------------------------------
  * k nearest neighbours and kth density (Alg. 2, Find-Knn and F_density loops;
  * Sec. 4.2 "kth density": rho_i = 1 / D(x_i, k-th neighbour)).
  *

@@ -161,6 +161,11 @@ struct PruneParams {
                               // list's bound; heavy list: truncation beyond it)
   int32_t *head;
   int32_t *overflow;          // counts truncations (candidates beyond capacity)
+  // NN-descent graph: Nout(i) = RobustPrune(i, list_i u rev_i) with the lists
+  // (lk keys per point, kNoKey = empty) and reverse lists (lk ids, -1 = empty)
+  const uint64_t *lists;
+  const int32_t *rlists;
+  int32_t lk;
   // optional work counters (nullptr: off): [0] row reads by forward prunes and
   // [1] by reverse prunes (32 per 16 x 16 tile), [2] targets pruned, [3] targets
   // appended
@@ -169,6 +174,57 @@ struct PruneParams {
 size_t prune_lds_bytes(int ccap, int R);
 hipError_t launch_prune_forward(int32_t dt, const PruneParams &p, int grid, hipStream_t s);
 hipError_t launch_prune_reverse(int32_t dt, const PruneParams &p, int grid, hipStream_t s);
+hipError_t launch_prune_lists(int32_t dt, const PruneParams &p, int grid, hipStream_t s);
+
+// NN-descent rounds (see nndescent.hip).  Lists: n x K keys (measure, index)
+// ascending, kNoKey = empty, with one flag byte per entry (1 = new).
+struct NndParams {
+  RowsDesc rows;
+  int32_t n;
+  int32_t K;
+  uint64_t *cur_keys;          // lists as the round began
+  uint8_t *cur_flags;
+  uint64_t *nxt_keys;          // lists after the round
+  uint8_t *nxt_flags;
+  int32_t *done;               // set once a round ends at or below the stop level
+  unsigned long long *updates; // new entries counted at a round's end
+  int32_t *rounds;             // rounds run
+  long long thr;               // stop level: floor(delta * n * K)
+  // reverse lists: per target the sources grouped (count, offset, ticket)
+  int32_t *rcnt, *roff, *rcursor, *rticket;
+  uint64_t *rseg;              // (measure, source) keys
+  uint8_t *rsegf;              // source's flag
+  int32_t *rnew, *rold;        // [n][K] closest new / old sources, -1 padded
+  // one chunk of local joins [c0, c1) and its proposals
+  int32_t c0, c1;
+  int32_t *head;               // work-queue head, 0 at launch
+  int32_t *pcount;             // proposals written
+  int64_t pcap;                // proposal capacity of the chunk
+  int32_t *ptgt;               // [pcap] target
+  uint64_t *pkey;              // [pcap] (measure, proposed index)
+  int32_t *pticket;            // [pcap] slot within the target's group
+  uint64_t *pseg;              // [pcap] keys grouped by target
+  int32_t *pcnt, *poff;        // [n] per target (pcnt 0 between chunks)
+  int32_t *pcursor;
+  int32_t *ptouch, *ptouch_n;  // targets with proposals
+  int32_t *overflow;           // proposals that did not fit (never, by sizing)
+  // optional work counters: [0] proposals, [1] 16 x 16 join tiles, [2] merges
+  unsigned long long *counters;
+};
+size_t nnd_join_lds_bytes(int K);
+hipError_t launch_nnd_init(int32_t dt, const NndParams &p, const int32_t *init, int grid, hipStream_t s);
+hipError_t launch_nnd_round_begin(const NndParams &p, int cus, hipStream_t s);
+hipError_t launch_nnd_reverse(const NndParams &p, int32_t split, int32_t ignore_done, int cus,
+                              hipStream_t s);
+hipError_t launch_nnd_join(int32_t dt, const NndParams &p, int grid, hipStream_t s);
+hipError_t launch_nnd_proposals(const NndParams &p, int cus, hipStream_t s);
+hipError_t launch_nnd_merge(const NndParams &p, int grid, hipStream_t s);
+hipError_t launch_nnd_round_end(const NndParams &p, int cus, hipStream_t s);
+hipError_t launch_nnd_acc_merge(const NndParams &p, uint64_t *acc, const uint64_t *src, int cus,
+                                hipStream_t s);
+hipError_t launch_nnd_out(const NndParams &p, const uint64_t *keys, int32_t *idx, float *dist, int cus,
+                          hipStream_t s);
+hipError_t launch_nnd_copy(const uint64_t *src, uint64_t *dst, int64_t n, int cus, hipStream_t s);
 
 // Plain (non-templated) kernels.
 hipError_t launch_prepare(const void *x, int32_t x_dtype, int64_t x_stride, int64_t n, int32_t d,

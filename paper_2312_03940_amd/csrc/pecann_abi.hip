@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "kernels.hpp"
@@ -64,9 +65,11 @@ extern "C" const char *pecann_last_error(void) { return g_err; }
 namespace {
 const char *const kFamilies[] = {"search_build", "search_knn", "search_dep", "prune_forward",
                                  "prune_reverse", "reverse_edges", "bf_knn", "bf_dep",
-                                 "exact_mfma", "prepare", "cluster", "other"};
+                                 "exact_mfma", "prepare", "cluster", "nnd_join", "nnd_update",
+                                 "nnd_lists", "nnd_prune", "other"};
 enum Family { F_SEARCH_BUILD, F_SEARCH_KNN, F_SEARCH_DEP, F_PRUNE_FWD, F_PRUNE_REV, F_REV,
-              F_BF_KNN, F_BF_DEP, F_EXACT_MFMA, F_PREPARE, F_CLUSTER, F_OTHER, F_COUNT };
+              F_BF_KNN, F_BF_DEP, F_EXACT_MFMA, F_PREPARE, F_CLUSTER, F_NND_JOIN, F_NND_UPDATE,
+              F_NND_LISTS, F_NND_PRUNE, F_OTHER, F_COUNT };
 struct ProfRec { int fam; hipEvent_t a, b; };
 struct Profiler {
   bool on = false;
@@ -711,6 +714,238 @@ static pecann_status build_impl(const pecann_dataset *ds, const pecann_build_par
       HIP_TRY_ROUND(launch_prune_reverse(dt, pp, heavy_grid, s));
     }
   }
+  return PECANN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// NN-descent graph
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t kNndPropBudget = (int64_t)3 << 29;  // 1.5 GiB of proposal buffers
+constexpr int64_t kNndPropBytes = 4 + 8 + 4 + 8;      // target, key, ticket, grouped key
+
+// Proposals of one local join at most: U and W hold at most 2K members each,
+// pairs U x U (unordered) and U x W, each proposed both ways.
+int64_t nnd_maxprop(int K) { return 12LL * K * K - 2LL * K; }
+
+int64_t nnd_chunk(const pecann_nnd_params *np, int64_t n) {
+  if (np->chunk > 0) return std::min<int64_t>(np->chunk, n);
+  const int64_t c = kNndPropBudget / (nnd_maxprop(np->K) * kNndPropBytes);
+  return std::max<int64_t>(1, std::min<int64_t>(n, c));
+}
+
+struct NndWs {
+  uint64_t *keys[2];
+  uint8_t *flags[2];
+  uint64_t *acc;
+  int32_t *rcnt, *roff, *rticket, *rnew, *rold;
+  uint64_t *rseg;
+  uint8_t *rsegf;
+  int32_t *ptgt, *pticket;
+  uint64_t *pkey, *pseg;
+  int32_t *pcnt, *poff, *ptouch;
+  int32_t *ctr;  // [0] done [1] rcursor [2] join head [3] merge head [4] proposals [5] cursor
+                 // [6] targets [7] overflow [8] prune head
+  unsigned long long *updates;
+  int32_t *rounds;
+};
+
+void carve_nnd(Carver &c, int64_t n, int K, int repeats, int64_t chunk, NndWs *w) {
+  const size_t nk = (size_t)(n * K);
+  const size_t pc = (size_t)(chunk * nnd_maxprop(K));
+  w->keys[0] = c.take<uint64_t>(nk);
+  w->keys[1] = c.take<uint64_t>(nk);
+  w->flags[0] = c.take<uint8_t>(nk);
+  w->flags[1] = c.take<uint8_t>(nk);
+  w->acc = repeats > 1 ? c.take<uint64_t>(nk) : nullptr;
+  w->rcnt = c.take<int32_t>((size_t)n);
+  w->roff = c.take<int32_t>((size_t)n);
+  w->rticket = c.take<int32_t>(nk);
+  w->rnew = c.take<int32_t>(nk);
+  w->rold = c.take<int32_t>(nk);
+  w->rseg = c.take<uint64_t>(nk);
+  w->rsegf = c.take<uint8_t>(nk);
+  w->ptgt = c.take<int32_t>(pc);
+  w->pticket = c.take<int32_t>(pc);
+  w->pkey = c.take<uint64_t>(pc);
+  w->pseg = c.take<uint64_t>(pc);
+  w->pcnt = c.take<int32_t>((size_t)n);
+  w->poff = c.take<int32_t>((size_t)n);
+  w->ptouch = c.take<int32_t>((size_t)n);
+  w->ctr = c.take<int32_t>(16);
+  w->updates = c.take<unsigned long long>(1);
+  w->rounds = c.take<int32_t>(16);
+}
+
+pecann_status check_nnd(const pecann_dataset *ds, const pecann_nnd_params *np) {
+  if (!np) return fail(PECANN_EINVAL, "NN-descent params are NULL");
+  if (np->K < 1 || np->K > 64) return fail(PECANN_EINVAL, "K must be in [1, 64]");
+  if (np->K > ds->n - 1) return fail(PECANN_EINVAL, "K must be <= n - 1");
+  if (np->R < 1 || np->R > 128) return fail(PECANN_EINVAL, "R must be in [1, 128]");
+  if (!(np->alpha >= 1.0f) || !std::isfinite(np->alpha)) return fail(PECANN_EINVAL, "alpha must be >= 1");
+  if (np->max_iters < 0 || np->max_iters > 1000) return fail(PECANN_EINVAL, "max_iters must be in [0, 1000]");
+  if (!(np->delta >= 0.0f) || !std::isfinite(np->delta)) return fail(PECANN_EINVAL, "delta must be >= 0");
+  if (np->num_repeats < 1 || np->num_repeats > 16) return fail(PECANN_EINVAL, "num_repeats must be in [1, 16]");
+  if (np->chunk < 0) return fail(PECANN_EINVAL, "chunk must be >= 0");
+  if (np->reserved != 0) return fail(PECANN_EINVAL, "NN-descent params reserved field must be 0");
+  if (nnd_chunk(np, ds->n) * nnd_maxprop(np->K) >= ((int64_t)1 << 31))
+    return fail(PECANN_EINVAL, "chunk too large: its proposal count must stay below 2^31");
+  return PECANN_OK;
+}
+}  // namespace
+
+extern "C" size_t pecann_build_graph_nndescent_workspace_size(const pecann_dataset *ds,
+                                                              const pecann_nnd_params *np) {
+  Layout L;
+  if (check_dataset(ds, &L) != PECANN_OK || check_nnd(ds, np) != PECANN_OK) return 0;
+  Carver c(nullptr);
+  NndWs w;
+  carve_nnd(c, ds->n, np->K, np->num_repeats, nnd_chunk(np, ds->n), &w);
+  return c.size();
+}
+
+extern "C" pecann_status pecann_build_graph_nndescent(const pecann_dataset *ds,
+                                                      const pecann_nnd_params *np,
+                                                      const int32_t *init, int32_t *adj,
+                                                      int32_t *deg, int32_t *knn_idx,
+                                                      float *knn_dist, int32_t *rounds,
+                                                      uint64_t *counters, void *ws,
+                                                      size_t ws_bytes, void *stream) {
+  clear_stale_error();
+  if (!ds) return fail(PECANN_EINVAL, "dataset is NULL");
+  Layout L;
+  pecann_status st = check_dataset(ds, &L);
+  if (st != PECANN_OK) return st;
+  if ((st = check_nnd(ds, np)) != PECANN_OK) return st;
+  if (!init || !adj || !deg) return fail(PECANN_EINVAL, "init/adj/deg are NULL");
+  const int64_t n = ds->n;
+  const int K = np->K, reps = np->num_repeats;
+  const int64_t chunk = nnd_chunk(np, n);
+  Carver c0(nullptr);
+  NndWs w;
+  carve_nnd(c0, n, K, reps, chunk, &w);
+  if (!ws || ws_bytes < c0.size() || !aligned(ws, 256))
+    return fail(PECANN_EWORKSPACE, "workspace needs %zu bytes (256-aligned), got %zu", c0.size(), ws_bytes);
+  Carver c(ws);
+  carve_nnd(c, n, K, reps, chunk, &w);
+  hipStream_t s = (hipStream_t)stream;
+  const int dt = ds->search_dtype;
+  const int cus = cu_count();
+  unsigned long long *ctrs = (unsigned long long *)counters;
+
+  NndParams P = {};
+  P.rows = rows_of(ds, L);
+  P.n = (int32_t)n;
+  P.K = K;
+  P.done = w.ctr + 0;
+  P.rcursor = w.ctr + 1;
+  P.pcount = w.ctr + 4;
+  P.pcursor = w.ctr + 5;
+  P.ptouch_n = w.ctr + 6;
+  P.overflow = w.ctr + 7;
+  P.updates = w.updates;
+  P.thr = (long long)std::floor((double)np->delta * (double)n * (double)K);
+  P.rcnt = w.rcnt;
+  P.roff = w.roff;
+  P.rticket = w.rticket;
+  P.rseg = w.rseg;
+  P.rsegf = w.rsegf;
+  P.rnew = w.rnew;
+  P.rold = w.rold;
+  P.pcap = chunk * nnd_maxprop(K);
+  P.ptgt = w.ptgt;
+  P.pkey = w.pkey;
+  P.pticket = w.pticket;
+  P.pseg = w.pseg;
+  P.pcnt = w.pcnt;
+  P.poff = w.poff;
+  P.ptouch = w.ptouch;
+  P.counters = ctrs;
+  int32_t *rounds_out = rounds ? rounds : w.rounds;
+
+  HIP_TRY(launch_fill_i32(w.ctr, 0, 16, s));
+  HIP_TRY(launch_fill_i32(w.rcnt, 0, n, s));
+  HIP_TRY(launch_fill_i32(w.pcnt, 0, n, s));
+  HIP_TRY(launch_fill_i32(rounds_out, 0, reps, s));
+  HIP_TRY(launch_fill_u64((uint64_t *)w.updates, 0, 1, s));
+
+  const uint64_t *final_keys = nullptr;
+  for (int r = 0; r < reps; ++r) {
+    P.cur_keys = w.keys[0];
+    P.cur_flags = w.flags[0];
+    P.nxt_keys = w.keys[1];
+    P.nxt_flags = w.flags[1];
+    P.rounds = rounds_out + r;
+    HIP_TRY(launch_fill_i32(P.done, 0, 1, s));
+    {
+      PROF(F_NND_LISTS, s);
+      HIP_TRY(launch_nnd_init(dt, P, init + (int64_t)r * n * K, (int)std::min<int64_t>(n, (int64_t)cus * 32), s));
+    }
+    for (int it = 0; it < np->max_iters; ++it) {
+      {
+        PROF(F_NND_LISTS, s);
+        HIP_TRY(launch_nnd_round_begin(P, cus, s));
+        HIP_TRY(launch_nnd_reverse(P, 1, 0, cus, s));
+      }
+      for (int64_t b = 0; b < n; b += chunk) {
+        P.c0 = (int32_t)b;
+        P.c1 = (int32_t)std::min<int64_t>(n, b + chunk);
+        HIP_TRY(launch_fill_i32(w.ctr + 2, 0, 5, s));  // heads, proposals, cursor, targets
+        P.head = w.ctr + 2;
+        {
+          PROF(F_NND_JOIN, s);
+          HIP_TRY(launch_nnd_join(dt, P, persistent_grid(P.c1 - P.c0), s));
+        }
+        {
+          PROF(F_NND_UPDATE, s);
+          HIP_TRY(launch_nnd_proposals(P, cus, s));
+          P.head = w.ctr + 3;
+          HIP_TRY(launch_nnd_merge(P, persistent_grid(n), s));
+        }
+      }
+      {
+        PROF(F_NND_LISTS, s);
+        HIP_TRY(launch_nnd_round_end(P, cus, s));
+      }
+      std::swap(P.cur_keys, P.nxt_keys);
+      std::swap(P.cur_flags, P.nxt_flags);
+    }
+    if (reps == 1) {
+      final_keys = P.cur_keys;
+    } else {
+      PROF(F_NND_LISTS, s);
+      if (r == 0)
+        HIP_TRY(launch_nnd_copy(P.cur_keys, w.acc, n * K, cus, s));
+      else
+        HIP_TRY(launch_nnd_acc_merge(P, w.acc, P.cur_keys, cus, s));
+      final_keys = w.acc;
+    }
+  }
+  // reverse lists of the final lists, then the pruned graph
+  NndParams Q = P;
+  Q.cur_keys = (uint64_t *)final_keys;
+  Q.cur_flags = nullptr;
+  {
+    PROF(F_NND_LISTS, s);
+    HIP_TRY(launch_nnd_reverse(Q, 0, 1, cus, s));
+  }
+  PruneParams pp = {};
+  pp.rows = P.rows;
+  pp.n = (int32_t)n;
+  pp.R = np->R;
+  pp.alpha = np->alpha;
+  pp.adj = adj;
+  pp.deg = deg;
+  pp.lists = final_keys;
+  pp.rlists = w.rnew;
+  pp.lk = K;
+  pp.head = w.ctr + 8;
+  pp.counters = ctrs ? ctrs + 3 : nullptr;
+  {
+    PROF(F_NND_PRUNE, s);
+    HIP_TRY(launch_prune_lists(dt, pp, persistent_grid(n), s));
+  }
+  if (knn_idx || knn_dist) HIP_TRY(launch_nnd_out(P, final_keys, knn_idx, knn_dist, cus, s));
   return PECANN_OK;
 }
 

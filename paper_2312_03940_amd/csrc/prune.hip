@@ -15,14 +15,11 @@
 //   new sources not yet present (ascending index) if they fit in R, else
 //   Nout(q) = RobustPrune(q, Nout(q) u sources).
 #include "beam.hpp"
+#include "tiles.hpp"
 
 namespace pecann {
 
 namespace {
-
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 struct PruneLds {
   int32_t *ids;    // candidates [ccap]
@@ -60,102 +57,6 @@ __device__ __forceinline__ void rank_sort_dups(const uint64_t *src, uint64_t *ds
     dst[r] = key;
   }
   wave_lds_sync();
-}
-
-// NT 16 x 16 tiles of dot products between search rows on the matrix cores,
-// sharing their A rows.  Lane l contributes row (l % 16) of the A tile (arow)
-// and of each B tile (brow[t]); at step s it loads 16-byte chunk (l / 16) + 4 s
-// of each.  The result is the MFMA accumulator layout: register r of lane l
-// holds A-row 4 (l / 16) + r against B-row l % 16.  U8 rows are shifted to
-// signed (x - 128) so that the integer dot is exact (its bits are returned in
-// the float lanes).  Missing rows (-1) contribute zeros.
-__device__ __forceinline__ uint4 load_chunk(const uint8_t *base, int32_t row, int64_t stride, int q,
-                                            bool in, bool u8) {
-  uint4 v = make_uint4(0, 0, 0, 0);
-  if (in && row >= 0) {
-    v = *(const uint4 *)(base + (int64_t)row * stride + 16 * q);
-    if (u8) { v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u; }
-  }
-  return v;
-}
-
-template <int DT>
-__device__ __forceinline__ void mfma_chunk(uint4 a, uint4 b, v4f &accf, v4i &acci) {
-  if (DT == PECANN_F32) {
-    accf = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), accf, 0, 0, 0);
-    accf = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), accf, 0, 0, 0);
-    accf = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), accf, 0, 0, 0);
-    accf = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), accf, 0, 0, 0);
-  } else if (DT == PECANN_U8) {
-    const v4i ai = {(int)a.x, (int)a.y, (int)a.z, (int)a.w};
-    const v4i bi = {(int)b.x, (int)b.y, (int)b.z, (int)b.w};
-    acci = __builtin_amdgcn_mfma_i32_16x16x64_i8(ai, bi, acci, 0, 0, 0);
-  } else if (DT == PECANN_BF16) {
-    const v8bf ab = __builtin_bit_cast(v8bf, a);
-    const v8bf bb = __builtin_bit_cast(v8bf, b);
-    accf = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bb, accf, 0, 0, 0);
-  } else {  // FP8 e4m3: two 8-byte halves
-    const long a0 = (long)(((uint64_t)a.y << 32) | a.x), a1 = (long)(((uint64_t)a.w << 32) | a.z);
-    const long b0 = (long)(((uint64_t)b.y << 32) | b.x), b1 = (long)(((uint64_t)b.w << 32) | b.z);
-    accf = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b0, accf, 0, 0, 0);
-    accf = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, accf, 0, 0, 0);
-  }
-}
-
-template <int DT, int NT>
-__device__ __forceinline__ void dot_tiles(const Rows &r, int32_t arow, const int32_t (&brow)[NT],
-                                          v4f (&out)[NT]) {
-  const int g = lane_id() >> 4;
-  const int steps = (r.nch + 3) >> 2;
-  constexpr bool u8 = DT == PECANN_U8;
-  v4f accf[NT];
-  v4i acci[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    accf[t] = v4f{0.f, 0.f, 0.f, 0.f};
-    acci[t] = v4i{0, 0, 0, 0};
-  }
-  // the loads of SG steps go out before any of their products (one memory
-  // round trip per SG steps instead of one per step)
-  constexpr int SG = 4;
-  for (int st0 = 0; st0 < steps; st0 += SG) {
-    uint4 a[SG], b[SG][NT];
-#pragma unroll
-    for (int u = 0; u < SG; ++u) {
-      const int q = g + 4 * (st0 + u);
-      const bool in = st0 + u < steps && q < r.nch;
-      a[u] = load_chunk(r.xs, arow, r.xs_stride, q, in, u8);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) b[u][t] = load_chunk(r.xs, brow[t], r.xs_stride, q, in, u8);
-    }
-#pragma unroll
-    for (int u = 0; u < SG; ++u) {
-#pragma unroll
-      for (int t = 0; t < NT; ++t) mfma_chunk<DT>(a[u], b[u][t], accf[t], acci[t]);
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    if (DT == PECANN_U8)
-      out[t] = v4f{__int_as_float(acci[t][0]), __int_as_float(acci[t][1]), __int_as_float(acci[t][2]),
-                   __int_as_float(acci[t][3])};
-    else
-      out[t] = accf[t];
-  }
-}
-
-// Measure (squared L2, or cosine distance) from a dot product and the two rows'
-// norms / scales, as the search keys define it.
-template <int DT>
-__device__ __forceinline__ float pair_measure(float dotv, uint32_t na, uint32_t nb, float sa, float sb,
-                                              int metric) {
-  if (DT == PECANN_U8) {
-    const int d2 = (int)na + (int)nb - 2 * __float_as_int(dotv);
-    return (float)(d2 < 0 ? 0 : d2);
-  }
-  const float dt = (DT == PECANN_FP8E4M3) ? dotv * sa * sb : dotv;
-  if (metric == PECANN_L2) return fmaxf(0.f, __uint_as_float(na) + __uint_as_float(nb) - 2.0f * dt);
-  return fmaxf(0.f, 1.0f - dt);
 }
 
 // Compacts the live entries of the sorted list [from, mv) toward `from`, keeping
@@ -510,6 +411,27 @@ __global__ __launch_bounds__(64) void prune_reverse_kernel(PruneParams p) {
   }
 }
 
+// NN-descent graph: Nout(i) = RobustPrune(i, list_i u rev_i) for every point.
+template <int DT>
+__global__ __launch_bounds__(64) void prune_lists_kernel(PruneParams p) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  PruneLds s = carve_prune(smem, 2 * p.lk, p.R);
+  const int l = lane_id();
+  for (;;) {
+    const int u = next_item(p.head);
+    if (u >= p.n) break;
+    for (int j = l; j < p.lk; j += kWave) {
+      const uint64_t k = p.lists[(int64_t)u * p.lk + j];
+      s.ids[j] = k == kNoKey ? -1 : key_id(k);
+      s.ids[p.lk + j] = p.rlists[(int64_t)u * p.lk + j];
+    }
+    wave_lds_sync();
+    const int rows = 32 * robust_prune_tiles<DT>(p, s, u, 2 * p.lk);
+    if (p.counters && l == 0) atomicAdd(p.counters + 0, (unsigned long long)rows);
+    wave_lds_sync();
+  }
+}
+
 size_t prune_lds_bytes(int ccap, int R) {
   return (size_t)ccap * (8 + 8 + 4 + 4 + 4 + 1) + 4 * 256 + 4 * (size_t)((R + 3) & ~3) + 16;
 }
@@ -525,6 +447,23 @@ static hipError_t launch_pr_t(const PruneParams &p, int grid, hipStream_t st) {
   hipLaunchKernelGGL((prune_reverse_kernel<DT>), dim3(grid), dim3(64),
                      prune_lds_bytes(p.R + p.capin, p.R), st, p);
   return hipGetLastError();
+}
+
+template <int DT>
+static hipError_t launch_pl_t(const PruneParams &p, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((prune_lists_kernel<DT>), dim3(grid), dim3(64), prune_lds_bytes(2 * p.lk, p.R), st,
+                     p);
+  return hipGetLastError();
+}
+
+hipError_t launch_prune_lists(int32_t dt, const PruneParams &p, int grid, hipStream_t st) {
+  switch (dt) {
+    case PECANN_F32: return launch_pl_t<PECANN_F32>(p, grid, st);
+    case PECANN_U8: return launch_pl_t<PECANN_U8>(p, grid, st);
+    case PECANN_BF16: return launch_pl_t<PECANN_BF16>(p, grid, st);
+    case PECANN_FP8E4M3: return launch_pl_t<PECANN_FP8E4M3>(p, grid, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_prune_forward(int32_t dt, const PruneParams &p, int grid, hipStream_t st) {

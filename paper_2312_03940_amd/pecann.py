@@ -47,6 +47,13 @@ class _BuildParams(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class _NndParams(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("R", ctypes.c_int32), ("alpha", ctypes.c_float),
+                ("max_iters", ctypes.c_int32), ("delta", ctypes.c_float),
+                ("num_repeats", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class _Instances(ctypes.Structure):
     _fields_ = [("num_instances", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("offsets", ctypes.POINTER(ctypes.c_int64)), ("k", ctypes.POINTER(ctypes.c_int32)),
@@ -132,6 +139,9 @@ def load():
         "pecann_density": (ctypes.c_int, [i64, N, i32, i32, vp, vp, vp, vp, vp, sz, vp]),
         "pecann_local_centers_workspace_size": (sz, [i64, N]),
         "pecann_local_centers": (ctypes.c_int, [i64, N, i32, vp, vp, vp, f32, vp, vp, sz, vp]),
+        "pecann_build_graph_nndescent_workspace_size": (sz, [D, ctypes.POINTER(_NndParams)]),
+        "pecann_build_graph_nndescent": (ctypes.c_int, [D, ctypes.POINTER(_NndParams), vp, vp, vp, vp,
+                                                        vp, vp, vp, vp, sz, vp]),
         "pecann_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "pecann_last_error": (ctypes.c_char_p, []),
     }
@@ -236,6 +246,47 @@ def build_graph(ds: Dataset, R: int, L: int, alpha: float, num_starts: int = 8,
     _check(lib.pecann_build_graph(ctypes.byref(s), ctypes.byref(bp), _ptr(perm), seed, _ptr(adj),
                                   _ptr(deg), _ptr(counters), _ptr(ws), ws.numel(), _stream()))
     return adj, deg
+
+
+def build_graph_nndescent(ds: Dataset, K: int, R: int, alpha: float, init: torch.Tensor,
+                          max_iters: int = 20, delta: float = 0.001, chunk: int = 0,
+                          ws: torch.Tensor | None = None, out=None, counters: torch.Tensor | None = None):
+    """NN-descent graph (second index).  init: int32 device tensor [num_repeats, n, K]
+    (or [n, K]) of starting neighbour ids.
+    -> (adj int32 [n, R], deg int32 [n], knn_idx int32 [n, K], knn_dist f32 [n, K],
+        rounds int32 [num_repeats])."""
+    lib = load()
+    s = ds.struct
+    _need_cuda(init)
+    if init.dim() == 2:
+        init = init.unsqueeze(0)
+    if init.dtype != torch.int32 or tuple(init.shape[1:]) != (ds.n, K) or not init.is_contiguous():
+        raise PecannError("init must be a contiguous int32 tensor [num_repeats, n, K]")
+    reps = init.shape[0]
+    npar = _NndParams(K, R, alpha, max_iters, delta, reps, chunk, 0)
+    need = lib.pecann_build_graph_nndescent_workspace_size(ctypes.byref(s), ctypes.byref(npar))
+    if need == 0:
+        raise PecannError("invalid NN-descent parameters")
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, ds.device)
+    if out is None:
+        out = (torch.empty((ds.n, R), dtype=torch.int32, device=ds.device),
+               torch.empty(ds.n, dtype=torch.int32, device=ds.device),
+               torch.empty((ds.n, K), dtype=torch.int32, device=ds.device),
+               torch.empty((ds.n, K), dtype=torch.float32, device=ds.device),
+               torch.empty(reps, dtype=torch.int32, device=ds.device))
+    adj, deg, idx, dist, rounds = out
+    _check(lib.pecann_build_graph_nndescent(ctypes.byref(s), ctypes.byref(npar), _ptr(init), _ptr(adj),
+                                            _ptr(deg), _ptr(idx), _ptr(dist), _ptr(rounds),
+                                            _ptr(counters), _ptr(ws), ws.numel(), _stream()))
+    return adj, deg, idx, dist, rounds
+
+
+def workspace_bytes_nndescent(ds: Dataset, K: int, R: int, alpha: float = 1.2, max_iters: int = 20,
+                              delta: float = 0.001, num_repeats: int = 1, chunk: int = 0) -> int:
+    npar = _NndParams(K, R, alpha, max_iters, delta, num_repeats, chunk, 0)
+    return int(load().pecann_build_graph_nndescent_workspace_size(ctypes.byref(ds.struct),
+                                                                   ctypes.byref(npar)))
 
 
 def knn_density(ds: Dataset, k: int, adj=None, deg=None, L_search: int = 64, rerank: int | None = None,

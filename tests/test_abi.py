@@ -124,3 +124,43 @@ def test_batched_instance_tables_are_validated(lib):
                                     ctypes.c_void_p(256), ctypes.c_void_p(256), 0, 1, 0.0, 0.0,
                                     ctypes.c_void_p(256), ctypes.c_void_p(256), None, 0, None)
     assert rc == 1 and b"n_c of instance 1" in lib.pecann_last_error()
+
+
+def test_nndescent_argument_errors(lib):
+    ds = pecann._Dataset(100, 16, pecann.L2, pecann.F32, 0, 256)
+    P = pecann._NndParams
+    ok = P(10, 16, 1.2, 10, 0.001, 1, 0, 0)
+    assert lib.pecann_build_graph_nndescent_workspace_size(ctypes.byref(ds), ctypes.byref(ok)) > 0
+    bad = [(P(0, 16, 1.2, 10, 0.001, 1, 0, 0), b"K"),      # K < 1
+           (P(65, 16, 1.2, 10, 0.001, 1, 0, 0), b"K"),     # K > 64
+           (P(10, 0, 1.2, 10, 0.001, 1, 0, 0), b"R"),
+           (P(10, 16, 0.5, 10, 0.001, 1, 0, 0), b"alpha"),
+           (P(10, 16, 1.2, -1, 0.001, 1, 0, 0), b"max_iters"),
+           (P(10, 16, 1.2, 10, -0.5, 1, 0, 0), b"delta"),
+           (P(10, 16, 1.2, 10, 0.001, 0, 0, 0), b"num_repeats"),
+           (P(10, 16, 1.2, 10, 0.001, 1, -3, 0), b"chunk"),
+           (P(10, 16, 1.2, 10, 0.001, 1, 0, 7), b"reserved")]
+    for prm, word in bad:
+        assert lib.pecann_build_graph_nndescent_workspace_size(ctypes.byref(ds), ctypes.byref(prm)) == 0
+        rc = lib.pecann_build_graph_nndescent(ctypes.byref(ds), ctypes.byref(prm), None, None, None, None,
+                                              None, None, None, None, 0, None)
+        assert rc == 1 and word in lib.pecann_last_error(), (word, lib.pecann_last_error())
+    # K must leave room for distinct neighbours
+    small = pecann._Dataset(8, 16, pecann.L2, pecann.F32, 0, 256)
+    assert lib.pecann_build_graph_nndescent_workspace_size(ctypes.byref(small), ctypes.byref(ok)) == 0
+    # missing init / outputs and a short workspace are refused before any launch
+    rc = lib.pecann_build_graph_nndescent(ctypes.byref(ds), ctypes.byref(ok), None, None, None, None,
+                                          None, None, None, None, 0, None)
+    assert rc == 1 and b"init" in lib.pecann_last_error()
+    fake = ctypes.c_void_p(4096)
+    rc = lib.pecann_build_graph_nndescent(ctypes.byref(ds), ctypes.byref(ok), fake, fake, fake, None,
+                                          None, None, None, fake, 16, None)
+    assert rc == 2 and b"workspace" in lib.pecann_last_error()
+    # the automatic chunk keeps the proposal buffer near 1.5 GiB; a given chunk sizes it
+    big = pecann._Dataset(1_000_000, 128, pecann.L2, pecann.BF16, 0, 256)
+    w_auto = lib.pecann_build_graph_nndescent_workspace_size(ctypes.byref(big), ctypes.byref(P(32, 64, 1.2, 10, 0.0, 1, 0, 0)))
+    w_small = lib.pecann_build_graph_nndescent_workspace_size(ctypes.byref(big), ctypes.byref(P(32, 64, 1.2, 10, 0.0, 1, 1000, 0)))
+    per_join = (12 * 32 * 32 - 2 * 32) * 24  # worst-case proposals x bytes per proposal
+    auto_chunk = (3 << 29) // per_join
+    assert abs((w_auto - w_small) - (auto_chunk - 1000) * per_join) < 4096
+    assert auto_chunk * per_join <= 3 << 29
