@@ -66,6 +66,11 @@ WORKLOADS = {
 }
 
 
+# NN-descent index of the variants (second graph index): list length K, rounds
+# and stop level; R and alpha are the workload's
+NND = dict(K=32, max_iters=12, delta=0.001, num_repeats=1)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,11 +161,12 @@ def recall_from_sample(idx, dist, sample, ref_dist, k):
 class Pipeline:
     """Buffers and launch sequence of one DPC step on a resident dataset."""
 
-    def __init__(self, x, wl, search, mode, args, perm, inst=None):
+    def __init__(self, x, wl, search, mode, args, perm, inst=None, index="vamana"):
         import torch
-        from paper_2312_03940_amd import pecann
+        from paper_2312_03940_amd import datagen, pecann
         self.torch, self.pecann = torch, pecann
         self.x, self.wl, self.mode, self.args, self.perm = x, wl, mode, args, perm
+        self.index = index
         self.inst = inst  # pecann.Instances: one batched call per step covers them all
         dev = x.device
         self.ds = ds = pecann.Dataset(x, wl["metric"], search)
@@ -180,7 +186,16 @@ class Pipeline:
             ws_exact = pecann.workspace_bytes_batched(ds, inst, k, self.Ls, args.kdep_cap, R, wl["L"],
                                                       wl["alpha"], args.num_starts, args.max_batch,
                                                       exact=True)
-        self.ws = torch.empty(max(ws_anns, ws_exact), dtype=torch.uint8, device=dev)
+        ws_nnd = 0
+        if index == "nndescent":
+            # seeded random starting lists: an input of the construction, resident in HBM
+            self.nnd_init = torch.from_numpy(datagen.random_neighbour_lists(n, NND["K"], 20231206)).to(dev)
+            ws_nnd = pecann.workspace_bytes_nndescent(ds, NND["K"], R, wl["alpha"], NND["max_iters"],
+                                                      NND["delta"])
+            self.nnd_out = (torch.empty((n, NND["K"]), dtype=torch.int32, device=dev),
+                            torch.empty((n, NND["K"]), dtype=torch.float32, device=dev),
+                            torch.empty(1, dtype=torch.int32, device=dev))
+        self.ws = torch.empty(max(ws_anns, ws_exact, ws_nnd), dtype=torch.uint8, device=dev)
         self.g_out = (torch.empty((n, R), dtype=torch.int32, device=dev),
                       torch.empty(n, dtype=torch.int32, device=dev))
         self.k_out = (torch.empty((n, k), dtype=torch.int32, device=dev),
@@ -202,7 +217,11 @@ class Pipeline:
         if ev:
             ev[1].record()
         adj = deg = None
-        if self.mode == "anns":
+        if self.mode == "anns" and self.index == "nndescent":
+            adj, deg, _, _, _ = p.build_graph_nndescent(self.ds, NND["K"], wl["R"], wl["alpha"], self.nnd_init,
+                                                        max_iters=NND["max_iters"], delta=NND["delta"],
+                                                        ws=self.ws, out=self.g_out + self.nnd_out)
+        elif self.mode == "anns":
             if inst is None:
                 adj, deg = p.build_graph(self.ds, wl["R"], wl["L"], wl["alpha"],
                                          num_starts=a.num_starts, perm=self.perm,
@@ -296,12 +315,13 @@ def ari_per_instance(a, b, off):
     return [ari(a[off[t]:off[t + 1]], b[off[t]:off[t + 1]]) for t in range(len(off) - 1)]
 
 
-def measure(x, wl, search, mode, args, perm, steps, warmup, ref=None, sample=None, inst=None):
+def measure(x, wl, search, mode, args, perm, steps, warmup, ref=None, sample=None, inst=None,
+            index="vamana"):
     """Time `steps` DPC steps and evaluate the quality gates.  `ref` holds the
     reference labels under the workload's noise cutoff ("labels"), and optionally
     under rho_min = 0 ("labels0") with the generator's component ids ("y")."""
-    log(f"measure {search}/{mode}: {warmup} warm-up + {steps} timed steps")
-    pl = Pipeline(x, wl, search, mode, args, perm, inst)
+    log(f"measure {search}/{mode}/{index}: {warmup} warm-up + {steps} timed steps")
+    pl = Pipeline(x, wl, search, mode, args, perm, inst, index)
     n = pl.ds.n
     wall, ph, kprof = pl.run(steps, warmup)
     rec = {"search_rows": search, "mode": mode, "ms_per_step": round(wall * 1e3 / steps, 3),
@@ -531,15 +551,23 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_variants:
         variants = {}
-        alt = {2: [("u8", "anns"), ("u8", "exact"), ("f32", "exact")],
-               3: [("f32", "anns")], 4: [("f32", "anns")], 5: [("f32", "anns")]}[args.config]
-        for vs, vm in alt:
-            if (vs, vm) == (search, args.mode):
+        alt = {2: [("u8", "anns", "vamana"), ("u8", "exact", "vamana"), ("f32", "exact", "vamana"),
+                   ("f32", "anns", "nndescent")],
+               3: [("f32", "anns", "vamana"), ("bf16", "anns", "nndescent")],
+               4: [("f32", "anns", "vamana")], 5: [("f32", "anns", "vamana")]}[args.config]
+        for vs, vm, vi in alt:
+            if (vs, vm, vi) == (search, args.mode, "vamana"):
                 continue
             vsteps = args.variant_steps or (3 if args.config == 2 else 1)
-            r, p2, _ = measure(x, wl, vs, vm, args, perm, vsteps, 1, ref_lab, sample, inst)
-            variants[f"{vs}_{vm}"] = {key: r[key] for key in ("value", "ms_per_step", "phases_ms",
-                                                              "quality", "knn_queries_per_s")}
+            r, p2, _ = measure(x, wl, vs, vm, args, perm, vsteps, 1, ref_lab, sample, inst, vi)
+            name = f"{vs}_{vm}" + ("" if vi == "vamana" else f"_{vi}")
+            variants[name] = {key: r[key] for key in ("value", "ms_per_step", "phases_ms",
+                                                      "quality", "knn_queries_per_s")}
+            if vi == "nndescent":
+                variants[name]["index"] = {"kind": "NN-descent", **NND, "R": wl["R"], "alpha": wl["alpha"],
+                                           "rounds_run": int(p2.nnd_out[2].item()),
+                                           "build_kernels_ms": {f: v for f, v in r["kernels_ms"].items()
+                                                                if f.startswith("nnd_")}}
             del p2
             torch.cuda.empty_cache()
         if not args.no_graph and args.mode == "anns":

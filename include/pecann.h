@@ -210,9 +210,10 @@ pecann_status pecann_build_graph(const pecann_dataset *ds, const pecann_build_pa
  *   counters  device 4 uint64 or NULL (caller zeroes): [0] proposals written,
  *             [1] 16 x 16 join tiles, [2] proposal merges (targets), [3] row
  *             reads of the final prune's tiles (32 per tile)
- * Local joins run in chunks of `chunk` points (0: as many as fit 1.5 GiB of
- * proposal buffers at the worst case of 12 K^2 proposals per join); the
- * result does not depend on the chunking.  The workspace grows with it.
+ * The proposal buffer holds `chunk` worst-case joins (12 K^2 - 2 K proposals
+ * each; 0: as many as fit 4 GiB); a round's joins run in passes that fill it
+ * at the actual counts.  The result does not depend on the chunking; the
+ * workspace grows with it.
  * Limits: 1 <= K <= 64, K <= n - 1, 1 <= R <= 128, alpha >= 1,
  * 0 <= max_iters <= 1000, delta >= 0, 1 <= num_repeats <= 16, chunk >= 0.
  * ------------------------------------------------------------------------- */

@@ -195,15 +195,16 @@ struct NndParams {
   uint64_t *rseg;              // (measure, source) keys
   uint8_t *rsegf;              // source's flag
   int32_t *rnew, *rold;        // [n][K] closest new / old sources, -1 padded
-  // one chunk of local joins [c0, c1) and its proposals
-  int32_t c0, c1;
-  int32_t *head;               // work-queue head, 0 at launch
-  int32_t *pcount;             // proposals written
-  int64_t pcap;                // proposal capacity of the chunk
-  int32_t *ptgt;               // [pcap] target
-  uint64_t *pkey;              // [pcap] (measure, proposed index)
-  int32_t *pticket;            // [pcap] slot within the target's group
-  uint64_t *pseg;              // [pcap] keys grouped by target
+  // local joins of one round (queue head kept across the round's passes) and
+  // the proposals of one pass: join wave w writes slots [w * seg, (w + 1) * seg)
+  int32_t *head;               // work-queue head
+  int64_t maxprop;             // proposals of one join at most
+  int64_t seg;                 // proposal slots per join wave (>= maxprop)
+  int32_t *pfill;              // [join grid] slots each wave filled
+  int32_t *ptgt;               // [slots] target
+  uint64_t *pkey;              // [slots] (measure, proposed index)
+  int32_t *pticket;            // [slots] slot within the target's group
+  uint64_t *pseg;              // [slots] keys grouped by target
   int32_t *pcnt, *poff;        // [n] per target (pcnt 0 between chunks)
   int32_t *pcursor;
   int32_t *ptouch, *ptouch_n;  // targets with proposals
@@ -217,7 +218,7 @@ hipError_t launch_nnd_round_begin(const NndParams &p, int cus, hipStream_t s);
 hipError_t launch_nnd_reverse(const NndParams &p, int32_t split, int32_t ignore_done, int cus,
                               hipStream_t s);
 hipError_t launch_nnd_join(int32_t dt, const NndParams &p, int grid, hipStream_t s);
-hipError_t launch_nnd_proposals(const NndParams &p, int cus, hipStream_t s);
+hipError_t launch_nnd_proposals(const NndParams &p, int join_grid, int cus, hipStream_t s);
 hipError_t launch_nnd_merge(const NndParams &p, int grid, hipStream_t s);
 hipError_t launch_nnd_round_end(const NndParams &p, int cus, hipStream_t s);
 hipError_t launch_nnd_acc_merge(const NndParams &p, uint64_t *acc, const uint64_t *src, int cus,

@@ -215,12 +215,19 @@ __global__ __launch_bounds__(64) void nnd_rev_select_kernel(NndParams p, int32_t
   }
 }
 
-// Local joins of points [c0, c1): proposals (target, key) into the chunk's
-// buffer.  Members: U (new entries, then new reverse sources) and W (old
-// entries, then old reverse sources), deduplicated through an LDS hash (one it
-// forgets costs a repeated pair, never a wrong one: self pairs are skipped and
-// the merge drops repeated keys).  Tiles: row block b of U against U blocks
-// b.. (upper triangle on the diagonal) and every W block, four at a time.
+// Local joins: proposals (target, key) into the pass's buffer, in which wave
+// (block) w owns the segment [w * seg, (w + 1) * seg).  A wave takes the next
+// point of the round's queue while its segment still has room for the
+// worst-case proposal count of one join, so with no shared counter a pass
+// covers at least floor(seg / worst) points per wave unless the queue runs
+// out; the wave records its segment's fill when it stops.  Members: U (new
+// entries, then new reverse sources) and W (old entries, then old reverse
+// sources), deduplicated through an LDS hash (one it forgets costs a repeated
+// pair, never a wrong one: self pairs are skipped and the merge drops repeated
+// keys).  Tiles: row block b of U against U blocks b.. (upper triangle on the
+// diagonal) and every W block, four at a time.  A proposal to t is kept only
+// if it beats the K-th key of t's next list as it stands after the previous
+// passes: that list only improves, so nothing dropped could enter it.
 template <int DT>
 __global__ __launch_bounds__(64) void nnd_join_kernel(NndParams p) {
   if (*p.done) return;
@@ -235,10 +242,13 @@ __global__ __launch_bounds__(64) void nnd_join_kernel(NndParams p) {
   h.bits = kJoinHashBits;
   const int l = lane_id(), col = l & 15, g = l >> 4;
   unsigned long long n_tiles = 0, n_prop = 0;
+  const int64_t sbase = (int64_t)blockIdx.x * p.seg;
+  int64_t fill = 0;
   for (;;) {
+    if (fill + p.maxprop > p.seg) break;
     const int it = next_item(p.head);
-    const int64_t i = (int64_t)p.c0 + it;
-    if (i >= p.c1) break;
+    const int64_t i = it;
+    if (i >= p.n) break;
     h.clear();
     wave_lds_sync();
     int cnt = 0, nu = 0;
@@ -267,7 +277,7 @@ __global__ __launch_bounds__(64) void nnd_join_kernel(NndParams p) {
     wave_lds_sync();
     for (int j = l; j < cnt; j += kWave) {
       const int32_t id = mem[j];
-      wk[j] = p.cur_keys[(int64_t)id * K + K - 1];
+      wk[j] = p.nxt_keys[(int64_t)id * K + K - 1];
       cn[j] = p.rows.sqn[id];
       cs[j] = (DT == PECANN_FP8E4M3) ? p.rows.scale[id] : 1.0f;
     }
@@ -320,14 +330,11 @@ __global__ __launch_bounds__(64) void nnd_join_kernel(NndParams p) {
         const int incl = wave_incl_sum(mine);
         const int total = __shfl(incl, kWave - 1);
         if (total == 0) continue;
-        int base = 0;
-        if (l == 0) base = atomicAdd(p.pcount, total);
-        base = __shfl(base, 0);
-        if ((int64_t)base + total > p.pcap) {  // cannot happen with the chunk sizing
+        if (fill + total > p.seg) {  // cannot happen: a join never exceeds maxprop
           if (l == 0) atomicAdd(p.overflow, 1);
           continue;
         }
-        int o = base + incl - mine;
+        int64_t o = sbase + fill + incl - mine;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
 #pragma unroll
@@ -341,21 +348,26 @@ __global__ __launch_bounds__(64) void nnd_join_kernel(NndParams p) {
           }
         }
         n_prop += total;
+        fill += total;
       }
     }
     wave_lds_sync();
   }
+  if (l == 0) p.pfill[blockIdx.x] = (int32_t)fill;
   if (p.counters && l == 0) {
     atomicAdd(p.counters + 0, n_prop);
     atomicAdd(p.counters + 1, n_tiles);
   }
 }
 
-// Proposals grouped by target: count (and list each target once), place, scatter.
+// Proposals grouped by target: count (and list each target once), place,
+// scatter.  Block b walks the filled part of join segment b.
 __global__ void nnd_prop_count_kernel(NndParams p) {
   if (*p.done) return;
-  const int np = (int)min((int64_t)*p.pcount, p.pcap);
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < np; e += gridDim.x * blockDim.x) {
+  const int64_t base = (int64_t)blockIdx.x * p.seg;
+  const int nf = p.pfill[blockIdx.x];
+  for (int j = threadIdx.x; j < nf; j += blockDim.x) {
+    const int64_t e = base + j;
     const int32_t t = p.ptgt[e];
     const int tk = atomicAdd(p.pcnt + t, 1);
     p.pticket[e] = tk;
@@ -374,9 +386,12 @@ __global__ void nnd_prop_alloc_kernel(NndParams p) {
 
 __global__ void nnd_prop_scatter_kernel(NndParams p) {
   if (*p.done) return;
-  const int np = (int)min((int64_t)*p.pcount, p.pcap);
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < np; e += gridDim.x * blockDim.x)
+  const int64_t base = (int64_t)blockIdx.x * p.seg;
+  const int nf = p.pfill[blockIdx.x];
+  for (int j = threadIdx.x; j < nf; j += blockDim.x) {
+    const int64_t e = base + j;
     p.pseg[(int64_t)p.poff[p.ptgt[e]] + p.pticket[e]] = p.pkey[e];
+  }
 }
 
 // Per proposed-to point: next list = the K smallest of it and its proposals.
@@ -525,11 +540,10 @@ hipError_t launch_nnd_reverse(const NndParams &p, int32_t split, int32_t ignore_
   return hipGetLastError();
 }
 
-hipError_t launch_nnd_proposals(const NndParams &p, int cus, hipStream_t s) {
-  const int g = cus * 16;
-  hipLaunchKernelGGL(nnd_prop_count_kernel, dim3(g), dim3(kBlock), 0, s, p);
-  hipLaunchKernelGGL(nnd_prop_alloc_kernel, dim3(g), dim3(kBlock), 0, s, p);
-  hipLaunchKernelGGL(nnd_prop_scatter_kernel, dim3(g), dim3(kBlock), 0, s, p);
+hipError_t launch_nnd_proposals(const NndParams &p, int join_grid, int cus, hipStream_t s) {
+  hipLaunchKernelGGL(nnd_prop_count_kernel, dim3(join_grid), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(nnd_prop_alloc_kernel, dim3(cus * 16), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(nnd_prop_scatter_kernel, dim3(join_grid), dim3(kBlock), 0, s, p);
   return hipGetLastError();
 }
 

@@ -721,7 +721,7 @@ static pecann_status build_impl(const pecann_dataset *ds, const pecann_build_par
 // NN-descent graph
 // ---------------------------------------------------------------------------
 namespace {
-constexpr int64_t kNndPropBudget = (int64_t)3 << 29;  // 1.5 GiB of proposal buffers
+constexpr int64_t kNndPropBudget = (int64_t)1 << 32;  // 4 GiB of proposal buffers
 constexpr int64_t kNndPropBytes = 4 + 8 + 4 + 8;      // target, key, ticket, grouped key
 
 // Proposals of one local join at most: U and W hold at most 2K members each,
@@ -744,11 +744,17 @@ struct NndWs {
   int32_t *ptgt, *pticket;
   uint64_t *pkey, *pseg;
   int32_t *pcnt, *poff, *ptouch;
-  int32_t *ctr;  // [0] done [1] rcursor [2] join head [3] merge head [4] proposals [5] cursor
-                 // [6] targets [7] overflow [8] prune head
+  int32_t *pfill;  // slots filled by each join wave
+  int32_t *ctr;    // [0] done [1] rcursor [2] join head [3] merge head [5] cursor
+                   // [6] targets [7] overflow [8] prune head
   unsigned long long *updates;
   int32_t *rounds;
 };
+
+// Join waves of a pass: each owns a segment of at least one worst-case join.
+int nnd_join_grid(int64_t n, int64_t chunk) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)cu_count() * 32, n, chunk}));
+}
 
 void carve_nnd(Carver &c, int64_t n, int K, int repeats, int64_t chunk, NndWs *w) {
   const size_t nk = (size_t)(n * K);
@@ -772,6 +778,7 @@ void carve_nnd(Carver &c, int64_t n, int K, int repeats, int64_t chunk, NndWs *w
   w->pcnt = c.take<int32_t>((size_t)n);
   w->poff = c.take<int32_t>((size_t)n);
   w->ptouch = c.take<int32_t>((size_t)n);
+  w->pfill = c.take<int32_t>((size_t)cu_count() * 32);
   w->ctr = c.take<int32_t>(16);
   w->updates = c.take<unsigned long long>(1);
   w->rounds = c.take<int32_t>(16);
@@ -839,11 +846,16 @@ extern "C" pecann_status pecann_build_graph_nndescent(const pecann_dataset *ds,
   P.K = K;
   P.done = w.ctr + 0;
   P.rcursor = w.ctr + 1;
-  P.pcount = w.ctr + 4;
   P.pcursor = w.ctr + 5;
   P.ptouch_n = w.ctr + 6;
   P.overflow = w.ctr + 7;
   P.updates = w.updates;
+  P.maxprop = nnd_maxprop(K);
+  const int jgrid = nnd_join_grid(n, chunk);
+  P.seg = chunk * nnd_maxprop(K) / jgrid;
+  P.pfill = w.pfill;
+  // points a pass joins at least (unless the round's queue runs out)
+  const int64_t per_pass = (int64_t)jgrid * (P.seg / P.maxprop);
   P.thr = (long long)std::floor((double)np->delta * (double)n * (double)K);
   P.rcnt = w.rcnt;
   P.roff = w.roff;
@@ -852,7 +864,6 @@ extern "C" pecann_status pecann_build_graph_nndescent(const pecann_dataset *ds,
   P.rsegf = w.rsegf;
   P.rnew = w.rnew;
   P.rold = w.rold;
-  P.pcap = chunk * nnd_maxprop(K);
   P.ptgt = w.ptgt;
   P.pkey = w.pkey;
   P.pticket = w.pticket;
@@ -887,18 +898,19 @@ extern "C" pecann_status pecann_build_graph_nndescent(const pecann_dataset *ds,
         HIP_TRY(launch_nnd_round_begin(P, cus, s));
         HIP_TRY(launch_nnd_reverse(P, 1, 0, cus, s));
       }
-      for (int64_t b = 0; b < n; b += chunk) {
-        P.c0 = (int32_t)b;
-        P.c1 = (int32_t)std::min<int64_t>(n, b + chunk);
-        HIP_TRY(launch_fill_i32(w.ctr + 2, 0, 5, s));  // heads, proposals, cursor, targets
+      // passes over the round's queue, enough for per_pass joins each; passes
+      // after the queue has drained return at once
+      HIP_TRY(launch_fill_i32(w.ctr + 2, 0, 1, s));  // join queue head
+      for (int64_t b = 0; b < n; b += per_pass) {
+        HIP_TRY(launch_fill_i32(w.ctr + 3, 0, 4, s));  // merge head, (unused), cursor, targets
         P.head = w.ctr + 2;
         {
           PROF(F_NND_JOIN, s);
-          HIP_TRY(launch_nnd_join(dt, P, persistent_grid(P.c1 - P.c0), s));
+          HIP_TRY(launch_nnd_join(dt, P, jgrid, s));
         }
         {
           PROF(F_NND_UPDATE, s);
-          HIP_TRY(launch_nnd_proposals(P, cus, s));
+          HIP_TRY(launch_nnd_proposals(P, jgrid, cus, s));
           P.head = w.ctr + 3;
           HIP_TRY(launch_nnd_merge(P, persistent_grid(n), s));
         }

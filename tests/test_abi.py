@@ -156,11 +156,11 @@ def test_nndescent_argument_errors(lib):
     rc = lib.pecann_build_graph_nndescent(ctypes.byref(ds), ctypes.byref(ok), fake, fake, fake, None,
                                           None, None, None, fake, 16, None)
     assert rc == 2 and b"workspace" in lib.pecann_last_error()
-    # the automatic chunk keeps the proposal buffer near 1.5 GiB; a given chunk sizes it
+    # the automatic chunk keeps the proposal buffer within 4 GiB; a given chunk sizes it
     big = pecann._Dataset(1_000_000, 128, pecann.L2, pecann.BF16, 0, 256)
     w_auto = lib.pecann_build_graph_nndescent_workspace_size(ctypes.byref(big), ctypes.byref(P(32, 64, 1.2, 10, 0.0, 1, 0, 0)))
     w_small = lib.pecann_build_graph_nndescent_workspace_size(ctypes.byref(big), ctypes.byref(P(32, 64, 1.2, 10, 0.0, 1, 1000, 0)))
     per_join = (12 * 32 * 32 - 2 * 32) * 24  # worst-case proposals x bytes per proposal
-    auto_chunk = (3 << 29) // per_join
+    auto_chunk = (1 << 32) // per_join
     assert abs((w_auto - w_small) - (auto_chunk - 1000) * per_join) < 4096
-    assert auto_chunk * per_join <= 3 << 29
+    assert auto_chunk * per_join <= 1 << 32
