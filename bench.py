@@ -98,6 +98,9 @@ def parse():
                     help="skip the reference clustering and the quality gates (profiling runs)")
     ap.add_argument("--variant-steps", type=int, default=None,
                     help="timed steps of each variant (default 3; 1 for the 1M-point workloads)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the launch settings (speed only) with the package's autotuner "
+                         "before timing; the cache lives in PECANN_AUTOTUNE_CACHE")
     ap.add_argument("--nnd-k", type=int, default=None, help="NN-descent list length of the variant")
     ap.add_argument("--nnd-repeats", type=int, default=None, help="NN-descent runs merged")
     ap.add_argument("--nnd-only", action="store_true",
@@ -323,13 +326,23 @@ def ari_per_instance(a, b, off):
 
 
 def measure(x, wl, search, mode, args, perm, steps, warmup, ref=None, sample=None, inst=None,
-            index="vamana"):
+            index="vamana", tune=False):
     """Time `steps` DPC steps and evaluate the quality gates.  `ref` holds the
     reference labels under the workload's noise cutoff ("labels"), and optionally
     under rho_min = 0 ("labels0") with the generator's component ids ("y")."""
     log(f"measure {search}/{mode}/{index}: {warmup} warm-up + {steps} timed steps")
     pl = Pipeline(x, wl, search, mode, args, perm, inst, index)
     n = pl.ds.n
+    tuning = None
+    if tune:
+        from paper_2312_03940_amd import autotune
+        log("autotune: launch settings for this shape (outside the timed region)")
+        t0 = time.perf_counter()
+        tuning = autotune.tune(pl.ds, wl["R"], wl["L"], wl["alpha"], wl["k"], pl.Ls, perm=perm,
+                               max_batch=args.max_batch, num_starts=args.num_starts)
+        tuning["seconds"] = round(time.perf_counter() - t0, 2)
+        tuning.pop("trials", None)
+        log(f"autotune: {tuning}")
     wall, ph, kprof = pl.run(steps, warmup)
     rec = {"search_rows": search, "mode": mode, "ms_per_step": round(wall * 1e3 / steps, 3),
            "value": round(n * steps / wall, 1),
@@ -368,6 +381,8 @@ def measure(x, wl, search, mode, args, perm, steps, warmup, ref=None, sample=Non
         q["gates_met"] = bool(q.get("ari_vs_reference", 1.0) >= 0.95 and all(v >= 0.95 for v in rk))
     rec["quality"] = q
     rec["dependent_stats"] = pl.d_out[2].cpu().numpy()[:8].tolist()
+    if tuning is not None:
+        rec["tuning"] = tuning
     return rec, pl, kprof
 
 
@@ -514,7 +529,8 @@ def main():
         torch.cuda.empty_cache()
 
     rec, pl, kprof = measure(x, wl, search, args.mode, args, perm, args.steps, args.warmup,
-                             ref_lab, sample, inst)
+                             ref_lab, sample, inst,
+                             tune=args.autotune and args.mode == "anns" and inst is None)
     if ref_kind:
         rec["quality"]["reference"] = ref_kind
     out = {
@@ -542,6 +558,8 @@ def main():
         "dependent_stats": rec["dependent_stats"],
         "kernels_ms": rec["kernels_ms"],
     }
+    if "tuning" in rec:
+        out["config"]["tuning"] = rec["tuning"]
     # dendrogram re-cut (Sec. 1): densities and dependents stay, each cut is one
     # cluster call; time a sweep of n_c on the last step's forest
     if inst is None and wl["n_c"]:
@@ -559,6 +577,9 @@ def main():
         out["roofline"] = roofline(pl, kprof, args.steps, search, n, d, wl["k"])
     del pl
     torch.cuda.empty_cache()
+    if "tuning" in rec:
+        from paper_2312_03940_amd import pecann
+        pecann.reset_tuning()  # variants run with the library's rules
     if not args.no_variants:
         variants = {}
         alt = {2: [("u8", "anns", "vamana"), ("u8", "exact", "vamana"), ("f32", "exact", "vamana"),

@@ -442,7 +442,8 @@ pecann_status pecann_local_centers(int64_t n, const pecann_instances *inst, int3
  * HIP events recorded on the launch stream, filed under its kernel family
  * ("search_build", "search_knn", "search_dep", "prune_forward",
  * "prune_reverse", "reverse_edges", "bf_knn", "bf_dep", "exact_mfma", "prepare",
- * "cluster", "other").  pecann_profile_enable(1) clears earlier records; enable(0) stops
+ * "cluster", "nnd_join", "nnd_update", "nnd_lists", "nnd_prune", "other").
+ * pecann_profile_enable(1) clears earlier records; enable(0) stops
  * recording.  pecann_profile_report synchronises the recorded events and
  * writes up to max_entries family totals into out; it returns the number
  * written, or -1 on a HIP error.  Events come from a pool the library keeps
@@ -456,6 +457,32 @@ typedef struct {
 
 pecann_status pecann_profile_enable(int32_t on);
 int32_t pecann_profile_report(pecann_profile_entry *out, int32_t max_entries);
+
+/* ---------------------------------------------------------------------------
+ * Launch tuning.  Settings that change speed only: every output of every call
+ * is the same, byte for byte, under any valid setting (the visited hash may
+ * forget ids, which costs repeated distance evaluations and nothing else, and
+ * every work item's result is independent of which wave takes it).  Chosen by
+ * the package's autotuner, which times candidates through these calls and
+ * keeps the winners in a JSON cache keyed by the workload's shape.
+ *   hash_bits_build   log2 visited-hash slots of build searches (0: the rule
+ *                     of about 10 L or 20 L slots; else 10..13)
+ *   hash_bits_search  the same for kNN and doubling-round searches (0: about
+ *                     20 L slots; else 10..13)
+ *   grid_per_cu       one-wave blocks per compute unit of the persistent
+ *                     search, prune and join launches (0: 32; else 4..64)
+ * The setting is process-wide; set it before the calls it should govern, not
+ * while another thread is inside the library.  NULL restores the rules.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t hash_bits_build;
+  int32_t hash_bits_search;
+  int32_t grid_per_cu;
+  int32_t reserved;  /* must be 0 */
+} pecann_tuning;
+
+pecann_status pecann_set_tuning(const pecann_tuning *t);
+pecann_status pecann_get_tuning(pecann_tuning *t);
 
 const char *pecann_status_string(pecann_status s);
 /* Thread-local description of the last error returned on this thread. */

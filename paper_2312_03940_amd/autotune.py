@@ -1,0 +1,135 @@
+"""Autotuner for the launch settings that change speed only (pecann_set_tuning):
+the visited-hash size of the build searches and of the kNN / doubling searches,
+and the persistent grid (one-wave blocks per compute unit).
+
+For a workload shape it times the graph build and the kNN search under a few
+candidate settings with HIP events, one knob at a time with the others at their
+best so far, keeps the fastest, applies it, and stores it in a JSON cache keyed
+by the shape (device name, n rounded to a power of two, d, search rows, metric,
+R, L, k, L_search).  Every output of the library is the same under any setting,
+so only times are compared.  The cache file is PECANN_AUTOTUNE_CACHE, else
+~/.cache/pecann/autotune.json."""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import torch
+
+from . import pecann
+
+BUILD_HASH_BITS = (0, 11, 12, 13)
+SEARCH_HASH_BITS = (0, 11, 12, 13)
+GRID_PER_CU = (0, 12, 20)
+
+
+def cache_path() -> str:
+    return os.environ.get("PECANN_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "pecann", "autotune.json"))
+
+
+def shape_key(ds: pecann.Dataset, R: int, L: int, k: int, L_search: int) -> str:
+    dev = torch.cuda.get_device_name(ds.device)
+    nb = 1 << max(0, int(math.log2(max(ds.n, 1))))
+    return (f"{dev}|n~{nb}|d={ds.d}|rows={ds.search_dtype}|metric={ds.metric}|R={R}|L={L}|k={k}"
+            f"|Ls={L_search}")
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(path, cache):
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _time(fn, reps: int) -> float:
+    """Best of reps timings of fn() on the current stream, in ms."""
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def tune(ds: pecann.Dataset, R: int, L: int, alpha: float, k: int, L_search: int,
+         perm: torch.Tensor | None = None, max_batch: int = 0, num_starts: int = 8,
+         reps: int = 1, path: str | None = None, use_cache: bool = True) -> dict:
+    """Pick and apply the fastest launch settings for this workload shape.
+    -> the chosen settings with the measured times (cached entries are returned
+    as stored, with "cached": True)."""
+    path = path or cache_path()
+    key = shape_key(ds, R, L, k, L_search)
+    cache = _load(path) if use_cache else {}
+    if key in cache:
+        e = cache[key]
+        pecann.set_tuning(e["hash_bits_build"], e["hash_bits_search"], e["grid_per_cu"])
+        return {**e, "cached": True}
+
+    dev = ds.device
+    n = ds.n
+    ws = torch.empty(pecann.workspace_bytes(ds, k, L_search, 1024, R, L, alpha, num_starts, max_batch),
+                     dtype=torch.uint8, device=dev)
+    g_out = (torch.empty((n, R), dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
+    k_out = (torch.empty((n, k), dtype=torch.int32, device=dev), torch.empty((n, k), dtype=torch.float32, device=dev),
+             torch.empty(n, dtype=torch.float32, device=dev), torch.empty(n, dtype=torch.int64, device=dev))
+
+    def build():
+        pecann.build_graph(ds, R, L, alpha, num_starts=num_starts, max_batch=max_batch, perm=perm,
+                           ws=ws, out=g_out)
+
+    def knn():
+        pecann.knn_density(ds, k, g_out[0], g_out[1], L_search=L_search, ws=ws, out=k_out)
+
+    cur = {"hash_bits_build": 0, "hash_bits_search": 0, "grid_per_cu": 0}
+
+    def apply(c):
+        pecann.set_tuning(c["hash_bits_build"], c["hash_bits_search"], c["grid_per_cu"])
+
+    apply(cur)
+    build()  # warm-up, and the graph the kNN timings search
+    torch.cuda.synchronize()
+    base_build = _time(build, reps)
+    base_knn = _time(knn, reps)
+    trials = []
+
+    def sweep(knob, values, fn, base):
+        best_v, best_t = cur[knob], base
+        for v in values:
+            if v == cur[knob]:
+                continue
+            c = dict(cur, **{knob: v})
+            apply(c)
+            t = _time(fn, reps)
+            trials.append({**c, "what": fn.__name__, "ms": round(t, 3)})
+            if t < best_t:
+                best_v, best_t = v, t
+        cur[knob] = best_v
+        apply(cur)
+        return best_t
+
+    t_build = sweep("hash_bits_build", BUILD_HASH_BITS, build, base_build)
+    t_build = sweep("grid_per_cu", GRID_PER_CU, build, t_build)
+    build()  # the graph under the chosen build settings, for the kNN timings
+    torch.cuda.synchronize()
+    t_knn = sweep("hash_bits_search", SEARCH_HASH_BITS, knn, _time(knn, reps))
+    entry = {**cur, "build_ms": round(t_build, 3), "knn_ms": round(t_knn, 3),
+             "rule_build_ms": round(base_build, 3), "rule_knn_ms": round(base_knn, 3), "trials": trials}
+    if use_cache:
+        cache = _load(path)
+        cache[key] = entry
+        _save(path, cache)
+    return {**entry, "cached": False}

@@ -20,6 +20,9 @@ using namespace pecann;
 // ---------------------------------------------------------------------------
 static thread_local char g_err[512] = "";
 
+// Launch tuning (speed only; see pecann_set_tuning).  Process-wide.
+static pecann_tuning g_tuning = {0, 0, 0, 0};
+
 static pecann_status fail(pecann_status s, const char *fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
@@ -112,6 +115,28 @@ struct ProfScope {
 #define PROF_CAT(a, b) PROF_CAT2(a, b)
 #define PROF(fam, s) ProfScope PROF_CAT(prof_scope_, __LINE__)(fam, s)
 
+extern "C" pecann_status pecann_set_tuning(const pecann_tuning *t) {
+  clear_stale_error();
+  if (!t) {
+    g_tuning = pecann_tuning{0, 0, 0, 0};
+    return PECANN_OK;
+  }
+  auto bits_ok = [](int32_t b) { return b == 0 || (b >= 10 && b <= 13); };
+  if (!bits_ok(t->hash_bits_build) || !bits_ok(t->hash_bits_search))
+    return fail(PECANN_EINVAL, "hash bits must be 0 or in [10, 13]");
+  if (t->grid_per_cu != 0 && (t->grid_per_cu < 4 || t->grid_per_cu > 64))
+    return fail(PECANN_EINVAL, "grid_per_cu must be 0 or in [4, 64]");
+  if (t->reserved != 0) return fail(PECANN_EINVAL, "tuning reserved field must be 0");
+  g_tuning = *t;
+  return PECANN_OK;
+}
+
+extern "C" pecann_status pecann_get_tuning(pecann_tuning *t) {
+  if (!t) return fail(PECANN_EINVAL, "tuning is NULL");
+  *t = g_tuning;
+  return PECANN_OK;
+}
+
 extern "C" pecann_status pecann_profile_enable(int32_t on) {
   if (on) g_prof.recycle();
   g_prof.on = on != 0;
@@ -159,7 +184,8 @@ static int cu_count() {
 // Persistent grids: enough one-wavefront blocks to fill every CU; surplus
 // blocks find the work queue empty and leave.
 static int persistent_grid(int64_t items) {
-  int64_t g = (int64_t)cu_count() * 32;
+  const int per_cu = g_tuning.grid_per_cu > 0 ? g_tuning.grid_per_cu : 32;
+  int64_t g = (int64_t)cu_count() * per_cu;
   if (items < g) g = items;
   if (g < 1) g = 1;
   return (int)g;
@@ -304,6 +330,8 @@ struct Carver {
 // 453 ms; 1024-d FP8, L = 200: 4096 and 2048 within 2 %.  The kNN search of
 // the 128-d BF16 rows (L = 64) was faster with 2048 slots than with 1024.
 static int hash_bits_for(int L, size_t row_bytes, bool build) {
+  const int forced = build ? g_tuning.hash_bits_build : g_tuning.hash_bits_search;
+  if (forced > 0) return forced;
   const int mult = (build && row_bytes < 512) ? 10 : 20;
   int b = 10;
   while (b < 13 && (1 << b) < mult * L) ++b;

@@ -54,6 +54,11 @@ class _NndParams(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("hash_bits_build", ctypes.c_int32), ("hash_bits_search", ctypes.c_int32),
+                ("grid_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class _Instances(ctypes.Structure):
     _fields_ = [("num_instances", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("offsets", ctypes.POINTER(ctypes.c_int64)), ("k", ctypes.POINTER(ctypes.c_int32)),
@@ -142,6 +147,8 @@ def load():
         "pecann_build_graph_nndescent_workspace_size": (sz, [D, ctypes.POINTER(_NndParams)]),
         "pecann_build_graph_nndescent": (ctypes.c_int, [D, ctypes.POINTER(_NndParams), vp, vp, vp, vp,
                                                         vp, vp, vp, vp, sz, vp]),
+        "pecann_set_tuning": (ctypes.c_int, [ctypes.POINTER(_Tuning)]),
+        "pecann_get_tuning": (ctypes.c_int, [ctypes.POINTER(_Tuning)]),
         "pecann_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "pecann_last_error": (ctypes.c_char_p, []),
     }
@@ -246,6 +253,23 @@ def build_graph(ds: Dataset, R: int, L: int, alpha: float, num_starts: int = 8,
     _check(lib.pecann_build_graph(ctypes.byref(s), ctypes.byref(bp), _ptr(perm), seed, _ptr(adj),
                                   _ptr(deg), _ptr(counters), _ptr(ws), ws.numel(), _stream()))
     return adj, deg
+
+
+def set_tuning(hash_bits_build: int = 0, hash_bits_search: int = 0, grid_per_cu: int = 0):
+    """Launch settings that change speed only (0 = the library's rule)."""
+    t = _Tuning(hash_bits_build, hash_bits_search, grid_per_cu, 0)
+    _check(load().pecann_set_tuning(ctypes.byref(t)))
+
+
+def reset_tuning():
+    _check(load().pecann_set_tuning(None))
+
+
+def get_tuning() -> dict:
+    t = _Tuning()
+    _check(load().pecann_get_tuning(ctypes.byref(t)))
+    return {"hash_bits_build": t.hash_bits_build, "hash_bits_search": t.hash_bits_search,
+            "grid_per_cu": t.grid_per_cu}
 
 
 def build_graph_nndescent(ds: Dataset, K: int, R: int, alpha: float, init: torch.Tensor,

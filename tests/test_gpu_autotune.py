@@ -1,0 +1,64 @@
+"""Launch tuning changes speed only: the graph, the kNN lists and the dependent
+points are the same bytes under every setting; the autotuner picks, applies and
+caches a setting."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2312_03940_amd import autotune, datagen, pecann
+
+pytestmark = pytest.mark.gpu
+
+SETTINGS = [(0, 0, 0), (10, 13, 4), (13, 10, 64), (11, 12, 12)]
+
+
+def _step(ds, perm, k):
+    adj, deg = pecann.build_graph(ds, 24, 48, 1.2, perm=perm)
+    idx, dist, rho, key = pecann.knn_density(ds, k, adj, deg, L_search=48)
+    dep, delta, _ = pecann.dependent_search(ds, key, idx, dist, adj, deg, L_d=32, L_search=48)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in (adj, deg, idx, dist, key, dep, delta)]
+
+
+@pytest.mark.parametrize("sdt", ["bf16", "u8"])
+def test_tuning_does_not_change_results(sdt):
+    dev = torch.device("cuda:0")
+    X, _ = datagen.mixture(5000, 40, 10, seed=4, grid=255 if sdt == "u8" else None)
+    x = torch.from_numpy(X.astype(np.uint8) if sdt == "u8" else X).to(dev)
+    perm = torch.from_numpy(datagen.permutation(5000, 1)).to(dev)
+    ds = pecann.Dataset(x, "l2", sdt)
+    try:
+        ref = None
+        for hb, hs, g in SETTINGS:
+            pecann.set_tuning(hb, hs, g)
+            assert pecann.get_tuning() == {"hash_bits_build": hb, "hash_bits_search": hs, "grid_per_cu": g}
+            got = _step(ds, perm, 8)
+            if ref is None:
+                ref = got
+            else:
+                for a, b in zip(got, ref):
+                    assert np.array_equal(a, b), (hb, hs, g)
+    finally:
+        pecann.reset_tuning()
+
+
+def test_autotune_picks_applies_and_caches(tmp_path):
+    dev = torch.device("cuda:0")
+    X, _ = datagen.mixture(4000, 32, 8, seed=6)
+    ds = pecann.Dataset(torch.from_numpy(X).to(dev), "l2", "bf16")
+    path = str(tmp_path / "tune.json")
+    try:
+        e = autotune.tune(ds, 24, 48, 1.2, 8, 48, path=path)
+        assert not e["cached"]
+        chosen = {kk: e[kk] for kk in ("hash_bits_build", "hash_bits_search", "grid_per_cu")}
+        assert pecann.get_tuning() == chosen
+        assert e["build_ms"] <= e["rule_build_ms"] and e["knn_ms"] > 0
+        stored = json.load(open(path))
+        assert len(stored) == 1 and autotune.shape_key(ds, 24, 48, 8, 48) in stored
+        pecann.reset_tuning()
+        e2 = autotune.tune(ds, 24, 48, 1.2, 8, 48, path=path)
+        assert e2["cached"] and pecann.get_tuning() == chosen
+    finally:
+        pecann.reset_tuning()
