@@ -437,8 +437,8 @@ def roofline(pl, kprof, steps, search, n, d, k):
     avg_ms = fam_ms[fam] / fam_l[fam]
     per_launch = alg[fam] / fam_l[fam]
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
-    mode = {"search_build": "MODE_BUILD", "search_knn": "MODE_KNN"}[fam]
-    return {"bound": "hbm", "kernel": f"search_kernel<{search}, {mode}>", "family": fam,
+    kname = f"search_kernel<{search}, MODE_BUILD>" if fam == "search_build" else f"search_knn_kernel<{search}>"
+    return {"bound": "hbm", "kernel": kname, "family": fam,
             "dominant_family": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": stored_traffic(f"{fam}@{search}"),
