@@ -255,7 +255,7 @@ __device__ __forceinline__ float reduce_scatter(float (&v)[U]) {
   return r;
 }
 
-template <int DT, int S, bool XR = false>
+template <int DT, int S, bool XR = false, int LC = 0>
 struct Engine {
   static_assert(S >= 4 && S <= 1024 && (S & (S - 1)) == 0, "shape must be a power of two in [4, 1024]");
   static_assert(!XR || DT == PECANN_F32, "the rerank rows are float32");
@@ -269,8 +269,8 @@ struct Engine {
   static constexpr int NPL = kWave / G;
   // chunks per lane in flight: 16 for float32 search rows, 8 for the narrower
   // formats and the rerank rows (whose kernels need more registers elsewhere;
-  // measured best on MI355X)
-  static constexpr int LCAP = (DT == PECANN_F32 && !XR) ? 16 : 8;
+  // measured best on MI355X); LC > 0 overrides it
+  static constexpr int LCAP = LC > 0 ? LC : ((DT == PECANN_F32 && !XR) ? 16 : 8);
   static constexpr int U = (LCAP / CPL) < 1 ? 1 : ((LCAP / CPL) < G ? LCAP / CPL : G);
   static constexpr bool INT = DT == PECANN_U8 && !XR;
   float q[CPL * EPC];

@@ -98,7 +98,13 @@ __device__ __forceinline__ void search_body(const SearchParams &p) {
   constexpr bool kNeedRerank = (DT == PECANN_BF16 || DT == PECANN_FP8E4M3);
 
 
-  Engine<DT, S> eng;
+  // build searches over float32 rows of 64 chunks or more run at most two
+  // waves per SIMD anyway (their beam and visited hash fill the LDS), so they
+  // spend the spare registers on twice the row loads in flight (784-d rows:
+  // 190 -> 186 ms per step; the FP8 and BF16 builds, whose time goes to
+  // decoding and FMAs, gained nothing)
+  constexpr int kLc = (DT == PECANN_F32 && MODE == MODE_BUILD && S >= 64) ? 32 : 0;
+  Engine<DT, S, false, kLc> eng;
   constexpr int SR = RerankShape<DT, S>::v;
   for (;;) {
     const int it = next_item(p.head);
