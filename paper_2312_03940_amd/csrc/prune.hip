@@ -87,6 +87,53 @@ __device__ __forceinline__ int compact_live(PruneLds &s, int from, int mv) {
   return out;
 }
 
+// Selections of the block of 16 candidates starting at o, in order, from the
+// block's own tile (register r of lane l: entries o + 4 (l / 16) + r and
+// o + l % 16).  Each lane works out which earlier entries of its column's
+// candidate would drop it (alpha^2 D^2(i, j) <= D^2(p, j) for i < j), the masks
+// are transposed with ballots, and the greedy pass runs on wave-uniform masks:
+// no LDS round trip per step.  Appends the selected ids to s.sel and returns
+// the mask of selected block entries; block entries end not alive.
+template <int DT>
+__device__ __forceinline__ uint32_t select_block(const PruneParams &p, PruneLds &s, const v4f &tile,
+                                                 int o, int mv, float a2, int &nsel) {
+  const int l = lane_id();
+  const int col = l & 15, g = l >> 4;
+  const int j = o + col;
+  uint32_t kb = 0;
+  if (j < mv) {
+    const float dpj = key_measure(s.k1[j]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 4 * g + r;
+      if (i < col) {
+        const float m = pair_measure<DT>(tile[r], s.cn[o + i], s.cn[j], s.cs[o + i], s.cs[j],
+                                         p.rows.metric);
+        if (a2 * m <= dpj) kb |= 1u << i;
+      }
+    }
+  }
+  kb |= __shfl_xor(kb, 16);
+  kb |= __shfl_xor(kb, 32);
+  uint32_t alive = (uint32_t)ballot(l < 16 && j < mv && s.alive[j]) & 0xffffu;
+  uint32_t sel = 0;
+  const int nsel0 = nsel;
+#pragma unroll 1
+  for (int i = 0; i < 16; ++i) {
+    if (!((alive >> i) & 1u)) continue;
+    sel |= 1u << i;
+    alive &= ~(1u << i);
+    if (++nsel == p.R) break;
+    alive &= ~((uint32_t)ballot(l < 16 && ((kb >> i) & 1u)) & 0xffffu);
+  }
+  if (l < 16 && j < mv) {
+    if ((sel >> l) & 1u) s.sel[nsel0 + __popc(sel & ((1u << l) - 1u))] = key_id(s.k1[j]);
+    s.alive[j] = 0;
+  }
+  wave_lds_sync();
+  return sel;
+}
+
 // Short lists (at most kSmallBlocks blocks of 16 live candidates): block B's
 // tiles against itself and every later block are formed in one round (rows
 // already dropped are not loaded), then the block's selections and kills are
@@ -110,29 +157,7 @@ __device__ __forceinline__ void short_block(const PruneParams &p, PruneLds &s, i
   v4f tt[NT];
   dot_tiles<DT, NT>(p.rows, br[0], br, tt);
   // (a) the block's own tile -> its selections, in order
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = 4 * g + r;
-    float m = 0.f;
-    if (o + i < mv && o + col < mv)
-      m = pair_measure<DT>(tt[0][r], s.cn[o + i], s.cn[o + col], s.cs[o + i], s.cs[o + col],
-                           p.rows.metric);
-    s.dg[i * 16 + col] = m;
-  }
-  wave_lds_sync();
-  uint32_t selmask = 0;
-  for (int i = 0; i < 16 && o + i < mv; ++i) {
-    if (!s.alive[o + i]) continue;
-    if (l == 0) { s.sel[nsel] = key_id(s.k1[o + i]); s.alive[o + i] = 0; }
-    selmask |= 1u << i;
-    ++nsel;
-    if (nsel == p.R) break;
-    if (l > i && l < 16 && o + l < mv && s.alive[o + l] &&
-        a2 * s.dg[i * 16 + l] <= key_measure(s.k1[o + l]))
-      s.alive[o + l] = 0;
-    wave_lds_sync();
-  }
-  wave_lds_sync();
+  const uint32_t selmask = select_block<DT>(p, s, tt[0], o, mv, a2, nsel);
   if (nsel == p.R) return;
   // (b) the block's selected points drop later candidates
 #pragma unroll
@@ -239,36 +264,15 @@ __device__ int robust_prune_tiles(const PruneParams &p, PruneLds &s, int32_t pt,
   for (int b = 0; b < mv && nsel < p.R; b += 16) {
     // (a) the block's own 16 x 16 tile (every entry of the block is live)
     const int32_t rb = b + col < mv ? key_id(s.k1[b + col]) : -1;
+    uint32_t selmask;
     {
       const int32_t br[1] = {rb};
       v4f t[1];
       dot_tiles<DT, 1>(p.rows, rb, br, t);
       ++tiles;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 4 * g + r;
-        float m = 0.f;
-        if (b + i < mv && b + col < mv)
-          m = pair_measure<DT>(t[0][r], s.cn[b + i], s.cn[b + col], s.cs[b + i], s.cs[b + col],
-                               p.rows.metric);
-        s.dg[i * 16 + col] = m;
-      }
+      // (b) selections of this block, in order
+      selmask = select_block<DT>(p, s, t[0], b, mv, a2, nsel);
     }
-    wave_lds_sync();
-    // (b) selections of this block, in order
-    uint32_t selmask = 0;
-    for (int i = 0; i < 16 && b + i < mv; ++i) {
-      if (!s.alive[b + i]) continue;
-      if (l == 0) { s.sel[nsel] = key_id(s.k1[b + i]); s.alive[b + i] = 0; }
-      selmask |= 1u << i;
-      ++nsel;
-      if (nsel == p.R) break;
-      if (l > i && l < 16 && b + l < mv && s.alive[b + l] &&
-          a2 * s.dg[i * 16 + l] <= key_measure(s.k1[b + l]))
-        s.alive[b + l] = 0;
-      wave_lds_sync();
-    }
-    wave_lds_sync();
     if (nsel == p.R) break;
     // (c) the block's selected points drop later candidates, NT tiles at a time
     for (int j0 = b + 16; j0 < mv; j0 += 16 * NT) {
@@ -370,33 +374,62 @@ __global__ __launch_bounds__(64) void prune_reverse_kernel(PruneParams p) {
     const int32_t *src = p.seg + p.toff[u];
     const int dq = min(p.deg[q], p.R);
     int32_t *row = p.adj + (int64_t)q * p.R;
-    // current out-neighbours, then the new sources in ascending index order,
-    // leaving out sources already among the out-neighbours (the sources of one
-    // batch are distinct; they are staged in LDS and ranked there)
-    int32_t *stage = (int32_t *)s.k1;
-    for (int j = l; j < dq; j += kWave) s.ids[j] = row[j];
-    for (int j = l; j < cnt; j += kWave) stage[j] = src[j];
-    wave_lds_sync();
-    for (int j = l; j < cnt; j += kWave) {
-      const int32_t v = stage[j];
-      int r = 0;
-      for (int t = 0; t < cnt; ++t) r += stage[t] < v;
-      bool present = false;
-      for (int t = 0; t < dq; ++t) present |= (s.ids[t] == v);
-      ((int32_t *)s.k0)[r] = present ? -1 : v;
-    }
-    wave_lds_sync();
     int nnew = 0;
-    for (int base = 0; base < cnt; base += kWave) {
-      const int j = base + l;
-      const int32_t v = j < cnt ? ((const int32_t *)s.k0)[j] : -1;
-      const uint64_t bm = ballot(v >= 0);
-      if (v >= 0) s.ids[dq + nnew + lanes_below(bm)] = v;
-      nnew += __popcll(bm);
+    if (!p.heavy) {
+      // at most 64 sources (one per lane) and R <= 128 out-neighbours (two per
+      // lane): membership and ascending order come from ballots and lane reads,
+      // and an append never touches the LDS
+      const int32_t v = l < cnt ? src[l] : -1;
+      const int32_t e0 = l < dq ? row[l] : -1;
+      const int32_t e1 = l + kWave < dq ? row[l + kWave] : -1;
+      uint64_t pres = 0;
+      for (int t = 0; t < cnt; ++t) {
+        const int32_t vt = __builtin_amdgcn_readlane(v, t);
+        if (ballot(e0 == vt || e1 == vt)) pres |= 1ull << t;
+      }
+      const bool keep = l < cnt && !((pres >> l) & 1ull);
+      const uint64_t km = ballot(keep);
+      int r = 0;  // rank among the kept sources by index
+      for (uint64_t m = km; m; m &= m - 1)
+        r += __builtin_amdgcn_readlane(v, __builtin_ctzll(m)) < v;
+      nnew = __popcll(km);
+      if (dq + nnew <= p.R) {
+        if (keep) row[dq + r] = v;
+      } else {
+        if (l < dq) s.ids[l] = e0;
+        if (l + kWave < dq) s.ids[l + kWave] = e1;
+        if (keep) s.ids[dq + r] = v;
+      }
+    } else {
+      // current out-neighbours, then the new sources in ascending index order,
+      // leaving out sources already among the out-neighbours (the sources of
+      // one batch are distinct; they are staged in LDS and ranked there)
+      int32_t *stage = (int32_t *)s.k1;
+      for (int j = l; j < dq; j += kWave) s.ids[j] = row[j];
+      for (int j = l; j < cnt; j += kWave) stage[j] = src[j];
+      wave_lds_sync();
+      for (int j = l; j < cnt; j += kWave) {
+        const int32_t v = stage[j];
+        int r = 0;
+        for (int t = 0; t < cnt; ++t) r += stage[t] < v;
+        bool present = false;
+        for (int t = 0; t < dq; ++t) present |= (s.ids[t] == v);
+        ((int32_t *)s.k0)[r] = present ? -1 : v;
+      }
+      wave_lds_sync();
+      for (int base = 0; base < cnt; base += kWave) {
+        const int j = base + l;
+        const int32_t v = j < cnt ? ((const int32_t *)s.k0)[j] : -1;
+        const uint64_t bm = ballot(v >= 0);
+        if (v >= 0) s.ids[dq + nnew + lanes_below(bm)] = v;
+        nnew += __popcll(bm);
+      }
+      wave_lds_sync();
+      if (dq + nnew <= p.R)
+        for (int j = l; j < nnew; j += kWave) row[dq + j] = s.ids[dq + j];
     }
     wave_lds_sync();
     if (dq + nnew <= p.R) {
-      for (int j = l; j < nnew; j += kWave) row[dq + j] = s.ids[dq + j];
       if (l == 0) p.deg[q] = dq + nnew;
       if (p.counters && l == 0) atomicAdd(p.counters + 3, 1ull);
     } else {
