@@ -1,0 +1,139 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (its workload table, insertion orders and defaults).  The oracle cannot
+run these sizes whole, so the checks are (a) sampled outputs against what the
+oracle computed one by one for a fixed 2,000-point sample
+(tests/golden/*_sample.npz, c2_reference.npz, written by scripts that call
+only the oracle), and (b) properties that hold at any size:
+  - tie-tolerant recall of the kNN lists >= 0.95 on the sample;
+  - no approximate k-th distance below the exact one (rho never overestimated);
+  - every reported distance equals the exact distance of the returned id;
+  - dependent pointers go to strictly smaller rank keys, inside the instance,
+    and only the densest point of an instance has none;
+  - labels are constant along dependent pointers and every root is a center
+    or a noise point; exactly n_c centers per instance.
+The MNIST-shaped workload also runs in exact mode on u8 rows, whose labels
+must equal the oracle's exact DPC of all 70,000 points bit for bit."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import bench
+import oracle
+from oracle import metrics
+from paper_2312_03940_amd import datagen, pecann
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _dpc(x, wl, search, perm, inst=None, exact=False):
+    ds = pecann.Dataset(x, wl["metric"], search)
+    Ls, Ld = wl["L_search"], wl["L_d"]
+    adj = deg = None
+    if inst is None:
+        if not exact:
+            adj, deg = pecann.build_graph(ds, wl["R"], wl["L"], wl["alpha"], num_starts=8, perm=perm)
+        idx, dist, rho, key = pecann.knn_density(ds, wl["k"], adj, deg, L_search=Ls, rerank=Ls)
+        dep, delta, _ = pecann.dependent_search(ds, key, idx, dist, adj, deg, L_d=Ld, L_search=Ls)
+        labels, isc = pecann.cluster(rho, dep, delta, n_c=wl["n_c"], rho_min=wl["rho_min"])
+    else:
+        adj, deg = pecann.build_graph_batched(ds, inst, wl["R"], wl["L"], wl["alpha"], num_starts=8,
+                                              perm=perm)
+        idx, dist, rho, key = pecann.knn_density_batched(ds, inst, wl["k"], adj, deg, L_search=Ls,
+                                                         rerank=Ls)
+        dep, delta, _ = pecann.dependent_search_batched(ds, inst, key, idx, dist, adj, deg, L_d=Ld,
+                                                        L_search=Ls)
+        labels, isc = pecann.cluster_batched(inst, rho, dep, delta, rho_min=wl["rho_min"])
+    torch.cuda.synchronize()
+    out = dict(idx=idx, dist=dist, rho=rho, key=key, dep=dep, labels=labels, isc=isc)
+    return {kk: v.cpu().numpy() for kk, v in out.items()}
+
+
+def _check_sample(X, metric, r, sample, ref_dist, ks):
+    P = oracle.Points(X, metric)
+    if ks.ndim == 0:
+        k = int(ks)
+        rec = metrics.recall_at_k(P, sample, r["idx"][sample][:, :k], ref_dist, k)
+    else:  # per-query k (instances)
+        hits = tot = 0
+        for t, q in enumerate(sample):
+            k = int(ks[t])
+            thr = ref_dist[t, k - 1]
+            got = [int(j) for j in r["idx"][q, :k] if j >= 0]
+            hits += min(k, sum(oracle.distance(P, int(q), j) <= thr for j in set(got)))
+            tot += k
+        rec = hits / tot
+    assert rec >= 0.95, rec
+    tol_r, tol_a = (1e-5, 1e-6) if metric == oracle.L2 else (0.0, 1e-5)
+    for t, q in enumerate(sample[::10]):
+        row = np.nonzero(sample == q)[0][0]
+        k = int(ks[row]) if ks.ndim else int(ks)
+        # rho never overestimated: the approximate k-th distance is at least the exact one
+        assert r["dist"][q, k - 1] >= ref_dist[row, k - 1] * (1 - tol_r) - tol_a
+        for j in range(k):
+            exact = oracle.distance(P, int(q), int(r["idx"][q, j]))
+            assert abs(r["dist"][q, j] - exact) <= tol_r * exact + tol_a, (q, j)
+
+
+def _check_forest(r, n_c, off=None):
+    n = len(r["key"])
+    key = r["key"].astype(np.uint64)
+    dep, lab, isc = r["dep"], r["labels"], r["isc"].astype(bool)
+    off = np.array([0, n]) if off is None else off
+    inst = np.searchsorted(off, np.arange(n), side="right") - 1
+    has = dep >= 0
+    assert np.all(key[dep[has]] < key[has])
+    assert np.all(inst[dep[has]] == inst[has])
+    assert np.array_equal(np.bincount(inst[~has], minlength=len(off) - 1), np.ones(len(off) - 1))
+    root = lab == np.arange(n)
+    assert np.all(lab[has & ~root] == lab[dep[has & ~root]])
+    assert np.all(root == (isc | ~has | (root & ~isc)))  # roots are exactly the self-labelled points
+    counts = np.bincount(inst[isc], minlength=len(off) - 1)
+    assert np.array_equal(counts, np.asarray(n_c))
+
+
+def test_fullsize_mnist_shaped_f32_anns_and_u8_exact():
+    dev = torch.device("cuda:0")
+    wl = bench.WORKLOADS[2]
+    X, _ = datagen.config2()
+    n = len(X)
+    ref = np.load(os.path.join(GOLDEN, "c2_reference.npz"))
+    perm = torch.from_numpy(datagen.permutation(n, 20231205)).to(dev)
+    x = torch.from_numpy(X).to(dev)
+    r = _dpc(x, wl, "f32", perm)
+    _check_sample(X, oracle.L2, r, ref["sample"], ref["sample_knn_dist"], np.array(wl["k"]))
+    _check_forest(r, [wl["n_c"]])
+    assert metrics.ari(r["labels"], ref["labels"]) >= 0.95
+    # exact mode on u8 rows: integer distances, so the whole clustering is the oracle's
+    e = _dpc(x, wl, "u8", perm, exact=True)
+    assert np.array_equal(e["labels"], ref["labels"])
+    assert np.allclose(e["dist"][ref["sample"]], ref["sample_knn_dist"], rtol=1e-7, atol=0)
+
+
+@pytest.mark.parametrize("cfg", [3, 4])
+def test_fullsize_large_anns(cfg):
+    dev = torch.device("cuda:0")
+    wl = bench.WORKLOADS[cfg]
+    X, _ = (datagen.config3 if cfg == 3 else datagen.config4)()
+    n = len(X)
+    z = np.load(os.path.join(GOLDEN, f"c{cfg}_sample.npz"))
+    perm = torch.from_numpy(datagen.permutation(n, 20231205)).to(dev)
+    r = _dpc(torch.from_numpy(X).to(dev), wl, wl["search"], perm)
+    metric = oracle.L2 if wl["metric"] == "l2" else oracle.COSINE
+    _check_sample(X, metric, r, z["sample"], z["knn_dist"], np.array(wl["k"]))
+    _check_forest(r, [wl["n_c"]])
+
+
+def test_fullsize_batched_instances():
+    dev = torch.device("cuda:0")
+    wl = bench.WORKLOADS[5]
+    X, _, off, ks, ncs = datagen.config5()
+    inst = pecann.Instances(off, k=ks, n_c=ncs)
+    perm = np.concatenate([datagen.permutation(int(off[t + 1] - off[t]), 20231205 + t) + off[t]
+                           for t in range(len(off) - 1)]).astype(np.int32)
+    z = np.load(os.path.join(GOLDEN, "c5_sample.npz"))
+    r = _dpc(torch.from_numpy(X).to(dev), wl, wl["search"], torch.from_numpy(perm).to(dev), inst)
+    _check_sample(X, oracle.L2, r, z["sample"], z["knn_dist"], z["k"])
+    _check_forest(r, ncs, off)
