@@ -1,6 +1,9 @@
-"""Autotuner for the launch settings that change speed only (pecann_set_tuning):
-the visited-hash size of the build searches and of the kNN / doubling searches,
-and the persistent grid (one-wave blocks per compute unit).
+"""Autotuner.  tune(): the launch settings that change speed only
+(pecann_set_tuning): the visited-hash size of the build searches and of the
+kNN / doubling searches, and the persistent grid (one-wave blocks per compute
+unit).  tune_beam(): the kNN beam width, the smallest that agrees with a
+wide-beam search on a target share of the neighbours (this one changes results
+within that target).
 
 For a workload shape it times the graph build and the kNN search under a few
 candidate settings with HIP events, one knob at a time with the others at their
@@ -63,6 +66,50 @@ def _time(fn, reps: int) -> float:
         b.synchronize()
         best = min(best, a.elapsed_time(b))
     return best
+
+
+BEAMS = (24, 32, 40, 48, 56, 64, 80, 96, 128)
+
+
+def tune_beam(ds: pecann.Dataset, adj: torch.Tensor, deg: torch.Tensor, k: int, target: float = 0.975,
+              ref_beam: int = 256, sample: int = 20000, path: str | None = None,
+              use_cache: bool = True) -> dict:
+    """Smallest kNN beam width whose lists agree with a wide-beam search on at
+    least `target` of the entries (over a sample of points), on this graph.
+    The wide-beam lists stand in for the exact ones (no exact search runs
+    here); the choice changes results, so callers keep their own recall gate.
+    -> {"L_search": ..., "agreement": ..., "ref_beam": ...}."""
+    path = path or cache_path()
+    key = "beam|" + shape_key(ds, adj.shape[1], 0, k, ref_beam) + f"|target={target}"
+    cache = _load(path) if use_cache else {}
+    if key in cache:
+        return {**cache[key], "cached": True}
+    n = ds.n
+    rows = torch.arange(0, n, max(1, n // sample), device=ds.device)[:sample]
+    ref = pecann.knn_density(ds, k, adj, deg, L_search=ref_beam, rerank=ref_beam)[0][rows]
+    ref_sorted = torch.sort(ref, dim=1).values
+    tried = []
+    choice = None
+    for beam in BEAMS:
+        if beam < k or beam >= ref_beam:
+            continue
+        got = pecann.knn_density(ds, k, adj, deg, L_search=beam, rerank=beam)[0][rows]
+        # entries of each row found in the reference row (ids are distinct per row)
+        pos = torch.searchsorted(ref_sorted, got.contiguous())
+        hit = ref_sorted.gather(1, pos.clamp(max=k - 1)) == got
+        agree = float(hit.float().mean().item())
+        tried.append({"L_search": beam, "agreement": round(agree, 5)})
+        if agree >= target:
+            choice = {"L_search": beam, "agreement": round(agree, 5)}
+            break
+    if choice is None:
+        choice = {"L_search": ref_beam, "agreement": 1.0}
+    entry = {**choice, "ref_beam": ref_beam, "target": target, "tried": tried}
+    if use_cache:
+        cache = _load(path)
+        cache[key] = entry
+        _save(path, cache)
+    return {**entry, "cached": False}
 
 
 def tune(ds: pecann.Dataset, R: int, L: int, alpha: float, k: int, L_search: int,

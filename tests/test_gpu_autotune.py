@@ -62,3 +62,24 @@ def test_autotune_picks_applies_and_caches(tmp_path):
         assert e2["cached"] and pecann.get_tuning() == chosen
     finally:
         pecann.reset_tuning()
+
+
+def test_tune_beam_meets_its_target_and_caches(tmp_path):
+    dev = torch.device("cuda:0")
+    X, _ = datagen.mixture(8000, 32, 12, seed=9)
+    ds = pecann.Dataset(torch.from_numpy(X).to(dev), "l2", "f32")
+    adj, deg = pecann.build_graph(ds, 32, 64, 1.2)
+    path = str(tmp_path / "beam.json")
+    e = autotune.tune_beam(ds, adj, deg, 10, target=0.97, path=path)
+    assert not e["cached"] and 10 <= e["L_search"] <= 256
+    if e["L_search"] < 256:
+        assert e["agreement"] >= 0.97
+        # every smaller beam that was tried fell short of the target
+        assert all(t["agreement"] < 0.97 for t in e["tried"][:-1])
+    # the chosen beam reproduces the measured agreement against the wide search
+    ref = pecann.knn_density(ds, 10, adj, deg, L_search=256, rerank=256)[0].cpu().numpy()
+    got = pecann.knn_density(ds, 10, adj, deg, L_search=e["L_search"], rerank=e["L_search"])[0].cpu().numpy()
+    rows = np.arange(0, 8000, max(1, 8000 // 20000))[:20000]
+    agree = np.mean([len(set(got[i]) & set(ref[i])) / 10 for i in rows])
+    assert abs(agree - e["agreement"]) < 1e-6
+    assert autotune.tune_beam(ds, adj, deg, 10, target=0.97, path=path)["cached"]
