@@ -350,9 +350,11 @@ def measure(x, wl, search, mode, args, perm, steps, warmup, ref=None, sample=Non
         if beam:
             # beam width of the kNN search, on this workload's graph (an untimed step)
             log("autotune: kNN beam width")
-            pl.step()
-            pl.torch.cuda.synchronize()
-            b = autotune.tune_beam(pl.ds, pl.g_out[0], pl.g_out[1], wl["k"])
+            b = autotune.cached_beam(pl.ds, wl["R"], wl["k"])
+            if b is None:
+                pl.step()  # the graph the beam is tuned on
+                pl.torch.cuda.synchronize()
+                b = autotune.tune_beam(pl.ds, pl.g_out[0], pl.g_out[1], wl["k"])
             pl.Ls = pl.rerank = b["L_search"]
             tuning["L_search"] = b["L_search"]
             tuning["beam_agreement"] = b["agreement"]
