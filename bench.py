@@ -350,11 +350,11 @@ def measure(x, wl, search, mode, args, perm, steps, warmup, ref=None, sample=Non
         if beam:
             # beam width of the kNN search, on this workload's graph (an untimed step)
             log("autotune: kNN beam width")
-            b = autotune.cached_beam(pl.ds, wl["R"], wl["k"])
+            b = autotune.cached_beam(pl.ds, wl["R"], wl["k"], inst=inst)
             if b is None:
                 pl.step()  # the graph the beam is tuned on
                 pl.torch.cuda.synchronize()
-                b = autotune.tune_beam(pl.ds, pl.g_out[0], pl.g_out[1], wl["k"])
+                b = autotune.tune_beam(pl.ds, pl.g_out[0], pl.g_out[1], wl["k"], inst=inst)
             pl.Ls = pl.rerank = b["L_search"]
             tuning["L_search"] = b["L_search"]
             tuning["beam_agreement"] = b["agreement"]
@@ -552,7 +552,7 @@ def main():
     rec, pl, kprof = measure(x, wl, search, args.mode, args, perm, args.steps, args.warmup,
                              ref_lab, sample, inst,
                              tune=args.autotune and args.mode == "anns" and inst is None,
-                             beam=args.autotune and args.mode == "anns" and inst is None)
+                             beam=args.autotune and args.mode == "anns")
     if ref_kind:
         rec["quality"]["reference"] = ref_kind
     out = {
@@ -618,7 +618,7 @@ def main():
             # stand-in for the exact neighbours, so that variant keeps the
             # workload's beam)
             r, p2, _ = measure(x, wl, vs, vm, args, perm, vsteps, 1, ref_lab, sample, inst, vi,
-                               beam=args.autotune and vm == "anns" and inst is None and vi == "vamana")
+                               beam=args.autotune and vm == "anns" and vi == "vamana")
             name = f"{vs}_{vm}" + ("" if vi == "vamana" else f"_{vi}")
             variants[name] = {key: r[key] for key in ("value", "ms_per_step", "phases_ms",
                                                       "quality", "knn_queries_per_s")}

@@ -82,44 +82,52 @@ def _time(fn, reps: int) -> float:
 BEAMS = (24, 32, 40, 48, 56, 64, 80, 96, 128)
 
 
-def _beam_key(ds, R, k, target, ref_beam):
-    return "beam|" + shape_key(ds, R, 0, k, ref_beam) + f"|target={target}"
+def _beam_key(ds, R, k, target, ref_beam, inst=None):
+    tail = "" if inst is None else f"|instances={inst.count}"
+    return "beam|" + shape_key(ds, R, 0, k, ref_beam) + f"|target={target}" + tail
 
 
 def cached_beam(ds: pecann.Dataset, R: int, k: int, target: float = 0.975, ref_beam: int = 256,
-                path: str | None = None):
+                path: str | None = None, inst: pecann.Instances | None = None):
     """The stored tune_beam() result for this shape, or None."""
-    e = _load(path or cache_path()).get(_beam_key(ds, R, k, target, ref_beam))
+    e = _load(path or cache_path()).get(_beam_key(ds, R, k, target, ref_beam, inst))
     return None if e is None else {**e, "cached": True}
 
 
 def tune_beam(ds: pecann.Dataset, adj: torch.Tensor, deg: torch.Tensor, k: int, target: float = 0.975,
               ref_beam: int = 256, sample: int = 20000, path: str | None = None,
-              use_cache: bool = True) -> dict:
+              use_cache: bool = True, inst: pecann.Instances | None = None) -> dict:
     """Smallest kNN beam width whose lists agree with a wide-beam search on at
     least `target` of the entries (over a sample of points), on this graph.
     The wide-beam lists stand in for the exact ones (no exact search runs
     here); the choice changes results, so callers keep their own recall gate.
     -> {"L_search": ..., "agreement": ..., "ref_beam": ...}."""
     path = path or cache_path()
-    key = _beam_key(ds, adj.shape[1], k, target, ref_beam)
+    key = _beam_key(ds, adj.shape[1], k, target, ref_beam, inst)
     cache = _load(path) if use_cache else {}
     if key in cache:
         return {**cache[key], "cached": True}
     n = ds.n
     rows = torch.arange(0, n, max(1, n // sample), device=ds.device)[:sample]
-    ref = pecann.knn_density(ds, k, adj, deg, L_search=ref_beam, rerank=ref_beam)[0][rows]
+    def knn(beam):
+        if inst is None:
+            return pecann.knn_density(ds, k, adj, deg, L_search=beam, rerank=beam)[0][rows]
+        # instances: k is the largest instance k; rows end in -1 after their own k
+        return pecann.knn_density_batched(ds, inst, k, adj, deg, L_search=beam, rerank=beam)[0][rows]
+
+    ref = knn(ref_beam)
     ref_sorted = torch.sort(ref, dim=1).values
     tried = []
     choice = None
     for beam in BEAMS:
         if beam < k or beam >= ref_beam:
             continue
-        got = pecann.knn_density(ds, k, adj, deg, L_search=beam, rerank=beam)[0][rows]
-        # entries of each row found in the reference row (ids are distinct per row)
+        got = knn(beam)
+        # entries of each row found in the reference row (ids are distinct per row;
+        # -1 marks the padding of instances with a smaller k)
         pos = torch.searchsorted(ref_sorted, got.contiguous())
-        hit = ref_sorted.gather(1, pos.clamp(max=k - 1)) == got
-        agree = float(hit.float().mean().item())
+        hit = (ref_sorted.gather(1, pos.clamp(max=k - 1)) == got) & (got >= 0)
+        agree = float((hit.float().sum() / (got >= 0).float().sum()).item())
         tried.append({"L_search": beam, "agreement": round(agree, 5)})
         if agree >= target:
             choice = {"L_search": beam, "agreement": round(agree, 5)}
