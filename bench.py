@@ -437,8 +437,19 @@ def measure_graph(x, wl, search, args, perm, steps, inst=None, Ls=None):
 
 
 def roofline(pl, kprof, steps, search, n, d, k):
-    """Roofline of the dominant gather kernel family, from its own work counters."""
-    bc, kc = pl.counters()
+    """Roofline of the dominant gather kernel family, from its own work counters.
+    The counters come from one more step with the largest visited hash (8,192
+    slots): the walks are the same under any hash size, and that one forgets
+    almost no ids, so rows gathered again for forgotten ids in the timed
+    setting count as waste (visible in the HBM counters), not as algorithmic
+    bytes."""
+    from paper_2312_03940_amd import pecann
+    timed = pecann.get_tuning()
+    pecann.set_tuning(13, 13, timed["grid_per_cu"])
+    try:
+        bc, kc = pl.counters()
+    finally:
+        pecann.set_tuning(timed["hash_bits_build"], timed["hash_bits_search"], timed["grid_per_cu"])
     row_bytes = {"f32": 4 * d, "u8": d, "bf16": 2 * d, "fp8": d}[search]
     # algorithmic bytes per step: per expansion the degree word and the neighbour ids,
     # per distance the candidate row, per search its own row (float32 for BF16/FP8
