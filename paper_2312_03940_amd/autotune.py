@@ -22,6 +22,7 @@ import torch
 
 from . import pecann
 
+MARGIN = 0.02  # speed-up a launch setting must show to replace the rule
 BUILD_HASH_BITS = (0, 11, 12, 13)
 SEARCH_HASH_BITS = (0, 11, 12, 13)
 GRID_PER_CU = (0, 12, 20)
@@ -184,6 +185,9 @@ def tune(ds: pecann.Dataset, R: int, L: int, alpha: float, k: int, L_search: int
     trials = []
 
     def sweep(knob, values, fn, base):
+        # a setting replaces the current one only if it is MARGIN faster: below
+        # that the difference is timing noise, and a smaller visited hash that
+        # wins by noise costs real re-read traffic
         best_v, best_t = cur[knob], base
         for v in values:
             if v == cur[knob]:
@@ -192,7 +196,7 @@ def tune(ds: pecann.Dataset, R: int, L: int, alpha: float, k: int, L_search: int
             apply(c)
             t = _time(fn, reps)
             trials.append({**c, "what": fn.__name__, "ms": round(t, 3)})
-            if t < best_t:
+            if t < best_t * (1.0 - MARGIN):
                 best_v, best_t = v, t
         cur[knob] = best_v
         apply(cur)
