@@ -172,6 +172,23 @@ def recall_from_sample(idx, dist, sample, ref_dist, k):
     return hits / float(ks.sum())
 
 
+def distance_error(idx, dist, ref_idx, ref_dist, k):
+    """Error of the reported distances against the oracle's FP64 ones, over the
+    returned ids that are among the oracle's k nearest (per sample row):
+    -> (max relative error, mean relative error, entries compared)."""
+    ks = np.broadcast_to(np.asarray(k), (len(idx),))
+    errs = []
+    for t in range(len(idx)):
+        kt = int(ks[t])
+        exact = {int(j): float(d) for j, d in zip(ref_idx[t][:kt], ref_dist[t][:kt])}
+        for j, dj in zip(idx[t][:kt], dist[t][:kt]):
+            ex = exact.get(int(j))
+            if ex is not None:
+                errs.append(abs(float(dj) - ex) / max(ex, 1e-30))
+    e = np.asarray(errs)
+    return (float(e.max()) if len(e) else 0.0, float(e.mean()) if len(e) else 0.0, int(len(e)))
+
+
 class Pipeline:
     """Buffers and launch sequence of one DPC step on a resident dataset."""
 
@@ -377,6 +394,9 @@ def measure(x, wl, search, mode, args, perm, steps, warmup, ref=None, sample=Non
         q["instances_below_0.95"] = int(sum(v < 0.95 for v in per))
     elif ref is not None:
         q["ari_vs_reference"] = ari(labels, ref["labels"])
+    if ref is not None and "dep" in ref:
+        # share of points whose dependent point is the exact one
+        q["dependent_agreement"] = float(np.mean(pl.d_out[0].cpu().numpy() == ref["dep"]))
         if wl["rho_min"] > 0:
             q["rho_min"] = wl["rho_min"]
             q["noise_points"] = int((labels == np.arange(labels.size)).sum()
@@ -394,6 +414,14 @@ def measure(x, wl, search, mode, args, perm, steps, warmup, ref=None, sample=Non
         name = f"recall_at_{k}" if inst is None else "recall_at_k_i"
         q[name] = recall_from_sample(pl.k_out[0].cpu().numpy()[s], pl.k_out[1].cpu().numpy()[s], s,
                                      sample["knn_dist"], sample.get("k", k))
+        if "knn_idx" in sample:
+            # reported distances (float32, reranked from float32 rows for BF16/FP8)
+            # against the oracle's FP64 distances of the same pairs
+            mx, mean, cnt = distance_error(pl.k_out[0].cpu().numpy()[s], pl.k_out[1].cpu().numpy()[s],
+                                           sample["knn_idx"], sample["knn_dist"], sample.get("k", k))
+            q["knn_dist_rel_err_max"] = mx
+            q["knn_dist_rel_err_mean"] = mean
+            q["knn_dist_pairs_compared"] = cnt
     if q:
         rk = [v for key, v in q.items() if key.startswith("recall")]
         q["gates_met"] = bool(q.get("ari_vs_reference", 1.0) >= 0.95 and all(v >= 0.95 for v in rk))
@@ -534,14 +562,15 @@ def main():
         pass
     elif args.config == 2 and os.path.exists(os.path.join(GOLDEN, "c2_reference.npz")):
         ref = np.load(os.path.join(GOLDEN, "c2_reference.npz"))
-        ref_lab = {"labels": ref["labels"]}
+        ref_lab = {"labels": ref["labels"], "dep": ref["dep"]}
         ref_kind = "oracle exact DPC (tests/golden/c2_reference.npz)"
-        sample = {"sample": ref["sample"], "knn_dist": ref["sample_knn_dist"]}
+        sample = {"sample": ref["sample"], "knn_dist": ref["sample_knn_dist"],
+                  "knn_idx": ref["sample_knn_idx"]}
     elif args.config in (3, 4, 5):
         sp = os.path.join(GOLDEN, f"c{args.config}_sample.npz")
         if os.path.exists(sp):
             z = np.load(sp)
-            sample = {"sample": z["sample"], "knn_dist": z["knn_dist"]}
+            sample = {"sample": z["sample"], "knn_dist": z["knn_dist"], "knn_idx": z["knn_idx"]}
             if args.config == 5:
                 sample["k"] = z["k"]
         # ARI reference: the GPU exact mode on float32 rows (bit-exact with the oracle in
@@ -551,7 +580,7 @@ def main():
         rp = Pipeline(x, wl, "f32", "exact", args, perm, inst)
         rp.step()
         torch.cuda.synchronize()
-        ref_lab = {"labels": rp.c_out[0].cpu().numpy()}
+        ref_lab = {"labels": rp.c_out[0].cpu().numpy(), "dep": rp.d_out[0].cpu().numpy()}
         if wl["rho_min"] > 0:
             ref_lab["labels0"] = rp.labels_at(0.0)
             ref_lab["y"] = Y

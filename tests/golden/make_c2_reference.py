@@ -5,8 +5,9 @@ parity test.  It calls only the oracle and the seeded generator:
 
     python tests/golden/make_c2_reference.py
 
-Stored: labels (int32 root index per point), rank (int32 density rank), and for a
-fixed sample of 2,000 query points their exact 10-NN indices and distances.
+Stored: labels (int32 root index per point), rank (int32 density rank), dep (int32
+exact dependent point, -1 for the densest), and for a fixed sample of 2,000 query
+points their exact 10-NN indices and distances.
 """
 import os
 import sys
@@ -30,7 +31,8 @@ def main():
     ref = oracle.exact_dpc(X, k=k, n_c=n_c)
     sample = np.arange(0, X.shape[0], X.shape[0] // 2000)[:2000].astype(np.int32)
     np.savez_compressed(OUT, labels=ref["labels"].astype(np.int32),
-                        rank=ref["rank"].astype(np.int32), sample=sample,
+                        rank=ref["rank"].astype(np.int32), dep=ref["dep"].astype(np.int32),
+                        sample=sample,
                         sample_knn_idx=ref["knn_idx"][sample].astype(np.int32),
                         sample_knn_dist=ref["knn_dist"][sample],
                         k=np.int32(k), n_c=np.int32(n_c))

@@ -11,8 +11,9 @@ only the oracle), and (b) properties that hold at any size:
     and only the densest point of an instance has none;
   - labels are constant along dependent pointers and every root is a center
     or a noise point; exactly n_c centers per instance.
-The MNIST-shaped workload also runs in exact mode on u8 rows, whose labels
-must equal the oracle's exact DPC of all 70,000 points bit for bit."""
+The MNIST-shaped workload also runs in exact mode on u8 rows, whose labels and
+dependent points must equal the oracle's exact DPC of all 70,000 points bit for
+bit."""
 import os
 
 import numpy as np
@@ -109,6 +110,7 @@ def test_fullsize_mnist_shaped_f32_anns_and_u8_exact():
     # exact mode on u8 rows: integer distances, so the whole clustering is the oracle's
     e = _dpc(x, wl, "u8", perm, exact=True)
     assert np.array_equal(e["labels"], ref["labels"])
+    assert np.array_equal(e["dep"], ref["dep"])
     assert np.allclose(e["dist"][ref["sample"]], ref["sample_knn_dist"], rtol=1e-7, atol=0)
 
 
