@@ -27,7 +27,6 @@ struct PruneLds {
   uint64_t *k1;    // sorted keys [ccap]
   uint32_t *cn;    // squared norm of each sorted candidate [ccap]
   float *cs;       // row scale of each sorted candidate (FP8) [ccap]
-  float *dg;       // 16 x 16 measures of the current diagonal tile
   int32_t *sel;    // selected [R]
   uint8_t *alive;  // [ccap]
 };
@@ -39,8 +38,7 @@ __device__ __forceinline__ PruneLds carve_prune(uint8_t *smem, int ccap, int R) 
   s.ids = (int32_t *)(s.k1 + ccap);
   s.cn = (uint32_t *)(s.ids + ccap);
   s.cs = (float *)(s.cn + ccap);
-  s.dg = s.cs + ccap;
-  s.sel = (int32_t *)(s.dg + 256);
+  s.sel = (int32_t *)(s.cs + ccap);
   s.alive = (uint8_t *)(s.sel + ((R + 3) & ~3));
   return s;
 }
@@ -466,7 +464,7 @@ __global__ __launch_bounds__(64) void prune_lists_kernel(PruneParams p) {
 }
 
 size_t prune_lds_bytes(int ccap, int R) {
-  return (size_t)ccap * (8 + 8 + 4 + 4 + 4 + 1) + 4 * 256 + 4 * (size_t)((R + 3) & ~3) + 16;
+  return (size_t)ccap * (8 + 8 + 4 + 4 + 4 + 1) + 4 * (size_t)((R + 3) & ~3) + 16;
 }
 
 template <int DT>
