@@ -352,7 +352,11 @@ __global__ __launch_bounds__(64) void prune_reverse_kernel(PruneParams p) {
   // queue atomic so that the queue head is not the serialising point
   constexpr int kLightChunk = 8;
   const int chunk = p.heavy ? 1 : kLightChunk;
-  int it = 0, end = 0;
+  int it = 0, end = 0, base = 0;
+  // light chunks: lane i holds target base + i's list entry, node, source count,
+  // segment offset and degree, all loaded at once when the chunk is taken (the
+  // targets of a launch are distinct, so no earlier item changes them)
+  int32_t pf_q = 0, pf_cnt = 0, pf_off = 0, pf_deg = 0;
   for (;;) {
     if (it >= end) {
       int v = 0;
@@ -360,17 +364,36 @@ __global__ __launch_bounds__(64) void prune_reverse_kernel(PruneParams p) {
       it = __shfl(v, 0);
       if (it >= items) break;
       end = min(items, it + chunk);
+      base = it;
+      if (!p.heavy && l < end - base) {
+        const int32_t uu = p.tord[base + l];
+        pf_q = p.tlist[uu];
+        pf_cnt = p.tcnt[uu];
+        pf_off = p.toff[uu];
+        pf_deg = p.deg[pf_q];
+      }
     }
-    const int u = p.heavy ? p.tord[nt - 1 - it] : p.tord[it];
+    int32_t q, cnt, off, dg;
+    if (!p.heavy) {
+      const int i = it - base;
+      q = __builtin_amdgcn_readlane(pf_q, i);
+      cnt = __builtin_amdgcn_readlane(pf_cnt, i);
+      off = __builtin_amdgcn_readlane(pf_off, i);
+      dg = __builtin_amdgcn_readlane(pf_deg, i);
+    } else {
+      const int u = p.tord[nt - 1 - it];
+      q = p.tlist[u];
+      cnt = p.tcnt[u];
+      off = p.toff[u];
+      dg = p.deg[q];
+    }
     ++it;
-    const int32_t q = p.tlist[u];
-    int cnt = p.tcnt[u];
     if (cnt > p.capin) {
       if (l == 0) atomicAdd(p.overflow, 1);
       cnt = p.capin;
     }
-    const int32_t *src = p.seg + p.toff[u];
-    const int dq = min(p.deg[q], p.R);
+    const int32_t *src = p.seg + off;
+    const int dq = min(dg, p.R);
     int32_t *row = p.adj + (int64_t)q * p.R;
     int nnew = 0;
     if (!p.heavy) {
