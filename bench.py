@@ -520,7 +520,7 @@ def main():
     if args.nnd_repeats:
         NND["num_repeats"] = args.nnd_repeats
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
