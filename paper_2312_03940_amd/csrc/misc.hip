@@ -185,39 +185,82 @@ hipError_t launch_identity_perm(int32_t *p, int64_t n, hipStream_t s) {
 //   scatter: source p goes to slot (segment of q) + ticket.
 // Arrival order is not deterministic; the merge sorts each segment by index.
 // ---------------------------------------------------------------------------
+// Wave-wide inclusive prefix sum.
+__device__ __forceinline__ int wave_prefix_sum(int v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int y = __shfl_up(v, off);
+    if (l >= off) v += y;
+  }
+  return v;
+}
+
+// Counting pass: each edge takes a ticket in its target's count; a target seen
+// for the first time joins the target list.  List slots are handed out once
+// per wavefront (ballot + one atomic), not once per target.
 __global__ void rev_count_kernel(const int32_t *adj, const int32_t *deg, const int32_t *items,
                                  int32_t nb, int32_t R, int32_t *rcnt,
                                  int32_t *ntargets, int32_t *tlist, int32_t *tidx,
                                  int32_t *ticket) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)nb * R) return;
-  const int t = (int)(i / R), e = (int)(i % R);
-  const int32_t p = items[t];
-  if (e >= deg[p]) return;
-  const int32_t q = adj[(int64_t)p * R + e];
-  const int slot = atomicAdd(&rcnt[q], 1);
-  ticket[i] = slot;
-  if (slot == 0) {
-    const int u = atomicAdd(ntargets, 1);
-    tlist[u] = q;
-    tidx[q] = u;
+  bool act = i < (int64_t)nb * R;
+  int32_t q = -1;
+  int slot = -1;
+  if (act) {
+    const int t = (int)(i / R), e = (int)(i % R);
+    const int32_t p = items[t];
+    act = e < deg[p];
+    if (act) {
+      q = adj[(int64_t)p * R + e];
+      slot = atomicAdd(&rcnt[q], 1);
+      ticket[i] = slot;
+    }
+  }
+  const uint64_t fm = ballot(act && slot == 0);
+  if (fm) {
+    int base = 0;
+    if (lane_id() == 0) base = atomicAdd(ntargets, __popcll(fm));
+    base = __shfl(base, 0);
+    if (act && slot == 0) {
+      const int u = base + lanes_below(fm);
+      tlist[u] = q;
+      tidx[q] = u;
+    }
   }
 }
 // Segment offsets of the targets, and two work lists in tord: targets with at
 // most `light` new sources from the front (tord[0, *front)), the others from the
 // back (tord[nt - *back, nt)).  The two lists are pruned by separate launches
-// whose LDS is sized for their candidate counts.
+// whose LDS is sized for their candidate counts.  Offsets and list slots are
+// handed out once per wavefront (prefix sum / ballot + one atomic each).
 __global__ void rev_alloc_kernel(const int32_t *tlist, const int32_t *ntargets, const int32_t *rcnt,
                                  int32_t *toff, int32_t *tcnt, int32_t *cursor, int32_t *tord,
                                  int32_t *front, int32_t *back, int32_t light, int32_t maxt) {
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
   const int nt = *ntargets;
-  if (u >= maxt || u >= nt) return;
-  const int c = rcnt[tlist[u]];
-  tcnt[u] = c;
-  toff[u] = atomicAdd(cursor, c);
-  const int pos = c <= light ? atomicAdd(front, 1) : nt - 1 - atomicAdd(back, 1);
-  tord[pos] = u;
+  const bool act = u < maxt && u < nt;
+  const int c = act ? rcnt[tlist[u]] : 0;
+  const int incl = wave_prefix_sum(c);
+  const int total = __shfl(incl, kWave - 1);
+  int base = 0;
+  if (lane_id() == 0 && total > 0) base = atomicAdd(cursor, total);
+  base = __shfl(base, 0);
+  if (act) {
+    tcnt[u] = c;
+    toff[u] = base + incl - c;
+  }
+  const bool li = act && c <= light;
+  const uint64_t lm = ballot(li), hm = ballot(act && !li);
+  int fb = 0, bb = 0;
+  if (lane_id() == 0) {
+    if (lm) fb = atomicAdd(front, __popcll(lm));
+    if (hm) bb = atomicAdd(back, __popcll(hm));
+  }
+  fb = __shfl(fb, 0);
+  bb = __shfl(bb, 0);
+  if (li) tord[fb + lanes_below(lm)] = u;
+  else if (act) tord[nt - 1 - (bb + lanes_below(hm))] = u;
 }
 __global__ void rev_scatter_kernel(const int32_t *adj, const int32_t *deg, const int32_t *items,
                                    int32_t nb, int32_t R, const int32_t *tidx,
