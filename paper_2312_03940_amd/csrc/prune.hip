@@ -182,6 +182,7 @@ __device__ __forceinline__ void short_block(const PruneParams &p, PruneLds &s, i
 }
 
 // RobustPrune of point pt over s.ids[0..nc); writes Nout(pt) into adj/deg.
+// The first npre candidates come with their keys (D(pt, c), c) already in s.k0.
 // Candidates are sorted by (D(pt, c), c), and empty entries and repeats are
 // dropped.  D(pt, c) comes from tiles whose A rows all hold pt, 64 candidates
 // per round; lanes 0-15 read their column's value in accumulator register 0.  The greedy pass then walks the live
@@ -191,7 +192,7 @@ __device__ __forceinline__ void short_block(const PruneParams &p, PruneLds &s, i
 // of its accumulator against its column), and the survivors are compacted.
 // Returns the number of 16 x 16 tiles formed.
 template <int DT>
-__device__ int robust_prune_tiles(const PruneParams &p, PruneLds &s, int32_t pt, int nc) {
+__device__ int robust_prune_tiles(const PruneParams &p, PruneLds &s, int32_t pt, int nc, int npre = 0) {
   constexpr int NT = 4;  // tiles in flight
   const int l = lane_id();
   const int col = l & 15, g = l >> 4;
@@ -200,7 +201,7 @@ __device__ int robust_prune_tiles(const PruneParams &p, PruneLds &s, int32_t pt,
   {
     const uint32_t npt = p.rows.sqn[pt];
     const float spt = (DT == PECANN_FP8E4M3) ? p.rows.scale[pt] : 1.0f;
-    for (int base = 0; base < nc; base += 16 * NT) {
+    for (int base = npre; base < nc; base += 16 * NT) {
       int32_t rj[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -326,15 +327,34 @@ __global__ __launch_bounds__(64) void prune_forward_kernel(PruneParams p) {
     const int t = next_item(p.head);
     if (t >= p.nb) break;
     const int32_t pt = p.items[t];
-    // candidates: the visited set V_p, then the current out-neighbours Nout(p)
+    // candidates: the visited set V_p, whose keys (D(p, v), v) the search has
+    // already formed, then the current out-neighbours Nout(p) that are not in
+    // V_p (their distances come from tiles; R <= 128, two per lane)
     const int nv = min(p.vis_count[t], p.vcap);
     const uint64_t *v = p.vis + (int64_t)t * p.vcap;
-    for (int j = l; j < nv; j += kWave) s.ids[j] = key_id(v[j]);
+    for (int j = l; j < nv; j += kWave) {
+      const uint64_t kv = v[j];
+      s.k0[j] = kv;
+      s.ids[j] = key_id(kv);
+    }
     const int dp = min(p.deg[pt], p.R);
     const int32_t *row = p.adj + (int64_t)pt * p.R;
-    for (int j = l; j < dp; j += kWave) s.ids[nv + j] = row[j];
+    int32_t e0 = l < dp ? row[l] : -1;
+    int32_t e1 = l + kWave < dp ? row[l + kWave] : -1;
     wave_lds_sync();
-    const int rows = 32 * robust_prune_tiles<DT>(p, s, pt, nv + dp);
+    if (dp > 0) {
+      for (int j = 0; j < nv; ++j) {
+        const int32_t vj = s.ids[j];
+        if (vj == e0) e0 = -1;
+        if (vj == e1) e1 = -1;
+      }
+    }
+    const uint64_t m0 = ballot(e0 >= 0), m1 = ballot(e1 >= 0);
+    if (e0 >= 0) s.ids[nv + lanes_below(m0)] = e0;
+    if (e1 >= 0) s.ids[nv + __popcll(m0) + lanes_below(m1)] = e1;
+    const int nout = __popcll(m0) + __popcll(m1);
+    wave_lds_sync();
+    const int rows = 32 * robust_prune_tiles<DT>(p, s, pt, nv + nout, nv);
     if (p.counters && l == 0) atomicAdd(p.counters + 0, (unsigned long long)rows);
     wave_lds_sync();
   }
