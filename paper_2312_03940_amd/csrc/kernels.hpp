@@ -161,6 +161,11 @@ struct PruneParams {
                               // list's bound; heavy list: truncation beyond it)
   int32_t *head;
   int32_t *overflow;          // counts truncations (candidates beyond capacity)
+  // keys (D(v, u), u) of the adjacency entries, kept beside adj (nullptr: none
+  // kept; every prune then forms its distances from tiles), and of the batch's
+  // reverse edges grouped by target ((D(p, q), p) for source p)
+  uint64_t *akey;
+  uint64_t *segk;
   // NN-descent graph: Nout(i) = RobustPrune(i, list_i u rev_i) with the lists
   // (lk keys per point, kNoKey = empty) and reverse lists (lk ids, -1 = empty)
   const uint64_t *lists;
@@ -266,7 +271,7 @@ hipError_t launch_rev_alloc(const int32_t *tlist, const int32_t *ntargets, const
 hipError_t launch_rev_scatter(const int32_t *adj, const int32_t *deg, const int32_t *items,
                               int32_t nb, int32_t R, const int32_t *tidx,
                               const int32_t *toff, const int32_t *ticket, int32_t *seg,
-                              hipStream_t s);
+                              const uint64_t *akey, uint64_t *segk, hipStream_t s);
 // Smallest rank key of each instance (one workgroup per instance).
 hipError_t launch_min_key(const uint64_t *key, const InstTable &inst, uint64_t *out, hipStream_t s);
 hipError_t launch_dep_in_knn(int64_t n, const InstTable &inst, int32_t kstride, const uint64_t *key,

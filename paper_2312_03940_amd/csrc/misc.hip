@@ -262,16 +262,22 @@ __global__ void rev_alloc_kernel(const int32_t *tlist, const int32_t *ntargets, 
   if (li) tord[fb + lanes_below(lm)] = u;
   else if (act) tord[nt - 1 - (bb + lanes_below(hm))] = u;
 }
+// Sources grouped by target; with adjacency keys, the source's key for the
+// target too: D(q, p) is taken as D(p, q), the measure p's prune formed.
 __global__ void rev_scatter_kernel(const int32_t *adj, const int32_t *deg, const int32_t *items,
                                    int32_t nb, int32_t R, const int32_t *tidx,
-                                   const int32_t *toff, const int32_t *ticket, int32_t *seg) {
+                                   const int32_t *toff, const int32_t *ticket, int32_t *seg,
+                                   const uint64_t *akey, uint64_t *segk) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)nb * R) return;
   const int t = (int)(i / R), e = (int)(i % R);
   const int32_t p = items[t];
   if (e >= deg[p]) return;
-  const int32_t q = adj[(int64_t)p * R + e];
-  seg[toff[tidx[q]] + ticket[i]] = p;
+  const int64_t ae = (int64_t)p * R + e;
+  const int32_t q = adj[ae];
+  const int64_t pos = (int64_t)toff[tidx[q]] + ticket[i];
+  seg[pos] = p;
+  if (akey) segk[pos] = (akey[ae] & 0xffffffff00000000ull) | (uint32_t)p;
 }
 hipError_t launch_rev_count(const int32_t *adj, const int32_t *deg, const int32_t *items,
                             int32_t nb, int32_t R, int32_t *rcnt, int32_t *ntargets,
@@ -292,10 +298,10 @@ hipError_t launch_rev_alloc(const int32_t *tlist, const int32_t *ntargets, const
 hipError_t launch_rev_scatter(const int32_t *adj, const int32_t *deg, const int32_t *items,
                               int32_t nb, int32_t R, const int32_t *tidx,
                               const int32_t *toff, const int32_t *ticket, int32_t *seg,
-                              hipStream_t s) {
+                              const uint64_t *akey, uint64_t *segk, hipStream_t s) {
   const int64_t tot = (int64_t)nb * R;
   hipLaunchKernelGGL(rev_scatter_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, adj,
-                     deg, items, nb, R, tidx, toff, ticket, seg);
+                     deg, items, nb, R, tidx, toff, ticket, seg, akey, segk);
   return hipGetLastError();
 }
 

@@ -510,6 +510,7 @@ struct BuildWs {
   int32_t *perm, *ctr, *vis_count, *rcnt, *tidx, *tlist, *tord, *toff, *tcnt, *ticket, *seg;
   int32_t *items, *item_sbase, *item_ns;
   uint64_t *vis;
+  uint64_t *akey, *segk;  // keys of the adjacency entries, of the grouped reverse edges
 };
 
 static void carve_build(Carver &c, int64_t n, int R, int64_t cap, int vcap, BuildWs *w) {
@@ -529,6 +530,8 @@ static void carve_build(Carver &c, int64_t n, int R, int64_t cap, int vcap, Buil
   w->tcnt = c.take<int32_t>(ce);
   w->ticket = c.take<int32_t>(ce);
   w->seg = c.take<int32_t>(ce);
+  w->akey = c.take<uint64_t>((size_t)n * R);
+  w->segk = c.take<uint64_t>(ce);
 }
 
 static int effective_vcap(const pecann_build_params *bp) {
@@ -684,6 +687,8 @@ static pecann_status build_impl(const pecann_dataset *ds, const pecann_build_par
   pp.toff = w.toff;
   pp.tcnt = w.tcnt;
   pp.seg = w.seg;
+  pp.akey = w.akey;
+  pp.segk = w.segk;
   pp.rcnt = w.rcnt;
   pp.overflow = overflow;
   pp.counters = counters ? (unsigned long long *)counters + 4 : nullptr;
@@ -727,7 +732,8 @@ static pecann_status build_impl(const pecann_dataset *ds, const pecann_build_par
                                      w.ticket, s));
       HIP_TRY_ROUND(launch_rev_alloc(w.tlist, ntargets, w.rcnt, w.toff, w.tcnt, cursor, w.tord,
                                      nlight, nheavy, kLightIn, (int32_t)((int64_t)nb * R), s));
-      HIP_TRY_ROUND(launch_rev_scatter(adj, deg, w.items, nb, R, w.tidx, w.toff, w.ticket, w.seg, s));
+      HIP_TRY_ROUND(launch_rev_scatter(adj, deg, w.items, nb, R, w.tidx, w.toff, w.ticket, w.seg,
+                                       w.akey, w.segk, s));
     }
     {
       PROF(F_PRUNE_REV, s);

@@ -4,9 +4,12 @@
 //   repeatedly move the closest surviving candidate c* to the output (stop at
 //   R) and drop every surviving c with alpha * D(c*, c) <= D(p, c)
 //   (alpha^2 * D^2 <= D^2 for L2 measures, which are squared distances).
-// All distances -- to p and between candidates -- come from dense 16 x 16
-// dot-product tiles on the matrix cores (f32, i8, bf16 or fp8 MFMA by row
-// format), turned into distances with the rows' stored norms.  After each
+// Distances between candidates come from dense 16 x 16 dot-product tiles on
+// the matrix cores (f32, i8, bf16 or fp8 MFMA by row format), turned into
+// distances with the rows' stored norms.  Distances to p are not formed again
+// in the graph build: the search hands over D(p, v) of the visited set, every
+// adjacency entry keeps the key (D(p, u), u) it was selected or appended with,
+// and a reverse edge p -> q carries D(p, q) as D(q, p).  After each
 // block of 16 the surviving candidates are compacted, so every later tile is
 // dense in live candidates; column tiles go four at a time to keep several row
 // loads in flight per lane.
@@ -25,9 +28,9 @@ struct PruneLds {
   int32_t *ids;    // candidates [ccap]
   uint64_t *k0;    // keys [ccap]
   uint64_t *k1;    // sorted keys [ccap]
+  uint64_t *sel;   // keys of the selected [R]
   uint32_t *cn;    // squared norm of each sorted candidate [ccap]
   float *cs;       // row scale of each sorted candidate (FP8) [ccap]
-  int32_t *sel;    // selected [R]
   uint8_t *alive;  // [ccap]
 };
 
@@ -35,11 +38,11 @@ __device__ __forceinline__ PruneLds carve_prune(uint8_t *smem, int ccap, int R) 
   PruneLds s;
   s.k0 = (uint64_t *)smem;
   s.k1 = s.k0 + ccap;
-  s.ids = (int32_t *)(s.k1 + ccap);
+  s.sel = s.k1 + ccap;
+  s.ids = (int32_t *)(s.sel + R);
   s.cn = (uint32_t *)(s.ids + ccap);
   s.cs = (float *)(s.cn + ccap);
-  s.sel = (int32_t *)(s.cs + ccap);
-  s.alive = (uint8_t *)(s.sel + ((R + 3) & ~3));
+  s.alive = (uint8_t *)(s.cs + ccap);
   return s;
 }
 
@@ -90,7 +93,7 @@ __device__ __forceinline__ int compact_live(PruneLds &s, int from, int mv) {
 // o + l % 16).  Each lane works out which earlier entries of its column's
 // candidate would drop it (alpha^2 D^2(i, j) <= D^2(p, j) for i < j), the masks
 // are transposed with ballots, and the greedy pass runs on wave-uniform masks:
-// no LDS round trip per step.  Appends the selected ids to s.sel and returns
+// no LDS round trip per step.  Appends the selected keys to s.sel and returns
 // the mask of selected block entries; block entries end not alive.
 template <int DT>
 __device__ __forceinline__ uint32_t select_block(const PruneParams &p, PruneLds &s, const v4f &tile,
@@ -125,7 +128,7 @@ __device__ __forceinline__ uint32_t select_block(const PruneParams &p, PruneLds 
     alive &= ~((uint32_t)ballot(l < 16 && ((kb >> i) & 1u)) & 0xffffu);
   }
   if (l < 16 && j < mv) {
-    if ((sel >> l) & 1u) s.sel[nsel0 + __popc(sel & ((1u << l) - 1u))] = key_id(s.k1[j]);
+    if ((sel >> l) & 1u) s.sel[nsel0 + __popc(sel & ((1u << l) - 1u))] = s.k1[j];
     s.alive[j] = 0;
   }
   wave_lds_sync();
@@ -179,6 +182,18 @@ __device__ __forceinline__ void short_block(const PruneParams &p, PruneLds &s, i
     if (l < 16 && ((k16 >> l) & 1u)) s.alive[o + 16 * t + l] = 0;
   }
   wave_lds_sync();
+}
+
+// Nout(pt) from the selected keys: ids into adj, the keys beside them (when
+// kept), the count into deg.
+__device__ __forceinline__ void write_nout(const PruneParams &p, const PruneLds &s, int32_t pt,
+                                           int nsel) {
+  const int l = lane_id();
+  int32_t *row = p.adj + (int64_t)pt * p.R;
+  for (int e = l; e < p.R; e += kWave) row[e] = e < nsel ? (int32_t)key_id(s.sel[e]) : -1;
+  if (p.akey)
+    for (int e = l; e < nsel; e += kWave) p.akey[(int64_t)pt * p.R + e] = s.sel[e];
+  if (l == 0) p.deg[pt] = nsel;
 }
 
 // RobustPrune of point pt over s.ids[0..nc); writes Nout(pt) into adj/deg.
@@ -246,7 +261,7 @@ __device__ int robust_prune_tiles(const PruneParams &p, PruneLds &s, int32_t pt,
   wave_lds_sync();
   int mv = compact_live(s, 0, nc);
 
-  int nsel = 0, tiles = (nc + 15) / 16;
+  int nsel = 0, tiles = nc > npre ? (nc - npre + 15) / 16 : 0;
   if (mv <= 16 * kSmallBlocks) {
     const int nb = (mv + 15) / 16;
     short_block<DT, 0>(p, s, mv, a2, nsel);
@@ -255,9 +270,7 @@ __device__ int robust_prune_tiles(const PruneParams &p, PruneLds &s, int32_t pt,
     short_block<DT, 3>(p, s, mv, a2, nsel);
     short_block<DT, 4>(p, s, mv, a2, nsel);
     tiles += nb * kSmallBlocks - nb * (nb - 1) / 2;
-    int32_t *row = p.adj + (int64_t)pt * p.R;
-    for (int e = l; e < p.R; e += kWave) row[e] = e < nsel ? s.sel[e] : -1;
-    if (l == 0) p.deg[pt] = nsel;
+    write_nout(p, s, pt, nsel);
     return tiles;
   }
   for (int b = 0; b < mv && nsel < p.R; b += 16) {
@@ -309,9 +322,7 @@ __device__ int robust_prune_tiles(const PruneParams &p, PruneLds &s, int32_t pt,
     // (d) survivors after this block move up behind it
     mv = compact_live(s, b + 16, mv);
   }
-  int32_t *row = p.adj + (int64_t)pt * p.R;
-  for (int e = l; e < p.R; e += kWave) row[e] = e < nsel ? s.sel[e] : -1;
-  if (l == 0) p.deg[pt] = nsel;
+  write_nout(p, s, pt, nsel);
   return tiles;
 }
 
@@ -329,7 +340,8 @@ __global__ __launch_bounds__(64) void prune_forward_kernel(PruneParams p) {
     const int32_t pt = p.items[t];
     // candidates: the visited set V_p, whose keys (D(p, v), v) the search has
     // already formed, then the current out-neighbours Nout(p) that are not in
-    // V_p (their distances come from tiles; R <= 128, two per lane)
+    // V_p with their kept keys (R <= 128, two per lane): no distance is formed
+    // before the greedy pass
     const int nv = min(p.vis_count[t], p.vcap);
     const uint64_t *v = p.vis + (int64_t)t * p.vcap;
     for (int j = l; j < nv; j += kWave) {
@@ -339,8 +351,11 @@ __global__ __launch_bounds__(64) void prune_forward_kernel(PruneParams p) {
     }
     const int dp = min(p.deg[pt], p.R);
     const int32_t *row = p.adj + (int64_t)pt * p.R;
+    const uint64_t *krow = p.akey + (int64_t)pt * p.R;
     int32_t e0 = l < dp ? row[l] : -1;
     int32_t e1 = l + kWave < dp ? row[l + kWave] : -1;
+    const uint64_t ke0 = l < dp ? krow[l] : kNoKey;
+    const uint64_t ke1 = l + kWave < dp ? krow[l + kWave] : kNoKey;
     wave_lds_sync();
     if (dp > 0) {
       for (int j = 0; j < nv; ++j) {
@@ -350,11 +365,19 @@ __global__ __launch_bounds__(64) void prune_forward_kernel(PruneParams p) {
       }
     }
     const uint64_t m0 = ballot(e0 >= 0), m1 = ballot(e1 >= 0);
-    if (e0 >= 0) s.ids[nv + lanes_below(m0)] = e0;
-    if (e1 >= 0) s.ids[nv + __popcll(m0) + lanes_below(m1)] = e1;
+    if (e0 >= 0) {
+      const int o = nv + lanes_below(m0);
+      s.ids[o] = e0;
+      s.k0[o] = ke0;
+    }
+    if (e1 >= 0) {
+      const int o = nv + __popcll(m0) + lanes_below(m1);
+      s.ids[o] = e1;
+      s.k0[o] = ke1;
+    }
     const int nout = __popcll(m0) + __popcll(m1);
     wave_lds_sync();
-    const int rows = 32 * robust_prune_tiles<DT>(p, s, pt, nv + nout, nv);
+    const int rows = 32 * robust_prune_tiles<DT>(p, s, pt, nv + nout, nv + nout);
     if (p.counters && l == 0) atomicAdd(p.counters + 0, (unsigned long long)rows);
     wave_lds_sync();
   }
@@ -412,15 +435,20 @@ __global__ __launch_bounds__(64) void prune_reverse_kernel(PruneParams p) {
       if (l == 0) atomicAdd(p.overflow, 1);
       cnt = p.capin;
     }
+    // each source p arrives with its key (D(p, q), p) and each out-neighbour
+    // with its kept key, so neither an append nor a prune forms a distance to q
     const int32_t *src = p.seg + off;
+    const uint64_t *srck = p.segk + off;
     const int dq = min(dg, p.R);
     int32_t *row = p.adj + (int64_t)q * p.R;
+    uint64_t *krow = p.akey + (int64_t)q * p.R;
     int nnew = 0;
     if (!p.heavy) {
       // at most 64 sources (one per lane) and R <= 128 out-neighbours (two per
       // lane): membership and ascending order come from ballots and lane reads,
       // and an append never touches the LDS
-      const int32_t v = l < cnt ? src[l] : -1;
+      const uint64_t kv = l < cnt ? srck[l] : kNoKey;
+      const int32_t v = l < cnt ? (int32_t)key_id(kv) : -1;
       const int32_t e0 = l < dq ? row[l] : -1;
       const int32_t e1 = l + kWave < dq ? row[l + kWave] : -1;
       uint64_t pres = 0;
@@ -435,17 +463,30 @@ __global__ __launch_bounds__(64) void prune_reverse_kernel(PruneParams p) {
         r += __builtin_amdgcn_readlane(v, __builtin_ctzll(m)) < v;
       nnew = __popcll(km);
       if (dq + nnew <= p.R) {
-        if (keep) row[dq + r] = v;
+        if (keep) {
+          row[dq + r] = v;
+          krow[dq + r] = kv;
+        }
       } else {
-        if (l < dq) s.ids[l] = e0;
-        if (l + kWave < dq) s.ids[l + kWave] = e1;
-        if (keep) s.ids[dq + r] = v;
+        if (l < dq) {
+          s.ids[l] = e0;
+          s.k0[l] = krow[l];
+        }
+        if (l + kWave < dq) {
+          s.ids[l + kWave] = e1;
+          s.k0[l + kWave] = krow[l + kWave];
+        }
+        if (keep) {
+          s.ids[dq + r] = v;
+          s.k0[dq + r] = kv;
+        }
       }
     } else {
       // current out-neighbours, then the new sources in ascending index order,
       // leaving out sources already among the out-neighbours (the sources of
-      // one batch are distinct; they are staged in LDS and ranked there)
-      int32_t *stage = (int32_t *)s.k1;
+      // one batch are distinct; their ids are staged in LDS and ranked there,
+      // and their keys land in s.k1 at their rank)
+      int32_t *stage = (int32_t *)s.cn;
       for (int j = l; j < dq; j += kWave) s.ids[j] = row[j];
       for (int j = l; j < cnt; j += kWave) stage[j] = src[j];
       wave_lds_sync();
@@ -455,26 +496,36 @@ __global__ __launch_bounds__(64) void prune_reverse_kernel(PruneParams p) {
         for (int t = 0; t < cnt; ++t) r += stage[t] < v;
         bool present = false;
         for (int t = 0; t < dq; ++t) present |= (s.ids[t] == v);
-        ((int32_t *)s.k0)[r] = present ? -1 : v;
+        s.k1[r] = present ? kNoKey : srck[j];
       }
       wave_lds_sync();
       for (int base = 0; base < cnt; base += kWave) {
         const int j = base + l;
-        const int32_t v = j < cnt ? ((const int32_t *)s.k0)[j] : -1;
-        const uint64_t bm = ballot(v >= 0);
-        if (v >= 0) s.ids[dq + nnew + lanes_below(bm)] = v;
+        const uint64_t kv = j < cnt ? s.k1[j] : kNoKey;
+        const uint64_t bm = ballot(kv != kNoKey);
+        if (kv != kNoKey) {
+          const int o = dq + nnew + lanes_below(bm);
+          s.ids[o] = (int32_t)key_id(kv);
+          s.k0[o] = kv;
+        }
         nnew += __popcll(bm);
       }
       wave_lds_sync();
-      if (dq + nnew <= p.R)
-        for (int j = l; j < nnew; j += kWave) row[dq + j] = s.ids[dq + j];
+      if (dq + nnew <= p.R) {
+        for (int j = l; j < nnew; j += kWave) {
+          row[dq + j] = s.ids[dq + j];
+          krow[dq + j] = s.k0[dq + j];
+        }
+      } else {
+        for (int j = l; j < dq; j += kWave) s.k0[j] = krow[j];
+      }
     }
     wave_lds_sync();
     if (dq + nnew <= p.R) {
       if (l == 0) p.deg[q] = dq + nnew;
       if (p.counters && l == 0) atomicAdd(p.counters + 3, 1ull);
     } else {
-      const int rows = 32 * robust_prune_tiles<DT>(p, s, q, dq + nnew);
+      const int rows = 32 * robust_prune_tiles<DT>(p, s, q, dq + nnew, dq + nnew);
       if (p.counters && l == 0) {
         atomicAdd(p.counters + 1, (unsigned long long)rows);
         atomicAdd(p.counters + 2, 1ull);
@@ -507,7 +558,7 @@ __global__ __launch_bounds__(64) void prune_lists_kernel(PruneParams p) {
 }
 
 size_t prune_lds_bytes(int ccap, int R) {
-  return (size_t)ccap * (8 + 8 + 4 + 4 + 4 + 1) + 4 * (size_t)((R + 3) & ~3) + 16;
+  return (size_t)ccap * (8 + 8 + 4 + 4 + 4 + 1) + 8 * (size_t)R + 16;
 }
 
 template <int DT>
