@@ -166,6 +166,9 @@ struct PruneParams {
   // reverse edges grouped by target ((D(p, q), p) for source p)
   uint64_t *akey;
   uint64_t *segk;
+  // per point, how many leading adjacency entries its last prune selected
+  // (nullptr: not kept)
+  int32_t *cons;
   // NN-descent graph: Nout(i) = RobustPrune(i, list_i u rev_i) with the lists
   // (lk keys per point, kNoKey = empty) and reverse lists (lk ids, -1 = empty)
   const uint64_t *lists;

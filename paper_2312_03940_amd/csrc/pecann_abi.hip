@@ -511,6 +511,7 @@ struct BuildWs {
   int32_t *items, *item_sbase, *item_ns;
   uint64_t *vis;
   uint64_t *akey, *segk;  // keys of the adjacency entries, of the grouped reverse edges
+  int32_t *cons;          // entries of each row its last prune selected
 };
 
 static void carve_build(Carver &c, int64_t n, int R, int64_t cap, int vcap, BuildWs *w) {
@@ -532,6 +533,7 @@ static void carve_build(Carver &c, int64_t n, int R, int64_t cap, int vcap, Buil
   w->seg = c.take<int32_t>(ce);
   w->akey = c.take<uint64_t>((size_t)n * R);
   w->segk = c.take<uint64_t>(ce);
+  w->cons = c.take<int32_t>((size_t)n);
 }
 
 static int effective_vcap(const pecann_build_params *bp) {
@@ -642,6 +644,7 @@ static pecann_status build_impl(const pecann_dataset *ds, const pecann_build_par
   HIP_TRY(launch_fill_i32(adj, -1, n * R, s));
   HIP_TRY(launch_fill_i32(deg, 0, n, s));
   HIP_TRY(launch_fill_i32(w.rcnt, 0, n, s));
+  HIP_TRY(launch_fill_i32(w.cons, 0, n, s));
 
   int32_t *head_search = w.ctr + 0, *head_pf = w.ctr + 1, *head_pr = w.ctr + 2;
   int32_t *ntargets = w.ctr + 3, *cursor = w.ctr + 4;
@@ -689,6 +692,7 @@ static pecann_status build_impl(const pecann_dataset *ds, const pecann_build_par
   pp.seg = w.seg;
   pp.akey = w.akey;
   pp.segk = w.segk;
+  pp.cons = w.cons;
   pp.rcnt = w.rcnt;
   pp.overflow = overflow;
   pp.counters = counters ? (unsigned long long *)counters + 4 : nullptr;

@@ -193,7 +193,10 @@ __device__ __forceinline__ void write_nout(const PruneParams &p, const PruneLds 
   for (int e = l; e < p.R; e += kWave) row[e] = e < nsel ? (int32_t)key_id(s.sel[e]) : -1;
   if (p.akey)
     for (int e = l; e < nsel; e += kWave) p.akey[(int64_t)pt * p.R + e] = s.sel[e];
-  if (l == 0) p.deg[pt] = nsel;
+  if (l == 0) {
+    p.deg[pt] = nsel;
+    if (p.cons) p.cons[pt] = nsel;
+  }
 }
 
 // RobustPrune of point pt over s.ids[0..nc); writes Nout(pt) into adj/deg.
@@ -207,7 +210,7 @@ __device__ __forceinline__ void write_nout(const PruneParams &p, const PruneLds 
 // of its accumulator against its column), and the survivors are compacted.
 // Returns the number of 16 x 16 tiles formed.
 template <int DT>
-__device__ int robust_prune_tiles(const PruneParams &p, PruneLds &s, int32_t pt, int nc, int npre = 0) {
+__device__ __forceinline__ int robust_prune_tiles(const PruneParams &p, PruneLds &s, int32_t pt, int nc, int npre = 0) {
   constexpr int NT = 4;  // tiles in flight
   const int l = lane_id();
   const int col = l & 15, g = l >> 4;
@@ -322,6 +325,165 @@ __device__ int robust_prune_tiles(const PruneParams &p, PruneLds &s, int32_t pt,
     // (d) survivors after this block move up behind it
     mv = compact_live(s, b + 16, mv);
   }
+  write_nout(p, s, pt, nsel);
+  return tiles;
+}
+
+// RobustPrune of pt over the keys s.k0[0..mv) (all known, distinct, none of
+// them pt) whose first c entries are the output of pt's previous prune: no
+// selected entry drops a later one, so none of them drops another here either
+// (the same keys, the same measures, and alpha never decreases -- measures are
+// at least 0, so a larger alpha drops less).  Only pairs with a member of
+// U = the other mv - c candidates can drop anything, and the greedy pass is
+// settled from the U x all tiles alone:
+//   kU[j] = U members before j that would drop j,
+//   cU[j] = U members after j that j would drop (j outside U),
+// then a walk over U in key order decides each member from the selected
+// entries before it.  The result is the full greedy pass's, with nu/16 rows of
+// tiles instead of the pairwise triangle.  Returns the tiles formed, or -1 when
+// the shape does not fit (more than kMaxU members of U or 3 * 64 candidates).
+constexpr int kMaxU = 32;
+
+template <int DT>
+__device__ __forceinline__ int prune_with_prefix(const PruneParams &p, PruneLds &s, int32_t pt, int mv, int c) {
+  constexpr int NT = 4;
+  const int nu = mv - c;
+  if (nu < 1 || nu > kMaxU || mv > 3 * kWave) return -1;
+  const int l = lane_id();
+  const int col = l & 15, g = l >> 4;
+  const float a2 = p.rows.metric == PECANN_L2 ? p.alpha * p.alpha : p.alpha;
+  // (1) sort by key (keys are distinct), marking the members of U
+  for (int j = l; j < mv; j += kWave) {
+    const uint64_t key = s.k0[j];
+    int r = 0;
+    for (int t = 0; t < mv; ++t) r += s.k0[t] < key;
+    s.k1[r] = key;
+    s.alive[r] = j >= c;
+    const int32_t id = key_id(key);
+    s.cn[r] = p.rows.sqn[id];
+    s.cs[r] = (DT == PECANN_FP8E4M3) ? p.rows.scale[id] : 1.0f;
+  }
+  wave_lds_sync();
+  // (2) positions of U in key order (s.ids), each member's index + 1 in alive
+  uint32_t *kU = (uint32_t *)s.k0;
+  uint32_t *cU = kU + mv;
+  int32_t *upos = s.ids;
+  for (int base = 0, cnt = 0; base < mv; base += kWave) {
+    const int jp = base + l;
+    const bool u = jp < mv && s.alive[jp];
+    const uint64_t bm = ballot(u);
+    if (u) {
+      const int ui = cnt + lanes_below(bm);
+      upos[ui] = jp;
+      s.alive[jp] = (uint8_t)(1 + ui);
+    }
+    if (jp < mv) {
+      kU[jp] = 0;
+      cU[jp] = 0;
+    }
+    cnt += __popcll(bm);
+  }
+  wave_lds_sync();
+  // (3) U x all tiles: A rows are U members, lanes 0-15 of each 16-group hold
+  // column j, register r of lane l row 4 (l / 16) + r
+  int tiles = 0;
+  for (int ub = 0; ub * 16 < nu; ++ub) {
+    const int ua = ub * 16 + col;
+    const int32_t aid = ua < nu ? (int32_t)key_id(s.k1[upos[ua]]) : -1;
+    int pr[4];
+    float dr[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ui = ub * 16 + 4 * g + r;
+      pr[r] = ui < nu ? upos[ui] : -1;
+      dr[r] = pr[r] >= 0 ? key_measure(s.k1[pr[r]]) : 0.f;
+    }
+    for (int c0 = 0; c0 < mv; c0 += 16 * NT) {
+      int32_t bj[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int jc = c0 + 16 * t + col;
+        bj[t] = jc < mv ? (int32_t)key_id(s.k1[jc]) : -1;
+      }
+      v4f tt[NT];
+      dot_tiles<DT, NT>(p.rows, aid, bj, tt);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int jc = c0 + 16 * t + col;
+        uint32_t kk = 0, cc = 0;
+        if (jc < mv) {
+          const float dc = key_measure(s.k1[jc]);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int pu = pr[r];
+            if (pu >= 0 && pu != jc) {
+              const float m = pair_measure<DT>(tt[t][r], s.cn[pu], s.cn[jc], s.cs[pu], s.cs[jc],
+                                               p.rows.metric);
+              const uint32_t bit = 1u << (ub * 16 + 4 * g + r);
+              if (pu < jc) {
+                if (a2 * m <= dc) kk |= bit;
+              } else if (a2 * m <= dr[r]) {
+                cc |= bit;
+              }
+            }
+          }
+        }
+        kk |= __shfl_xor(kk, 16);
+        kk |= __shfl_xor(kk, 32);
+        cc |= __shfl_xor(cc, 16);
+        cc |= __shfl_xor(cc, 32);
+        if (l < 16 && jc < mv) {
+          kU[jc] |= kk;
+          cU[jc] |= cc;
+        }
+        tiles += c0 + 16 * t < mv;
+      }
+    }
+  }
+  wave_lds_sync();
+  // (4) the walk: member t of U is dropped by a selected U member before it
+  // (kU of its position) or by a selected entry j outside U before it (j is
+  // selected when no selected U member before j drops it)
+  uint32_t rk[3], rc[3];
+  bool rin[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int jp = l + kWave * i;
+    rin[i] = jp < mv && s.alive[jp] == 0;
+    rk[i] = rin[i] ? kU[jp] : 0u;
+    rc[i] = rin[i] ? cU[jp] : 0u;
+  }
+  uint32_t selU = 0;
+#pragma unroll 1
+  for (int t = 0; t < nu; ++t) {
+    const int pu = upos[t];
+    bool dead = (kU[pu] & selU) != 0;
+    if (!dead) {
+      bool hit = false;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        hit |= rin[i] && l + kWave * i < pu && !(rk[i] & selU) && ((rc[i] >> t) & 1u);
+      dead = ballot(hit) != 0;
+    }
+    if (!dead) selU |= 1u << t;
+  }
+  // (5) the selected entries in key order, at most R of them
+  int nsel = 0;
+  for (int base = 0; base < mv && nsel < p.R; base += kWave) {
+    const int jp = base + l;
+    bool sel = false;
+    if (jp < mv) {
+      const int a = s.alive[jp];
+      sel = a ? ((selU >> (a - 1)) & 1u) != 0 : (kU[jp] & selU) == 0;
+    }
+    const uint64_t bm = ballot(sel);
+    if (sel) {
+      const int o = nsel + lanes_below(bm);
+      if (o < p.R) s.sel[o] = s.k1[jp];
+    }
+    nsel = min(p.R, nsel + __popcll(bm));
+  }
+  wave_lds_sync();
   write_nout(p, s, pt, nsel);
   return tiles;
 }
@@ -525,7 +687,11 @@ __global__ __launch_bounds__(64) void prune_reverse_kernel(PruneParams p) {
       if (l == 0) p.deg[q] = dq + nnew;
       if (p.counters && l == 0) atomicAdd(p.counters + 3, 1ull);
     } else {
-      const int rows = 32 * robust_prune_tiles<DT>(p, s, q, dq + nnew, dq + nnew);
+      // the leading entries that q's last prune selected need no tiles among themselves
+      int tiles = -1;
+      if (!p.heavy) tiles = prune_with_prefix<DT>(p, s, q, dq + nnew, min(p.cons[q], dq));
+      if (tiles < 0) tiles = robust_prune_tiles<DT>(p, s, q, dq + nnew, dq + nnew);
+      const int rows = 32 * tiles;
       if (p.counters && l == 0) {
         atomicAdd(p.counters + 1, (unsigned long long)rows);
         atomicAdd(p.counters + 2, 1ull);
