@@ -234,6 +234,23 @@ def test_build_graph_bit_exact_u8_rows(dev, alpha):
     assert np.array_equal(_np(adj), adj_o)
 
 
+@pytest.mark.parametrize("alpha", [1.0, 2.0])
+def test_build_wide_lists_bit_exact(dev, alpha):
+    # R = 64 with batches of 400: full lists that receive many sources at once,
+    # so reverse prunes see up to R + 64 candidates of which up to 64 are new
+    # since the target's last prune
+    n, d = 4000, 12
+    X, _ = datagen.mixture(n, d, 10, seed=17, grid=1023)
+    P = oracle.Points(X)
+    perm = datagen.permutation(n, 23)
+    adj_o, deg_o = oracle.vamana_build(P, 64, 80, alpha, perm, num_starts=4, max_batch=400)
+    ds = pecann.Dataset(_t(X, dev), "l2", "f32")
+    adj, deg = pecann.build_graph(ds, 64, 80, alpha, num_starts=4, visited_cap=1024,
+                                  perm=_t(perm, dev), max_batch=400)
+    assert np.array_equal(_np(deg), deg_o)
+    assert np.array_equal(_np(adj), adj_o)
+
+
 def test_build_many_batches_bit_exact(dev, grid_case):
     # 3000 points in batches of at most 20: > 150 batches per pass
     X, P, perm = grid_case["X"], grid_case["P"], grid_case["perm"]
