@@ -147,7 +147,14 @@ pecann_status pecann_prepare_vectors(const void *x, int32_t x_dtype, int64_t x_r
  * Nout(q) = RobustPrune(q, Nout(q) u new, alpha, R).  RobustPrune is DiskANN's:
  * repeatedly keep the closest surviving candidate c* and drop every candidate
  * c with alpha * D(c*, c) <= D(p, c) (compared as alpha^2 * D^2 <= D^2 for L2).
- * Distances use the search rows.
+ * Distances use the search rows.  Each D(p, v) to a pruned point is formed once
+ * and reused: the search's value for the visited set, and for an adjacency
+ * entry the value it was selected or appended with (a reverse edge p -> q
+ * carries D(p, q) as D(q, p)); distances between candidates come from
+ * matrix-core tiles.  On float rows the search's and the tiles' roundings of
+ * one pair may differ in the last bits; on integer-valued rows both are exact.
+ * The workspace holds, besides the round's batch state, one 8-byte key per
+ * adjacency entry (n * R * 8 bytes) and one int32 per point.
  *
  * Output adj (device, n*R int32): row v holds Nout(v) in adj[v*R .. v*R+deg[v]),
  * the rest -1; deg (device, n int32).
