@@ -7,6 +7,7 @@
 //   K11 labels        -- roots of the dependent forest by pointer jumping
 #include <hip/hip_runtime.h>
 
+#include "claim.hpp"
 #include "device_common.hpp"
 
 namespace pecann {
@@ -186,48 +187,6 @@ hipError_t launch_identity_perm(int32_t *p, int64_t n, hipStream_t s) {
 // Arrival order is not deterministic; the merge sorts each segment by index.
 // ---------------------------------------------------------------------------
 // Wave-wide inclusive prefix sum.
-__device__ __forceinline__ int wave_prefix_sum(int v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const int y = __shfl_up(v, off);
-    if (l >= off) v += y;
-  }
-  return v;
-}
-
-// Shared counters (list lengths, segment cursors) are advanced once per
-// 1024-thread block: device-scope atomics on one address serialise, and one per
-// wavefront made them the cost of the grouping (1M-point build: 207 and 113 us
-// per launch of the two kernels below).
-constexpr int kAggThreads = 1024;
-constexpr int kAggWaves = kAggThreads / kWave;
-
-// Block-wide exclusive offsets of NV per-wave counts (cnt[v] from lane 0 of
-// each wave): one atomic per counter and block; every thread of the block calls it.
-template <int NV>
-__device__ __forceinline__ void block_claim(const int (&cnt)[NV], int32_t *const (&ctr)[NV],
-                                            int (&base)[NV]) {
-  __shared__ int wsum[NV][kAggWaves];
-  __shared__ int bbase[NV];
-  const int w = threadIdx.x / kWave;
-  if (lane_id() == 0)
-#pragma unroll
-    for (int v = 0; v < NV; ++v) wsum[v][w] = cnt[v];
-  __syncthreads();
-  if (threadIdx.x < NV) {
-    int tot = 0;
-    for (int i = 0; i < kAggWaves; ++i) tot += wsum[threadIdx.x][i];
-    bbase[threadIdx.x] = tot > 0 ? atomicAdd(ctr[threadIdx.x], tot) : 0;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    int b = bbase[v];
-    for (int i = 0; i < w; ++i) b += wsum[v][i];
-    base[v] = b;
-  }
-}
 
 // Counting pass: each edge takes a ticket in its target's count; a target seen
 // for the first time joins the target list (slots handed out per block).

@@ -19,6 +19,7 @@
 // A device flag ends the rounds once a round leaves at most the stop level of
 // new entries; later rounds then only copy the lists, so the host never waits.
 #include "beam.hpp"
+#include "claim.hpp"
 #include "kernels.hpp"
 #include "tiles.hpp"
 
@@ -160,11 +161,20 @@ __global__ void nnd_rev_count_kernel(NndParams p, int32_t ignore_done) {
   }
 }
 
+// Segment offsets per block (block_claim), the loop's trip count uniform in the block.
 __global__ void nnd_rev_alloc_kernel(NndParams p, int32_t ignore_done) {
   if (!ignore_done && *p.done) return;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < p.n;
-       t += (int64_t)gridDim.x * blockDim.x)
-    p.roff[t] = atomicAdd(p.rcursor, p.rcnt[t]);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < p.n; t0 += stride) {
+    const int64_t t = t0 + threadIdx.x;
+    const int c = t < p.n ? p.rcnt[t] : 0;
+    const int incl = wave_prefix_sum(c);
+    const int cnt[1] = {__shfl(incl, kWave - 1)};
+    int32_t *const ctr[1] = {p.rcursor};
+    int base[1];
+    block_claim<1>(cnt, ctr, base);
+    if (t < p.n) p.roff[t] = base[0] + incl - c;
+  }
 }
 
 __global__ void nnd_rev_scatter_kernel(NndParams p, int32_t ignore_done) {
@@ -366,21 +376,43 @@ __global__ void nnd_prop_count_kernel(NndParams p) {
   if (*p.done) return;
   const int64_t base = (int64_t)blockIdx.x * p.seg;
   const int nf = p.pfill[blockIdx.x];
-  for (int j = threadIdx.x; j < nf; j += blockDim.x) {
-    const int64_t e = base + j;
-    const int32_t t = p.ptgt[e];
-    const int tk = atomicAdd(p.pcnt + t, 1);
-    p.pticket[e] = tk;
-    if (tk == 0) p.ptouch[atomicAdd(p.ptouch_n, 1)] = t;
+  for (int j0 = 0; j0 < nf; j0 += blockDim.x) {
+    const int j = j0 + threadIdx.x;
+    int32_t t = -1;
+    int tk = -1;
+    if (j < nf) {
+      const int64_t e = base + j;
+      t = p.ptgt[e];
+      tk = atomicAdd(p.pcnt + t, 1);
+      p.pticket[e] = tk;
+    }
+    // first proposals to a target list it once; slots handed out per block
+    const uint64_t fm = ballot(tk == 0);
+    const int cnt[1] = {(int)__popcll(fm)};
+    int32_t *const ctr[1] = {p.ptouch_n};
+    int b[1];
+    block_claim<1>(cnt, ctr, b);
+    if (tk == 0) p.ptouch[b[0] + lanes_below(fm)] = t;
   }
 }
 
 __global__ void nnd_prop_alloc_kernel(NndParams p) {
   if (*p.done) return;
   const int nt = *p.ptouch_n;
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nt; j += gridDim.x * blockDim.x) {
-    const int32_t t = p.ptouch[j];
-    p.poff[t] = atomicAdd(p.pcursor, p.pcnt[t]);
+  for (int j0 = blockIdx.x * blockDim.x; j0 < nt; j0 += gridDim.x * blockDim.x) {
+    const int j = j0 + threadIdx.x;
+    int32_t t = -1;
+    int c = 0;
+    if (j < nt) {
+      t = p.ptouch[j];
+      c = p.pcnt[t];
+    }
+    const int incl = wave_prefix_sum(c);
+    const int cnt[1] = {__shfl(incl, kWave - 1)};
+    int32_t *const ctr[1] = {p.pcursor};
+    int b[1];
+    block_claim<1>(cnt, ctr, b);
+    if (j < nt) p.poff[t] = b[0] + incl - c;
   }
 }
 
