@@ -86,7 +86,8 @@ def load():
         lib.oracle_greedy_search.restype = i32
         lib.oracle_robust_prune.argtypes = [P, i64, vp, i32, f64, i32, vp]
         lib.oracle_robust_prune.restype = i32
-        lib.oracle_vamana_build.argtypes = [P, i32, i32, f64, vp, i32, i64, i32, vp, vp]
+        lib.oracle_vamana_build.argtypes = [P, i32, i32, f64, vp, i32, i64, i32, i32, vp, i64,
+                                            vp, vp, vp]
         lib.oracle_vamana_build.restype = ctypes.c_int
         lib.oracle_dependent_alg3.argtypes = [P, vp, vp, i32, vp, vp, i32, i32, i64, i32,
                                               i32, vp, vp, vp, i32]
@@ -273,14 +274,22 @@ def batch_schedule(n: int, max_batch: int = 0):
 
 
 def vamana_build(P: Points, R: int, L: int, alpha: float, perm, num_starts: int = 8,
-                 max_batch: int = 0, passes: int = 2):
-    """passes=2: DiskANN's schedule (alpha = 1, then alpha); passes=1: alpha only."""
+                 max_batch: int = 0, passes: int = 2, max_vis: int = 0, want_batches: bool = False):
+    """passes=2: DiskANN's schedule (alpha = 1, then alpha); passes=1: alpha only.
+    max_vis > 0 keeps the max_vis closest points of each visited set (0: all).
+    want_batches: also return the batches the build ran, as (pass, first, size) rows."""
     perm = np.ascontiguousarray(perm, dtype=np.int64)
     adj = np.empty((P.n, R), dtype=np.int32)
     deg = np.empty(P.n, dtype=np.int32)
+    cap = 4 * P.n + 64
+    log = np.empty((cap, 3), dtype=np.int64)
+    nlog = ctypes.c_int64(0)
     if load().oracle_vamana_build(P.ref, R, L, alpha, _ptr(perm), num_starts, max_batch,
-                                  passes, _ptr(adj), _ptr(deg)) != 0:
+                                  passes, max_vis, _ptr(log), cap, ctypes.byref(nlog),
+                                  _ptr(adj), _ptr(deg)) != 0:
         raise MemoryError("oracle_vamana_build")
+    if want_batches:
+        return adj, deg, log[:min(nlog.value, cap)].copy()
     return adj, deg
 
 

@@ -522,6 +522,11 @@ int32_t oracle_robust_prune(const opoints *P, int64_t p, const int64_t *cand,
 /*   then for each target q, the batch's new in-edges (sources in ascending     */
 /*   index, those already present skipped) are appended to Nout(q) if they fit */
 /*   in R, otherwise Nout(q) = RobustPrune(q, Nout(q) u new, alpha, R).        */
+/* max_vis > 0 bounds V_p (the paper keeps all of it): when a search expands    */
+/* more points, the max_vis closest by (D, index) are kept.                   */
+/* batch_log (may be NULL) receives up to log_cap triples (pass, index in perm */
+/* of the batch's first point, batch size), one per batch in the order run;    */
+/* *n_log (may be NULL) the number of batches run.                            */
 /* adj must hold n*R entries; unused slots are set to -1.  Returns 0 or -1.   */
 /* ------------------------------------------------------------------------ */
 typedef struct { int64_t tgt, src; } edge_t;
@@ -531,9 +536,15 @@ static int cmp_edge(const void *a, const void *b) {
   return (x->src > y->src) - (x->src < y->src);
 }
 
+static int cmp_cand(const void *a, const void *b) {
+  const cand_t *x = (const cand_t *)a, *y = (const cand_t *)b;
+  return before(x->d, x->id, y->d, y->id) ? -1 : (before(y->d, y->id, x->d, x->id) ? 1 : 0);
+}
+
 int oracle_vamana_build(const opoints *P, int32_t R, int32_t L, double alpha,
                         const int64_t *perm, int32_t num_starts, int64_t max_batch,
-                        int32_t passes, int32_t *adj, int32_t *deg) {
+                        int32_t passes, int32_t max_vis, int64_t *batch_log,
+                        int64_t log_cap, int64_t *n_log, int32_t *adj, int32_t *deg) {
   int64_t n = P->n;
   for (int64_t i = 0; i < n * (int64_t)R; ++i) adj[i] = -1;
   for (int64_t i = 0; i < n; ++i) deg[i] = 0;
@@ -549,6 +560,7 @@ int oracle_vamana_build(const opoints *P, int32_t R, int32_t L, double alpha,
     return -1;
   }
   int rc = 0;
+  int64_t nlog = 0;
   for (int32_t pass = 0; pass < passes && rc == 0; ++pass) {
     const double a = (passes > 1 && pass == 0) ? 1.0 : alpha;
     /* first pass: perm[0] starts the graph unsearched, batches ramp up from 1;  */
@@ -562,25 +574,43 @@ int oracle_vamana_build(const opoints *P, int32_t R, int32_t L, double alpha,
       int64_t in_graph = pass == 0 ? inserted : n;
       int32_t ns = (int32_t)(in_graph < num_starts ? in_graph : num_starts);
       int err = 0;
+      if (batch_log && nlog < log_cap) {
+        batch_log[3 * nlog + 0] = pass;
+        batch_log[3 * nlog + 1] = b0;
+        batch_log[3 * nlog + 2] = nb;
+      }
+      ++nlog;
       /* searches and forward prunes, all against the batch-start graph */
 #pragma omp parallel for schedule(dynamic, 1)
       for (int64_t t = 0; t < nb; ++t) {
         int64_t p = perm[b0 + t];
         int64_t *myvis = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + R));
+        double *myvd = (double *)malloc(sizeof(double) * (size_t)(n + 1));
         int64_t dummy_id;
         double dummy_d;
         int32_t nvis = 0;
-        if (!myvis) { err = 1; continue; }
+        if (!myvis || !myvd) { free(myvis); free(myvd); err = 1; continue; }
         if (oracle_greedy_search(P, adj, deg, R, p, p, perm, ns, L, 0, &dummy_id,
-                                 &dummy_d, myvis, NULL, (int32_t)n, &nvis) < 0) {
+                                 &dummy_d, myvis, myvd, (int32_t)n, &nvis) < 0) {
           err = 1;
         } else {
+          if (max_vis > 0 && nvis > max_vis) {
+            /* keep the max_vis closest expanded points */
+            cand_t *cv = (cand_t *)malloc(sizeof(cand_t) * (size_t)nvis);
+            if (!cv) { free(myvis); free(myvd); err = 1; continue; }
+            for (int32_t t = 0; t < nvis; ++t) { cv[t].d = myvd[t]; cv[t].id = myvis[t]; }
+            qsort(cv, (size_t)nvis, sizeof(cand_t), cmp_cand);
+            for (int32_t t = 0; t < max_vis; ++t) myvis[t] = cv[t].id;
+            nvis = max_vis;
+            free(cv);
+          }
           for (int32_t e = 0; e < deg[p]; ++e) myvis[nvis++] = adj[p * R + e];
           int32_t no = oracle_robust_prune(P, p, myvis, nvis, a, R, new_out + t * R);
           new_deg[t] = no < 0 ? 0 : no;
           if (no < 0) err = 1;
         }
         free(myvis);
+        free(myvd);
       }
       if (err) { rc = -1; break; }
       /* write the batch's out-edges; gather reverse edges */
@@ -627,6 +657,7 @@ int oracle_vamana_build(const opoints *P, int32_t R, int32_t L, double alpha,
     }
   }
   free(new_out); free(new_deg); free(edges); free(vis); free(tmp);
+  if (n_log) *n_log = nlog;
   return rc;
 }
 
