@@ -139,8 +139,9 @@ pecann_status pecann_prepare_vectors(const void *x, int32_t x_dtype, int64_t x_r
  * batch sees the graph as it was when the batch began.  The start set S of a batch is the first
  * min(num_starts, points in the graph) points of perm (the random multi-start
  * of Sec. 3.2).  For each point p of the batch: V_p = the points expanded by a
- * greedy beam search (Alg. 1, beam width L) for p from S, p excluded, at most
- * visited_cap of them (the earliest expanded);
+ * greedy beam search (Alg. 1, beam width L) for p from S, p excluded; when a
+ * search expands more than visited_cap points, the visited_cap closest by
+ * (D, index) are kept (the final beam and the closest of the rest);
  * Nout(p) = RobustPrune(p, V_p u Nout(p), alpha, R).  Then each target q
  * receives the batch's new in-edges not already present, in ascending source
  * index: appended if they fit in R, otherwise
@@ -174,7 +175,7 @@ typedef struct {
 
 /* counters (device, may be NULL): 8 uint64 work tallies accumulated over the
  * call -- [0] search expansions, [1] neighbour ids read, [2] rows gathered by
- * the searches, [3] 0, [4] row reads of the forward prunes' 16 x 16 distance
+ * the searches, [3] searches that expanded more than visited_cap points, [4] row reads of the forward prunes' 16 x 16 distance
  * tiles (32 per tile), [5] the same for the reverse prunes, [6] targets pruned,
  * [7] targets appended.  The caller zeroes
  * them; they measure the work that algorithmic-traffic figures are built on. */
@@ -422,8 +423,11 @@ pecann_status pecann_cluster_batched(int64_t n, const pecann_instances *inst, co
  * given, inst NULL: one instance with this k).  Rank key: (~ordered(rho) << 32)
  * | index, where ordered() maps a float to an unsigned integer of the same
  * order, so a smaller key is a strictly higher density with ties to the lower
- * index, as for the kth keys.  rho and rank_key may be the arrays written by
- * pecann_knn_density (no element is read after it is written).  Densities of
+ * index.  rho and rank_key may be the arrays written by pecann_knn_density (no
+ * element is read after it is written).  PECANN_DENSITY_KTH writes rho =
+ * 1 / D_k and leaves rank_key untouched: the kth keys are the ones
+ * pecann_knn_density wrote, which order by the k-th neighbour's measure itself
+ * (its reciprocal square root can round distinct measures to one value).  Densities of
  * duplicate points (D = 0) are +inf (kth, normalized numerators) and the
  * normalized density is then undefined.
  *
@@ -478,8 +482,8 @@ int32_t pecann_profile_report(pecann_profile_entry *out, int32_t max_entries);
  *                     20 L slots; else 10..13)
  *   grid_per_cu       one-wave blocks per compute unit of the persistent
  *                     search, prune and join launches (0: 32; else 4..64)
- * The setting is process-wide; set it before the calls it should govern, not
- * while another thread is inside the library.  NULL restores the rules.
+ * The setting belongs to the calling host thread (each thread starts with the
+ * rules); it governs that thread's later calls.  NULL restores the rules.
  * ------------------------------------------------------------------------- */
 typedef struct {
   int32_t hash_bits_build;
@@ -490,6 +494,21 @@ typedef struct {
 
 pecann_status pecann_set_tuning(const pecann_tuning *t);
 pecann_status pecann_get_tuning(pecann_tuning *t);
+
+/* ---------------------------------------------------------------------------
+ * Measurement aid, not a step of the method: reads `bytes` of device memory at
+ * `buf` `passes` times with 16-byte vector loads spread over every compute
+ * unit, asynchronously on `stream`, so that a caller timing the call gets the
+ * achievable read bandwidth -- of HBM for a buffer much larger than the 256 MB
+ * Infinity Cache read once, of the cache for a smaller one read many times.
+ * Roofline figures put the search kernels' algorithmic bandwidth beside it.
+ *   buf     device, 16-byte aligned; bytes a positive multiple of 16
+ *   passes  >= 1 full reads of the buffer
+ *   key     any value; sink (device uint32) is or-ed with 1 only if the XOR
+ *           fold of the data equals key, so nothing else is written
+ * ------------------------------------------------------------------------- */
+pecann_status pecann_read_probe(const void *buf, size_t bytes, int32_t passes, uint32_t key,
+                                uint32_t *sink, void *stream);
 
 const char *pecann_status_string(pecann_status s);
 /* Thread-local description of the last error returned on this thread. */

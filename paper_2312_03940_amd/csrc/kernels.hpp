@@ -157,10 +157,9 @@ struct PruneParams {
   const int32_t *tcnt;
   const int32_t *seg;
   int32_t *rcnt;
-  int32_t capin;              // max new in-edges merged per target (light list: the
-                              // list's bound; heavy list: truncation beyond it)
+  int32_t capin;              // new in-edges a target's LDS holds at once (light list:
+                              // the list's bound; heavy list: more are pruned in slices)
   int32_t *head;
-  int32_t *overflow;          // counts truncations (candidates beyond capacity)
   // keys (D(v, u), u) of the adjacency entries, kept beside adj (nullptr: none
   // kept; every prune then forms its distances from tiles), and of the batch's
   // reverse edges grouped by target ((D(p, q), p) for source p)
@@ -264,6 +263,8 @@ hipError_t launch_exact_mfma(int32_t dt, int S, const ExactMfmaParams &p, hipStr
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t s);
 hipError_t launch_identity_perm(int32_t *p, int64_t n, hipStream_t s);
+hipError_t launch_read_probe(const void *buf, int64_t bytes, int32_t passes, uint32_t key,
+                             uint32_t *sink, int grid, hipStream_t s);
 hipError_t launch_rev_count(const int32_t *adj, const int32_t *deg, const int32_t *items,
                             int32_t nb, int32_t R, int32_t *rcnt, int32_t *ntargets,
                             int32_t *tlist, int32_t *tidx, int32_t *ticket, hipStream_t s);

@@ -179,6 +179,38 @@ hipError_t launch_identity_perm(int32_t *p, int64_t n, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// Read-bandwidth probe (a measurement aid, not a step of the method): every
+// thread streams 16-byte loads over the buffer, four in flight, and folds them
+// into an XOR that is stored only if it equals a value the caller picks, so
+// the loads are kept and nothing but the reads reaches memory.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void read_probe_kernel(const uint4 *p, int64_t n16, int32_t passes,
+                                                         uint32_t key, uint32_t *sink) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  uint32_t acc = 0;
+  for (int32_t r = 0; r < passes; ++r) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+      const uint4 a = p[i], b = p[i + stride], c = p[i + 2 * stride], d = p[i + 3 * stride];
+      acc ^= (a.x ^ a.y ^ a.z ^ a.w) ^ (b.x ^ b.y ^ b.z ^ b.w) ^ (c.x ^ c.y ^ c.z ^ c.w) ^
+             (d.x ^ d.y ^ d.z ^ d.w);
+    }
+    for (; i < n16; i += stride) {
+      const uint4 a = p[i];
+      acc ^= a.x ^ a.y ^ a.z ^ a.w;
+    }
+    acc = acc * 2654435761u + (uint32_t)r;
+  }
+  if (acc == key) atomicOr(sink, 1u);
+}
+hipError_t launch_read_probe(const void *buf, int64_t bytes, int32_t passes, uint32_t key,
+                             uint32_t *sink, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(read_probe_kernel, dim3(grid), dim3(256), 0, s, (const uint4 *)buf, bytes / 16,
+                     passes, key, sink);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // K9a-c: reverse edges of a batch grouped by target.
 //   count:   rcnt[q] += 1 per edge (p -> q); the first edge to reach q puts q in
 //            the target list; each edge keeps its arrival ticket;
@@ -421,7 +453,9 @@ __global__ void density_kernel(int64_t n, InstTable inst, int32_t kstride, int32
     v = -s;
   }
   rho[i] = v;
-  rank_key[i] = ((uint64_t)(~ordered_bits(v)) << 32) | (uint32_t)i;
+  // the kth keys stay those of the kNN search, which order by the k-th
+  // neighbour's measure itself (1 / sqrt of it can tie where the measure does not)
+  if (fn != PECANN_DENSITY_KTH) rank_key[i] = ((uint64_t)(~ordered_bits(v)) << 32) | (uint32_t)i;
 }
 hipError_t launch_density(int64_t n, const InstTable &inst, int32_t kstride, int32_t fn,
                           const int32_t *knn_idx, const float *knn_dist, float *rho,

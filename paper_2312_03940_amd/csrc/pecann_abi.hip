@@ -20,8 +20,8 @@ using namespace pecann;
 // ---------------------------------------------------------------------------
 static thread_local char g_err[512] = "";
 
-// Launch tuning (speed only; see pecann_set_tuning).  Process-wide.
-static pecann_tuning g_tuning = {0, 0, 0, 0};
+// Launch tuning (speed only; see pecann_set_tuning).  Per host thread.
+static thread_local pecann_tuning g_tuning = {0, 0, 0, 0};
 
 static pecann_status fail(pecann_status s, const char *fmt, ...) {
   va_list ap;
@@ -436,7 +436,9 @@ static InstTable table_of(const InstDev &d, int count) {
 // ---------------------------------------------------------------------------
 // Graph build
 // ---------------------------------------------------------------------------
-static constexpr int kCapIn = 1024;  // new in-edges merged per target per batch
+// new in-edges a heavy target takes into the LDS at once; a target with more
+// is pruned over its sorted candidates in slices of this size
+static constexpr int kCapIn = 1024;
 
 // Batch cap: the paper's 0.02 n, but never below 8192 concurrent searches (a
 // wavefront each), which is what it takes to occupy 256 CUs.
@@ -649,8 +651,6 @@ static pecann_status build_impl(const pecann_dataset *ds, const pecann_build_par
   int32_t *head_search = w.ctr + 0, *head_pf = w.ctr + 1, *head_pr = w.ctr + 2;
   int32_t *ntargets = w.ctr + 3, *cursor = w.ctr + 4;
   int32_t *nlight = w.ctr + 5, *nheavy = w.ctr + 6, *head_ph = w.ctr + 7;
-  int32_t *overflow = w.ctr + 8;
-  HIP_TRY(launch_fill_i32(overflow, 0, 1, s));
 
   SearchParams sp = {};
   sp.rows = rows;
@@ -694,7 +694,6 @@ static pecann_status build_impl(const pecann_dataset *ds, const pecann_build_par
   pp.segk = w.segk;
   pp.cons = w.cons;
   pp.rcnt = w.rcnt;
-  pp.overflow = overflow;
   pp.counters = counters ? (unsigned long long *)counters + 4 : nullptr;
 
   for (int ri = 0; ri < (int)sched.size(); ++ri) {
@@ -1589,5 +1588,20 @@ extern "C" pecann_status pecann_local_centers(int64_t n, const pecann_instances 
   PROF(F_CLUSTER, s);
   HIP_TRY(launch_local_centers(n, table_of(d, sp.count()), k, knn_idx, rank_key, rho, rho_min,
                                is_center, s));
+  return PECANN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Measurement aid
+// ---------------------------------------------------------------------------
+extern "C" pecann_status pecann_read_probe(const void *buf, size_t bytes, int32_t passes,
+                                           uint32_t key, uint32_t *sink, void *stream) {
+  clear_stale_error();
+  if (!buf || !sink) return fail(PECANN_EINVAL, "buf/sink are NULL");
+  if (bytes == 0 || bytes % 16 != 0 || !aligned(buf, 16))
+    return fail(PECANN_EINVAL, "bytes must be a positive multiple of 16 and buf 16-byte aligned");
+  if (passes < 1) return fail(PECANN_EINVAL, "passes must be >= 1");
+  HIP_TRY(launch_read_probe(buf, (int64_t)bytes, passes, key, sink, cu_count() * 8,
+                            (hipStream_t)stream));
   return PECANN_OK;
 }

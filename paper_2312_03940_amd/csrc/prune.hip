@@ -550,6 +550,96 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == PECANN
   }
 }
 
+// A target with more new sources than the launch's capacity (capin): the
+// greedy pass of RobustPrune visits the candidates in key order and only the
+// points it selects drop later ones, so it can run over the sorted candidate
+// list in consecutive slices -- slice t is pruned together with the points
+// selected so far, which come first in key order and drop none of each other
+// again -- until R points are selected or the list ends.  The result equals one
+// pass over all candidates.  A slice is the capin smallest keys not yet taken,
+// bounded by bisection over the key space; the candidates are Nout(q) (two
+// per lane) and the sources not already in it, whose keys stay in the
+// target's segment (a source already present has its key cleared there;
+// entry j of the segment is only read and written by lane j % 64).
+template <int DT>
+__device__ __forceinline__ int prune_reverse_sliced(const PruneParams &p, PruneLds &s, int32_t q,
+                                                 uint64_t *srck, int cnt, int dq) {
+  const int l = lane_id();
+  const int32_t *row = p.adj + (int64_t)q * p.R;
+  const uint64_t *krow = p.akey + (int64_t)q * p.R;
+  const uint64_t ke0 = l < dq ? krow[l] : kNoKey;
+  const uint64_t ke1 = l + kWave < dq ? krow[l + kWave] : kNoKey;
+  for (int j = l; j < dq; j += kWave) s.ids[j] = row[j];
+  wave_lds_sync();
+  for (int j = l; j < cnt; j += kWave) {
+    const int32_t v = key_id(srck[j]);
+    bool present = false;
+    for (int t = 0; t < dq; ++t) present |= (s.ids[t] == v);
+    if (present) srck[j] = kNoKey;
+  }
+  wave_lds_sync();
+  constexpr uint64_t kTop = kNoKey - 1;  // largest key a candidate can hold
+  // candidates with keys in [lo, hi]
+  auto count_in = [&](uint64_t lo, uint64_t hi) {
+    int c = (ke0 >= lo && ke0 <= hi) + (ke1 >= lo && ke1 <= hi);
+    for (int j = l; j < cnt; j += kWave) {
+      const uint64_t k = srck[j];
+      c += k >= lo && k <= hi;
+    }
+    return wave_sum_i32(c);
+  };
+  int nsel = 0, tiles = 0;
+  uint64_t lo = 0;
+  for (;;) {
+    const int rem = count_in(lo, kTop);
+    if (rem == 0) break;
+    uint64_t hi = kTop;
+    if (rem > p.capin) {
+      uint64_t a = lo, b = kTop;  // count_in(lo, b) >= capin throughout
+      while (a < b) {
+        const uint64_t mid = a + (b - a) / 2;
+        if (count_in(lo, mid) >= p.capin) b = mid; else a = mid + 1;
+      }
+      hi = b;
+    }
+    // the points selected so far, then the slice
+    for (int j = l; j < nsel; j += kWave) {
+      const uint64_t k = s.sel[j];
+      s.k0[j] = k;
+      s.ids[j] = key_id(k);
+    }
+    int m = nsel;
+    {
+      const bool in0 = ke0 >= lo && ke0 <= hi, in1 = ke1 >= lo && ke1 <= hi;
+      const uint64_t b0 = ballot(in0), b1 = ballot(in1);
+      if (in0) { const int o = m + lanes_below(b0); s.k0[o] = ke0; s.ids[o] = key_id(ke0); }
+      if (in1) {
+        const int o = m + __popcll(b0) + lanes_below(b1);
+        s.k0[o] = ke1;
+        s.ids[o] = key_id(ke1);
+      }
+      m += __popcll(b0) + __popcll(b1);
+    }
+    for (int j0 = 0; j0 < cnt; j0 += kWave) {
+      const int j = j0 + l;
+      const uint64_t k = j < cnt ? srck[j] : kNoKey;
+      const bool in = k >= lo && k <= hi;
+      const uint64_t bm = ballot(in);
+      if (in) { const int o = m + lanes_below(bm); s.k0[o] = k; s.ids[o] = key_id(k); }
+      m += __popcll(bm);
+    }
+    wave_lds_sync();
+    tiles += robust_prune_tiles<DT>(p, s, q, m, m);
+    int v = 0;
+    if (l == 0) v = p.deg[q];  // written by lane 0 in write_nout
+    nsel = __shfl(v, 0);
+    wave_lds_sync();
+    if (nsel >= p.R || hi == kTop) break;
+    lo = hi + 1;
+  }
+  return tiles;
+}
+
 // Three waves per SIMD for every row format but float32, with no spills: the
 // compiler then gives up the accumulation registers (1M x 128 BF16 build:
 // reverse prune 142.7 -> 112.9 ms per step; 1.28M x 1024 FP8: 332 -> 282 ms).
@@ -602,15 +692,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == PECANN
       dg = p.deg[q];
     }
     ++it;
-    if (cnt > p.capin) {
-      if (l == 0) atomicAdd(p.overflow, 1);
-      cnt = p.capin;
-    }
     // each source p arrives with its key (D(p, q), p) and each out-neighbour
     // with its kept key, so neither an append nor a prune forms a distance to q
     const int32_t *src = p.seg + off;
     const uint64_t *srck = p.segk + off;
     const int dq = min(dg, p.R);
+    if (cnt > p.capin) {
+      // more sources than the LDS holds (heavy list only: light targets have
+      // at most capin by construction); more than capin - R of them are new,
+      // so the target is always pruned
+      const int rows = 32 * prune_reverse_sliced<DT>(p, s, q, p.segk + off, cnt, dq);
+      if (p.counters && l == 0) {
+        atomicAdd(p.counters + 1, (unsigned long long)rows);
+        atomicAdd(p.counters + 2, 1ull);
+      }
+      if (l == 0) p.rcnt[q] = 0;
+      wave_lds_sync();
+      continue;
+    }
     int32_t *row = p.adj + (int64_t)q * p.R;
     uint64_t *krow = p.akey + (int64_t)q * p.R;
     int nnew = 0;

@@ -76,6 +76,48 @@ __device__ __forceinline__ void expand(const E &eng, const SearchParams &p, Lds 
   }
 }
 
+// The expanded points of an insertion's search (V_p), at most `cap` of them:
+// once the slot is full, a newly expanded point replaces the farthest kept one
+// when it is closer, so the slot ends with the `cap` closest by (D, index).
+// (An expanded point is never expanded again: it either stays in the beam or
+// was pushed out by closer keys and can never re-enter, so the keys are
+// distinct.)  Entry e is written and read by lane e % 64 only, so each lane
+// reads back its own stores.
+struct VisitedSlot {
+  uint64_t *v;
+  int cap;
+  int n;        // points expanded so far (may exceed cap)
+  uint64_t mx;  // largest kept key, once the slot is full
+  int mpos;     // its entry
+
+  __device__ __forceinline__ void find_max() {
+    const int l = lane_id();
+    uint64_t best = 0;
+    int bp = -1;
+    for (int e = l; e < cap; e += kWave) {
+      const uint64_t k = v[e];
+      if (bp < 0 || k > best) { best = k; bp = e; }
+    }
+    mx = ~wave_min_u64(~best);
+    const uint64_t who = ballot(bp >= 0 && best == mx);
+    mpos = __shfl(bp, __builtin_ctzll(who));
+  }
+
+  // every lane calls with the same key
+  __device__ __forceinline__ void add(uint64_t key) {
+    const int l = lane_id();
+    if (n < cap) {
+      if (l == (n & (kWave - 1))) v[n] = key;
+      if (++n == cap) find_max();
+      return;
+    }
+    ++n;
+    if (key >= mx) return;
+    if (l == (mpos & (kWave - 1))) v[mpos] = key;
+    find_max();
+  }
+};
+
 // Re-score the first r beam entries from float32 rows and sort them (into beam.a).
 template <int SR>
 __device__ __forceinline__ void rerank_beam(const SearchParams &p, Lds &s, int32_t qid, int r) {
@@ -147,24 +189,23 @@ __device__ __forceinline__ void search_body(const SearchParams &p) {
       score_and_merge(eng, p.rows, s, id);
     }
 
-    int nv = 0;
+    VisitedSlot vs{MODE == MODE_BUILD ? p.vis + (int64_t)it * p.vcap : nullptr, p.vcap, 0, 0, 0};
     for (;;) {
       uint64_t kj = kNoKey;
       const int j = s.beam.first_unflagged(kj);
       if (j < 0) break;
-      if (l == 0) {
-        s.beam.fa[j] = 1;
-        if (MODE == MODE_BUILD && nv < p.vcap) p.vis[(int64_t)it * p.vcap + nv] = kj;
-      }
-      ++nv;
+      if (l == 0) s.beam.fa[j] = 1;
+      if (MODE == MODE_BUILD) vs.add(kj);
       wave_lds_sync();
       expand(eng, p, s, key_id(kj));
     }
+    const int nv = vs.n;
 
     const int m = s.beam.m;
     unsigned long long n_rerank = 0;
     if (MODE == MODE_BUILD) {
       if (l == 0) p.vis_count[it] = nv;
+      n_rerank = nv > p.vcap;  // build counter [3]: searches whose V_p was capped
     } else if (MODE == MODE_KNN) {
       const int k = p.inst.k[ti];
       int mm = m;

@@ -149,6 +149,7 @@ def load():
                                                         vp, vp, vp, vp, sz, vp]),
         "pecann_set_tuning": (ctypes.c_int, [ctypes.POINTER(_Tuning)]),
         "pecann_get_tuning": (ctypes.c_int, [ctypes.POINTER(_Tuning)]),
+        "pecann_read_probe": (ctypes.c_int, [vp, sz, i32, ctypes.c_uint32, vp, vp]),
         "pecann_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "pecann_last_error": (ctypes.c_char_p, []),
     }
@@ -536,9 +537,13 @@ def workspace_bytes_batched(ds: Dataset, inst: Instances, k_max: int, L_search: 
 def density(knn_idx, knn_dist, fn: str = "normalized", inst: Instances | None = None,
             out=None, ws: torch.Tensor | None = None):
     """Density of another function from the kNN lists (rows of stride knn_idx.shape[1]).
-    -> (rho f32 [n], rank_key int64 [n]); out may be knn_density's (rho, rank_key)."""
+    -> (rho f32 [n], rank_key int64 [n]); out may be knn_density's (rho, rank_key).
+    fn="kth" leaves rank_key as it is (the keys knn_density wrote for these
+    lists), so it needs out=(rho, rank_key) holding them."""
     lib = load()
     n, k = knn_idx.shape
+    if fn == "kth" and out is None:
+        raise ValueError("density(fn='kth') keeps knn_density's rank keys: pass out=(rho, rank_key)")
     ni = None if inst is None else ctypes.byref(inst.struct)
     need = lib.pecann_density_workspace_size(n, ni)
     if need == 0:
@@ -569,3 +574,16 @@ def local_centers(knn_idx, rank_key, rho, rho_min: float = 0.0, inst: Instances 
     _check(lib.pecann_local_centers(n, ni, k, _ptr(knn_idx), _ptr(rank_key), _ptr(rho), rho_min,
                                     _ptr(isc), _ptr(ws), ws.numel(), _stream()))
     return isc
+
+
+def read_probe(buf: torch.Tensor, passes: int = 1, sink: torch.Tensor | None = None):
+    """Read the whole of `buf` `passes` times on the current stream (a bandwidth
+    measurement aid).  -> the sink tensor the kernel may write."""
+    lib = load()
+    _need_cuda(buf)
+    if sink is None:
+        sink = torch.zeros(1, dtype=torch.int32, device=buf.device)
+    nbytes = buf.numel() * buf.element_size()
+    _check(lib.pecann_read_probe(_ptr(buf), nbytes - nbytes % 16, passes, 0x5bd1e995, _ptr(sink),
+                                 _stream()))
+    return sink

@@ -46,7 +46,8 @@ def _order_ok(ref_rho, gpu_key, rtol):
 @pytest.mark.parametrize("fn", FNS)
 def test_density_function_matches_oracle(case, fn):
     ref = oracle.density(case["ref_idx"], case["ref_dist"], fn)
-    rho, key = pecann.density(case["idx"], case["dist"], fn)
+    out = (torch.empty_like(case["rho"]), case["key"].clone()) if fn == "kth" else None
+    rho, key = pecann.density(case["idx"], case["dist"], fn, out=out)
     rho, key = rho.cpu().numpy(), key.cpu().numpy()
     assert np.allclose(rho, ref, rtol=2e-5, atol=0), fn
     assert _order_ok(ref, key, 4e-5), fn
@@ -97,3 +98,21 @@ def test_dpc_with_other_density_matches_oracle(case, fn):
     assert metrics.ari(labels.cpu().numpy(), rlab) >= 0.99
     agree = np.mean(dep.cpu().numpy() == rdep)
     assert agree >= 0.99, agree
+
+
+def test_kth_density_keeps_the_knn_keys(case):
+    # the kth function's order is the k-th neighbour's measure with ties to the
+    # lower index (Sec. 3 ranking); its keys stay those of the kNN search, so
+    # both entry points hand the dependent search the same order.  On this
+    # integer grid every D_k^2 is an exact integer: the order equals the
+    # oracle's (D_k, index) rank exactly, near-ties of 1 / D_k included.
+    rho, key = pecann.density(case["idx"], case["dist"], "kth",
+                              out=(torch.empty_like(case["rho"]), case["key"].clone()))
+    assert torch.equal(key, case["key"])
+    assert torch.equal(rho, case["rho"])
+    key_n = key.cpu().numpy()
+    order_g = np.lexsort((np.arange(len(key_n)), key_n.astype(np.uint64)))
+    order_o, _ = oracle.rank_from_dk(case["ref_dist"][:, case["k"] - 1])
+    assert np.array_equal(order_o, order_g)
+    with pytest.raises(ValueError):
+        pecann.density(case["idx"], case["dist"], "kth")

@@ -280,6 +280,61 @@ def test_build_heavy_target_bit_exact(dev):
     assert np.array_equal(_np(adj), adj_o) and np.array_equal(_np(deg), deg_o)
 
 
+@pytest.mark.parametrize("alpha", [1.0, 2.0])
+def test_build_default_visited_cap_bit_exact(dev, grid_case, alpha):
+    # the default visited_cap (2L) with a narrow beam: many searches expand more
+    # than 2L points, and both sides keep the 2L closest (D, index) of them
+    X, P, perm = grid_case["X"], grid_case["P"], grid_case["perm"]
+    R, L = 12, 10
+    adj_o, deg_o = oracle.vamana_build(P, R, L, alpha, perm, num_starts=4, max_batch=200,
+                                       max_vis=2 * L)
+    ds = pecann.Dataset(_t(X, dev), "l2", "f32")
+    cnt = torch.zeros(8, dtype=torch.int64, device=dev)
+    adj, deg = pecann.build_graph(ds, R, L, alpha, num_starts=4, perm=_t(perm, dev),
+                                  max_batch=200, counters=cnt)
+    c = _np(cnt)
+    assert c[3] > 100, c  # searches whose visited set was capped
+    assert np.array_equal(_np(deg), deg_o)
+    assert np.array_equal(_np(adj), adj_o)
+
+
+def _line_star():
+    """A hub with 16 rays of 300 integer points (both directions of 8 axes): in
+    the alpha = 2 pass every point keeps the hub, so one batch gives it more
+    than 1024 new in-edges, and its prune keeps about one point per ray (fewer
+    than R), so every slice of the sliced prune is walked."""
+    d, T, t0, c = 8, 300, 100, 400
+    pts = [np.full(d, c)]
+    for g in range(d):
+        for sgn in (1, -1):
+            for t in range(t0, t0 + T):
+                x = np.full(d, c)
+                x[g] += sgn * t
+                pts.append(x)
+    X = np.array(pts, np.float32)
+    p = np.random.default_rng(5).permutation(len(X))
+    return X[p], int(np.nonzero(p == 0)[0][0])
+
+
+def test_build_giant_reverse_target_bit_exact(dev):
+    X, hub = _line_star()
+    n = len(X)
+    P = oracle.Points(X)
+    perm = datagen.permutation(n, 11)
+    adj_o, deg_o = oracle.vamana_build(P, 32, 32, 2.0, perm, num_starts=4, max_batch=4096,
+                                       max_vis=64)
+    # the hub stays in the out-lists of more than 1024 points of the first
+    # full batch of pass 2, so that batch gave it more than 1024 in-edges
+    first = perm[:4096]
+    assert np.count_nonzero(np.any(adj_o[first] == hub, axis=1)) > 1024
+    assert deg_o[hub] < 32
+    ds = pecann.Dataset(_t(X, dev), "l2", "f32")
+    adj, deg = pecann.build_graph(ds, 32, 32, 2.0, num_starts=4, perm=_t(perm, dev),
+                                  max_batch=4096)
+    assert np.array_equal(_np(deg), deg_o)
+    assert np.array_equal(_np(adj), adj_o)
+
+
 def test_search_and_dependent_rounds_bit_exact(dev, grid_case):
     X, P, perm, n = grid_case["X"], grid_case["P"], grid_case["perm"], grid_case["n"]
     R, L, k = 16, 32, 10
