@@ -19,8 +19,8 @@ def test_more_than_one_gpu_is_refused_before_any_gpu_work():
 
 
 def test_workload_table_matches_the_benchmark_configurations():
-    # the headline is the MNIST-shaped float32 step; the larger workloads run
-    # their reduced-precision rows with a float32 rerank
+    # the headline is the largest single-GPU workload (1.28M x 1024 cosine, FP8
+    # rows with a float32 rerank); the MNIST-shaped one runs float32 rows
     wl = bench.WORKLOADS
     assert set(wl) == {2, 3, 4, 5}
     assert (wl[2]["search"], wl[2]["R"], wl[2]["L"], wl[2]["alpha"], wl[2]["k"], wl[2]["n_c"]) == \
@@ -34,4 +34,4 @@ def test_workload_table_matches_the_benchmark_configurations():
         args = bench.parse()
     finally:
         sys.argv = sys_argv
-    assert args.gpus == 1 and args.config == 2
+    assert args.gpus == 1 and args.config == 4
