@@ -110,6 +110,9 @@ def parse():
                     help="skip the package's autotuner (by default it picks the launch settings, "
                          "which change speed only, and the kNN beam width before timing; its "
                          "cache lives in PECANN_AUTOTUNE_CACHE)")
+    ap.add_argument("--scorer", type=int, default=None, choices=[0, 1, 2],
+                    help="where BF16 / FP8 candidates are scored (0 rule, 1 vector units, 2 matrix "
+                         "cores); default: the autotuner's choice")
     ap.add_argument("--nnd-k", type=int, default=None, help="NN-descent list length of the variant")
     ap.add_argument("--nnd-repeats", type=int, default=None, help="NN-descent runs merged")
     ap.add_argument("--nnd-only", action="store_true",
@@ -415,6 +418,9 @@ def measure(x, wl, search, mode, args, perm, steps, warmup, ref=None, sample=Non
         tuning["seconds"] = round(time.perf_counter() - t0, 2)
         tuning.pop("trials", None)
         log(f"autotune: {tuning}")
+    if args.scorer is not None:
+        from paper_2312_03940_amd import pecann
+        pecann.set_tuning(**{**pecann.get_tuning(), "scorer": args.scorer})
     wall, ph, kprof = pl.run(steps, warmup)
     rec = {"search_rows": search, "mode": mode, "ms_per_step": round(wall * 1e3 / steps, 3),
            "value": round(n * steps / wall, 1),
@@ -510,11 +516,11 @@ def roofline(pl, kprof, steps, search, n, d, k):
     bytes."""
     from paper_2312_03940_amd import pecann
     timed = pecann.get_tuning()
-    pecann.set_tuning(13, 13, timed["grid_per_cu"])
+    pecann.set_tuning(13, 13, timed["grid_per_cu"], timed["scorer"])
     try:
         bc, kc = pl.counters()
     finally:
-        pecann.set_tuning(timed["hash_bits_build"], timed["hash_bits_search"], timed["grid_per_cu"])
+        pecann.set_tuning(**timed)
     row_bytes = {"f32": 4 * d, "u8": d, "bf16": 2 * d, "fp8": d}[search]
     # algorithmic bytes per step: per expansion the degree word and the neighbour ids,
     # per distance the candidate row, per search its own row (float32 for BF16/FP8

@@ -85,7 +85,8 @@ typedef enum {
  * pecann_prepare_vectors converts the caller's rows once into a "prepared"
  * buffer, owned by the caller, that every later call reads:
  *   search rows  n rows of the search element type (F32, U8, BF16 or FP8E4M3),
- *                each padded with zeros to a multiple of 16 bytes;
+ *                each padded with zeros to a multiple of 16 bytes (BF16: 64,
+ *                FP8E4M3: 128 -- one matrix-core step of the search's scoring);
  *   rerank rows  n float32 rows padded to 16 bytes, present when the search
  *                type is BF16 or FP8E4M3 (used to re-score candidates so that
  *                every reported distance and every ordering is float32);
@@ -470,18 +471,26 @@ pecann_status pecann_profile_enable(int32_t on);
 int32_t pecann_profile_report(pecann_profile_entry *out, int32_t max_entries);
 
 /* ---------------------------------------------------------------------------
- * Launch tuning.  Settings that change speed only: every output of every call
- * is the same, byte for byte, under any valid setting (the visited hash may
- * forget ids, which costs repeated distance evaluations and nothing else, and
- * every work item's result is independent of which wave takes it).  Chosen by
- * the package's autotuner, which times candidates through these calls and
- * keeps the winners in a JSON cache keyed by the workload's shape.
+ * Launch tuning.  Chosen by the package's autotuner, which times candidates
+ * through these calls and keeps the winners in a JSON cache keyed by the
+ * workload's shape.
  *   hash_bits_build   log2 visited-hash slots of build searches (0: the rule
  *                     of about 10 L or 20 L slots; else 10..13)
  *   hash_bits_search  the same for kNN and doubling-round searches (0: about
  *                     20 L slots; else 10..13)
  *   grid_per_cu       one-wave blocks per compute unit of the persistent
  *                     search, prune and join launches (0: 32; else 4..64)
+ *   scorer            where the searches score BF16 / FP8 candidate rows:
+ *                     0 the rule (matrix cores for FP8 rows of 512 bytes or
+ *                     more, else vector units), 1 vector units, 2 matrix cores
+ * The first three change speed only: every output of every call is the same,
+ * byte for byte, under any valid setting (the visited hash may forget ids,
+ * which costs repeated distance evaluations and nothing else, and every work
+ * item's result is independent of which wave takes it).  The scorer changes
+ * the rounding of the reduced-precision search measures (an FMA chain on the
+ * vector units, the matrix cores' sums of a two-part query), so approximate
+ * graphs and lists over BF16 / FP8 rows may differ between its values;
+ * float32 and uint8 rows and the exact mode are not affected.
  * The setting belongs to the calling host thread (each thread starts with the
  * rules); it governs that thread's later calls.  NULL restores the rules.
  * ------------------------------------------------------------------------- */
@@ -489,7 +498,7 @@ typedef struct {
   int32_t hash_bits_build;
   int32_t hash_bits_search;
   int32_t grid_per_cu;
-  int32_t reserved;  /* must be 0 */
+  int32_t scorer;    /* 0 rule, 1 vector units, 2 matrix cores */
 } pecann_tuning;
 
 pecann_status pecann_set_tuning(const pecann_tuning *t);

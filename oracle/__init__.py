@@ -37,7 +37,8 @@ __all__ = [
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dpc_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# PECANN_ORACLE_LIB: another build of dpc_oracle.c (the sanitizer test's)
+_LIB = os.environ.get("PECANN_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 L2, COSINE = 0, 1
 F32, U8 = 0, 1

@@ -1,9 +1,11 @@
-"""Autotuner.  tune(): the launch settings that change speed only
-(pecann_set_tuning): the visited-hash size of the build searches and of the
+"""Autotuner.  tune(): the launch settings (pecann_set_tuning): where BF16 / FP8
+candidates are scored (vector units or matrix cores; this changes the
+rounding of the reduced-precision search measures), and the settings that
+change speed only: the visited-hash size of the build searches and of the
 kNN / doubling searches, and the persistent grid (one-wave blocks per compute
 unit).  tune_beam(): the kNN beam width, the smallest that agrees with a
 wide-beam search on a target share of the neighbours (this one changes results
-within that target).
+within that target).  The callers' quality gates judge every choice.
 
 For a workload shape it times the graph build and the kNN search under a few
 candidate settings with HIP events, one knob at a time with the others at their
@@ -26,6 +28,8 @@ MARGIN = 0.02  # speed-up a launch setting must show to replace the rule
 BUILD_HASH_BITS = (0, 11, 12, 13)
 SEARCH_HASH_BITS = (0, 11, 12, 13)
 GRID_PER_CU = (0, 12, 20)
+SCORERS = (0, 1, 2)  # rule, vector units, matrix cores (BF16 / FP8 rows only)
+KNOBS = ("hash_bits_build", "hash_bits_search", "grid_per_cu", "scorer")
 
 
 # Settings tuned on MI355X for the benchmark workloads, shipped with the package
@@ -152,9 +156,9 @@ def tune(ds: pecann.Dataset, R: int, L: int, alpha: float, k: int, L_search: int
     path = path or cache_path()
     key = shape_key(ds, R, L, k, L_search)
     cache = _load(path) if use_cache else {}
-    if key in cache:
+    if key in cache and all(kk in cache[key] for kk in KNOBS):
         e = cache[key]
-        pecann.set_tuning(e["hash_bits_build"], e["hash_bits_search"], e["grid_per_cu"])
+        pecann.set_tuning(*(e[kk] for kk in KNOBS))
         return {**e, "cached": True}
 
     dev = ds.device
@@ -172,10 +176,10 @@ def tune(ds: pecann.Dataset, R: int, L: int, alpha: float, k: int, L_search: int
     def knn():
         pecann.knn_density(ds, k, g_out[0], g_out[1], L_search=L_search, ws=ws, out=k_out)
 
-    cur = {"hash_bits_build": 0, "hash_bits_search": 0, "grid_per_cu": 0}
+    cur = {kk: 0 for kk in KNOBS}
 
     def apply(c):
-        pecann.set_tuning(c["hash_bits_build"], c["hash_bits_search"], c["grid_per_cu"])
+        pecann.set_tuning(*(c[kk] for kk in KNOBS))
 
     apply(cur)
     build()  # warm-up, and the graph the kNN timings search
@@ -202,7 +206,10 @@ def tune(ds: pecann.Dataset, R: int, L: int, alpha: float, k: int, L_search: int
         apply(cur)
         return best_t
 
-    t_build = sweep("hash_bits_build", BUILD_HASH_BITS, build, base_build)
+    t_build = base_build
+    if ds.search_dtype in (pecann.DTYPES["bf16"], pecann.DTYPES["fp8"]):
+        t_build = sweep("scorer", SCORERS, build, t_build)
+    t_build = sweep("hash_bits_build", BUILD_HASH_BITS, build, t_build)
     t_build = sweep("grid_per_cu", GRID_PER_CU, build, t_build)
     build()  # the graph under the chosen build settings, for the kNN timings
     torch.cuda.synchronize()

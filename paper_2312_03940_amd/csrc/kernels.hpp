@@ -63,6 +63,7 @@ struct SearchParams {
   int32_t hbits;              // log2 of visited-hash slots
   int32_t mode;
   int32_t rerank;             // entries re-scored in float32 (0: none)
+  int32_t mfma;               // BF16 / FP8 rows: score candidates on the matrix cores
   // MODE_KNN (k: the instance's, kstride: row stride of knn_idx / knn_dist)
   int32_t k;
   int32_t kstride;
@@ -94,6 +95,8 @@ struct SearchParams {
 
 size_t search_lds_bytes(int L, int hbits);
 hipError_t launch_search(int32_t dt, int S, const SearchParams &p, int grid, hipStream_t s);
+// the matrix-core scoring variant (BF16 / FP8 rows); launch_search dispatches to it
+hipError_t launch_search_mfma(int32_t dt, int S, const SearchParams &p, int grid, hipStream_t s);
 
 // Exact (brute-force) kNN over the query's instance for a list of queries.
 struct BfKnnParams {

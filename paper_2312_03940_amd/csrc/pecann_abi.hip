@@ -126,7 +126,7 @@ extern "C" pecann_status pecann_set_tuning(const pecann_tuning *t) {
     return fail(PECANN_EINVAL, "hash bits must be 0 or in [10, 13]");
   if (t->grid_per_cu != 0 && (t->grid_per_cu < 4 || t->grid_per_cu > 64))
     return fail(PECANN_EINVAL, "grid_per_cu must be 0 or in [4, 64]");
-  if (t->reserved != 0) return fail(PECANN_EINVAL, "tuning reserved field must be 0");
+  if (t->scorer < 0 || t->scorer > 2) return fail(PECANN_EINVAL, "scorer must be 0, 1 or 2");
   g_tuning = *t;
   return PECANN_OK;
 }
@@ -227,7 +227,9 @@ static bool make_layout(int64_t n, int32_t d, int32_t metric, int32_t sdt, Layou
   if (sdt == PECANN_U8 && metric != PECANN_L2) return false;
   const size_t bytes = sdt == PECANN_F32 ? 4 : sdt == PECANN_BF16 ? 2 : 1;
   L->off_xs = 0;
-  L->xs_stride = up((size_t)d * bytes, 16);
+  // BF16 / FP8 rows end on a whole matrix-core step of the search's scoring
+  // (32 BF16 or 128 FP8 values), zero padded, so its loads need no bounds
+  L->xs_stride = up((size_t)d * bytes, sdt == PECANN_BF16 ? 64 : sdt == PECANN_FP8E4M3 ? 128 : 16);
   size_t off = up(L->xs_stride * (size_t)n, 256);
   L->has_xr = (sdt == PECANN_BF16 || sdt == PECANN_FP8E4M3);
   L->xr_stride = up((size_t)d, 4);
@@ -329,6 +331,17 @@ struct Carver {
 // 4096 slots 196 ms, 2048 223 ms; 128-d BF16 rows, L = 128: 4096 496 ms, 2048
 // 453 ms; 1024-d FP8, L = 200: 4096 and 2048 within 2 %.  The kNN search of
 // the 128-d BF16 rows (L = 64) was faster with 2048 slots than with 1024.
+// Where the searches score BF16 / FP8 candidates, unless the tuning says
+// otherwise: the matrix cores for FP8 rows of 512 bytes or more, whose decode
+// dominates on the vector units (1.28M x 1024 FP8 build search: 2,240 ->
+// 1,945 ms per step); the vector units for BF16 rows, which unpack with a
+// shift (1M x 128: 408 vs 424 ms; 64 instances x 384-d: 1,086 vs 1,407 ms).
+static int use_mfma(int32_t sdt, size_t row_bytes) {
+  if (sdt != PECANN_BF16 && sdt != PECANN_FP8E4M3) return 0;
+  if (g_tuning.scorer != 0) return g_tuning.scorer == 2;
+  return sdt == PECANN_FP8E4M3 && row_bytes >= 512;
+}
+
 static int hash_bits_for(int L, size_t row_bytes, bool build) {
   const int forced = build ? g_tuning.hash_bits_build : g_tuning.hash_bits_search;
   if (forced > 0) return forced;
@@ -666,6 +679,7 @@ static pecann_status build_impl(const pecann_dataset *ds, const pecann_build_par
   sp.items = w.items;
   sp.L = bp->L;
   sp.hbits = hash_bits_for(bp->L, L.xs_stride, true);
+  sp.mfma = use_mfma(ds->search_dtype, L.xs_stride);
   sp.mode = MODE_BUILD;
   sp.vis = w.vis;
   sp.vis_count = w.vis_count;
@@ -1184,6 +1198,7 @@ static pecann_status knn_impl(const pecann_dataset *ds, const InstSpec &spec, co
   sp.inst = itab;
   sp.L = L_search;
   sp.hbits = hash_bits_for(L_search, L.xs_stride, false);
+  sp.mfma = use_mfma(ds->search_dtype, L.xs_stride);
   sp.mode = MODE_KNN;
   sp.rerank = rerank;
   sp.k = k;
@@ -1354,6 +1369,7 @@ static pecann_status dep_impl(const pecann_dataset *ds, const InstSpec &spec, co
       sp.inst = itab;
       sp.L = (int32_t)std::max<int64_t>(kd, L_search);
       sp.hbits = hash_bits_for(sp.L, L.xs_stride, false);
+      sp.mfma = use_mfma(ds->search_dtype, L.xs_stride);
       sp.mode = MODE_DEP;
       sp.rerank = (int32_t)kd;
       sp.kdep = (int32_t)kd;

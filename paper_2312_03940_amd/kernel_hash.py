@@ -5,7 +5,8 @@ import hashlib
 import os
 
 _CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
-SEARCH_SOURCES = ("device_common.hpp", "beam.hpp", "kernels.hpp", "search.hip")
+SEARCH_SOURCES = ("device_common.hpp", "beam.hpp", "kernels.hpp", "tiles.hpp", "mfma_score.hpp",
+                  "search_impl.hpp", "search.hip", "search_mfma.hip")
 
 
 def search_kernel_hash() -> str:

@@ -33,7 +33,8 @@ def test_tuning_does_not_change_results(sdt):
         ref = None
         for hb, hs, g in SETTINGS:
             pecann.set_tuning(hb, hs, g)
-            assert pecann.get_tuning() == {"hash_bits_build": hb, "hash_bits_search": hs, "grid_per_cu": g}
+            assert pecann.get_tuning() == {"hash_bits_build": hb, "hash_bits_search": hs, "grid_per_cu": g,
+                                           "scorer": 0}
             got = _step(ds, perm, 8)
             if ref is None:
                 ref = got
@@ -52,7 +53,7 @@ def test_autotune_picks_applies_and_caches(tmp_path):
     try:
         e = autotune.tune(ds, 24, 48, 1.2, 8, 48, path=path)
         assert not e["cached"]
-        chosen = {kk: e[kk] for kk in ("hash_bits_build", "hash_bits_search", "grid_per_cu")}
+        chosen = {kk: e[kk] for kk in ("hash_bits_build", "hash_bits_search", "grid_per_cu", "scorer")}
         assert pecann.get_tuning() == chosen
         assert e["build_ms"] <= e["rule_build_ms"] and e["knn_ms"] > 0
         stored = json.load(open(path))
