@@ -415,6 +415,26 @@ pecann_status pecann_cluster_batched(int64_t n, const pecann_instances *inst, co
                                      void *ws, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * pecann_cluster for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same computation and outputs as pecann_cluster, with no workspace
+ * argument.  Its scratch (8 bytes per point and a few hundred bytes more) is a
+ * fixed device array inside the library, one copy per GPU, held until the
+ * process ends; the call itself allocates nothing.
+ *   n        1 <= n <= 2,097,152 (2^21, the array's capacity); larger n
+ *            returns PECANN_EINVAL
+ *   others   as pecann_cluster (device pointers, asynchronous on stream)
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (other streams, other host threads) race and give undefined outputs; calls
+ * ordered on one stream are safe.  What must start at zero is cleared by each
+ * call with a kernel (no memset node under capture).
+ * ------------------------------------------------------------------------- */
+pecann_status pecann_cluster_noalloc(int64_t n, const float *rho, const int32_t *dep,
+                                     const float *delta, int32_t center_mode, int32_t n_c,
+                                     float delta_min, float rho_min, int32_t *labels,
+                                     uint8_t *is_center, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Other density functions (Sec. 4.2: normalized; appendix A: exp-sum, sum-exp,
  * sum; see pecann_density_fn) and the local center function (appendix A).
  *

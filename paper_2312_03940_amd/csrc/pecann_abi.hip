@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "kernels.hpp"
@@ -1526,6 +1527,78 @@ extern "C" pecann_status pecann_cluster_batched(int64_t n, const pecann_instance
   if (st != PECANN_OK) return st;
   return cluster_impl(n, sp, rho, dep, delta, center_mode, delta_min, rho_min, labels, is_center, ws,
                       ws_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------
+// pecann_cluster without a workspace argument.  Its scratch (the gamma keys,
+// the pointer-jumping flag, a one-instance table) lives in a file-scope
+// device array: every GPU the library runs on holds its own copy until the
+// process ends.  The array's name is a host-side stand-in in host code, so the
+// device address is looked up once per device and only that address is used.
+// ---------------------------------------------------------------------------
+static constexpr int64_t kNoAllocMaxN = (int64_t)1 << 21;
+static constexpr size_t kScratchBytes = (size_t)kNoAllocMaxN * 8 + 4096;
+static constexpr int kMaxDevices = 64;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static pecann_status scratch_of_current_device(void **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(PECANN_EUNSUPPORTED, "device %d is beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(PECANN_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PECANN_OK;
+}
+
+extern "C" pecann_status pecann_cluster_noalloc(int64_t n, const float *rho, const int32_t *dep,
+                                                const float *delta, int32_t center_mode, int32_t n_c,
+                                                float delta_min, float rho_min, int32_t *labels,
+                                                uint8_t *is_center, void *stream) {
+  clear_stale_error();
+  if (n < 1 || n > kNoAllocMaxN)
+    return fail(PECANN_EINVAL, "n must be in [1, %lld] (the no-allocation entry point's fixed scratch)",
+                (long long)kNoAllocMaxN);
+  if (!rho || !dep || !delta || !labels || !is_center) return fail(PECANN_EINVAL, "pointer is NULL");
+  if (center_mode != PECANN_CENTER_PRODUCT && center_mode != PECANN_CENTER_THRESHOLD &&
+      center_mode != PECANN_CENTER_GIVEN)
+    return fail(PECANN_EINVAL, "center_mode");
+  if (center_mode == PECANN_CENTER_PRODUCT && (n_c < 1 || n_c > n))
+    return fail(PECANN_EINVAL, "n_c must be in [1, n]");
+  void *base = nullptr;
+  pecann_status st = scratch_of_current_device(&base);
+  if (st != PECANN_OK) return st;
+  Carver c(base);
+  uint64_t *gkey = c.take<uint64_t>((size_t)n);
+  int32_t *flag = c.take<int32_t>(64);
+  InstDev d;
+  carve_inst(c, 1, &d);
+  if (c.size() > kScratchBytes) return fail(PECANN_EWORKSPACE, "scratch layout exceeds the array");
+  hipStream_t s = (hipStream_t)stream;
+  // the table of one instance goes through kernel arguments (no host buffer)
+  I64Chunk off;
+  off.v[0] = 0;
+  off.v[1] = n;
+  I32Chunk kk, nc;
+  kk.v[0] = 1;
+  nc.v[0] = n_c;
+  HIP_TRY(launch_fill_i32(flag, 0, 1, s));  // left set by the last call
+  HIP_TRY(launch_put_i64(off, 2, d.off, s));
+  HIP_TRY(launch_put_i32(kk, 1, d.k, s));
+  HIP_TRY(launch_put_i32(nc, 1, d.nc, s));
+  HIP_TRY(launch_cluster(n, table_of(d, 1), rho, dep, delta, center_mode, delta_min, rho_min, labels,
+                         is_center, gkey, flag, s));
+  return PECANN_OK;
 }
 
 // ---------------------------------------------------------------------------

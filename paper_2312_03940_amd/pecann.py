@@ -150,6 +150,7 @@ def load():
         "pecann_set_tuning": (ctypes.c_int, [ctypes.POINTER(_Tuning)]),
         "pecann_get_tuning": (ctypes.c_int, [ctypes.POINTER(_Tuning)]),
         "pecann_read_probe": (ctypes.c_int, [vp, sz, i32, ctypes.c_uint32, vp, vp]),
+        "pecann_cluster_noalloc": (ctypes.c_int, [i64, vp, vp, vp, i32, i32, f32, f32, vp, vp, vp]),
         "pecann_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "pecann_last_error": (ctypes.c_char_p, []),
     }
@@ -591,3 +592,21 @@ def read_probe(buf: torch.Tensor, passes: int = 1, sink: torch.Tensor | None = N
     _check(lib.pecann_read_probe(_ptr(buf), nbytes - nbytes % 16, passes, 0x5bd1e995, _ptr(sink),
                                  _stream()))
     return sink
+
+
+def cluster_noalloc(rho, dep, delta, n_c: int = 1, center_mode: int | None = None,
+                    delta_min: float = 0.0, rho_min: float = 0.0, out=None):
+    """pecann_cluster through the entry point that allocates nothing (its scratch
+    is the library's fixed device array; n <= 2^21).  out: (labels, is_center),
+    preallocated by a caller that cannot allocate.  -> (labels, is_center)."""
+    lib = load()
+    _need_cuda(rho, dep, delta)
+    n = rho.numel()
+    mode = CENTER_PRODUCT if center_mode is None else center_mode
+    if out is None:
+        out = (torch.empty(n, dtype=torch.int32, device=rho.device),
+               torch.empty(n, dtype=torch.uint8, device=rho.device))
+    labels, isc = out
+    _check(lib.pecann_cluster_noalloc(n, _ptr(rho), _ptr(dep), _ptr(delta), mode, n_c, delta_min, rho_min,
+                                      _ptr(labels), _ptr(isc), _stream()))
+    return labels, isc
