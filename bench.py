@@ -553,8 +553,40 @@ def roofline(pl, kprof, steps, search, n, d, k):
                            "per_query": {"expansions": kc[0] / n, "ids_read": kc[1] / n,
                                          "rows_gathered": kc[2] / n, "rows_rescored": kc[3] / n}},
             "build_work": {"search_expansions": int(bc[0]), "search_rows": int(bc[2]),
+                           "searches_capped": int(bc[3]),
                            "forward_prune_rows": int(bc[4]), "reverse_prune_rows": int(bc[5]),
-                           "targets_pruned": int(bc[6]), "targets_appended": int(bc[7])}}
+                           "targets_pruned": int(bc[6]), "targets_appended": int(bc[7])},
+            "prunes": prune_roofline(bc, fam_ms, fam_l, search, d)}
+
+
+# Dense matrix-core peaks of MI355X (AMD's published figures, no sparsity) for the
+# tiles' operand types, TFLOP/s (TOP/s for int8).
+MFMA_PEAK = {"f32": 157.3, "u8": 5000.0, "bf16": 2500.0, "fp8": 5000.0}
+
+
+def prune_roofline(bc, fam_ms, fam_l, search, d):
+    """RobustPrune kernels: their 16 x 16 distance tiles on the matrix cores.
+    Work per launch from the build counters ([4] forward, [5] reverse: row
+    reads, 32 per tile): tiles x 16 x 16 x d multiply-adds, and the rows the
+    tiles read (L2-resident gathers: a batch's candidates are few).  Both are
+    reported against the launch's average HIP-event time."""
+    row_bytes = {"f32": 4 * d, "u8": d, "bf16": 2 * d, "fp8": d}[search]
+    out = {}
+    for fam, rows in (("prune_forward", bc[4]), ("prune_reverse", bc[5])):
+        if fam not in fam_ms or not fam_l.get(fam):
+            continue
+        launches = fam_l[fam]
+        avg_s = fam_ms[fam] / launches * 1e-3
+        tiles = rows / 32.0 / launches
+        flop = tiles * 16 * 16 * d * 2
+        tflops = flop / avg_s / 1e12
+        out[fam] = {"launches_per_step": launches, "avg_launch_ms": round(avg_s * 1e3, 4),
+                    "tiles_per_launch": int(tiles), "matrix_flop_per_launch": int(flop),
+                    "achieved_TFLOPs": round(tflops, 2), "peak_TFLOPs": MFMA_PEAK[search],
+                    "frac_of_matrix_peak": round(tflops / MFMA_PEAK[search], 4),
+                    "tile_row_bytes_per_launch": int(rows / launches * row_bytes),
+                    "tile_row_GBps": round(rows / launches * row_bytes / avg_s / 1e9, 1)}
+    return out
 
 
 def main():
@@ -694,26 +726,37 @@ def main():
         pecann.reset_tuning()  # variants run with the library's rules
     if not args.no_variants:
         variants = {}
+        # (row format, mode, index[, argument overrides]); "paper_batches": the
+        # paper's batch cap of 0.02 n (Sec. 4.1 footnote) where the library's
+        # default raises it to 8,192 concurrent searches (n < 409,600)
+        paper_cap = {"max_batch": max(1, n // 50)}
         alt = {2: [("u8", "anns", "vamana"), ("u8", "exact", "vamana"), ("f32", "exact", "vamana"),
-                   ("f32", "anns", "nndescent")],
+                   ("f32", "anns", "nndescent"), ("f32", "anns", "vamana", paper_cap)],
                3: [("f32", "anns", "vamana"), ("bf16", "anns", "nndescent")],
                4: [("f32", "anns", "vamana")], 5: [("f32", "anns", "vamana")]}[args.config]
-        for vs, vm, vi in alt:
-            if (vs, vm, vi) == (search, args.mode, "vamana") or (args.nnd_only and vi != "nndescent"):
+        for var in alt:
+            vs, vm, vi = var[:3]
+            over = var[3] if len(var) > 3 else None
+            if over is None and (vs, vm, vi) == (search, args.mode, "vamana"):
                 continue
+            if args.nnd_only and vi != "nndescent":
+                continue
+            vargs = argparse.Namespace(**{**vars(args), **(over or {})})
             vsteps = args.variant_steps or (3 if args.config == 2 else 1)
             # variants get the same beam-width tuning as the headline (not the
             # launch-setting sweep, which would rebuild the graph many times)
             # (Vamana graphs only: on the NN-descent graph a wide search is a poor
             # stand-in for the exact neighbours, so that variant keeps the
             # workload's beam)
-            r, p2, _ = measure(x, wl, vs, vm, args, perm, vsteps, 1, ref_lab, sample, inst, vi,
+            r, p2, _ = measure(x, wl, vs, vm, vargs, perm, vsteps, 1, ref_lab, sample, inst, vi,
                                beam=args.autotune and vm == "anns" and vi == "vamana")
-            name = f"{vs}_{vm}" + ("" if vi == "vamana" else f"_{vi}")
+            name = f"{vs}_{vm}" + ("" if vi == "vamana" else f"_{vi}") + ("_paper_batches" if over else "")
             variants[name] = {key: r[key] for key in ("value", "ms_per_step", "phases_ms",
                                                       "quality", "knn_queries_per_s")}
             if "tuning" in r:
                 variants[name]["L_search"] = r["tuning"]["L_search"]
+            if over:
+                variants[name]["max_batch"] = over["max_batch"]
             if vi == "nndescent":
                 variants[name]["index"] = {"kind": "NN-descent", **NND, "R": wl["R"], "alpha": wl["alpha"],
                                            "rounds_run": p2.nnd_out[2].cpu().tolist(),

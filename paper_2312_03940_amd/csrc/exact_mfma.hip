@@ -1,16 +1,20 @@
 // Exact kNN on the matrix cores (the BruteForce index of Sec. 4.1 at scale).
 //
 // scan:   a workgroup of 4 wavefronts takes 64 queries (16 per wavefront) and
-//         streams every point past them in blocks of 64 candidates.  Candidate
-//         rows are staged through LDS four 64-byte steps at a time; each
-//         wavefront forms a 16 x 64 block of dot products on the matrix cores
-//         (f32 16x16x4, or i8 16x16x64 on uint8 rows shifted to x - 128, which
-//         is exact) and turns them into distance measures with the stored row
-//         norms.  Every lane keeps, for each of its 4 query rows, the 16 smallest
-//         (measure, index) pairs of its column stream in registers.
-// rerank: one wavefront per query re-scores the 256 kept candidates by direct
-//         differences -- the same float32 arithmetic as the brute-force kernel
-//         -- and keeps the k best.  A candidate the scan dropped had a
+//         streams every point past them in blocks of 64 candidates, each block
+//         in rounds of kSPB 64-byte steps.  A round's candidate chunks are
+//         staged through a double-buffered LDS tile; the loads of the next
+//         round (candidate chunks, the wavefront's query chunks, the block's
+//         norms) are issued before the products of the current one, so the
+//         memory latency of a round hides behind the matrix work of the one
+//         before.  Each wavefront forms a 16 x 64 block of dot products (f32
+//         16x16x4, or i8 16x16x64 on uint8 rows shifted to x - 128, which is
+//         exact) and turns them into distance measures with the stored row
+//         norms.  Every lane keeps, for each of its 4 query rows, the kKQ
+//         smallest (measure, index) pairs of its column stream in registers.
+// rerank: one wavefront per query re-scores the 16 kKQ kept candidates by
+//         direct differences -- the same float32 arithmetic as the brute-force
+//         kernel -- and keeps the k best.  A candidate the scan dropped had a
 //         matrix-core measure >= thr (the smallest value any queue dropped), so
 //         its exact measure is >= thr - E, with E a bound on the rounding of
 //         |a|^2 + |b|^2 - 2 a.b; if the k-th re-scored measure is < thr - E the
@@ -26,9 +30,14 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kQT = 64;   // queries per workgroup
 constexpr int kCT = 64;   // candidates per block
-constexpr int kKQ = 16;   // queue length per lane and query row
-constexpr int kSPB = 4;   // 64-byte steps staged per barrier
-constexpr int kCand = 16 * kKQ;
+// queue length per lane and query row: 8 for float32 rows, 4 for uint8 rows,
+// whose measures are exact integers (a dropped threshold far below the 16 x 8
+// kept candidates cannot fail the exactness check by rounding); the inserts of
+// a wave are divergent, so a shorter queue is also a cheaper one
+template <int SDT>
+constexpr int kq_of() { return SDT == PECANN_U8 ? 4 : kExactCand / 16; }
+constexpr int kSPB = 4;   // 64-byte steps per round
+constexpr int kCand = kExactCand;
 
 struct ScanRows {
   const uint8_t *rows;
@@ -46,82 +55,118 @@ __device__ __forceinline__ uint4 shift_u8(uint4 v) {
   return v;
 }
 
+// The global loads of one round: this thread's candidate chunks (row
+// tid / 4, chunks tid % 4 + 4 step), its lane's query chunks (row of A: the
+// lane's query, chunks g + 4 step) and, with a block's first round, the norm
+// of candidate tid.  Loads are not guarded by branches (indices are clamped;
+// chunks past the row are zeroed after all loads are out), so they issue back
+// to back.
 template <int SDT>
-__global__ __launch_bounds__(256) void exact_scan_kernel(ScanRows sr, int32_t n, int32_t metric,
+struct Round {
+  uint4 b[kSPB], a[kSPB];
+  uint32_t nrm;
+  __device__ __forceinline__ void load(const ScanRows &sr, int32_t n, int tid, int g, int qa, int cb,
+                                       int step0, bool first) {
+    const int br = min(cb + (tid >> 2), n - 1);
+    const uint8_t *pb = sr.rows + (int64_t)br * sr.stride;
+    const uint8_t *pa = sr.rows + (int64_t)min(qa, n - 1) * sr.stride;
+    int cbq[kSPB], caq[kSPB];
+#pragma unroll
+    for (int u = 0; u < kSPB; ++u) {
+      cbq[u] = (tid & 3) + 4 * (step0 + u);
+      caq[u] = g + 4 * (step0 + u);
+      b[u] = *(const uint4 *)(pb + 16 * min(cbq[u], sr.nch - 1));
+      a[u] = *(const uint4 *)(pa + 16 * min(caq[u], sr.nch - 1));
+    }
+    nrm = (first && tid < kCT) ? sr.norms[min(cb + tid, n - 1)] : 0u;
+    // uint8 rows are shifted to signed first; chunks past the row are zero
+    // after the shift (they add nothing to a dot product)
+#pragma unroll
+    for (int u = 0; u < kSPB; ++u) {
+      if (SDT == PECANN_U8) {
+        b[u] = shift_u8(b[u]);
+        a[u] = shift_u8(a[u]);
+      }
+      if (cbq[u] >= sr.nch) b[u] = make_uint4(0, 0, 0, 0);
+      if (caq[u] >= sr.nch) a[u] = make_uint4(0, 0, 0, 0);
+    }
+  }
+};
+
+template <int SDT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void exact_scan_kernel(ScanRows sr, int32_t n, int32_t metric,
                                                          int32_t *cand, float *thr) {
-  __shared__ uint4 bs[kCT][4 * kSPB + 1];
-  __shared__ uint32_t bn[kCT];
+  __shared__ uint4 bs[2][kCT][4 * kSPB + 1];
+  __shared__ uint32_t bn[2][kCT];
+  constexpr int kKQ = kq_of<SDT>();
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, c16 = l & 15;
   const int q0 = blockIdx.x * kQT + 16 * w;  // this wavefront's first query
   const int qa = q0 + c16;                    // the query row this lane feeds as A
   const int steps = (sr.nch + 3) >> 2;
-  const uint8_t *pa = sr.rows + (int64_t)(qa < n ? qa : 0) * sr.stride;
+  const int rpb = (steps + kSPB - 1) / kSPB;  // rounds per block
+  const int total = ((n + kCT - 1) / kCT) * rpb;
 
   float qd[4][kKQ];
   int qi[4][kKQ];
+  float qlo[4];  // smallest measure this lane's queue of row r has dropped
   float nq[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int q = q0 + 4 * g + r;
+    qlo[r] = __int_as_float(0x7f800000);
     nq[r] = 0.f;
     if (q < n) nq[r] = SDT == PECANN_U8 ? (float)(int)sr.norms[q] : __uint_as_float(sr.norms[q]);
 #pragma unroll
     for (int s = 0; s < kKQ; ++s) { qd[r][s] = __int_as_float(0x7f800000); qi[r][s] = -1; }
   }
 
-  for (int cb = 0; cb < n; cb += kCT) {
-    if (tid < kCT) bn[tid] = (cb + tid < n) ? sr.norms[cb + tid] : 0u;
-    v4f accf[4];
-    v4i acci[4];
+  v4f accf[4];
+  v4i acci[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) { accf[t] = v4f{0.f, 0.f, 0.f, 0.f}; acci[t] = v4i{0, 0, 0, 0}; }
-    const int br = cb + (tid >> 2);  // candidate row this thread stages
-    const uint8_t *pb = sr.rows + (int64_t)(br < n ? br : 0) * sr.stride;
-    for (int s0 = 0; s0 < steps; s0 += kSPB) {
-      uint4 bv[kSPB], av[kSPB];
+  for (int t = 0; t < 4; ++t) { accf[t] = v4f{0.f, 0.f, 0.f, 0.f}; acci[t] = v4i{0, 0, 0, 0}; }
+  Round<SDT> nxt;
+  nxt.load(sr, n, tid, g, qa, 0, 0, true);
+  for (int rd = 0; rd < total; ++rd) {
+    const int blk = rd / rpb, rr = rd - blk * rpb, buf = rd & 1;
+    // stage this round (its loads were issued during the previous round)
 #pragma unroll
-      for (int u = 0; u < kSPB; ++u) {
-        const int bq = (tid & 3) + 4 * (s0 + u);
-        bv[u] = make_uint4(0, 0, 0, 0);
-        if (br < n && bq < sr.nch) {
-          bv[u] = *(const uint4 *)(pb + 16 * bq);
-          if (SDT == PECANN_U8) bv[u] = shift_u8(bv[u]);
-        }
-        const int aq = g + 4 * (s0 + u);
-        av[u] = make_uint4(0, 0, 0, 0);
-        if (qa < n && aq < sr.nch) {
-          av[u] = *(const uint4 *)(pa + 16 * aq);
-          if (SDT == PECANN_U8) av[u] = shift_u8(av[u]);
-        }
-      }
-      __syncthreads();  // the previous group's operands have been read
+    for (int u = 0; u < kSPB; ++u) bs[buf][tid >> 2][4 * u + (tid & 3)] = nxt.b[u];
+    if (rr == 0 && tid < kCT) bn[blk & 1][tid] = nxt.nrm;
+    uint4 av[kSPB];
 #pragma unroll
-      for (int u = 0; u < kSPB; ++u) bs[tid >> 2][4 * u + (tid & 3)] = bv[u];
-      __syncthreads();
+    for (int u = 0; u < kSPB; ++u) av[u] = nxt.a[u];
+    // one barrier per round: the tile written now was last read in round
+    // rd - 2, and every wavefront has passed this barrier's predecessor since
+    __syncthreads();
+    if (rd + 1 < total) {
+      const int nb = (rd + 1) / rpb, nr = rd + 1 - nb * rpb;
+      nxt.load(sr, n, tid, g, qa, nb * kCT, nr * kSPB, nr == 0);
+    }
 #pragma unroll
-      for (int u = 0; u < kSPB; ++u) {
-        if (s0 + u >= steps) break;
+    for (int u = 0; u < kSPB; ++u) {
+      if (rr * kSPB + u >= steps) break;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const uint4 b = bs[16 * t + c16][4 * u + g];
-          if (SDT == PECANN_U8) {
-            const v4i ai = {(int)av[u].x, (int)av[u].y, (int)av[u].z, (int)av[u].w};
-            const v4i bi = {(int)b.x, (int)b.y, (int)b.z, (int)b.w};
-            acci[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ai, bi, acci[t], 0, 0, 0);
-          } else {
-            accf[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av[u].x), __uint_as_float(b.x), accf[t], 0, 0, 0);
-            accf[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av[u].y), __uint_as_float(b.y), accf[t], 0, 0, 0);
-            accf[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av[u].z), __uint_as_float(b.z), accf[t], 0, 0, 0);
-            accf[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av[u].w), __uint_as_float(b.w), accf[t], 0, 0, 0);
-          }
+      for (int t = 0; t < 4; ++t) {
+        const uint4 b = bs[buf][16 * t + c16][4 * u + g];
+        if (SDT == PECANN_U8) {
+          const v4i ai = {(int)av[u].x, (int)av[u].y, (int)av[u].z, (int)av[u].w};
+          const v4i bi = {(int)b.x, (int)b.y, (int)b.z, (int)b.w};
+          acci[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ai, bi, acci[t], 0, 0, 0);
+        } else {
+          accf[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av[u].x), __uint_as_float(b.x), accf[t], 0, 0, 0);
+          accf[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av[u].y), __uint_as_float(b.y), accf[t], 0, 0, 0);
+          accf[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av[u].z), __uint_as_float(b.z), accf[t], 0, 0, 0);
+          accf[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(av[u].w), __uint_as_float(b.w), accf[t], 0, 0, 0);
         }
       }
     }
-    // epilogue: measures of this block into the lane's queues
+    if (rr != rpb - 1) continue;
+    // the block's last round: its measures into the lane's queues
+    const int cb = blk * kCT;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int col = cb + 16 * t + c16;
-      const uint32_t nbits = bn[16 * t + c16];
+      const uint32_t nbits = bn[blk & 1][16 * t + c16];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int q = q0 + 4 * g + r;
@@ -135,7 +180,10 @@ __global__ __launch_bounds__(256) void exact_scan_kernel(ScanRows sr, int32_t n,
         } else {
           m = fmaxf(0.f, 1.0f - accf[t][r]);
         }
-        if (kv_less(m, col, qd[r][kKQ - 1], qi[r][kKQ - 1])) {
+        if (!kv_less(m, col, qd[r][kKQ - 1], qi[r][kKQ - 1])) {
+          qlo[r] = fminf(qlo[r], m);  // rejected
+        } else {
+          qlo[r] = fminf(qlo[r], qd[r][kKQ - 1]);  // the entry it evicts (+inf: none)
           float cd = m;
           int ci = col;
 #pragma unroll
@@ -151,14 +199,16 @@ __global__ __launch_bounds__(256) void exact_scan_kernel(ScanRows sr, int32_t n,
         }
       }
     }
-    __syncthreads();  // bn is rewritten by the next block
+#pragma unroll
+    for (int t = 0; t < 4; ++t) { accf[t] = v4f{0.f, 0.f, 0.f, 0.f}; acci[t] = v4i{0, 0, 0, 0}; }
   }
 
   // queues out; thr = smallest measure any of the 16 lanes of a row dropped
+  // (a lane that kept all of a query's best candidates dropped none of them)
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int q = q0 + 4 * g + r;
-    float last = qd[r][kKQ - 1];
+    float last = qlo[r];
 #pragma unroll
     for (int m = 8; m >= 1; m >>= 1) last = fminf(last, __shfl_xor(last, m));
     if (q < n) {
@@ -211,7 +261,8 @@ __global__ __launch_bounds__(64) void exact_rerank_kernel(ExactMfmaParams p, flo
     top.reset();
     wave_lds_sync();
     const int32_t *c = p.cand + (int64_t)q * kCand;
-    for (int base = 0; base < kCand; base += kWave) {
+    constexpr int kKept = 16 * kq_of<DT == PECANN_U8 ? PECANN_U8 : PECANN_F32>();
+    for (int base = 0; base < kKept; base += kWave) {
       score_keys(eng, p.rows, kWave, [&](int i) { return c[base + i]; }, kb);
       wave_lds_sync();
       const uint64_t key = kb[l];
@@ -299,12 +350,13 @@ hipError_t launch_exact_mfma(int32_t dt, int S, const ExactMfmaParams &p, hipStr
   // at most gamma_d of its magnitudes, the direct sum gamma_d of D^2 <= 2
   // (|a|^2 + |b|^2), plus the final additions: E <= 4 (d + 4) u (|a|^2 + |b|^2),
   // u = 2^-24, and |b|^2 <= the largest row norm.  Cosine rows are unit:
-  // E <= 4 (d + 4) u * 2.  uint8 rows: both measures are exact integers,
-  // each rounded once to float32, so E <= 2 u * d * 255^2.
+  // E <= 4 (d + 4) u * 2.  uint8 rows: both measures are the same exact
+  // integer sum of squared differences, rounded once to float32 the same way,
+  // so E = 0.
   const float u = 5.9604645e-8f;
   const float dd = (float)r.d;
   float ce;
-  if (u8) ce = 2.0f * u * dd * 65025.0f;
+  if (u8) ce = 0.0f;
   else if (r.metric == PECANN_L2) ce = 4.0f * (dd + 4.0f) * u;
   else ce = 8.0f * (dd + 4.0f) * u;
   const int grid = (int)std::min<int64_t>((int64_t)p.n, 256 * 32);

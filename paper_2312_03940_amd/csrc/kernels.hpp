@@ -114,9 +114,22 @@ struct BfKnnParams {
   float *knn_dist;
   float *rho;
   uint64_t *rank_key;
+  int32_t item_from;          // bf_knn takes items [item_from, count)
+  // split path (launch_bf_knn_split): items [0, min(count, split_cap)), each
+  // scanned as nchunk chunks of `chunk` candidates by separate wavefronts; a
+  // chunk's kpart best keys go to part[item][chunk][0 .. kpart), then one
+  // wavefront per item merges them
+  uint64_t *part;
+  int32_t split_cap;
+  int32_t nchunk;
+  int32_t chunk;
+  int32_t kpart;
+  int32_t *head2;             // work queue of the merge
 };
 size_t bf_knn_lds_bytes(int k);
 hipError_t launch_bf_knn(int32_t dt, int S, const BfKnnParams &p, int grid, hipStream_t s);
+hipError_t launch_bf_knn_split(int32_t dt, int S, const BfKnnParams &p, int grid_chunks, int grid_merge,
+                               hipStream_t s);
 
 // Exact dependent point for a list of unfinished points: chunked argmin over
 // the points of strictly smaller rank key.
@@ -245,13 +258,16 @@ hipError_t launch_prepare(const void *x, int32_t x_dtype, int64_t x_stride, int6
 // Exact kNN on the matrix cores: a scan that keeps, per query, the 16 best
 // candidates of each lane's column stream by matrix-core distance, then an
 // exact (direct-difference) re-score with a rounding-bound check.
+// candidates the exact matrix-core scan keeps per query (16 lanes x 8)
+constexpr int kExactCand = 128;
+
 struct ExactMfmaParams {
   RowsDesc rows;              // one instance's rows (row 0 = global index base)
   int32_t n;
   int32_t k;
   int32_t kstride;            // row stride of knn_idx / knn_dist
   int32_t base;               // global index of row 0
-  int32_t *cand;               // [n][256] candidate ids of the scan
+  int32_t *cand;               // [n][kExactCand] candidate ids of the scan
   float *thr;                  // [n] smallest measure a scan queue dropped (+inf: none)
   float *nmax;                 // [1] largest row norm (device)
   int32_t *head;

@@ -1048,19 +1048,29 @@ static constexpr int64_t kExactMfmaMin = 4096;
 struct KnnWs {
   int32_t *ctr, *fb, *cand;
   float *thr, *nmax;
+  uint64_t *part;  // exact mode: chunk-local best keys of the split brute force
   InstDev inst;
 };
+// Exact brute force of the queries the matrix-core scan does not settle (and of
+// every query of a small instance): the first kSplitCap of them are scanned
+// in chunks of kSplitChunk candidates by separate wavefronts and merged; any
+// beyond take one wavefront each.
+static constexpr int kSplitCap = 2048;
+static constexpr int kSplitChunk = 4096;
+static int split_chunks(int64_t max_size) { return (int)((max_size + kSplitChunk - 1) / kSplitChunk); }
 static bool any_large(const InstSpec &sp) {
   for (int t = 0; t < sp.count(); ++t)
     if (sp.size(t) >= kExactMfmaMin) return true;
   return false;
 }
-static void carve_knn(Carver &c, int64_t n, bool exact_mfma, int ninst, KnnWs *w) {
+static void carve_knn(Carver &c, int64_t n, bool exact, bool exact_mfma, int ninst, int64_t max_size,
+                      int32_t k, KnnWs *w) {
   w->ctr = c.take<int32_t>(64);
   w->fb = c.take<int32_t>((size_t)n);
   w->nmax = c.take<float>(64);
-  w->cand = exact_mfma ? c.take<int32_t>((size_t)n * 256) : nullptr;
+  w->cand = exact_mfma ? c.take<int32_t>((size_t)n * kExactCand) : nullptr;
   w->thr = exact_mfma ? c.take<float>((size_t)n) : nullptr;
+  w->part = exact ? c.take<uint64_t>((size_t)kSplitCap * split_chunks(max_size) * k) : nullptr;
   carve_inst(c, ninst, &w->inst);
 }
 
@@ -1068,10 +1078,11 @@ extern "C" size_t pecann_knn_density_workspace_size(const pecann_dataset *ds, in
                                                     int32_t L_search, int32_t exact) {
   Layout L;
   if (check_dataset(ds, &L) != PECANN_OK) return 0;
-  (void)k; (void)L_search;
+  (void)L_search;
+  if (k < 1 || k > 64) return 0;
   Carver c(nullptr);
   KnnWs w;
-  carve_knn(c, ds->n, exact != 0 && ds->n >= kExactMfmaMin, 1, &w);
+  carve_knn(c, ds->n, exact != 0, exact != 0 && ds->n >= kExactMfmaMin, 1, ds->n, k, &w);
   return c.size();
 }
 
@@ -1085,7 +1096,7 @@ extern "C" size_t pecann_knn_density_batched_workspace_size(const pecann_dataset
   (void)L_search;
   Carver c(nullptr);
   KnnWs w;
-  carve_knn(c, ds->n, exact != 0 && any_large(sp), sp.count(), &w);
+  carve_knn(c, ds->n, exact != 0, exact != 0 && any_large(sp), sp.count(), sp.max_size(), k_max, &w);
   return c.size();
 }
 
@@ -1122,17 +1133,17 @@ static pecann_status knn_impl(const pecann_dataset *ds, const InstSpec &spec, co
   const bool exact_mfma = !adj && any_large(spec);
   Carver c0(nullptr);
   KnnWs w;
-  carve_knn(c0, n, exact_mfma, I, &w);
+  carve_knn(c0, n, !adj, exact_mfma, I, spec.max_size(), k, &w);
   if (!ws || ws_bytes < c0.size() || !aligned(ws, 256))
     return fail(PECANN_EWORKSPACE, "workspace needs %zu bytes (256-aligned), got %zu", c0.size(), ws_bytes);
   Carver c(ws);
-  carve_knn(c, n, exact_mfma, I, &w);
+  carve_knn(c, n, !adj, exact_mfma, I, spec.max_size(), k, &w);
   int32_t *ctr = w.ctr, *fb = w.fb;
   hipStream_t s = (hipStream_t)stream;
   const RowsDesc rows = rows_of(ds, L);
   const int dt = ds->search_dtype;
   const int S = engine_shape(dt, ds->d);
-  HIP_TRY(launch_fill_i32(ctr, 0, 4, s));
+  HIP_TRY(launch_fill_i32(ctr, 0, 8, s));
   HIP_TRY(upload_inst(spec, w.inst, s));
   const InstTable itab = table_of(w.inst, I);
 
@@ -1165,7 +1176,7 @@ static pecann_status knn_impl(const pecann_dataset *ds, const InstSpec &spec, co
       ep.k = spec.k[t];
       ep.kstride = k;
       ep.base = (int32_t)lo;
-      ep.cand = w.cand + lo * 256;
+      ep.cand = w.cand + lo * kExactCand;
       ep.thr = w.thr + lo;
       ep.nmax = w.nmax;
       ep.head = ctr + 0;
@@ -1181,6 +1192,17 @@ static pecann_status knn_impl(const pecann_dataset *ds, const InstSpec &spec, co
     }
     HIP_TRY(launch_small_instance_points(n, itab, (int32_t)kExactMfmaMin, fb, ctr + 1, s));
     PROF(F_BF_KNN, s);
+    bp.part = w.part;
+    bp.split_cap = kSplitCap;
+    bp.nchunk = split_chunks(spec.max_size());
+    bp.chunk = kSplitChunk;
+    bp.kpart = k;
+    bp.head = ctr + 3;
+    bp.head2 = ctr + 4;
+    HIP_TRY(launch_bf_knn_split(dt, S, bp, persistent_grid((int64_t)kSplitCap * bp.nchunk),
+                                persistent_grid(kSplitCap), s));
+    bp.head = ctr + 2;
+    bp.item_from = kSplitCap;
     HIP_TRY(launch_bf_knn(dt, S, bp, persistent_grid(n), s));
     return PECANN_OK;
   }
