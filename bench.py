@@ -544,7 +544,7 @@ def roofline(pl, kprof, steps, search, n, d, k):
     return {"bound": "hbm", "kernel": kname, "family": fam,
             "dominant_family": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": stored_traffic(f"{fam}@{search}"),
+            "traffic": stored_traffic(f"{fam}@{search}@{n}x{d}"),
             "alg_bytes_per_launch": int(per_launch), "avg_launch_ms": round(avg_ms, 4),
             "launches_per_step": fam_l[fam],
             "knn_launch": {"ms": round(fam_ms.get("search_knn", 0.0), 3),

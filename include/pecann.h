@@ -91,7 +91,10 @@ typedef enum {
  *                type is BF16 or FP8E4M3 (used to re-score candidates so that
  *                every reported distance and every ordering is float32);
  *   row scale    n floats (FP8E4M3 only): row t of the search copy holds
- *                x_t / scale_t with scale_t = max_j |x_tj| / 448;
+ *                x_t / scale_t with scale_t = max_j |x_tj| / 448 for L2, and
+ *                scale_t = 1 / 448 for every row under PECANN_COSINE (unit
+ *                rows: one scale keeps e4m3's relative precision, and the
+ *                searches need not gather a scale per candidate);
  *   row norms    n 32-bit squared norms of the search rows, and for BF16/FP8
  *                also of the float32 rerank rows (used when distances are
  *                formed from matrix-core dot products);

@@ -196,6 +196,16 @@ using Rows = RowsDesc;
 // their measures are exact integers (rounded once to float).  XR = true makes
 // a float32 engine over the rerank rows instead of the search rows.
 // ---------------------------------------------------------------------------
+// Scale of an FP8 search row.  Cosine rows are unit vectors stored as x * 448
+// (e4m3's largest normal) with one scale for all rows: a floating-point code
+// keeps its relative precision under any scale that avoids overflow, and the
+// scorers then read no per-candidate scale (a 4-byte gather that costs a
+// 64-byte line per candidate).  L2 rows keep max|x| / 448 per row.
+constexpr float kFp8UnitInv = 448.0f;
+__device__ __forceinline__ float fp8_row_scale(const Rows &r, int32_t row) {
+  return r.metric == PECANN_COSINE ? 1.0f / kFp8UnitInv : r.scale[row];
+}
+
 constexpr int max_shape(int dt) { return dt == PECANN_F32 ? 1024 : dt == PECANN_BF16 ? 512 : 256; }
 
 // Launch-time dispatch over (row format, shape).  FN<DT, S> is a function
@@ -305,7 +315,7 @@ struct Engine {
       }
     } else {
       const uint8_t *base = r.xs + (int64_t)row * r.xs_stride;
-      const float s = (DT == PECANN_FP8E4M3) ? r.scale[row] : 1.0f;
+      const float s = (DT == PECANN_FP8E4M3) ? fp8_row_scale(r, row) : 1.0f;
 #pragma unroll
       for (int t = 0; t < CPL; ++t) {
         const int c = g + G * t;
@@ -379,7 +389,7 @@ struct Engine {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint8_t *base = row_ptr(r, row[u] < 0 ? 0 : row[u]);
-      sc[u] = (DT == PECANN_FP8E4M3 && !XR && row[u] >= 0) ? r.scale[row[u]] : 1.0f;
+      sc[u] = (DT == PECANN_FP8E4M3 && !XR && row[u] >= 0) ? fp8_row_scale(r, row[u]) : 1.0f;
 #pragma unroll
       for (int t = 0; t < CPL; ++t) {
         const int c = g + G * t;
@@ -405,7 +415,7 @@ struct Engine {
       v[t] = make_uint4(0, 0, 0, 0);
       if (row >= 0 && c < nch) v[t] = *(const uint4 *)(base + 16 * c);
     }
-    const float s = (DT == PECANN_FP8E4M3 && !XR && row >= 0) ? r.scale[row] : 1.0f;
+    const float s = (DT == PECANN_FP8E4M3 && !XR && row >= 0) ? fp8_row_scale(r, row) : 1.0f;
     float part[1] = {partial(v, s, r.metric)};
     return finish(reduce_scatter<G, 1, INT>(part), r.metric);
   }

@@ -173,7 +173,7 @@ struct MfmaScorer {
         uint64_t key = kNoKey;
         if (row >= 0) {
           float dot = acc[0] + acc[1];
-          if (FP8) dot *= qs * r.scale[row];
+          if (FP8) dot *= qs * fp8_row_scale(r, row);
           const float m = r.metric == PECANN_L2 ? fmaxf(0.f, qn + __uint_as_float(r.sqn[row]) - 2.0f * dot)
                                                 : fmaxf(0.f, 1.0f - dot);
           key = make_key(m, row);

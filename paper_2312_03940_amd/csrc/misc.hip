@@ -7,6 +7,8 @@
 //   K11 labels        -- roots of the dependent forest by pointer jumping
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "claim.hpp"
 #include "device_common.hpp"
 
@@ -16,7 +18,8 @@ namespace pecann {
 // K0: one wavefront per row.  Reads the caller's row (F32 or U8), divides by
 // its norm for the cosine metric, writes the float32 rerank row (if any) and
 // the search row: F32 copy, U8 copy, BF16 round-to-nearest-even, or FP8 e4m3
-// of x / scale with scale = max|x| / 448 (OCP e4m3 largest normal).
+// of x / scale with scale = max|x| / 448 (OCP e4m3 largest normal) for L2 and
+// 1 / 448 for the (unit) cosine rows.
 // Padding up to the 16-byte row stride is written as zeros.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
@@ -26,6 +29,9 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
   return (uint16_t)(u >> 16);
 }
 
+// T = values per lane (the row's padded length / 64, rounded up to a power of
+// two); every loop over them is unrolled so the row stays in registers.
+template <int T>
 __global__ __launch_bounds__(256) void prepare_kernel(const void *x, int32_t x_dtype, int64_t x_stride,
                                                       int64_t n, int32_t d, int32_t metric,
                                                       int32_t sdt, RowsDesc r, uint8_t *xs,
@@ -34,7 +40,7 @@ __global__ __launch_bounds__(256) void prepare_kernel(const void *x, int32_t x_d
   const int l = lane_id();
   const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (row >= n) return;
-  constexpr int kMaxPerLane = 64;  // d <= 4096
+  constexpr int kMaxPerLane = T;
   float v[kMaxPerLane];
   float ss = 0.f, mx = 0.f;
 #pragma unroll
@@ -58,6 +64,7 @@ __global__ __launch_bounds__(256) void prepare_kernel(const void *x, int32_t x_d
   if (xr) {
     float *o = xr + row * r.xr_stride;
     float nr = 0.f;
+#pragma unroll
     for (int t = 0; t < kMaxPerLane; ++t) {
       const int e = l + 64 * t;
       if (e < r.xr_stride) {
@@ -76,6 +83,7 @@ __global__ __launch_bounds__(256) void prepare_kernel(const void *x, int32_t x_d
   if (sdt == PECANN_F32) {
     float *of = (float *)o;
     const int64_t cap = r.xs_stride / 4;
+#pragma unroll
     for (int t = 0; t < kMaxPerLane; ++t) {
       const int e = l + 64 * t;
       if (e < cap) {
@@ -85,6 +93,7 @@ __global__ __launch_bounds__(256) void prepare_kernel(const void *x, int32_t x_d
       }
     }
   } else if (sdt == PECANN_U8) {
+#pragma unroll
     for (int t = 0; t < kMaxPerLane; ++t) {
       const int e = l + 64 * t;
       if (e < r.xs_stride) {
@@ -96,6 +105,7 @@ __global__ __launch_bounds__(256) void prepare_kernel(const void *x, int32_t x_d
   } else if (sdt == PECANN_BF16) {
     uint16_t *ob = (uint16_t *)o;
     const int64_t cap = r.xs_stride / 2;
+#pragma unroll
     for (int t = 0; t < kMaxPerLane; ++t) {
       const int e = l + 64 * t;
       if (e < cap) {
@@ -110,9 +120,11 @@ __global__ __launch_bounds__(256) void prepare_kernel(const void *x, int32_t x_d
     for (int t = 0; t < kMaxPerLane; ++t) mx = fmaxf(mx, fabsf(v[t]));
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) mx = fmaxf(mx, __shfl_xor(mx, m));
-    const float inv = mx > 0.f ? 448.0f / mx : 1.0f;
-    const float sc = 1.0f / inv;
+    const bool unit = metric == PECANN_COSINE;  // one scale for all unit rows
+    const float inv = unit ? kFp8UnitInv : mx > 0.f ? 448.0f / mx : 1.0f;
+    const float sc = unit ? 1.0f / kFp8UnitInv : 1.0f / inv;
     if (l == 0) scale[row] = sc;
+#pragma unroll
     for (int t = 0; t < kMaxPerLane; ++t) {
       const int e = l + 64 * t;
       if (e < r.xs_stride) {
@@ -136,8 +148,22 @@ hipError_t launch_prepare(const void *x, int32_t x_dtype, int64_t x_stride, int6
                           int32_t metric, int32_t sdt, const RowsDesc &rows, uint8_t *xs,
                           float *xr, float *scale, uint32_t *sqn, float *sqn_r, hipStream_t s) {
   const int64_t blocks = (n + 3) / 4;
-  hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, x_dtype, x_stride,
-                     n, d, metric, sdt, rows, xs, xr, scale, sqn, sqn_r);
+  // values per lane: the longest of the caller's row and the two stored rows
+  const int64_t elems = std::max<int64_t>({(int64_t)d, rows.xr_stride, sdt == PECANN_F32 ? rows.xs_stride / 4
+                                           : sdt == PECANN_BF16 ? rows.xs_stride / 2 : rows.xs_stride});
+  const int64_t per = (elems + 63) / 64;
+  const dim3 g((unsigned)blocks), b(256);
+#define PECANN_PREP(T)                                                                             \
+  hipLaunchKernelGGL(prepare_kernel<T>, g, b, 0, s, x, x_dtype, x_stride, n, d, metric, sdt, rows, xs, \
+                     xr, scale, sqn, sqn_r)
+  if (per <= 2) PECANN_PREP(2);
+  else if (per <= 4) PECANN_PREP(4);
+  else if (per <= 8) PECANN_PREP(8);
+  else if (per <= 16) PECANN_PREP(16);
+  else if (per <= 32) PECANN_PREP(32);
+  else if (per <= 64) PECANN_PREP(64);
+  else return hipErrorInvalidValue;
+#undef PECANN_PREP
   return hipGetLastError();
 }
 

@@ -106,12 +106,12 @@ __global__ __launch_bounds__(64) void nnd_init_kernel(NndParams p, const int32_t
     dot_tiles<DT, 4>(p.rows, (int32_t)u, rj, tt);
     if (g == 0) {
       const uint32_t nu = p.rows.sqn[u];
-      const float su = (DT == PECANN_FP8E4M3) ? p.rows.scale[u] : 1.0f;
+      const float su = (DT == PECANN_FP8E4M3) ? fp8_row_scale(p.rows, u) : 1.0f;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         uint64_t key = kNoKey;
         if (rj[t] >= 0) {
-          const float sc = (DT == PECANN_FP8E4M3) ? p.rows.scale[rj[t]] : 1.0f;
+          const float sc = (DT == PECANN_FP8E4M3) ? fp8_row_scale(p.rows, rj[t]) : 1.0f;
           key = make_key(pair_measure<DT>(tt[t][0], nu, p.rows.sqn[rj[t]], su, sc, p.rows.metric),
                          rj[t]);
         }
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(64) void nnd_join_kernel(NndParams p) {
       const int32_t id = mem[j];
       wk[j] = p.nxt_keys[(int64_t)id * K + K - 1];
       cn[j] = p.rows.sqn[id];
-      cs[j] = (DT == PECANN_FP8E4M3) ? p.rows.scale[id] : 1.0f;
+      cs[j] = (DT == PECANN_FP8E4M3) ? fp8_row_scale(p.rows, id) : 1.0f;
     }
     wave_lds_sync();
     const int nub = (nu + 15) >> 4, nwb = (nw + 15) >> 4;

@@ -218,7 +218,7 @@ __device__ __forceinline__ int robust_prune_tiles(const PruneParams &p, PruneLds
 
   {
     const uint32_t npt = p.rows.sqn[pt];
-    const float spt = (DT == PECANN_FP8E4M3) ? p.rows.scale[pt] : 1.0f;
+    const float spt = (DT == PECANN_FP8E4M3) ? fp8_row_scale(p.rows, pt) : 1.0f;
     for (int base = npre; base < nc; base += 16 * NT) {
       int32_t rj[NT];
 #pragma unroll
@@ -236,7 +236,7 @@ __device__ __forceinline__ int robust_prune_tiles(const PruneParams &p, PruneLds
           if (j < nc) {
             uint64_t key = kNoKey;
             if (rj[t] >= 0) {
-              const float sc = (DT == PECANN_FP8E4M3) ? p.rows.scale[rj[t]] : 1.0f;
+              const float sc = (DT == PECANN_FP8E4M3) ? fp8_row_scale(p.rows, rj[t]) : 1.0f;
               key = make_key(pair_measure<DT>(tt[t][0], npt, p.rows.sqn[rj[t]], spt, sc,
                                               p.rows.metric), rj[t]);
             }
@@ -257,7 +257,7 @@ __device__ __forceinline__ int robust_prune_tiles(const PruneParams &p, PruneLds
       if (live) {
         const int32_t id = key_id(key);
         s.cn[j] = p.rows.sqn[id];
-        s.cs[j] = (DT == PECANN_FP8E4M3) ? p.rows.scale[id] : 1.0f;
+        s.cs[j] = (DT == PECANN_FP8E4M3) ? fp8_row_scale(p.rows, id) : 1.0f;
       }
     }
   }
@@ -361,7 +361,7 @@ __device__ __forceinline__ int prune_with_prefix(const PruneParams &p, PruneLds 
     s.alive[r] = j >= c;
     const int32_t id = key_id(key);
     s.cn[r] = p.rows.sqn[id];
-    s.cs[r] = (DT == PECANN_FP8E4M3) ? p.rows.scale[id] : 1.0f;
+    s.cs[r] = (DT == PECANN_FP8E4M3) ? fp8_row_scale(p.rows, id) : 1.0f;
   }
   wave_lds_sync();
   // (2) positions of U in key order (s.ids), each member's index + 1 in alive

@@ -96,23 +96,33 @@ def test_prepare_bf16_rne(dev):
     assert np.array_equal(rows, _bf16_rne(X))
 
 
-def test_prepare_fp8_scaled(dev):
+@pytest.mark.parametrize("metric", ["cosine", "l2"])
+def test_prepare_fp8_scaled(dev, metric):
     rng = np.random.default_rng(2)
     n, d = 300, 1024
     X = rng.standard_normal((n, d)).astype(np.float32)
-    X /= np.linalg.norm(X, axis=1, keepdims=True)
-    ds = pecann.Dataset(_t(X, dev), "cosine", "fp8")
+    if metric == "cosine":
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+    else:
+        X *= rng.uniform(0.01, 100.0, size=(n, 1)).astype(np.float32)  # rows of very different ranges
+    ds = pecann.Dataset(_t(X, dev), metric, "fp8")
     prep = _np(ds.prep)
     codes = prep[: n * d].reshape(n, d)
     off_xr = (n * d + 255) // 256 * 256
     xr = prep[off_xr: off_xr + n * d * 4].view(np.float32).reshape(n, d)
     off_sc = off_xr + (n * d * 4 + 255) // 256 * 256
     scale = prep[off_sc: off_sc + 4 * n].view(np.float32)
-    Xn = X / np.linalg.norm(X, axis=1, keepdims=True)
-    assert np.allclose(xr, Xn, rtol=2e-6, atol=1e-7)
-    assert np.allclose(scale, np.abs(xr).max(axis=1) / 448.0, rtol=1e-6)
+    if metric == "cosine":
+        Xn = X / np.linalg.norm(X, axis=1, keepdims=True)
+        assert np.allclose(xr, Xn, rtol=2e-6, atol=1e-7)
+        # unit rows share one scale, 1 / 448
+        assert np.all(scale == np.float32(1.0) / np.float32(448.0))
+    else:
+        assert np.array_equal(xr, X)
+        assert np.allclose(scale, np.abs(xr).max(axis=1) / 448.0, rtol=1e-6)
     dec = _fp8_e4m3_decode(codes) * scale[:, None]
-    # e4m3: relative step 2^-3 for normals -> error <= 2^-4 relative (plus subnormal floor)
+    # e4m3: relative step 2^-3 for normals -> error <= 2^-4 relative (plus the
+    # subnormal floor, half of the 2^-9 step)
     err = np.abs(dec - xr)
     bound = np.maximum(np.abs(xr) * 2.0 ** -4, scale[:, None] * 2.0 ** -10) * 1.0001
     assert np.all(err <= bound)
