@@ -194,7 +194,7 @@ struct PruneParams {
   // appended
   unsigned long long *counters;
 };
-size_t prune_lds_bytes(int ccap, int R);
+size_t prune_lds_bytes(int ccap, int R, int dt, int metric);
 hipError_t launch_prune_forward(int32_t dt, const PruneParams &p, int grid, hipStream_t s);
 hipError_t launch_prune_reverse(int32_t dt, const PruneParams &p, int grid, hipStream_t s);
 hipError_t launch_prune_lists(int32_t dt, const PruneParams &p, int grid, hipStream_t s);

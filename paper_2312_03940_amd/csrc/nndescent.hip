@@ -103,7 +103,7 @@ __global__ __launch_bounds__(64) void nnd_init_kernel(NndParams p, const int32_t
 #pragma unroll
     for (int t = 0; t < 4; ++t) rj[t] = __shfl(id, 16 * t + col);
     v4f tt[4];
-    dot_tiles<DT, 4>(p.rows, (int32_t)u, rj, tt);
+    dot_tiles<DT, 4>(p.rows, col == 0 ? (int32_t)u : -1, rj, tt);  // A row 0 holds u
     if (g == 0) {
       const uint32_t nu = p.rows.sqn[u];
       const float su = (DT == PECANN_FP8E4M3) ? fp8_row_scale(p.rows, u) : 1.0f;

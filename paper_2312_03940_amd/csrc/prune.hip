@@ -29,20 +29,33 @@ struct PruneLds {
   uint64_t *k0;    // keys [ccap]
   uint64_t *k1;    // sorted keys [ccap]
   uint64_t *sel;   // keys of the selected [R]
-  uint32_t *cn;    // squared norm of each sorted candidate [ccap]
-  float *cs;       // row scale of each sorted candidate (FP8) [ccap]
+  uint32_t *cn;    // squared norm of each sorted candidate [ccap] (L2 only)
+  float *cs;       // row scale of each sorted candidate [ccap] (FP8 L2 only)
   uint8_t *alive;  // [ccap]
+  // a candidate's norm and scale: cosine measures need no norm, and cosine FP8
+  // rows share one scale, so those arrays are left out of the LDS
+  __device__ __forceinline__ uint32_t norm(int j) const { return cn ? cn[j] : 0u; }
+  __device__ __forceinline__ float scl(int j) const { return cs ? cs[j] : 1.0f / kFp8UnitInv; }
 };
 
-__device__ __forceinline__ PruneLds carve_prune(uint8_t *smem, int ccap, int R) {
+__host__ __device__ __forceinline__ bool prune_has_norms(int metric) { return metric == PECANN_L2; }
+__host__ __device__ __forceinline__ bool prune_has_scales(int dt, int metric) {
+  return dt == PECANN_FP8E4M3 && metric == PECANN_L2;
+}
+
+template <int DT>
+__device__ __forceinline__ PruneLds carve_prune(uint8_t *smem, int ccap, int R, int metric) {
   PruneLds s;
   s.k0 = (uint64_t *)smem;
   s.k1 = s.k0 + ccap;
   s.sel = s.k1 + ccap;
   s.ids = (int32_t *)(s.sel + R);
-  s.cn = (uint32_t *)(s.ids + ccap);
-  s.cs = (float *)(s.cn + ccap);
-  s.alive = (uint8_t *)(s.cs + ccap);
+  uint8_t *q = (uint8_t *)(s.ids + ccap);
+  s.cn = prune_has_norms(metric) ? (uint32_t *)q : nullptr;
+  if (s.cn) q += 4 * (size_t)ccap;
+  s.cs = prune_has_scales(DT, metric) ? (float *)q : nullptr;
+  if (s.cs) q += 4 * (size_t)ccap;
+  s.alive = q;
   return s;
 }
 
@@ -72,14 +85,18 @@ __device__ __forceinline__ int compact_live(PruneLds &s, int from, int mv) {
     uint64_t key = 0;
     uint32_t cn = 0;
     float cs = 0.f;
-    if (live) { key = s.k1[j]; cn = s.cn[j]; cs = s.cs[j]; }
+    if (live) {
+      key = s.k1[j];
+      if (s.cn) cn = s.cn[j];
+      if (s.cs) cs = s.cs[j];
+    }
     const uint64_t bm = ballot(live);
     wave_lds_sync();
     if (live) {
       const int o = out + lanes_below(bm);
       s.k1[o] = key;
-      s.cn[o] = cn;
-      s.cs[o] = cs;
+      if (s.cn) s.cn[o] = cn;
+      if (s.cs) s.cs[o] = cs;
       s.alive[o] = 1;
     }
     out += __popcll(bm);
@@ -108,7 +125,7 @@ __device__ __forceinline__ uint32_t select_block(const PruneParams &p, PruneLds 
     for (int r = 0; r < 4; ++r) {
       const int i = 4 * g + r;
       if (i < col) {
-        const float m = pair_measure<DT>(tile[r], s.cn[o + i], s.cn[j], s.cs[o + i], s.cs[j],
+        const float m = pair_measure<DT>(tile[r], s.norm(o + i), s.norm(j), s.scl(o + i), s.scl(j),
                                          p.rows.metric);
         if (a2 * m <= dpj) kb |= 1u << i;
       }
@@ -171,7 +188,7 @@ __device__ __forceinline__ void short_block(const PruneParams &p, PruneLds &s, i
       for (int r = 0; r < 4; ++r) {
         const int i = 4 * g + r;
         if ((selmask >> i) & 1u) {
-          const float m = pair_measure<DT>(tt[t][r], s.cn[o + i], s.cn[j], s.cs[o + i], s.cs[j],
+          const float m = pair_measure<DT>(tt[t][r], s.norm(o + i), s.norm(j), s.scl(o + i), s.scl(j),
                                            p.rows.metric);
           kill |= a2 * m <= dpc;
         }
@@ -202,8 +219,9 @@ __device__ __forceinline__ void write_nout(const PruneParams &p, const PruneLds 
 // RobustPrune of point pt over s.ids[0..nc); writes Nout(pt) into adj/deg.
 // The first npre candidates come with their keys (D(pt, c), c) already in s.k0.
 // Candidates are sorted by (D(pt, c), c), and empty entries and repeats are
-// dropped.  D(pt, c) comes from tiles whose A rows all hold pt, 64 candidates
-// per round; lanes 0-15 read their column's value in accumulator register 0.  The greedy pass then walks the live
+// dropped.  D(pt, c) comes from tiles whose A row 0 holds pt (rows 1-15 are
+// zeros), 64 candidates per round; lanes 0-15 read their column's value in
+// accumulator register 0.  The greedy pass then walks the live
 // list in blocks of 16: one matrix-core tile gives the block's own pairwise
 // distances, which settle the block's selections in order; the block's selected
 // points then drop later candidates tile by tile (each lane testing the 4 rows
@@ -228,7 +246,7 @@ __device__ __forceinline__ int robust_prune_tiles(const PruneParams &p, PruneLds
         rj[t] = id == pt ? -1 : id;
       }
       v4f tt[NT];
-      dot_tiles<DT, NT>(p.rows, pt, rj, tt);
+      dot_tiles<DT, NT>(p.rows, col == 0 ? pt : -1, rj, tt);  // A row 0 holds pt, rows 1-15 zeros
       if (g == 0) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
@@ -256,8 +274,8 @@ __device__ __forceinline__ int robust_prune_tiles(const PruneParams &p, PruneLds
       s.alive[j] = live;
       if (live) {
         const int32_t id = key_id(key);
-        s.cn[j] = p.rows.sqn[id];
-        s.cs[j] = (DT == PECANN_FP8E4M3) ? fp8_row_scale(p.rows, id) : 1.0f;
+        if (s.cn) s.cn[j] = p.rows.sqn[id];
+        if (s.cs) s.cs[j] = fp8_row_scale(p.rows, id);
       }
     }
   }
@@ -289,7 +307,10 @@ __device__ __forceinline__ int robust_prune_tiles(const PruneParams &p, PruneLds
       selmask = select_block<DT>(p, s, t[0], b, mv, a2, nsel);
     }
     if (nsel == p.R) break;
-    // (c) the block's selected points drop later candidates, NT tiles at a time
+    // (c) the block's selected points drop later candidates, NT tiles at a time;
+    // A rows of block entries that were not selected are not loaded (zeros:
+    // their accumulator rows are never read)
+    const int32_t ra = ((selmask >> col) & 1u) ? rb : -1;
     for (int j0 = b + 16; j0 < mv; j0 += 16 * NT) {
       int32_t rj[NT];
 #pragma unroll
@@ -298,7 +319,7 @@ __device__ __forceinline__ int robust_prune_tiles(const PruneParams &p, PruneLds
         rj[t] = j < mv ? key_id(s.k1[j]) : -1;
       }
       v4f tt[NT];
-      dot_tiles<DT, NT>(p.rows, rb, rj, tt);
+      dot_tiles<DT, NT>(p.rows, ra, rj, tt);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const int j = j0 + 16 * t + col;
@@ -309,7 +330,7 @@ __device__ __forceinline__ int robust_prune_tiles(const PruneParams &p, PruneLds
           for (int r = 0; r < 4; ++r) {
             const int i = 4 * g + r;
             if ((selmask >> i) & 1u) {
-              const float m = pair_measure<DT>(tt[t][r], s.cn[b + i], s.cn[j], s.cs[b + i], s.cs[j],
+              const float m = pair_measure<DT>(tt[t][r], s.norm(b + i), s.norm(j), s.scl(b + i), s.scl(j),
                                                p.rows.metric);
               kill |= a2 * m <= dpc;
             }
@@ -360,8 +381,8 @@ __device__ __forceinline__ int prune_with_prefix(const PruneParams &p, PruneLds 
     s.k1[r] = key;
     s.alive[r] = j >= c;
     const int32_t id = key_id(key);
-    s.cn[r] = p.rows.sqn[id];
-    s.cs[r] = (DT == PECANN_FP8E4M3) ? fp8_row_scale(p.rows, id) : 1.0f;
+    if (s.cn) s.cn[r] = p.rows.sqn[id];
+    if (s.cs) s.cs[r] = fp8_row_scale(p.rows, id);
   }
   wave_lds_sync();
   // (2) positions of U in key order (s.ids), each member's index + 1 in alive
@@ -417,7 +438,7 @@ __device__ __forceinline__ int prune_with_prefix(const PruneParams &p, PruneLds 
           for (int r = 0; r < 4; ++r) {
             const int pu = pr[r];
             if (pu >= 0 && pu != jc) {
-              const float m = pair_measure<DT>(tt[t][r], s.cn[pu], s.cn[jc], s.cs[pu], s.cs[jc],
+              const float m = pair_measure<DT>(tt[t][r], s.norm(pu), s.norm(jc), s.scl(pu), s.scl(jc),
                                                p.rows.metric);
               const uint32_t bit = 1u << (ub * 16 + 4 * g + r);
               if (pu < jc) {
@@ -499,7 +520,7 @@ template <int DT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == PECANN_BF16 || DT == PECANN_U8 ? 4 : 1))) void prune_forward_kernel(PruneParams p) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int ccap = p.vcap + p.R;
-  PruneLds s = carve_prune(smem, ccap, p.R);
+  PruneLds s = carve_prune<DT>(smem, ccap, p.R, p.rows.metric);
   const int l = lane_id();
   for (;;) {
     const int t = next_item(p.head);
@@ -648,7 +669,7 @@ template <int DT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == PECANN_F32 ? 1 : 3))) void prune_reverse_kernel(PruneParams p) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int ccap = p.R + p.capin;
-  PruneLds s = carve_prune(smem, ccap, p.R);
+  PruneLds s = carve_prune<DT>(smem, ccap, p.R, p.rows.metric);
   const int l = lane_id();
   const int nt = *p.ntargets;
   const int items = p.heavy ? *p.nheavy : *p.nlight;
@@ -754,9 +775,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == PECANN
     } else {
       // current out-neighbours, then the new sources in ascending index order,
       // leaving out sources already among the out-neighbours (the sources of
-      // one batch are distinct; their ids are staged in LDS and ranked there,
-      // and their keys land in s.k1 at their rank)
-      int32_t *stage = (int32_t *)s.cn;
+      // one batch are distinct; their ids are staged in s.k0, free until the
+      // keys are gathered, and ranked there, and their keys land in s.k1 at
+      // their rank)
+      int32_t *stage = (int32_t *)s.k0;
       for (int j = l; j < dq; j += kWave) s.ids[j] = row[j];
       for (int j = l; j < cnt; j += kWave) stage[j] = src[j];
       wave_lds_sync();
@@ -814,7 +836,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == PECANN
 template <int DT>
 __global__ __launch_bounds__(64) void prune_lists_kernel(PruneParams p) {
   extern __shared__ __align__(16) uint8_t smem[];
-  PruneLds s = carve_prune(smem, 2 * p.lk, p.R);
+  PruneLds s = carve_prune<DT>(smem, 2 * p.lk, p.R, p.rows.metric);
   const int l = lane_id();
   for (;;) {
     const int u = next_item(p.head);
@@ -831,26 +853,27 @@ __global__ __launch_bounds__(64) void prune_lists_kernel(PruneParams p) {
   }
 }
 
-size_t prune_lds_bytes(int ccap, int R) {
-  return (size_t)ccap * (8 + 8 + 4 + 4 + 4 + 1) + 8 * (size_t)R + 16;
+size_t prune_lds_bytes(int ccap, int R, int dt, int metric) {
+  const size_t per = 8 + 8 + 4 + 1 + (prune_has_norms(metric) ? 4 : 0) + (prune_has_scales(dt, metric) ? 4 : 0);
+  return (size_t)ccap * per + 8 * (size_t)R + 16;
 }
 
 template <int DT>
 static hipError_t launch_pf_t(const PruneParams &p, int grid, hipStream_t st) {
   hipLaunchKernelGGL((prune_forward_kernel<DT>), dim3(grid), dim3(64),
-                     prune_lds_bytes(p.vcap + p.R, p.R), st, p);
+                     prune_lds_bytes(p.vcap + p.R, p.R, DT, p.rows.metric), st, p);
   return hipGetLastError();
 }
 template <int DT>
 static hipError_t launch_pr_t(const PruneParams &p, int grid, hipStream_t st) {
   hipLaunchKernelGGL((prune_reverse_kernel<DT>), dim3(grid), dim3(64),
-                     prune_lds_bytes(p.R + p.capin, p.R), st, p);
+                     prune_lds_bytes(p.R + p.capin, p.R, DT, p.rows.metric), st, p);
   return hipGetLastError();
 }
 
 template <int DT>
 static hipError_t launch_pl_t(const PruneParams &p, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((prune_lists_kernel<DT>), dim3(grid), dim3(64), prune_lds_bytes(2 * p.lk, p.R), st,
+  hipLaunchKernelGGL((prune_lists_kernel<DT>), dim3(grid), dim3(64), prune_lds_bytes(2 * p.lk, p.R, DT, p.rows.metric), st,
                      p);
   return hipGetLastError();
 }
