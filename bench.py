@@ -1,7 +1,7 @@
 """Benchmark of the DPC hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
-                    [--config 2|3|4|5] [--search f32|u8|bf16|fp8] [--mode anns|exact]
+                    [--config 2|3|4|5] [--search f32|u8|bf16|fp8|mxfp6] [--mode anns|exact]
 
 Default workload (the ImageNet-shaped configuration, the largest single-GPU one):
 1,280,000 x 1024 float32 unit vectors, 1,000 clusters of normalised Gaussian
@@ -86,7 +86,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=4, choices=[2, 3, 4, 5])
-    ap.add_argument("--search", default=None, choices=["f32", "u8", "bf16", "fp8"])
+    ap.add_argument("--search", default=None, choices=["f32", "u8", "bf16", "fp8", "mxfp6"])
     ap.add_argument("--mode", default="anns", choices=["anns", "exact"])
     ap.add_argument("--L-search", type=int, default=None)
     ap.add_argument("--L-d", type=int, default=None)
@@ -521,11 +521,13 @@ def roofline(pl, kprof, steps, search, n, d, k):
         bc, kc = pl.counters()
     finally:
         pecann.set_tuning(**timed)
-    row_bytes = {"f32": 4 * d, "u8": d, "bf16": 2 * d, "fp8": d}[search]
+    # MXFP6: 24 bytes of codes and one scale byte per 32 dims
+    row_bytes = {"f32": 4 * d, "u8": d, "bf16": 2 * d, "fp8": d,
+                 "mxfp6": 100 * ((d + 127) // 128)}[search]
     # algorithmic bytes per step: per expansion the degree word and the neighbour ids,
     # per distance the candidate row, per search its own row (float32 for BF16/FP8
     # queries) and its outputs, plus the float32 rows re-scored
-    q_bytes = 4 * d if search in ("bf16", "fp8") else row_bytes
+    q_bytes = 4 * d if search in ("bf16", "fp8", "mxfp6") else row_bytes
     nsb = 2 * n - 1
     alg = {
         "search_knn": (4 * (kc[0] + kc[1]) + row_bytes * kc[2] + n * q_bytes + 4 * d * kc[3]
@@ -561,7 +563,7 @@ def roofline(pl, kprof, steps, search, n, d, k):
 
 # Dense matrix-core peaks of MI355X (AMD's published figures, no sparsity) for the
 # tiles' operand types, TFLOP/s (TOP/s for int8).
-MFMA_PEAK = {"f32": 157.3, "u8": 5000.0, "bf16": 2500.0, "fp8": 5000.0}
+MFMA_PEAK = {"f32": 157.3, "u8": 5000.0, "bf16": 2500.0, "fp8": 5000.0, "mxfp6": 5000.0}
 
 
 def prune_roofline(bc, fam_ms, fam_l, search, d):
@@ -569,8 +571,9 @@ def prune_roofline(bc, fam_ms, fam_l, search, d):
     Work per launch from the build counters ([4] forward, [5] reverse: row
     reads, 32 per tile): tiles x 16 x 16 x d multiply-adds, and the rows the
     tiles read (L2-resident gathers: a batch's candidates are few).  Both are
-    reported against the launch's average HIP-event time."""
-    row_bytes = {"f32": 4 * d, "u8": d, "bf16": 2 * d, "fp8": d}[search]
+    reported against the launch's average HIP-event time.  MXFP6 datasets prune
+    on their FP8 copy."""
+    row_bytes = {"f32": 4 * d, "u8": d, "bf16": 2 * d, "fp8": d, "mxfp6": d}[search]
     out = {}
     for fam, rows in (("prune_forward", bc[4]), ("prune_reverse", bc[5])):
         if fam not in fam_ms or not fam_l.get(fam):
@@ -726,14 +729,16 @@ def main():
         pecann.reset_tuning()  # variants run with the library's rules
     if not args.no_variants:
         variants = {}
-        # (row format, mode, index[, argument overrides]); "paper_batches": the
+        # (row format, mode, index[, argument overrides]); MXFP6: the searches
+        # score 6-bit block-scaled rows (the prunes keep the FP8 copy); "paper_batches": the
         # paper's batch cap of 0.02 n (Sec. 4.1 footnote) where the library's
         # default raises it to 8,192 concurrent searches (n < 409,600)
         paper_cap = {"max_batch": max(1, n // 50)}
         alt = {2: [("u8", "anns", "vamana"), ("u8", "exact", "vamana"), ("f32", "exact", "vamana"),
                    ("f32", "anns", "nndescent"), ("f32", "anns", "vamana", paper_cap)],
                3: [("f32", "anns", "vamana"), ("bf16", "anns", "nndescent")],
-               4: [("f32", "anns", "vamana")], 5: [("f32", "anns", "vamana")]}[args.config]
+               4: [("f32", "anns", "vamana"), ("mxfp6", "anns", "vamana")],
+               5: [("f32", "anns", "vamana")]}[args.config]
         for var in alt:
             vs, vm, vi = var[:3]
             over = var[3] if len(var) > 3 else None

@@ -55,7 +55,10 @@ typedef enum {
   PECANN_F32 = 0,     /* IEEE float32 */
   PECANN_U8 = 1,      /* unsigned 8-bit integer */
   PECANN_BF16 = 2,    /* bfloat16, round-to-nearest-even from float32 */
-  PECANN_FP8E4M3 = 3  /* OCP float8 e4m3 with a float32 scale per row */
+  PECANN_FP8E4M3 = 3, /* OCP float8 e4m3 with a float32 scale per row */
+  PECANN_MXFP6 = 4    /* search rows only: OCP MX FP6 e2m3 (blocks of 32 values
+                         sharing a power-of-two scale) for the beam searches,
+                         with an FP8E4M3 copy for the distance tiles */
 } pecann_dtype;
 
 /* Distance D(x, y) (Sec. 2.1; the paper's experiments use Euclidean). */

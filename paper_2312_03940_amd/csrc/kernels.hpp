@@ -26,6 +26,12 @@ struct RowsDesc {  // host copy of the row description (mirrors Rows)
   // the padded row for U8
   const uint32_t *sqn;
   const float *sqn_r;  // squared norms of the float32 rerank rows (BF16/FP8), else nullptr
+  // MXFP6 search rows (PECANN_MXFP6 only, else nullptr): the rows the beam
+  // searches score; every other kernel reads the FP8 copy in xs
+  const uint8_t *xg;
+  int64_t xg_stride;  // bytes
+  int32_t xg_soff;    // byte offset of a row's scale words
+  const uint32_t *sqn_g;  // squared norms of the dequantised MXFP6 rows (float bits)
   int32_t nch;
   int32_t nch_r;
   int32_t d;
@@ -253,7 +259,8 @@ hipError_t launch_nnd_copy(const uint64_t *src, uint64_t *dst, int64_t n, int cu
 // Plain (non-templated) kernels.
 hipError_t launch_prepare(const void *x, int32_t x_dtype, int64_t x_stride, int64_t n, int32_t d,
                           int32_t metric, int32_t sdt, const RowsDesc &rows, uint8_t *xs,
-                          float *xr, float *scale, uint32_t *sqn, float *sqn_r, hipStream_t s);
+                          float *xr, float *scale, uint32_t *sqn, float *sqn_r, uint8_t *xg,
+                          uint32_t *sqn_g, hipStream_t s);
 
 // Exact kNN on the matrix cores: a scan that keeps, per query, the 16 best
 // candidates of each lane's column stream by matrix-core distance, then an

@@ -27,6 +27,16 @@
 // the candidate row (W = 128 bytes FP8, 64 bytes BF16), so the dot product
 // pairs equal elements whatever order the instruction sums them in.  Row bytes
 // past the row's chunks are zeros on both sides.
+//
+// MXFP6 rows (OCP MX FP6 e2m3: 32 consecutive values share a power-of-two
+// scale) are the B operand in their own format: 16x16x128 f8f6f4 with A FP8
+// (the query parts) and B FP6.  For a 6-bit B the instruction reads lane group
+// g's 32 packed values (24 bytes, value i in bits [6i, 6i + 6)) as K = 32 g ..
+// 32 g + 31, and the lane's scale byte covers exactly those; an 8-bit A lane
+// holds K = 16 g .. 16 g + 15 in its first 16 bytes and K = 64 + 16 g .. in its
+// last 16.  So the row's block of 32 values (dims 128 s + 32 g ..) sits in one
+// lane group with its own scale, and the query parts are stored permuted
+// within each step: dim 128 s + 64 h + 16 g + j at byte 128 s + 32 g + 16 h + j.
 #pragma once
 
 #include <type_traits>
@@ -39,8 +49,10 @@ typedef int v8i __attribute__((ext_vector_type(8)));
 
 template <int DT, int S>
 struct MfmaScorer {
-  static_assert(DT == PECANN_BF16 || DT == PECANN_FP8E4M3, "matrix-core scoring is for BF16/FP8 rows");
-  static constexpr bool FP8 = DT == PECANN_FP8E4M3;
+  static_assert(DT == PECANN_BF16 || DT == PECANN_FP8E4M3 || DT == PECANN_MXFP6,
+                "matrix-core scoring is for BF16/FP8/MXFP6 rows");
+  static constexpr bool MX6 = DT == PECANN_MXFP6;
+  static constexpr bool FP8 = DT == PECANN_FP8E4M3 || MX6;  // FP8 query parts
   static constexpr int NC = FP8 ? 2 : 1;         // 16-byte chunks per lane per step
   static constexpr int CPS = 4 * NC;             // chunks per step (four lane groups)
   static constexpr int STEPS = (S + CPS - 1) / CPS;
@@ -52,7 +64,7 @@ struct MfmaScorer {
   static constexpr int SB = (16 / NC) < STEPS ? 16 / NC : STEPS;
 
   uint8_t *qp;  // LDS, 16-byte aligned: part 0 (hi), part 1 (lo), 32 zero bytes
-  float qs;     // FP8: the query's scale s_q; BF16: 1
+  float qs;     // FP8 / MXFP6: the query's scale s_q; BF16: 1
   float qn;     // squared norm of the float32 query (L2)
 
   // Splits the float32 query row into its two parts (LDS) and keeps its scale
@@ -92,8 +104,9 @@ struct MfmaScorer {
         o[0] = h[0] - b0[0]; o[1] = h[1] - b0[1]; o[2] = h[2] - b1[0]; o[3] = h[3] - b1[1];
         int wl = __builtin_amdgcn_cvt_pk_fp8_f32(o[0], o[1], 0, false);
         wl = __builtin_amdgcn_cvt_pk_fp8_f32(o[2], o[3], wl, true);
-        *(int *)(qp + e) = wh;
-        *(int *)(qp + QB + e) = wl;
+        const int at = MX6 ? qperm(e) : e;
+        *(int *)(qp + at) = wh;
+        *(int *)(qp + QB + at) = wl;
       } else {
         uint32_t hb[4], lb[4];
 #pragma unroll
@@ -110,6 +123,13 @@ struct MfmaScorer {
     qn = r.metric == PECANN_L2 ? r.sqn_r[qid] : 0.f;
   }
 
+  // byte of query dim e in the MXFP6 A layout (e a multiple of 4: four
+  // consecutive dims stay consecutive)
+  __device__ __forceinline__ static int qperm(int e) {
+    const int s = e >> 7, el = e & 127;
+    return 128 * s + 32 * ((el >> 4) & 3) + 16 * (el >> 6) + (el & 15);
+  }
+
   __device__ __forceinline__ static uint32_t bf16_rne(float f) {
     uint32_t u = __float_as_uint(f);
     u += 0x7fffu + ((u >> 16) & 1u);
@@ -117,13 +137,37 @@ struct MfmaScorer {
   }
 
   typedef typename std::conditional<FP8, v8i, v4i>::type Frag;
+  // one step's B operand of a lane: its chunk(s) of the row and, for MXFP6,
+  // the scale word of the step shifted so that the lane's block scale is byte 0
+  struct Op {
+    Frag b;
+    int sc;
+  };
+
+  __device__ __forceinline__ static Op load(const Rows &r, const uint8_t *rb, int st, int g) {
+    Op o;
+    if constexpr (MX6) {
+      const uint8_t *cb = rb + 24 * (4 * st + g);
+      const uint2 d0 = *(const uint2 *)cb, d1 = *(const uint2 *)(cb + 8), d2 = *(const uint2 *)(cb + 16);
+      o.b = v8i{(int)d0.x, (int)d0.y, (int)d1.x, (int)d1.y, (int)d2.x, (int)d2.y, 0, 0};
+      o.sc = (int)(*(const uint32_t *)(rb + r.xg_soff + 4 * st) >> (8 * g));
+    } else {
+      o.b = *(const Frag *)(rb + 16 * (st * CPS + g * NC));
+      o.sc = 0;
+    }
+    return o;
+  }
 
   // acc += A x B for step st: the query fragment is read from the LDS right
   // before its product (rows 2-15 read the zero block)
   __device__ __forceinline__ static void product(v4f &acc, const uint8_t *qa, int qstep, int st, int g,
-                                                 const Frag &b) {
+                                                 const Op &op) {
     const Frag a = *(const Frag *)(qa + 16 * qstep * (st * CPS + g * NC));
-    if constexpr (FP8) {
+    const Frag &b = op.b;
+    if constexpr (MX6) {
+      // formats 0/2: e4m3 A with unit scale, e2m3 B with the lane's block scale
+      acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc, 0, 2, 0, 127, 0, op.sc);
+    } else if constexpr (FP8) {
       // formats 0/0: e4m3 for both operands; block scales 127 (2^0)
       acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc, 0, 0, 0, 127, 0, 127);
     } else {
@@ -133,17 +177,17 @@ struct MfmaScorer {
   }
 
   template <int B>
-  __device__ __forceinline__ static void blocks(v4f &acc, const uint8_t *qa, int qstep, int g,
+  __device__ __forceinline__ static void blocks(const Rows &r, v4f &acc, const uint8_t *qa, int qstep, int g,
                                                 const uint8_t *rb, int &s0, int steps) {
 #pragma unroll 1
     for (; s0 + B <= steps; s0 += B) {
-      Frag b[B];
+      Op b[B];
 #pragma unroll
-      for (int u = 0; u < B; ++u) b[u] = *(const Frag *)(rb + 16 * ((s0 + u) * CPS + g * NC));
+      for (int u = 0; u < B; ++u) b[u] = load(r, rb, s0 + u, g);
 #pragma unroll
       for (int u = 0; u < B; ++u) product(acc, qa, qstep, s0 + u, g, b[u]);
     }
-    if constexpr (B > 1) blocks<B / 2>(acc, qa, qstep, g, rb, s0, steps);
+    if constexpr (B > 1) blocks<B / 2>(r, acc, qa, qstep, g, rb, s0, steps);
   }
 
   // Keys (measure, id) of the candidates id_of(i), i in [0, c), into out[0, c)
@@ -161,20 +205,23 @@ struct MfmaScorer {
       const int ci = base + col;
       const int32_t row = ci < c ? id_of(ci) : -1;
       // a missing candidate reads row 0 (its column's result is dropped)
-      const uint8_t *rb = r.xs + (int64_t)(row < 0 ? 0 : row) * r.xs_stride;
+      const uint8_t *rb = MX6 ? r.xg + (int64_t)(row < 0 ? 0 : row) * r.xg_stride
+                              : r.xs + (int64_t)(row < 0 ? 0 : row) * r.xs_stride;
       v4f acc = {0.f, 0.f, 0.f, 0.f};
       // blocks of SB steps (the loop is kept rolled): the row loads of a block
       // go out together, then its products; the rest in blocks of SB / 2,
       // SB / 4, ... steps, so a row of any length costs few round trips.  The
       // rows end on a whole step (zero padded): no load needs a bound
       int s0 = 0;
-      blocks<SB>(acc, qa, qstep, g, rb, s0, steps);
+      blocks<SB>(r, acc, qa, qstep, g, rb, s0, steps);
       if (l < 16 && ci < c) {
         uint64_t key = kNoKey;
         if (row >= 0) {
           float dot = acc[0] + acc[1];
-          if (FP8) dot *= qs * fp8_row_scale(r, row);
-          const float m = r.metric == PECANN_L2 ? fmaxf(0.f, qn + __uint_as_float(r.sqn[row]) - 2.0f * dot)
+          if constexpr (MX6) dot *= qs;  // the block scales are applied by the instruction
+          else if (FP8) dot *= qs * fp8_row_scale(r, row);
+          const uint32_t xn = MX6 ? r.sqn_g[row] : r.sqn[row];
+          const float m = r.metric == PECANN_L2 ? fmaxf(0.f, qn + __uint_as_float(xn) - 2.0f * dot)
                                                 : fmaxf(0.f, 1.0f - dot);
           key = make_key(m, row);
         }

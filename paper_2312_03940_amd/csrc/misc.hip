@@ -31,12 +31,79 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
 
 // T = values per lane (the row's padded length / 64, rounded up to a power of
 // two); every loop over them is unrolled so the row stays in registers.
+// MXFP6 element e2m3 (sign, 2 exponent bits with bias 1, 3 mantissa bits):
+// value of a 6-bit code
+__device__ __forceinline__ float e2m3_value(int c) {
+  const int e = (c >> 3) & 3, m = c & 7;
+  const float v = e == 0 ? 0.125f * (float)m : ldexpf(1.0f + 0.125f * (float)m, e - 1);
+  return (c & 32) ? -v : v;
+}
+
+// MXFP6 copy of one row (wavefront-wide; v[t] holds dim 64 t + lane, zero past
+// d): blocks of 32 dims share the power-of-two scale 2^E with E the smallest
+// integer that puts the block's largest magnitude at or below 7.5 (e2m3's
+// largest value); each value x / 2^E is rounded to the nearest e2m3 value,
+// ties to even.  Block b = 4 s + g of step s: 24 bytes of codes at 24 b (code
+// i in bits [6i, 6i + 6)), its scale E + 127 in byte b of the scale words.
+// Returns the squared norm of the dequantised row.
+template <int T>
+__device__ __forceinline__ float write_mxfp6(const float (&v)[T], const RowsDesc &r, uint8_t *og) {
+  const int l = lane_id(), h = l >> 5, j = l & 31;
+  const int nblk = 4 * (r.xg_soff / 96);
+  float ng = 0.f;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    if (2 * t >= nblk) break;  // wave-uniform: nblk is even
+    const int blk = 2 * t + h;  // dims 64 t + 32 h .. + 31, one per lane of the half
+    const float x = v[t];
+    float amax = fabsf(x);
+#pragma unroll
+    for (int m = 16; m >= 1; m >>= 1) amax = fmaxf(amax, __shfl_xor(amax, m));
+    int E = -127;
+    if (amax > 0.f) {
+      int k;
+      const float fr = frexpf(amax, &k);  // amax = fr 2^k, fr in [0.5, 1)
+      E = (k - 3) + (fr > 0.9375f ? 1 : 0);  // 7.5 2^(k-3) = 0.9375 2^k
+      E = E < -127 ? -127 : E > 127 ? 127 : E;
+    }
+    const float y = ldexpf(x, -E);
+    const float a = fabsf(y);
+    int code;
+    if (a < 1.0f) {
+      code = (int)rintf(a * 8.0f);  // 8 is the code of 1.0
+    } else {
+      int k2;
+      frexpf(a, &k2);
+      const int kk = k2 - 1;  // floor(log2 a), 0..2
+      code = 8 * kk + (int)rintf(ldexpf(a, 3 - kk));
+    }
+    if (y < 0.f) code |= 32;
+    const float dq = ldexpf(e2m3_value(code), E);
+    ng = fmaf(dq, dq, ng);
+    // lane j < 6 forms word j of the block's 24 bytes from the (at most six)
+    // codes that touch it, i0 = floor(32 j / 6) onwards
+    const int i0 = (16 * (j < 6 ? j : 0)) / 3;
+    uint32_t w = 0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const int i = i0 + q < 31 ? i0 + q : 31;
+      const uint32_t c = (uint32_t)__shfl(code, 32 * h + i);
+      const int sh = 6 * (i0 + q) - 32 * j;
+      if (i0 + q < 32 && sh > -6 && sh < 32) w |= sh >= 0 ? c << sh : c >> (-sh);
+    }
+    if (j < 6) *(uint32_t *)(og + 24 * blk + 4 * j) = w;
+    if (j == 0) og[r.xg_soff + blk] = (uint8_t)(E + 127);
+  }
+  for (int b = r.xg_soff + nblk + l; b < r.xg_stride; b += kWave) og[b] = 0;
+  return ng;
+}
+
 template <int T>
 __global__ __launch_bounds__(256) void prepare_kernel(const void *x, int32_t x_dtype, int64_t x_stride,
                                                       int64_t n, int32_t d, int32_t metric,
                                                       int32_t sdt, RowsDesc r, uint8_t *xs,
                                                       float *xr, float *scale, uint32_t *sqn,
-                                                      float *sqn_r) {
+                                                      float *sqn_r, uint8_t *xg, uint32_t *sqn_g) {
   const int l = lane_id();
   const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (row >= n) return;
@@ -142,11 +209,18 @@ __global__ __launch_bounds__(256) void prepare_kernel(const void *x, int32_t x_d
     ni += __shfl_xor(ni, m);
   }
   if (l == 0) sqn[row] = sdt == PECANN_U8 ? (uint32_t)ni : __float_as_uint(nf);
+  if (xg) {
+    float ng = write_mxfp6<T>(v, r, xg + row * r.xg_stride);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) ng += __shfl_xor(ng, m);
+    if (l == 0) sqn_g[row] = __float_as_uint(ng);
+  }
 }
 
 hipError_t launch_prepare(const void *x, int32_t x_dtype, int64_t x_stride, int64_t n, int32_t d,
                           int32_t metric, int32_t sdt, const RowsDesc &rows, uint8_t *xs,
-                          float *xr, float *scale, uint32_t *sqn, float *sqn_r, hipStream_t s) {
+                          float *xr, float *scale, uint32_t *sqn, float *sqn_r, uint8_t *xg,
+                          uint32_t *sqn_g, hipStream_t s) {
   const int64_t blocks = (n + 3) / 4;
   // values per lane: the longest of the caller's row and the two stored rows
   const int64_t elems = std::max<int64_t>({(int64_t)d, rows.xr_stride, sdt == PECANN_F32 ? rows.xs_stride / 4
@@ -155,7 +229,7 @@ hipError_t launch_prepare(const void *x, int32_t x_dtype, int64_t x_stride, int6
   const dim3 g((unsigned)blocks), b(256);
 #define PECANN_PREP(T)                                                                             \
   hipLaunchKernelGGL(prepare_kernel<T>, g, b, 0, s, x, x_dtype, x_stride, n, d, metric, sdt, rows, xs, \
-                     xr, scale, sqn, sqn_r)
+                     xr, scale, sqn, sqn_r, xg, sqn_g)
   if (per <= 2) PECANN_PREP(2);
   else if (per <= 4) PECANN_PREP(4);
   else if (per <= 8) PECANN_PREP(8);

@@ -213,30 +213,48 @@ struct Layout {
   size_t off_scale;
   size_t off_sqn;
   size_t off_sqn_r;
+  size_t off_xg, xg_stride, xg_soff;  // MXFP6 rows: offset, bytes per row, scale words
+  size_t off_sqn_g;
   size_t total;
-  bool has_xr, has_scale;
+  bool has_xr, has_scale, has_xg;
 };
 
 static size_t up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-static bool valid_dtype(int32_t t) { return t >= PECANN_F32 && t <= PECANN_FP8E4M3; }
+static bool valid_dtype(int32_t t) { return t >= PECANN_F32 && t <= PECANN_MXFP6; }
+
+// Row format of the distance tiles, brute-force scans and fallbacks: MXFP6
+// datasets keep an FP8 copy for them.
+static int32_t tile_dtype(int32_t sdt) { return sdt == PECANN_MXFP6 ? PECANN_FP8E4M3 : sdt; }
 
 static bool make_layout(int64_t n, int32_t d, int32_t metric, int32_t sdt, Layout *L) {
   if (n < 2 || n >= (int64_t)1 << 31 || d < 1 || d > 4096) return false;
   if (metric != PECANN_L2 && metric != PECANN_COSINE) return false;
   if (!valid_dtype(sdt)) return false;
   if (sdt == PECANN_U8 && metric != PECANN_L2) return false;
-  const size_t bytes = sdt == PECANN_F32 ? 4 : sdt == PECANN_BF16 ? 2 : 1;
+  const int32_t tdt = tile_dtype(sdt);
+  const size_t bytes = tdt == PECANN_F32 ? 4 : tdt == PECANN_BF16 ? 2 : 1;
   L->off_xs = 0;
   // BF16 / FP8 rows end on a whole matrix-core step of the search's scoring
   // (32 BF16 or 128 FP8 values), zero padded, so its loads need no bounds
-  L->xs_stride = up((size_t)d * bytes, sdt == PECANN_BF16 ? 64 : sdt == PECANN_FP8E4M3 ? 128 : 16);
+  L->xs_stride = up((size_t)d * bytes, tdt == PECANN_BF16 ? 64 : tdt == PECANN_FP8E4M3 ? 128 : 16);
   size_t off = up(L->xs_stride * (size_t)n, 256);
-  L->has_xr = (sdt == PECANN_BF16 || sdt == PECANN_FP8E4M3);
+  // MXFP6 rows: per step of 128 values, four 24-byte blocks of 32 packed
+  // codes, then one 32-bit word of the four block scales per step; rows padded
+  // to 64 bytes
+  L->has_xg = sdt == PECANN_MXFP6;
+  const size_t steps6 = up((size_t)d, 128) / 128;
+  L->xg_soff = 96 * steps6;
+  L->xg_stride = up(100 * steps6, 64);
+  L->off_xg = off;
+  if (L->has_xg) off = up(off + L->xg_stride * (size_t)n, 256);
+  L->off_sqn_g = off;
+  if (L->has_xg) off = up(off + 4 * (size_t)n, 256);
+  L->has_xr = (tdt == PECANN_BF16 || tdt == PECANN_FP8E4M3);
   L->xr_stride = up((size_t)d, 4);
   L->off_xr = off;
   if (L->has_xr) off = up(off + L->xr_stride * 4 * (size_t)n, 256);
-  L->has_scale = (sdt == PECANN_FP8E4M3);
+  L->has_scale = (tdt == PECANN_FP8E4M3);
   L->off_scale = off;
   if (L->has_scale) off = up(off + 4 * (size_t)n, 256);
   L->off_sqn = off;
@@ -257,6 +275,10 @@ static RowsDesc rows_of(const pecann_dataset *ds, const Layout &L) {
   r.xr_stride = (int64_t)L.xr_stride;
   r.sqn = (const uint32_t *)(base + L.off_sqn);
   r.sqn_r = L.has_xr ? (const float *)(base + L.off_sqn_r) : nullptr;
+  r.xg = L.has_xg ? base + L.off_xg : nullptr;
+  r.xg_stride = (int64_t)L.xg_stride;
+  r.xg_soff = (int32_t)L.xg_soff;
+  r.sqn_g = L.has_xg ? (const uint32_t *)(base + L.off_sqn_g) : nullptr;
   r.nch = (int32_t)(L.xs_stride / 16);
   r.nch_r = (int32_t)(L.xr_stride / 4);
   r.d = ds->d;
@@ -303,7 +325,9 @@ extern "C" pecann_status pecann_prepare_vectors(const void *x, int32_t x_dtype, 
                          L.has_xr ? (float *)(base + L.off_xr) : nullptr,
                          L.has_scale ? (float *)(base + L.off_scale) : nullptr,
                          (uint32_t *)(base + L.off_sqn),
-                         L.has_xr ? (float *)(base + L.off_sqn_r) : nullptr, (hipStream_t)stream));
+                         L.has_xr ? (float *)(base + L.off_sqn_r) : nullptr,
+                         L.has_xg ? base + L.off_xg : nullptr,
+                         L.has_xg ? (uint32_t *)(base + L.off_sqn_g) : nullptr, (hipStream_t)stream));
   return PECANN_OK;
 }
 
@@ -338,6 +362,7 @@ struct Carver {
 // 1,945 ms per step); the vector units for BF16 rows, which unpack with a
 // shift (1M x 128: 408 vs 424 ms; 64 instances x 384-d: 1,086 vs 1,407 ms).
 static int use_mfma(int32_t sdt, size_t row_bytes) {
+  if (sdt == PECANN_MXFP6) return 1;  // scored on the matrix cores only
   if (sdt != PECANN_BF16 && sdt != PECANN_FP8E4M3) return 0;
   if (g_tuning.scorer != 0) return g_tuning.scorer == 2;
   return sdt == PECANN_FP8E4M3 && row_bytes >= 512;
@@ -635,6 +660,7 @@ static pecann_status build_impl(const pecann_dataset *ds, const pecann_build_par
   hipStream_t s = (hipStream_t)stream;
   const RowsDesc rows = rows_of(ds, L);
   const int dt = ds->search_dtype;
+  const int tdt = tile_dtype(dt);
   const int S = engine_shape(dt, ds->d);
   const int passes = bp->passes == 0 ? 2 : bp->passes;
   const std::vector<BuildRound> sched = build_schedule(spec, bp, passes);
@@ -742,7 +768,7 @@ static pecann_status build_impl(const pecann_dataset *ds, const pecann_build_par
     pp.head = head_pf;
     {
       PROF(F_PRUNE_FWD, s);
-      HIP_TRY_ROUND(launch_prune_forward(dt, pp, persistent_grid(nb), s));
+      HIP_TRY_ROUND(launch_prune_forward(tdt, pp, persistent_grid(nb), s));
     }
     {
       PROF(F_REV, s);
@@ -758,12 +784,12 @@ static pecann_status build_impl(const pecann_dataset *ds, const pecann_build_par
       pp.heavy = 0;
       pp.head = head_pr;
       pp.capin = kLightIn;
-      HIP_TRY_ROUND(launch_prune_reverse(dt, pp, persistent_grid((int64_t)nb * R), s));
+      HIP_TRY_ROUND(launch_prune_reverse(tdt, pp, persistent_grid((int64_t)nb * R), s));
       pp.heavy = 1;
       pp.head = head_ph;
       pp.capin = kCapIn;
       const int heavy_grid = (int)std::min<int64_t>((int64_t)nb * R, (int64_t)cu_count() * kHeavyGridPerCu);
-      HIP_TRY_ROUND(launch_prune_reverse(dt, pp, heavy_grid, s));
+      HIP_TRY_ROUND(launch_prune_reverse(tdt, pp, heavy_grid, s));
     }
   }
   return PECANN_OK;
@@ -889,6 +915,7 @@ extern "C" pecann_status pecann_build_graph_nndescent(const pecann_dataset *ds,
   carve_nnd(c, n, K, reps, chunk, &w);
   hipStream_t s = (hipStream_t)stream;
   const int dt = ds->search_dtype;
+  const int tdt = tile_dtype(dt);
   const int cus = cu_count();
   unsigned long long *ctrs = (unsigned long long *)counters;
 
@@ -942,7 +969,7 @@ extern "C" pecann_status pecann_build_graph_nndescent(const pecann_dataset *ds,
     HIP_TRY(launch_fill_i32(P.done, 0, 1, s));
     {
       PROF(F_NND_LISTS, s);
-      HIP_TRY(launch_nnd_init(dt, P, init + (int64_t)r * n * K, (int)std::min<int64_t>(n, (int64_t)cus * 32), s));
+      HIP_TRY(launch_nnd_init(tdt, P, init + (int64_t)r * n * K, (int)std::min<int64_t>(n, (int64_t)cus * 32), s));
     }
     for (int it = 0; it < np->max_iters; ++it) {
       {
@@ -958,7 +985,7 @@ extern "C" pecann_status pecann_build_graph_nndescent(const pecann_dataset *ds,
         P.head = w.ctr + 2;
         {
           PROF(F_NND_JOIN, s);
-          HIP_TRY(launch_nnd_join(dt, P, jgrid, s));
+          HIP_TRY(launch_nnd_join(tdt, P, jgrid, s));
         }
         {
           PROF(F_NND_UPDATE, s);
@@ -1007,7 +1034,7 @@ extern "C" pecann_status pecann_build_graph_nndescent(const pecann_dataset *ds,
   pp.counters = ctrs ? ctrs + 3 : nullptr;
   {
     PROF(F_NND_PRUNE, s);
-    HIP_TRY(launch_prune_lists(dt, pp, persistent_grid(n), s));
+    HIP_TRY(launch_prune_lists(tdt, pp, persistent_grid(n), s));
   }
   if (knn_idx || knn_dist) HIP_TRY(launch_nnd_out(P, final_keys, knn_idx, knn_dist, cus, s));
   return PECANN_OK;
@@ -1107,6 +1134,8 @@ static RowsDesc shift_rows(RowsDesc r, int64_t lo) {
   if (r.scale) r.scale += lo;
   r.sqn += lo;
   if (r.sqn_r) r.sqn_r += lo;
+  if (r.xg) r.xg += lo * r.xg_stride;
+  if (r.sqn_g) r.sqn_g += lo;
   return r;
 }
 
@@ -1125,7 +1154,8 @@ static pecann_status knn_impl(const pecann_dataset *ds, const InstSpec &spec, co
     if (!deg) return fail(PECANN_EINVAL, "deg is NULL");
     if (R < 1 || R > 128) return fail(PECANN_EINVAL, "R must be in [1, 128]");
     if (L_search < k || L_search > 1024) return fail(PECANN_EINVAL, "L_search must be in [k, 1024]");
-    const bool lp = ds->search_dtype == PECANN_BF16 || ds->search_dtype == PECANN_FP8E4M3;
+    const bool lp = ds->search_dtype == PECANN_BF16 || ds->search_dtype == PECANN_FP8E4M3 ||
+                      ds->search_dtype == PECANN_MXFP6;
     if (lp && (rerank < k || rerank > L_search))
       return fail(PECANN_EINVAL, "rerank must be in [k, L_search]");
   }
@@ -1142,6 +1172,7 @@ static pecann_status knn_impl(const pecann_dataset *ds, const InstSpec &spec, co
   hipStream_t s = (hipStream_t)stream;
   const RowsDesc rows = rows_of(ds, L);
   const int dt = ds->search_dtype;
+  const int tdt = tile_dtype(dt);
   const int S = engine_shape(dt, ds->d);
   HIP_TRY(launch_fill_i32(ctr, 0, 8, s));
   HIP_TRY(upload_inst(spec, w.inst, s));
@@ -1188,7 +1219,7 @@ static pecann_status knn_impl(const pecann_dataset *ds, const InstSpec &spec, co
       ep.fb_count = ctr + 1;
       HIP_TRY(launch_fill_i32(ctr, 0, 1, s));
       PROF(F_EXACT_MFMA, s);
-      HIP_TRY(launch_exact_mfma(dt, S, ep, s));
+      HIP_TRY(launch_exact_mfma(tdt, S, ep, s));
     }
     HIP_TRY(launch_small_instance_points(n, itab, (int32_t)kExactMfmaMin, fb, ctr + 1, s));
     PROF(F_BF_KNN, s);
@@ -1199,11 +1230,11 @@ static pecann_status knn_impl(const pecann_dataset *ds, const InstSpec &spec, co
     bp.kpart = k;
     bp.head = ctr + 3;
     bp.head2 = ctr + 4;
-    HIP_TRY(launch_bf_knn_split(dt, S, bp, persistent_grid((int64_t)kSplitCap * bp.nchunk),
+    HIP_TRY(launch_bf_knn_split(tdt, S, bp, persistent_grid((int64_t)kSplitCap * bp.nchunk),
                                 persistent_grid(kSplitCap), s));
     bp.head = ctr + 2;
     bp.item_from = kSplitCap;
-    HIP_TRY(launch_bf_knn(dt, S, bp, persistent_grid(n), s));
+    HIP_TRY(launch_bf_knn(tdt, S, bp, persistent_grid(n), s));
     return PECANN_OK;
   }
   SearchParams sp = {};
@@ -1239,7 +1270,7 @@ static pecann_status knn_impl(const pecann_dataset *ds, const InstSpec &spec, co
   }
   // too-few-results fallback: exact search for those queries
   PROF(F_BF_KNN, s);
-  HIP_TRY(launch_bf_knn(dt, S, bp, cu_count() * 4, s));
+  HIP_TRY(launch_bf_knn(tdt, S, bp, cu_count() * 4, s));
   return PECANN_OK;
 }
 
@@ -1360,6 +1391,7 @@ static pecann_status dep_impl(const pecann_dataset *ds, const InstSpec &spec, co
   hipStream_t s = (hipStream_t)stream;
   const RowsDesc rows = rows_of(ds, L);
   const int dt = ds->search_dtype;
+  const int tdt = tile_dtype(dt);
   const int S = engine_shape(dt, ds->d);
 
   HIP_TRY(launch_fill_i32(w.ctr, 0, 64, s));
@@ -1427,7 +1459,7 @@ static pecann_status dep_impl(const pecann_dataset *ds, const InstSpec &spec, co
   bd.best = w.best;
   {
     PROF(F_BF_DEP, s);
-    HIP_TRY(launch_bf_dep(dt, S, bd, persistent_grid(n * (int64_t)bd.nchunks), s));
+    HIP_TRY(launch_bf_dep(tdt, S, bd, persistent_grid(n * (int64_t)bd.nchunks), s));
   }
   HIP_TRY(launch_bf_dep_finalize(cur, w.ucnt + nr, w.best, ds->metric, dep, delta, (int32_t)n, s));
   if (stats) {

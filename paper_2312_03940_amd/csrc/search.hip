@@ -15,7 +15,8 @@ static hipError_t launch_search_vec(const SearchParams &p, int grid, hipStream_t
 }
 
 hipError_t launch_search(int32_t dt, int S, const SearchParams &p, int grid, hipStream_t st) {
-  if (p.mfma && (dt == PECANN_BF16 || dt == PECANN_FP8E4M3)) return launch_search_mfma(dt, S, p, grid, st);
+  if (dt == PECANN_MXFP6 || (p.mfma && (dt == PECANN_BF16 || dt == PECANN_FP8E4M3)))
+    return launch_search_mfma(dt, S, p, grid, st);
   PECANN_DISPATCH_SHAPE(launch_search_vec, dt, S, p, grid, st)
 }
 

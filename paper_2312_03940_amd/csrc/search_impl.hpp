@@ -153,7 +153,10 @@ __device__ __forceinline__ void search_body(const SearchParams &p) {
   Lds s = carve(smem, p.L, p.hbits);
   const int l = lane_id();
   const int count = p.item_count ? *p.item_count : p.nitems;
-  constexpr bool kNeedRerank = (DT == PECANN_BF16 || DT == PECANN_FP8E4M3);
+  constexpr bool kNeedRerank = (DT == PECANN_BF16 || DT == PECANN_FP8E4M3 || DT == PECANN_MXFP6);
+  // MXFP6 rows are scored on the matrix cores only; the vector-unit types below
+  // are then those of the FP8 copy and go unused
+  constexpr int DTE = DT == PECANN_MXFP6 ? PECANN_FP8E4M3 : DT;
 
 
   // build searches over float32 rows of 64 chunks or more run at most two
@@ -162,8 +165,9 @@ __device__ __forceinline__ void search_body(const SearchParams &p) {
   // 190 -> 186 ms per step; the FP8 and BF16 builds, whose time goes to
   // decoding and FMAs, gained nothing)
   constexpr int kLc = (DT == PECANN_F32 && MODE == MODE_BUILD && S >= 64) ? 32 : 0;
-  Engine<DT, S, false, kLc> eng;
-  constexpr bool kMfma = MF && (DT == PECANN_BF16 || DT == PECANN_FP8E4M3);
+  Engine<DTE, S, false, kLc> eng;
+  constexpr bool kMfma = MF && (DT == PECANN_BF16 || DT == PECANN_FP8E4M3 || DT == PECANN_MXFP6);
+  static_assert(DT != PECANN_MXFP6 || kMfma, "MXFP6 rows need the matrix-core scorer");
   using Scorer = typename std::conditional<kMfma, MfmaScorer<kMfma ? DT : PECANN_BF16, S>, int>::type;
   Scorer msc{};
   if constexpr (kMfma) msc.qp = s.qp;
@@ -171,7 +175,7 @@ __device__ __forceinline__ void search_body(const SearchParams &p) {
     if constexpr (kMfma) msc.score(p.rows, c, id_of, out);
     else score_keys(eng, p.rows, c, id_of, out);
   };
-  constexpr int SR = RerankShape<DT, S>::v;
+  constexpr int SR = RerankShape<DTE, S>::v;
   for (;;) {
     const int it = next_item(p.head);
     if (it >= count) break;
@@ -308,7 +312,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void se
 
 template <int DT, int S, bool MF>
 constexpr int scorer_lds_bytes() {
-  if constexpr (MF && (DT == PECANN_BF16 || DT == PECANN_FP8E4M3)) return MfmaScorer<DT, S>::LDS_BYTES;
+  if constexpr (MF && (DT == PECANN_BF16 || DT == PECANN_FP8E4M3 || DT == PECANN_MXFP6))
+    return MfmaScorer<DT, S>::LDS_BYTES;
   else return 0;
 }
 

@@ -1,5 +1,5 @@
 // K2 greedy beam search with the candidates scored on the matrix cores
-// (mfma_score.hpp): BF16 and FP8 search rows.
+// (mfma_score.hpp): BF16, FP8 and MXFP6 search rows.
 #include "search_impl.hpp"
 
 namespace pecann {
@@ -13,6 +13,7 @@ hipError_t launch_search_mfma(int32_t dt, int S, const SearchParams &p, int grid
   switch (dt) {
     case PECANN_BF16: PECANN_SHAPES(launch_search_mf, PECANN_BF16, S, p, grid, st)
     case PECANN_FP8E4M3: PECANN_SHAPES(launch_search_mf, PECANN_FP8E4M3, S, p, grid, st)
+    case PECANN_MXFP6: PECANN_SHAPES(launch_search_mf, PECANN_MXFP6, S, p, grid, st)
     default: return hipErrorInvalidValue;
   }
 }

@@ -17,11 +17,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpecann.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "pecann.h")
 
-F32, U8, BF16, FP8E4M3 = 0, 1, 2, 3
+F32, U8, BF16, FP8E4M3, MXFP6 = 0, 1, 2, 3, 4
 L2, COSINE = 0, 1
 CENTER_PRODUCT, CENTER_THRESHOLD, CENTER_GIVEN = 0, 1, 2
 DENSITY_FNS = {"kth": 0, "normalized": 1, "exp-sum": 2, "sum-exp": 3, "sum": 4}
-DTYPES = {"f32": F32, "u8": U8, "bf16": BF16, "fp8": FP8E4M3}
+DTYPES = {"f32": F32, "u8": U8, "bf16": BF16, "fp8": FP8E4M3, "mxfp6": MXFP6}
 METRICS = {"l2": L2, "cosine": COSINE}
 
 

@@ -51,6 +51,11 @@ def test_prepared_bytes_layout(lib):
     assert bf == up(256 * n) + up(512 * n) + 2 * nrm
     f8 = lib.pecann_prepared_bytes(n, 1024, pecann.COSINE, pecann.FP8E4M3)
     assert f8 == up(1024 * n) + up(4096 * n) + up(4 * n) + 2 * nrm
+    # MXFP6: the FP8 copy, the MXFP6 rows (8 steps of 100 bytes, padded to
+    # 832) with their norms, then what FP8 keeps
+    mx = lib.pecann_prepared_bytes(n, 1000, pecann.L2, pecann.MXFP6)
+    assert mx == up(1024 * n) + up(832 * n) + nrm + up(4000 * n) + up(4 * n) + 2 * nrm
+    assert lib.pecann_prepared_bytes(n, 16, pecann.L2, 5) == 0
     assert lib.pecann_prepared_bytes(n, 5, pecann.L2, pecann.U8) == up(16 * n) + nrm
     assert lib.pecann_prepared_bytes(n, 7, pecann.L2, pecann.F32) == up(32 * n) + nrm
     # invalid combinations

@@ -129,6 +129,89 @@ def test_prepare_fp8_scaled(dev, metric):
     assert not np.isnan(dec).any()
 
 
+def _e2m3_value(c):
+    """OCP MX FP6 e2m3: 1 sign, 2 exponent bits (bias 1), 3 mantissa bits."""
+    c = np.asarray(c, dtype=np.int64)
+    e = (c >> 3) & 3
+    m = c & 7
+    v = np.where(e == 0, m / 8.0, (1 + m / 8.0) * 2.0 ** (e - 1))
+    return np.where(c & 32, -v, v)
+
+
+_E2M3_GRID = np.unique(np.abs(_e2m3_value(np.arange(32))))  # 0, 0.125, ..., 7.5
+
+
+def _mxfp6_layout(n, d):
+    xs_stride = (d + 127) // 128 * 128          # FP8 copy
+    off_xg = (xs_stride * n + 255) // 256 * 256
+    steps = (d + 127) // 128
+    stride = (100 * steps + 63) // 64 * 64
+    off_sqng = (off_xg + stride * n + 255) // 256 * 256
+    return off_xg, stride, 96 * steps, steps, off_sqng
+
+
+@pytest.mark.parametrize("metric", ["cosine", "l2"])
+def test_prepare_mxfp6_blocks(dev, metric):
+    # MXFP6 search rows (OCP MX e2m3 with E8M0 block scales over 32 dims)
+    # decoded here independently: each block's scale is the smallest power of
+    # two that fits its largest magnitude under 7.5, and each value is the
+    # nearest e2m3 value of x / 2^E (ties to an even mantissa)
+    rng = np.random.default_rng(5)
+    n, d = 257, 1000
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    X[:, :40] *= 1e-3  # blocks of very different ranges
+    X[3] = 0.0         # an all-zero row
+    if metric == "l2":
+        X *= rng.uniform(0.01, 100.0, size=(n, 1)).astype(np.float32)
+    ds = pecann.Dataset(_t(X, dev), metric, "mxfp6")
+    prep = _np(ds.prep)
+    off_xg, stride, soff, steps, off_sqng = _mxfp6_layout(n, d)
+    rows = prep[off_xg: off_xg + stride * n].reshape(n, stride)
+    # the float32 rows the codes were made from: the rerank copy after the norms
+    off_xr = (off_sqng + 4 * n + 255) // 256 * 256
+    xr_stride = (d + 3) // 4 * 4
+    ref = prep[off_xr: off_xr + 4 * xr_stride * n].view(np.float32).reshape(n, xr_stride)[:, :d]
+    if metric == "cosine":
+        nr = np.linalg.norm(X.astype(np.float64), axis=1, keepdims=True)
+        assert np.allclose(ref, X / np.where(nr > 0, nr, 1), rtol=2e-6, atol=1e-7)
+    else:
+        assert np.array_equal(ref, X)
+    nblk = 4 * steps
+    ref_p = np.zeros((n, 128 * steps), np.float64)
+    ref_p[:, :d] = ref
+    blocks = ref_p.reshape(n, nblk, 32)
+    # codes: block b's 24 bytes, value i in bits [6i, 6i + 6)
+    raw = rows[:, : 24 * nblk].reshape(n, nblk, 24).astype(np.uint64)
+    words = [sum(raw[:, :, 8 * w + t] << np.uint64(8 * t) for t in range(8)) for w in range(3)]
+    codes = np.zeros((n, nblk, 32), np.int64)
+    for i in range(32):
+        bit = 6 * i
+        w, o = bit // 64, bit % 64
+        v = words[w] >> np.uint64(o)
+        if o > 58:
+            v = v | (words[w + 1] << np.uint64(64 - o))
+        codes[:, :, i] = (v & np.uint64(63)).astype(np.int64)
+    E = rows[:, soff: soff + nblk].astype(np.int64) - 127
+    assert np.all(rows[:, soff + nblk:] == 0)
+    amax = np.abs(blocks).max(axis=2)
+    live = amax > 0
+    assert np.all(amax[live] <= 7.5 * 2.0 ** E[live])
+    assert np.all(amax[live] > 7.5 * 2.0 ** (E[live] - 1))
+    assert np.all((codes[~live] & 31) == 0)
+    y = blocks / 2.0 ** E[:, :, None]
+    dq = _e2m3_value(codes)
+    # nearest grid value, ties to the even mantissa
+    dist = np.abs(np.abs(y)[..., None] - _E2M3_GRID)
+    best = dist.min(axis=-1)
+    assert np.all(np.abs(np.abs(dq) - np.abs(y)) <= best + 1e-12)
+    tie = (np.sort(dist, axis=-1)[..., 1] - best) <= 1e-12
+    assert np.all((codes[tie] & 1) == 0)
+    assert np.all((np.sign(dq) == np.sign(y)) | (dq == 0))
+    sqn = prep[off_sqng: off_sqng + 4 * n].view(np.float32)
+    want = (dq * 2.0 ** E[:, :, None]) ** 2
+    assert np.allclose(sqn, want.sum(axis=(1, 2)), rtol=1e-5, atol=1e-30)
+
+
 # ----------------------------------------------------------------------------
 # exact mode (K1 + K5 + K7 + K10 + K11)
 # ----------------------------------------------------------------------------
@@ -465,12 +548,13 @@ def test_c3_shaped_bf16_vs_oracle(dev, sdt):
     assert np.all(key[dep[ok]] < key[ok]) and (~ok).sum() == 1
 
 
-def test_c4_shaped_fp8_cosine_vs_oracle(dev):
+@pytest.mark.parametrize("sdt", ["fp8", "mxfp6"])
+def test_c4_shaped_fp8_cosine_vs_oracle(dev, sdt):
     X, _ = datagen.config4(n_clusters=40, per_cluster=400, d=1024)
     n = X.shape[0]
     P = oracle.Points(X, oracle.COSINE)
     ref = oracle.exact_dpc(X, k=10, n_c=40, metric=oracle.COSINE)
-    idx, dist, labels, dep, key = _anns_gpu(X, "cosine", "fp8", 10, 40, 64, 200, 1.2, 64, 64, dev)
+    idx, dist, labels, dep, key = _anns_gpu(X, "cosine", sdt, 10, 40, 64, 200, 1.2, 64, 64, dev)
     q = np.arange(0, n, 41)
     rec = metrics.recall_at_k(P, q, idx[q], ref["knn_dist"][q], 10)
     a = metrics.ari(labels, ref["labels"])
