@@ -36,9 +36,10 @@ struct SortedList {
   }
 
   // Merge one candidate key per lane (kNoKey = none) into the list, keeping the
-  // `cap` smallest.  Keys already present are ignored; the keys of one call are
+  // `cap` smallest.  The merges are always inlined: an out-of-line copy would
+  // reach the LDS through generic pointers from a scratch stack.  Keys already present are ignored; the keys of one call are
   // distinct.  Returns the number of keys that entered the list.
-  __device__ int merge(uint64_t mykey) {
+  __device__ __forceinline__ int merge(uint64_t mykey) {
     if (m == cap && mykey >= tail) mykey = kNoKey;
     const uint64_t cm = ballot(mykey != kNoKey);
     if (cm == 0) return 0;
@@ -49,7 +50,7 @@ struct SortedList {
   // rank among the others by direct comparison (no sort); the list is updated
   // in place, moving only the entries behind the first insertion point (in
   // 64-entry chunks from the top, each read before any of it is written).
-  __device__ int merge_few(uint64_t mykey) {
+  __device__ __forceinline__ int merge_few(uint64_t mykey) {
     const int l = lane_id();
     bool valid = mykey != kNoKey;
     int pos = 0;
@@ -96,7 +97,7 @@ struct SortedList {
   }
 
   // Many candidates: bitonic sort across the wave, then merge by ranks.
-  __device__ int merge_sorted(uint64_t mykey) {
+  __device__ __forceinline__ int merge_sorted(uint64_t mykey) {
     const int l = lane_id();
     uint64_t s = wave_sort_u64(mykey);
     bool valid = (s != kNoKey);
