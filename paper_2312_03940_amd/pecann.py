@@ -14,7 +14,8 @@ import re
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpecann.so")
+# PECANN_LIB: another build of the library to load (the sanitizer tests use it)
+LIB_PATH = os.environ.get("PECANN_LIB") or os.path.join(_HERE, "libpecann.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "pecann.h")
 
 F32, U8, BF16, FP8E4M3, MXFP6 = 0, 1, 2, 3, 4

@@ -183,3 +183,47 @@ def test_tuning_validation(lib):
     pecann.reset_tuning()
     assert pecann.get_tuning() == {"hash_bits_build": 0, "hash_bits_search": 0, "grid_per_cu": 0,
                                    "scorer": 0}
+
+
+def test_workspace_sizes_host_only(lib):
+    # every workspace-size query is host arithmetic (no GPU): sizes are positive
+    # for valid shapes, grow with n, and are 0 for invalid arguments; the
+    # batched queries read the caller's host instance table
+    for sdt, metric, d in ((pecann.F32, pecann.L2, 16), (pecann.U8, pecann.L2, 784),
+                           (pecann.BF16, pecann.L2, 128), (pecann.FP8E4M3, pecann.COSINE, 1024),
+                           (pecann.MXFP6, pecann.COSINE, 1000)):
+        prev = None
+        for n in (2, 1000, 70000):
+            ds = pecann._Dataset(n, d, metric, sdt, 0, 256)
+            bp = pecann._BuildParams(64, 128, 1.2, 8, 0, 0, 2, 0)
+            sizes = [lib.pecann_build_graph_workspace_size(ctypes.byref(ds), ctypes.byref(bp)),
+                     lib.pecann_knn_density_workspace_size(ctypes.byref(ds), 10, 64, 0),
+                     lib.pecann_knn_density_workspace_size(ctypes.byref(ds), 10, 64, 1),
+                     lib.pecann_dependent_search_workspace_size(ctypes.byref(ds), 32, 1024),
+                     lib.pecann_cluster_workspace_size(n)]
+            assert all(s > 0 for s in sizes), (sdt, n, sizes)
+            if prev is not None:
+                assert all(a >= b for a, b in zip(sizes, prev)), (sdt, n)
+            prev = sizes
+            nnd = pecann._NndParams(16, 32, 1.2, 10, 0.001, 1, 0, 0)
+            assert lib.pecann_build_graph_nndescent_workspace_size(ctypes.byref(ds), ctypes.byref(nnd)) >= 0
+        bad = pecann._BuildParams(0, 128, 1.2, 8, 0, 0, 2, 0)
+        assert lib.pecann_build_graph_workspace_size(ctypes.byref(ds), ctypes.byref(bad)) == 0
+        assert lib.pecann_knn_density_workspace_size(ctypes.byref(ds), 0, 64, 0) == 0
+    # batched: three instances over 9,000 points
+    off = (ctypes.c_int64 * 4)(0, 1000, 4000, 9000)
+    ks = (ctypes.c_int32 * 3)(5, 10, 20)
+    ncs = (ctypes.c_int32 * 3)(2, 3, 4)
+    inst = pecann._Instances(3, 0, off, ks, ncs)
+    ds = pecann._Dataset(9000, 64, pecann.L2, pecann.BF16, 0, 256)
+    bp = pecann._BuildParams(32, 64, 1.2, 4, 0, 0, 2, 0)
+    assert lib.pecann_build_graph_batched_workspace_size(ctypes.byref(ds), ctypes.byref(bp), ctypes.byref(inst)) > 0
+    assert lib.pecann_knn_density_batched_workspace_size(ctypes.byref(ds), ctypes.byref(inst), 20, 64, 0) > 0
+    assert lib.pecann_dependent_search_batched_workspace_size(ctypes.byref(ds), ctypes.byref(inst), 32, 256) > 0
+    assert lib.pecann_cluster_batched_workspace_size(9000, ctypes.byref(inst)) > 0
+    assert lib.pecann_density_workspace_size(9000, ctypes.byref(inst)) >= 0
+    assert lib.pecann_local_centers_workspace_size(9000, ctypes.byref(inst)) >= 0
+    # instance offsets that do not cover the point set are rejected
+    off_bad = (ctypes.c_int64 * 4)(0, 1000, 4000, 8000)
+    inst_bad = pecann._Instances(3, 0, off_bad, ks, ncs)
+    assert lib.pecann_knn_density_batched_workspace_size(ctypes.byref(ds), ctypes.byref(inst_bad), 20, 64, 0) == 0
