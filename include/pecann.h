@@ -47,7 +47,9 @@ typedef enum {
   PECANN_EINVAL = 1,       /* an argument is out of range or misaligned */
   PECANN_EWORKSPACE = 2,   /* ws is NULL or smaller than *_workspace_size() */
   PECANN_EHIP = 3,         /* a HIP runtime call or launch failed */
-  PECANN_EUNSUPPORTED = 4  /* valid but not supported combination */
+  PECANN_EUNSUPPORTED = 4, /* valid but not supported combination */
+  PECANN_ECHECK = 5        /* checked builds only (PECANN_CHECKED): a kernel found
+                              a broken invariant; pecann_last_error() names it */
 } pecann_status;
 
 /* Element type of a row store. */

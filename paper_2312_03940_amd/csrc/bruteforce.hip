@@ -179,8 +179,10 @@ __global__ __launch_bounds__(64) void bf_dep_kernel(BfDepParams p) {
     const int u = it / p.nchunks;
     const int ch = it - u * p.nchunks;
     const int32_t qid = p.ulist[u];
+    PECANN_CHECK(qid >= 0 && qid < p.n, CK_ITEM);
     const int ti = find_instance(p.inst, qid);
     const int32_t lo = (int32_t)p.inst.off[ti], hi = (int32_t)p.inst.off[ti + 1];
+    PECANN_CHECK(lo <= qid && qid < hi, CK_INSTANCE);
     const int j0 = lo + ch * p.chunk;
     if (j0 >= hi) continue;  // beyond this instance
     const int j1 = min(hi, j0 + p.chunk);
@@ -249,5 +251,7 @@ hipError_t launch_bf_knn_split(int32_t dt, int S, const BfKnnParams &p, int grid
 hipError_t launch_bf_dep(int32_t dt, int S, const BfDepParams &p, int grid, hipStream_t st) {
   PECANN_DISPATCH_SHAPE(launch_bf_dep_t, dt, S, p, grid, st)
 }
+
+PECANN_CHECK_READER(bruteforce)
 
 }  // namespace pecann

@@ -15,6 +15,43 @@ namespace pecann {
 constexpr int kWave = 64;
 constexpr uint64_t kNoKey = ~0ull;
 
+// Checked builds (compiled with -DPECANN_CHECKED): kernels test invariants of
+// their inputs and state and record a broken one as a bit of a device word of
+// their translation unit; after each entry point the host synchronises, reads
+// and clears the words and fails the call with PECANN_ECHECK.  Other builds
+// compile the checks away.
+enum CheckBit : uint32_t {
+  CK_ITEM = 1u << 0,       // a work item or query outside the point set
+  CK_NEIGHBOUR = 1u << 1,  // an adjacency entry or degree outside its range
+  CK_BEAM = 1u << 2,       // a beam longer than its capacity or out of order
+  CK_INSTANCE = 1u << 3,   // a point outside the instance found for it
+  CK_PRUNE = 1u << 4,      // a prune's candidate count or output beyond its bound
+  CK_REVERSE = 1u << 5,    // a reverse edge written outside its batch's segments
+  CK_CHUNK = 1u << 6,      // a scan chunk outside its instance
+  CK_LABEL = 1u << 7,      // a cluster label or dependent outside the point set
+};
+#ifdef PECANN_CHECKED
+static __device__ uint32_t g_check_word;
+#define PECANN_CHECK(cond, bit)                                               \
+  do {                                                                        \
+    if (!(cond)) atomicOr(&::pecann::g_check_word, (uint32_t)(bit));           \
+  } while (0)
+#define PECANN_CHECK_READER(name)                                             \
+  uint32_t check_take_##name() {                                              \
+    uint32_t v = 0, z = 0;                                                    \
+    if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_check_word), 4, 0, hipMemcpyDeviceToHost) != hipSuccess) \
+      return 0x80000000u;                                                     \
+    if (hipMemcpyToSymbol(HIP_SYMBOL(g_check_word), &z, 4, 0, hipMemcpyHostToDevice) != hipSuccess) \
+      return 0x80000000u;                                                     \
+    return v;                                                                 \
+  }
+#else
+#define PECANN_CHECK(cond, bit) \
+  do {                          \
+  } while (0)
+#define PECANN_CHECK_READER(name)
+#endif
+
 // ---------------------------------------------------------------------------
 // Keys.  A candidate is (distance measure, index) packed as
 // float_bits(measure) << 32 | index.  The measure is never negative (squared

@@ -263,6 +263,7 @@ __global__ __launch_bounds__(64) void exact_rerank_kernel(ExactMfmaParams p, flo
     const int32_t *c = p.cand + (int64_t)q * kCand;
     constexpr int kKept = 16 * kq_of<DT == PECANN_U8 ? PECANN_U8 : PECANN_F32>();
     for (int base = 0; base < kKept; base += kWave) {
+      PECANN_CHECK(c[base + l] >= -1 && c[base + l] < p.n, CK_ITEM);  // kept candidates (-1: none)
       score_keys(eng, p.rows, kWave, [&](int i) { return c[base + i]; }, kb);
       wave_lds_sync();
       const uint64_t key = kb[l];
@@ -362,5 +363,7 @@ hipError_t launch_exact_mfma(int32_t dt, int S, const ExactMfmaParams &p, hipStr
   const int grid = (int)std::min<int64_t>((int64_t)p.n, 256 * 32);
   return launch_rerank(dt, S, p, ce, u8 ? 1 : 0, grid, st);
 }
+
+PECANN_CHECK_READER(exact)
 
 }  // namespace pecann

@@ -40,6 +40,17 @@ struct RowsDesc {  // host copy of the row description (mirrors Rows)
 
 enum SearchMode { MODE_KNN = 0, MODE_DEP = 1, MODE_BUILD = 2 };
 
+#ifdef PECANN_CHECKED
+// invariant-check words of each translation unit (read and cleared)
+uint32_t check_take_search();
+uint32_t check_take_search_mfma();
+uint32_t check_take_prune();
+uint32_t check_take_misc();
+uint32_t check_take_bruteforce();
+uint32_t check_take_exact();
+uint32_t check_take_nndescent();
+#endif
+
 // Independent instances over one point set (device tables): instance t owns
 // points [off[t], off[t+1]); k[t] and nc[t] are its kNN size and center count.
 struct InstTable {

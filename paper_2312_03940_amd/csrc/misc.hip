@@ -391,6 +391,7 @@ __global__ void rev_scatter_kernel(const int32_t *adj, const int32_t *deg, const
   const int64_t ae = (int64_t)p * R + e;
   const int32_t q = adj[ae];
   const int64_t pos = (int64_t)toff[tidx[q]] + ticket[i];
+  PECANN_CHECK(pos >= 0 && pos < (int64_t)nb * R, CK_REVERSE);  // segments hold the batch's edges
   seg[pos] = p;
   if (akey) segk[pos] = (akey[ae] & 0xffffffff00000000ull) | (uint32_t)p;
 }
@@ -685,6 +686,7 @@ __global__ void jump_kernel(int64_t n, int32_t *labels, int32_t *flag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int32_t cur = __hip_atomic_load(&labels[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  PECANN_CHECK(cur >= 0 && cur < n, CK_LABEL);
   for (int64_t step = 0; step <= n; ++step) {
     const int32_t nxt = __hip_atomic_load(&labels[cur], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (nxt == cur) {
@@ -766,5 +768,7 @@ hipError_t launch_small_instance_points(int64_t n, const InstTable &inst, int32_
                      n, inst, below, list, count);
   return hipGetLastError();
 }
+
+PECANN_CHECK_READER(misc)
 
 }  // namespace pecann

@@ -610,4 +610,6 @@ hipError_t launch_nnd_copy(const uint64_t *src, uint64_t *dst, int64_t n, int cu
   return hipGetLastError();
 }
 
+PECANN_CHECK_READER(nndescent)
+
 }  // namespace pecann

@@ -32,6 +32,23 @@ static pecann_status fail(pecann_status s, const char *fmt, ...) {
   return s;
 }
 
+// Checked builds: after an entry point's launches, wait for them and fail the
+// call if a kernel recorded a broken invariant.
+static pecann_status check_device(pecann_status st) {
+#ifdef PECANN_CHECKED
+  if (st != PECANN_OK) return st;
+  const hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return fail(PECANN_EHIP, "hipDeviceSynchronize: %s", hipGetErrorString(e));
+  using namespace pecann;
+  const uint32_t w = check_take_search() | check_take_search_mfma() | check_take_prune() | check_take_misc() |
+                     check_take_bruteforce() | check_take_exact() | check_take_nndescent();
+  if (w)
+    return fail(PECANN_ECHECK, "device invariant check failed: bits 0x%x (1 item, 2 neighbour, 4 beam, "
+                "8 instance, 16 prune, 32 reverse edge, 64 chunk, 128 label)", w);
+#endif
+  return st;
+}
+
 #define HIP_TRY(expr)                                                                        \
   do {                                                                                       \
     hipError_t e_ = (expr);                                                                  \
@@ -58,6 +75,7 @@ extern "C" const char *pecann_status_string(pecann_status s) {
     case PECANN_EWORKSPACE: return "workspace too small";
     case PECANN_EHIP: return "HIP error";
     case PECANN_EUNSUPPORTED: return "unsupported";
+    case PECANN_ECHECK: return "device invariant check failed";
   }
   return "unknown status";
 }
@@ -1037,7 +1055,7 @@ extern "C" pecann_status pecann_build_graph_nndescent(const pecann_dataset *ds,
     HIP_TRY(launch_prune_lists(tdt, pp, persistent_grid(n), s));
   }
   if (knn_idx || knn_dist) HIP_TRY(launch_nnd_out(P, final_keys, knn_idx, knn_dist, cus, s));
-  return PECANN_OK;
+  return check_device(PECANN_OK);
 }
 
 extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const pecann_build_params *bp,
@@ -1046,8 +1064,8 @@ extern "C" pecann_status pecann_build_graph(const pecann_dataset *ds, const peca
                                             size_t ws_bytes, void *stream) {
   clear_stale_error();
   if (!ds) return fail(PECANN_EINVAL, "dataset is NULL");
-  return build_impl(ds, bp, single_spec(ds->n, 1, 1), perm, seed, adj, deg, counters, ws, ws_bytes,
-                    stream);
+  return check_device(build_impl(ds, bp, single_spec(ds->n, 1, 1), perm, seed, adj, deg, counters, ws, ws_bytes,
+                    stream));
 }
 
 extern "C" pecann_status pecann_build_graph_batched(const pecann_dataset *ds,
@@ -1062,7 +1080,7 @@ extern "C" pecann_status pecann_build_graph_batched(const pecann_dataset *ds,
   InstSpec sp;
   pecann_status st = make_spec(ds->n, inst, 1, 1, &sp);
   if (st != PECANN_OK) return st;
-  return build_impl(ds, bp, sp, perm, seed, adj, deg, counters, ws, ws_bytes, stream);
+  return check_device(build_impl(ds, bp, sp, perm, seed, adj, deg, counters, ws, ws_bytes, stream));
 }
 
 // ---------------------------------------------------------------------------
@@ -1283,8 +1301,8 @@ extern "C" pecann_status pecann_knn_density(const pecann_dataset *ds, const int3
   clear_stale_error();
   if (!ds) return fail(PECANN_EINVAL, "dataset is NULL");
   if (k < 1 || k > 64 || k > ds->n - 1) return fail(PECANN_EINVAL, "k must be in [1, min(n-1, 64)]");
-  return knn_impl(ds, single_spec(ds->n, k, 1), adj, deg, R, k, L_search, rerank, knn_idx, knn_dist,
-                  rho, rank_key, counters, ws, ws_bytes, stream);
+  return check_device(knn_impl(ds, single_spec(ds->n, k, 1), adj, deg, R, k, L_search, rerank, knn_idx, knn_dist,
+                  rho, rank_key, counters, ws, ws_bytes, stream));
 }
 
 extern "C" pecann_status pecann_knn_density_batched(const pecann_dataset *ds,
@@ -1300,8 +1318,8 @@ extern "C" pecann_status pecann_knn_density_batched(const pecann_dataset *ds,
   InstSpec sp;
   pecann_status st = make_spec(ds->n, inst, k_max, 1, &sp);
   if (st != PECANN_OK) return st;
-  return knn_impl(ds, sp, adj, deg, R, k_max, L_search, rerank, knn_idx, knn_dist, rho, rank_key,
-                  counters, ws, ws_bytes, stream);
+  return check_device(knn_impl(ds, sp, adj, deg, R, k_max, L_search, rerank, knn_idx, knn_dist, rho, rank_key,
+                  counters, ws, ws_bytes, stream));
 }
 
 // ---------------------------------------------------------------------------
@@ -1480,8 +1498,8 @@ extern "C" pecann_status pecann_dependent_search(const pecann_dataset *ds, const
   clear_stale_error();
   if (!ds) return fail(PECANN_EINVAL, "dataset is NULL");
   if (k < 1 || k > 64 || k > ds->n - 1) return fail(PECANN_EINVAL, "k must be in [1, min(n-1, 64)]");
-  return dep_impl(ds, single_spec(ds->n, k, 1), adj, deg, R, rank_key, knn_idx, knn_dist, k, L_d,
-                  L_search, threshold, kdep_cap, dep, delta, stats, ws, ws_bytes, stream);
+  return check_device(dep_impl(ds, single_spec(ds->n, k, 1), adj, deg, R, rank_key, knn_idx, knn_dist, k, L_d,
+                  L_search, threshold, kdep_cap, dep, delta, stats, ws, ws_bytes, stream));
 }
 
 extern "C" pecann_status pecann_dependent_search_batched(const pecann_dataset *ds,
@@ -1499,8 +1517,8 @@ extern "C" pecann_status pecann_dependent_search_batched(const pecann_dataset *d
   InstSpec sp;
   pecann_status st = make_spec(ds->n, inst, k_max, 1, &sp);
   if (st != PECANN_OK) return st;
-  return dep_impl(ds, sp, adj, deg, R, rank_key, knn_idx, knn_dist, k_max, L_d, L_search, threshold,
-                  kdep_cap, dep, delta, stats, ws, ws_bytes, stream);
+  return check_device(dep_impl(ds, sp, adj, deg, R, rank_key, knn_idx, knn_dist, k_max, L_d, L_search, threshold,
+                  kdep_cap, dep, delta, stats, ws, ws_bytes, stream));
 }
 
 // ---------------------------------------------------------------------------
@@ -1564,8 +1582,8 @@ extern "C" pecann_status pecann_cluster(int64_t n, const float *rho, const int32
   if (n < 1 || n >= (int64_t)1 << 31) return fail(PECANN_EINVAL, "n out of range");
   if (center_mode == PECANN_CENTER_PRODUCT && (n_c < 1 || n_c > n))
     return fail(PECANN_EINVAL, "n_c must be in [1, n]");
-  return cluster_impl(n, single_spec(n, 1, n_c), rho, dep, delta, center_mode, delta_min, rho_min,
-                      labels, is_center, ws, ws_bytes, stream);
+  return check_device(cluster_impl(n, single_spec(n, 1, n_c), rho, dep, delta, center_mode, delta_min, rho_min,
+                      labels, is_center, ws, ws_bytes, stream));
 }
 
 extern "C" pecann_status pecann_cluster_batched(int64_t n, const pecann_instances *inst,
@@ -1579,8 +1597,8 @@ extern "C" pecann_status pecann_cluster_batched(int64_t n, const pecann_instance
   InstSpec sp;
   pecann_status st = make_spec(n, inst, 1, n_c, &sp);
   if (st != PECANN_OK) return st;
-  return cluster_impl(n, sp, rho, dep, delta, center_mode, delta_min, rho_min, labels, is_center, ws,
-                      ws_bytes, stream);
+  return check_device(cluster_impl(n, sp, rho, dep, delta, center_mode, delta_min, rho_min, labels, is_center, ws,
+                      ws_bytes, stream));
 }
 
 // ---------------------------------------------------------------------------

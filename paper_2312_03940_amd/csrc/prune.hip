@@ -206,6 +206,8 @@ __device__ __forceinline__ void short_block(const PruneParams &p, PruneLds &s, i
 __device__ __forceinline__ void write_nout(const PruneParams &p, const PruneLds &s, int32_t pt,
                                            int nsel) {
   const int l = lane_id();
+  PECANN_CHECK(nsel >= 0 && nsel <= p.R, CK_PRUNE);
+  PECANN_CHECK(pt >= 0 && pt < p.n, CK_ITEM);
   int32_t *row = p.adj + (int64_t)pt * p.R;
   for (int e = l; e < p.R; e += kWave) row[e] = e < nsel ? (int32_t)key_id(s.sel[e]) : -1;
   if (p.akey)
@@ -718,6 +720,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == PECANN
     const int32_t *src = p.seg + off;
     const uint64_t *srck = p.segk + off;
     const int dq = min(dg, p.R);
+    PECANN_CHECK(q >= 0 && q < p.n && dg >= 0 && dg <= p.R, CK_PRUNE);
+    PECANN_CHECK(p.heavy || cnt <= p.capin, CK_PRUNE);  // light targets fit the LDS
     if (cnt > p.capin) {
       // more sources than the LDS holds (heavy list only: light targets have
       // at most capin by construction); more than capin - R of them are new,
@@ -906,5 +910,7 @@ hipError_t launch_prune_reverse(int32_t dt, const PruneParams &p, int grid, hipS
     default: return hipErrorInvalidValue;
   }
 }
+
+PECANN_CHECK_READER(prune)
 
 }  // namespace pecann

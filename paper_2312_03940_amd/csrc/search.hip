@@ -20,4 +20,6 @@ hipError_t launch_search(int32_t dt, int S, const SearchParams &p, int grid, hip
   PECANN_DISPATCH_SHAPE(launch_search_vec, dt, S, p, grid, st)
 }
 
+PECANN_CHECK_READER(search)
+
 }  // namespace pecann

@@ -80,12 +80,14 @@ __device__ __forceinline__ void expand(F &score, const SearchParams &p, Lds &s, 
   // row always has R entries), so the expansion costs one memory round trip
   const int e_first = lane_id();
   const int32_t nb_first = e_first < p.R ? row[e_first] : -1;
+  PECANN_CHECK(p.deg[v] >= 0 && p.deg[v] <= p.R, CK_NEIGHBOUR);
   const int dg = min(p.deg[v], p.R);
   s.n_exp += 1;
   s.n_ids += dg;
   for (int e0 = 0; e0 < dg; e0 += kWave) {
     const int e = e0 + lane_id();
     int32_t nb = e < dg ? (e0 == 0 ? nb_first : row[e]) : -1;
+    PECANN_CHECK(nb < p.n, CK_NEIGHBOUR);
     if (nb >= p.n) nb = -1;  // ids outside the point set are ignored
     if (nb >= 0 && !s.hash.insert(nb)) nb = -1;
     score_and_merge(score, s, nb);
@@ -180,8 +182,12 @@ __device__ __forceinline__ void search_body(const SearchParams &p) {
     const int it = next_item(p.head);
     if (it >= count) break;
     const int32_t qid = p.items ? p.items[it] : it;
+    PECANN_CHECK(qid >= 0 && qid < p.n, CK_ITEM);
     int ti = 0;  // the query's instance
-    if (MODE != MODE_BUILD) ti = find_instance(p.inst, qid);
+    if (MODE != MODE_BUILD) {
+      ti = find_instance(p.inst, qid);
+      PECANN_CHECK(p.inst.off[ti] <= qid && qid < p.inst.off[ti + 1], CK_INSTANCE);
+    }
     if (MODE == MODE_DEP) {
       // this instance's doubling has ended (few enough points left, or k_dep
       // beyond its limit): carry the point over to the next list unchanged
@@ -231,6 +237,11 @@ __device__ __forceinline__ void search_body(const SearchParams &p) {
     const int nv = vs.n;
 
     const int m = s.beam.m;
+#ifdef PECANN_CHECKED
+    // the beam holds at most L keys, strictly increasing
+    PECANN_CHECK(m <= s.beam.cap, CK_BEAM);
+    for (int j = l; j + 1 < m; j += kWave) PECANN_CHECK(s.beam.a[j] < s.beam.a[j + 1], CK_BEAM);
+#endif
     unsigned long long n_rerank = 0;
     if (MODE == MODE_BUILD) {
       if (l == 0) p.vis_count[it] = nv;

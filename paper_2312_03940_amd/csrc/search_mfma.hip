@@ -18,4 +18,6 @@ hipError_t launch_search_mfma(int32_t dt, int S, const SearchParams &p, int grid
   }
 }
 
+PECANN_CHECK_READER(search_mfma)
+
 }  // namespace pecann

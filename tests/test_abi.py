@@ -93,6 +93,7 @@ def test_argument_errors_are_synchronous(lib):
     rc = lib.pecann_cluster(10, 256, 256, 256, 0, 1, 0.0, 0.0, 256, 256, 256, 8, None)
     assert rc == 2
     assert lib.pecann_status_string(2) == b"workspace too small"
+    assert lib.pecann_status_string(5) == b"device invariant check failed"
 
 
 def test_batched_instance_tables_are_validated(lib):
