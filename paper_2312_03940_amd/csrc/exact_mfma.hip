@@ -19,6 +19,9 @@
 //         its exact measure is >= thr - E, with E a bound on the rounding of
 //         |a|^2 + |b|^2 - 2 a.b; if the k-th re-scored measure is < thr - E the
 //         answer is exact, otherwise the query goes to the brute-force kernel.
+//         uint8 measures are exact integers on both sides (E = 0), so there the
+//         (measure, index) keys are compared: a tie with a dropped candidate
+//         of larger index is no reason to fall back.
 #include "beam.hpp"
 
 namespace pecann {
@@ -30,12 +33,15 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kQT = 64;   // queries per workgroup
 constexpr int kCT = 64;   // candidates per block
-// queue length per lane and query row: 8 for float32 rows, 4 for uint8 rows,
+// queue length per lane and query row: 8 for float32 rows, 5 for uint8 rows,
 // whose measures are exact integers (a dropped threshold far below the 16 x 8
 // kept candidates cannot fail the exactness check by rounding); the inserts of
-// a wave are divergent, so a shorter queue is also a cheaper one
+// a wave are divergent, so a shorter queue is also a cheaper one.  Four per
+// lane sent ~0.3 % of the 70,000-point uint8 queries to the brute force (a
+// lane holding five of a query's ten nearest; 2.0 ms of fallback per step), five
+// cost 0.5 ms more scan and cut the fallback to its launch floor
 template <int SDT>
-constexpr int kq_of() { return SDT == PECANN_U8 ? 4 : kExactCand / 16; }
+constexpr int kq_of() { return SDT == PECANN_U8 ? 5 : kExactCand / 16; }
 constexpr int kSPB = 4;   // 64-byte steps per round
 constexpr int kCand = kExactCand;
 
@@ -46,9 +52,6 @@ struct ScanRows {
   const uint32_t *norms;   // float bits (F32) or int32 (U8)
 };
 
-__device__ __forceinline__ bool kv_less(float a, int ia, float b, int ib) {
-  return a < b || (a == b && ia < ib);
-}
 
 __device__ __forceinline__ uint4 shift_u8(uint4 v) {
   v.x ^= 0x80808080u; v.y ^= 0x80808080u; v.z ^= 0x80808080u; v.w ^= 0x80808080u;
@@ -95,7 +98,7 @@ struct Round {
 
 template <int SDT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void exact_scan_kernel(ScanRows sr, int32_t n, int32_t metric,
-                                                         int32_t *cand, float *thr) {
+                                                         int32_t *cand, uint64_t *thr) {
   __shared__ uint4 bs[2][kCT][4 * kSPB + 1];
   __shared__ uint32_t bn[2][kCT];
   constexpr int kKQ = kq_of<SDT>();
@@ -106,18 +109,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void e
   const int rpb = (steps + kSPB - 1) / kSPB;  // rounds per block
   const int total = ((n + kCT - 1) / kCT) * rpb;
 
-  float qd[4][kKQ];
-  int qi[4][kKQ];
-  float qlo[4];  // smallest measure this lane's queue of row r has dropped
+  // the lane's queue of row r: keys (measure bits << 32 | candidate), sorted;
+  // one 64-bit comparison orders (measure, index) pairs
+  uint64_t qk[4][kKQ];
+  uint64_t qlo[4];  // smallest key this lane's queue of row r has dropped
   float nq[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int q = q0 + 4 * g + r;
-    qlo[r] = __int_as_float(0x7f800000);
+    qlo[r] = kNoKey;
     nq[r] = 0.f;
     if (q < n) nq[r] = SDT == PECANN_U8 ? (float)(int)sr.norms[q] : __uint_as_float(sr.norms[q]);
 #pragma unroll
-    for (int s = 0; s < kKQ; ++s) { qd[r][s] = __int_as_float(0x7f800000); qi[r][s] = -1; }
+    for (int s = 0; s < kKQ; ++s) qk[r][s] = kNoKey;
   }
 
   v4f accf[4];
@@ -180,22 +184,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void e
         } else {
           m = fmaxf(0.f, 1.0f - accf[t][r]);
         }
-        if (!kv_less(m, col, qd[r][kKQ - 1], qi[r][kKQ - 1])) {
-          qlo[r] = fminf(qlo[r], m);  // rejected
+        // measures are >= 0; clearing the sign bit keeps a -0 from ordering last
+        m = __uint_as_float(__float_as_uint(m) & 0x7fffffffu);
+        const uint64_t ck = make_key(m, col);
+        if (!(ck < qk[r][kKQ - 1])) {
+          qlo[r] = min(qlo[r], ck);  // rejected
         } else {
-          qlo[r] = fminf(qlo[r], qd[r][kKQ - 1]);  // the entry it evicts (+inf: none)
-          float cd = m;
-          int ci = col;
+          qlo[r] = min(qlo[r], qk[r][kKQ - 1]);  // the entry it evicts (~0: an empty slot)
 #pragma unroll
           for (int s = kKQ - 1; s > 0; --s) {
-            const bool shift = kv_less(cd, ci, qd[r][s - 1], qi[r][s - 1]);
-            const bool here = !shift && kv_less(cd, ci, qd[r][s], qi[r][s]);
-            const float od = qd[r][s];
-            const int oi = qi[r][s];
-            qd[r][s] = shift ? qd[r][s - 1] : (here ? cd : od);
-            qi[r][s] = shift ? qi[r][s - 1] : (here ? ci : oi);
+            const bool shift = ck < qk[r][s - 1];
+            const bool here = !shift && ck < qk[r][s];
+            qk[r][s] = shift ? qk[r][s - 1] : (here ? ck : qk[r][s]);
           }
-          if (kv_less(cd, ci, qd[r][0], qi[r][0])) { qd[r][0] = cd; qi[r][0] = ci; }
+          if (ck < qk[r][0]) qk[r][0] = ck;
         }
       }
     }
@@ -208,13 +210,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void e
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int q = q0 + 4 * g + r;
-    float last = qlo[r];
+    uint64_t last = qlo[r];
 #pragma unroll
-    for (int m = 8; m >= 1; m >>= 1) last = fminf(last, __shfl_xor(last, m));
+    for (int m = 8; m >= 1; m >>= 1) last = min(last, shfl_xor_u64(last, m));
     if (q < n) {
       int32_t *o = cand + (int64_t)q * kCand + c16 * kKQ;
 #pragma unroll
-      for (int s = 0; s < kKQ; ++s) o[s] = qi[r][s];
+      for (int s = 0; s < kKQ; ++s) o[s] = key_id(qk[r][s]);  // an empty slot gives -1
       if (c16 == 0) thr[q] = last;
     }
   }
@@ -263,8 +265,8 @@ __global__ __launch_bounds__(64) void exact_rerank_kernel(ExactMfmaParams p, flo
     const int32_t *c = p.cand + (int64_t)q * kCand;
     constexpr int kKept = 16 * kq_of<DT == PECANN_U8 ? PECANN_U8 : PECANN_F32>();
     for (int base = 0; base < kKept; base += kWave) {
-      PECANN_CHECK(c[base + l] >= -1 && c[base + l] < p.n, CK_ITEM);  // kept candidates (-1: none)
-      score_keys(eng, p.rows, kWave, [&](int i) { return c[base + i]; }, kb);
+      PECANN_CHECK(base + l >= kKept || (c[base + l] >= -1 && c[base + l] < p.n), CK_ITEM);  // (-1: none)
+      score_keys(eng, p.rows, kWave, [&](int i) { return base + i < kKept ? c[base + i] : -1; }, kb);
       wave_lds_sync();
       const uint64_t key = kb[l];
       wave_lds_sync();
@@ -277,8 +279,10 @@ __global__ __launch_bounds__(64) void exact_rerank_kernel(ExactMfmaParams p, flo
       if (u8rows) nqv = 0.f;
       else nqv = p.rows.xr ? p.rows.sqn_r[q] : __uint_as_float(p.rows.sqn[q]);
       const float e = u8rows ? ce : ce * (nqv + *p.nmax);
-      const float t = p.thr[q];
-      ok = key_measure(top.a[k - 1]) < t - e;
+      const uint64_t tk = p.thr[q];
+      if (tk == kNoKey) ok = true;  // no queue dropped anything
+      else if (u8rows) ok = top.a[k - 1] < tk;
+      else ok = key_measure(top.a[k - 1]) < key_measure(tk) - e;
     }
     if (ok) {
       // rows, outputs and ids of this call are the instance's: global index =

@@ -286,7 +286,7 @@ struct ExactMfmaParams {
   int32_t kstride;            // row stride of knn_idx / knn_dist
   int32_t base;               // global index of row 0
   int32_t *cand;               // [n][kExactCand] candidate ids of the scan
-  float *thr;                  // [n] smallest measure a scan queue dropped (+inf: none)
+  uint64_t *thr;               // [n] smallest (measure, index) key a scan queue dropped (~0: none)
   float *nmax;                 // [1] largest row norm (device)
   int32_t *head;
   int32_t *knn_idx;

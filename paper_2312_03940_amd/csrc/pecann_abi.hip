@@ -1092,7 +1092,8 @@ static constexpr int64_t kExactMfmaMin = 4096;
 
 struct KnnWs {
   int32_t *ctr, *fb, *cand;
-  float *thr, *nmax;
+  uint64_t *thr;  // exact mode: smallest key each query's scan queues dropped
+  float *nmax;
   uint64_t *part;  // exact mode: chunk-local best keys of the split brute force
   InstDev inst;
 };
@@ -1114,7 +1115,7 @@ static void carve_knn(Carver &c, int64_t n, bool exact, bool exact_mfma, int nin
   w->fb = c.take<int32_t>((size_t)n);
   w->nmax = c.take<float>(64);
   w->cand = exact_mfma ? c.take<int32_t>((size_t)n * kExactCand) : nullptr;
-  w->thr = exact_mfma ? c.take<float>((size_t)n) : nullptr;
+  w->thr = exact_mfma ? c.take<uint64_t>((size_t)n) : nullptr;
   w->part = exact ? c.take<uint64_t>((size_t)kSplitCap * split_chunks(max_size) * k) : nullptr;
   carve_inst(c, ninst, &w->inst);
 }
@@ -1248,11 +1249,19 @@ static pecann_status knn_impl(const pecann_dataset *ds, const InstSpec &spec, co
     bp.kpart = k;
     bp.head = ctr + 3;
     bp.head2 = ctr + 4;
-    HIP_TRY(launch_bf_knn_split(tdt, S, bp, persistent_grid((int64_t)kSplitCap * bp.nchunk),
-                                persistent_grid(kSplitCap), s));
+    // grids sized for the queries expected here: every point of an instance
+    // below the scan's minimum, plus the few the scan's check sends back (the
+    // work queues take any count; mostly empty grids cost launch time: 18k
+    // idle waves were 0.9 ms of the 70,000-point uint8 step)
+    int64_t small = 0;
+    for (int t = 0; t < spec.count(); ++t)
+      if (spec.size(t) < kExactMfmaMin) small += spec.size(t);
+    const int64_t few = (int64_t)cu_count() * 4;
+    const int64_t expect = std::min<int64_t>(kSplitCap, small + few);
+    HIP_TRY(launch_bf_knn_split(tdt, S, bp, persistent_grid(expect * bp.nchunk), persistent_grid(expect), s));
     bp.head = ctr + 2;
     bp.item_from = kSplitCap;
-    HIP_TRY(launch_bf_knn(tdt, S, bp, persistent_grid(n), s));
+    HIP_TRY(launch_bf_knn(tdt, S, bp, persistent_grid(std::max<int64_t>(small - kSplitCap, 0) + few), s));
     return PECANN_OK;
   }
   SearchParams sp = {};
