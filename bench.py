@@ -516,7 +516,7 @@ def roofline(pl, kprof, steps, search, n, d, k):
     bytes."""
     from paper_2312_03940_amd import pecann
     timed = pecann.get_tuning()
-    pecann.set_tuning(13, 13, timed["grid_per_cu"], timed["scorer"])
+    pecann.set_tuning(13, 13, timed["grid_per_cu"], timed["scorer"], timed["prune_steps"])
     try:
         bc, kc = pl.counters()
     finally:

@@ -511,7 +511,11 @@ int32_t pecann_profile_report(pecann_profile_entry *out, int32_t max_entries);
  *   scorer            where the searches score BF16 / FP8 candidate rows:
  *                     0 the rule (matrix cores for FP8 rows of 512 bytes or
  *                     more, else vector units), 1 vector units, 2 matrix cores
- * The first three change speed only: every output of every call is the same,
+ *   prune_steps       the RobustPrune distance tiles' row steps per memory
+ *                     round trip (0: the rule, 4 for float32 rows, 2 for the
+ *                     narrower ones; else 2 or 4): more loads in flight
+ *                     against fewer waves per SIMD
+ * Hash sizes, grid and prune_steps change speed only: every output of every call is the same,
  * byte for byte, under any valid setting (the visited hash may forget ids,
  * which costs repeated distance evaluations and nothing else, and every work
  * item's result is independent of which wave takes it).  The scorer changes
@@ -527,6 +531,7 @@ typedef struct {
   int32_t hash_bits_search;
   int32_t grid_per_cu;
   int32_t scorer;    /* 0 rule, 1 vector units, 2 matrix cores */
+  int32_t prune_steps; /* 0 rule, 2 or 4 */
 } pecann_tuning;
 
 pecann_status pecann_set_tuning(const pecann_tuning *t);

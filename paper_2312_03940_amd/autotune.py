@@ -2,8 +2,9 @@
 candidates are scored (vector units or matrix cores; this changes the
 rounding of the reduced-precision search measures), and the settings that
 change speed only: the visited-hash size of the build searches and of the
-kNN / doubling searches, and the persistent grid (one-wave blocks per compute
-unit).  tune_beam(): the kNN beam width, the smallest that agrees with a
+kNN / doubling searches, the persistent grid (one-wave blocks per compute
+unit, i.e. how many queries run at once), and the RobustPrune tiles' row steps
+per memory round trip (a tile shape: loads in flight against waves per SIMD).  tune_beam(): the kNN beam width, the smallest that agrees with a
 wide-beam search on a target share of the neighbours (this one changes results
 within that target).  The callers' quality gates judge every choice.
 
@@ -29,7 +30,8 @@ BUILD_HASH_BITS = (0, 11, 12, 13)
 SEARCH_HASH_BITS = (0, 11, 12, 13)
 GRID_PER_CU = (0, 12, 20)
 SCORERS = (0, 1, 2)  # rule, vector units, matrix cores (BF16 / FP8 rows only)
-KNOBS = ("hash_bits_build", "hash_bits_search", "grid_per_cu", "scorer")
+PRUNE_STEPS = (0, 2, 4)  # rule, or the prune tiles' row steps per memory round trip
+KNOBS = ("hash_bits_build", "hash_bits_search", "grid_per_cu", "scorer", "prune_steps")
 
 
 # Settings tuned on MI355X for the benchmark workloads, shipped with the package
@@ -211,6 +213,7 @@ def tune(ds: pecann.Dataset, R: int, L: int, alpha: float, k: int, L_search: int
         t_build = sweep("scorer", SCORERS, build, t_build)
     t_build = sweep("hash_bits_build", BUILD_HASH_BITS, build, t_build)
     t_build = sweep("grid_per_cu", GRID_PER_CU, build, t_build)
+    t_build = sweep("prune_steps", PRUNE_STEPS, build, t_build)
     build()  # the graph under the chosen build settings, for the kNN timings
     torch.cuda.synchronize()
     t_knn = sweep("hash_bits_search", SEARCH_HASH_BITS, knn, _time(knn, reps))

@@ -210,6 +210,7 @@ struct PruneParams {
   // [1] by reverse prunes (32 per 16 x 16 tile), [2] targets pruned, [3] targets
   // appended
   unsigned long long *counters;
+  int32_t sg;  // tile steps per memory round trip (0: the rule; else 2 or 4)
 };
 size_t prune_lds_bytes(int ccap, int R, int dt, int metric);
 hipError_t launch_prune_forward(int32_t dt, const PruneParams &p, int grid, hipStream_t s);

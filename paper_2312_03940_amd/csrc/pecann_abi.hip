@@ -22,7 +22,7 @@ using namespace pecann;
 static thread_local char g_err[512] = "";
 
 // Launch tuning (speed only; see pecann_set_tuning).  Per host thread.
-static thread_local pecann_tuning g_tuning = {0, 0, 0, 0};
+static thread_local pecann_tuning g_tuning = {0, 0, 0, 0, 0};
 
 static pecann_status fail(pecann_status s, const char *fmt, ...) {
   va_list ap;
@@ -137,7 +137,7 @@ struct ProfScope {
 extern "C" pecann_status pecann_set_tuning(const pecann_tuning *t) {
   clear_stale_error();
   if (!t) {
-    g_tuning = pecann_tuning{0, 0, 0, 0};
+    g_tuning = pecann_tuning{0, 0, 0, 0, 0};
     return PECANN_OK;
   }
   auto bits_ok = [](int32_t b) { return b == 0 || (b >= 10 && b <= 13); };
@@ -146,6 +146,8 @@ extern "C" pecann_status pecann_set_tuning(const pecann_tuning *t) {
   if (t->grid_per_cu != 0 && (t->grid_per_cu < 4 || t->grid_per_cu > 64))
     return fail(PECANN_EINVAL, "grid_per_cu must be 0 or in [4, 64]");
   if (t->scorer < 0 || t->scorer > 2) return fail(PECANN_EINVAL, "scorer must be 0, 1 or 2");
+  if (t->prune_steps != 0 && t->prune_steps != 2 && t->prune_steps != 4)
+    return fail(PECANN_EINVAL, "prune_steps must be 0, 2 or 4");
   g_tuning = *t;
   return PECANN_OK;
 }
@@ -734,6 +736,7 @@ static pecann_status build_impl(const pecann_dataset *ds, const pecann_build_par
   PruneParams pp = {};
   pp.rows = rows;
   pp.n = (int32_t)n;
+  pp.sg = g_tuning.prune_steps;
   pp.R = R;
   pp.adj = adj;
   pp.deg = deg;
@@ -1041,6 +1044,7 @@ extern "C" pecann_status pecann_build_graph_nndescent(const pecann_dataset *ds,
   PruneParams pp = {};
   pp.rows = P.rows;
   pp.n = (int32_t)n;
+  pp.sg = g_tuning.prune_steps;
   pp.R = np->R;
   pp.alpha = np->alpha;
   pp.adj = adj;

@@ -158,7 +158,7 @@ __device__ __forceinline__ uint32_t select_block(const PruneParams &p, PruneLds 
 // settled from them -- one memory round trip per block instead of two or three.
 constexpr int kSmallBlocks = 5;
 
-template <int DT, int B>
+template <int DT, int B, int SG>
 __device__ __forceinline__ void short_block(const PruneParams &p, PruneLds &s, int mv, float a2,
                                             int &nsel) {
   if (16 * B >= mv || nsel >= p.R) return;
@@ -173,7 +173,7 @@ __device__ __forceinline__ void short_block(const PruneParams &p, PruneLds &s, i
     br[t] = (j < mv && s.alive[j]) ? key_id(s.k1[j]) : -1;
   }
   v4f tt[NT];
-  dot_tiles<DT, NT>(p.rows, br[0], br, tt);
+  dot_tiles<DT, NT, SG>(p.rows, br[0], br, tt);
   // (a) the block's own tile -> its selections, in order
   const uint32_t selmask = select_block<DT>(p, s, tt[0], o, mv, a2, nsel);
   if (nsel == p.R) return;
@@ -229,7 +229,7 @@ __device__ __forceinline__ void write_nout(const PruneParams &p, const PruneLds 
 // points then drop later candidates tile by tile (each lane testing the 4 rows
 // of its accumulator against its column), and the survivors are compacted.
 // Returns the number of 16 x 16 tiles formed.
-template <int DT>
+template <int DT, int SG>
 __device__ __forceinline__ int robust_prune_tiles(const PruneParams &p, PruneLds &s, int32_t pt, int nc, int npre = 0) {
   constexpr int NT = 4;  // tiles in flight
   const int l = lane_id();
@@ -248,7 +248,7 @@ __device__ __forceinline__ int robust_prune_tiles(const PruneParams &p, PruneLds
         rj[t] = id == pt ? -1 : id;
       }
       v4f tt[NT];
-      dot_tiles<DT, NT>(p.rows, col == 0 ? pt : -1, rj, tt);  // A row 0 holds pt, rows 1-15 zeros
+      dot_tiles<DT, NT, SG>(p.rows, col == 0 ? pt : -1, rj, tt);  // A row 0 holds pt, rows 1-15 zeros
       if (g == 0) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
@@ -287,11 +287,11 @@ __device__ __forceinline__ int robust_prune_tiles(const PruneParams &p, PruneLds
   int nsel = 0, tiles = nc > npre ? (nc - npre + 15) / 16 : 0;
   if (mv <= 16 * kSmallBlocks) {
     const int nb = (mv + 15) / 16;
-    short_block<DT, 0>(p, s, mv, a2, nsel);
-    short_block<DT, 1>(p, s, mv, a2, nsel);
-    short_block<DT, 2>(p, s, mv, a2, nsel);
-    short_block<DT, 3>(p, s, mv, a2, nsel);
-    short_block<DT, 4>(p, s, mv, a2, nsel);
+    short_block<DT, 0, SG>(p, s, mv, a2, nsel);
+    short_block<DT, 1, SG>(p, s, mv, a2, nsel);
+    short_block<DT, 2, SG>(p, s, mv, a2, nsel);
+    short_block<DT, 3, SG>(p, s, mv, a2, nsel);
+    short_block<DT, 4, SG>(p, s, mv, a2, nsel);
     tiles += nb * kSmallBlocks - nb * (nb - 1) / 2;
     write_nout(p, s, pt, nsel);
     return tiles;
@@ -303,7 +303,7 @@ __device__ __forceinline__ int robust_prune_tiles(const PruneParams &p, PruneLds
     {
       const int32_t br[1] = {rb};
       v4f t[1];
-      dot_tiles<DT, 1>(p.rows, rb, br, t);
+      dot_tiles<DT, 1, SG>(p.rows, rb, br, t);
       ++tiles;
       // (b) selections of this block, in order
       selmask = select_block<DT>(p, s, t[0], b, mv, a2, nsel);
@@ -321,7 +321,7 @@ __device__ __forceinline__ int robust_prune_tiles(const PruneParams &p, PruneLds
         rj[t] = j < mv ? key_id(s.k1[j]) : -1;
       }
       v4f tt[NT];
-      dot_tiles<DT, NT>(p.rows, ra, rj, tt);
+      dot_tiles<DT, NT, SG>(p.rows, ra, rj, tt);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const int j = j0 + 16 * t + col;
@@ -367,7 +367,7 @@ __device__ __forceinline__ int robust_prune_tiles(const PruneParams &p, PruneLds
 // the shape does not fit (more than kMaxU members of U or 3 * 64 candidates).
 constexpr int kMaxU = 32;
 
-template <int DT>
+template <int DT, int SG>
 __device__ __forceinline__ int prune_with_prefix(const PruneParams &p, PruneLds &s, int32_t pt, int mv, int c) {
   constexpr int NT = 4;
   const int nu = mv - c;
@@ -429,7 +429,7 @@ __device__ __forceinline__ int prune_with_prefix(const PruneParams &p, PruneLds 
         bj[t] = jc < mv ? (int32_t)key_id(s.k1[jc]) : -1;
       }
       v4f tt[NT];
-      dot_tiles<DT, NT>(p.rows, aid, bj, tt);
+      dot_tiles<DT, NT, SG>(p.rows, aid, bj, tt);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const int jc = c0 + 16 * t + col;
@@ -518,7 +518,7 @@ __device__ __forceinline__ int prune_with_prefix(const PruneParams &p, PruneLds 
 // SIMD with a few spilled bytes (1M x 128 BF16 build: 58.1 -> 52.6 ms per step);
 // over float32 rows the spills cost more than the extra wave, and FP8 builds
 // with their wide visited sets are held below three waves by the LDS.
-template <int DT>
+template <int DT, int SG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == PECANN_BF16 || DT == PECANN_U8 ? 4 : 1))) void prune_forward_kernel(PruneParams p) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int ccap = p.vcap + p.R;
@@ -567,7 +567,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == PECANN
     }
     const int nout = __popcll(m0) + __popcll(m1);
     wave_lds_sync();
-    const int rows = 32 * robust_prune_tiles<DT>(p, s, pt, nv + nout, nv + nout);
+    const int rows = 32 * robust_prune_tiles<DT, SG>(p, s, pt, nv + nout, nv + nout);
     if (p.counters && l == 0) atomicAdd(p.counters + 0, (unsigned long long)rows);
     wave_lds_sync();
   }
@@ -584,7 +584,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == PECANN
 // per lane) and the sources not already in it, whose keys stay in the
 // target's segment (a source already present has its key cleared there;
 // entry j of the segment is only read and written by lane j % 64).
-template <int DT>
+template <int DT, int SG>
 __device__ __forceinline__ int prune_reverse_sliced(const PruneParams &p, PruneLds &s, int32_t q,
                                                  uint64_t *srck, int cnt, int dq) {
   const int l = lane_id();
@@ -652,7 +652,7 @@ __device__ __forceinline__ int prune_reverse_sliced(const PruneParams &p, PruneL
       m += __popcll(bm);
     }
     wave_lds_sync();
-    tiles += robust_prune_tiles<DT>(p, s, q, m, m);
+    tiles += robust_prune_tiles<DT, SG>(p, s, q, m, m);
     int v = 0;
     if (l == 0) v = p.deg[q];  // written by lane 0 in write_nout
     nsel = __shfl(v, 0);
@@ -667,7 +667,7 @@ __device__ __forceinline__ int prune_reverse_sliced(const PruneParams &p, PruneL
 // compiler then gives up the accumulation registers (1M x 128 BF16 build:
 // reverse prune 142.7 -> 112.9 ms per step; 1.28M x 1024 FP8: 332 -> 282 ms).
 // Float32 would spill and ran slower.
-template <int DT>
+template <int DT, int SG>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == PECANN_F32 ? 1 : 3))) void prune_reverse_kernel(PruneParams p) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int ccap = p.R + p.capin;
@@ -726,7 +726,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == PECANN
       // more sources than the LDS holds (heavy list only: light targets have
       // at most capin by construction); more than capin - R of them are new,
       // so the target is always pruned
-      const int rows = 32 * prune_reverse_sliced<DT>(p, s, q, p.segk + off, cnt, dq);
+      const int rows = 32 * prune_reverse_sliced<DT, SG>(p, s, q, p.segk + off, cnt, dq);
       if (p.counters && l == 0) {
         atomicAdd(p.counters + 1, (unsigned long long)rows);
         atomicAdd(p.counters + 2, 1ull);
@@ -823,8 +823,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == PECANN
     } else {
       // the leading entries that q's last prune selected need no tiles among themselves
       int tiles = -1;
-      if (!p.heavy) tiles = prune_with_prefix<DT>(p, s, q, dq + nnew, min(p.cons[q], dq));
-      if (tiles < 0) tiles = robust_prune_tiles<DT>(p, s, q, dq + nnew, dq + nnew);
+      if (!p.heavy) tiles = prune_with_prefix<DT, SG>(p, s, q, dq + nnew, min(p.cons[q], dq));
+      if (tiles < 0) tiles = robust_prune_tiles<DT, SG>(p, s, q, dq + nnew, dq + nnew);
       const int rows = 32 * tiles;
       if (p.counters && l == 0) {
         atomicAdd(p.counters + 1, (unsigned long long)rows);
@@ -851,7 +851,7 @@ __global__ __launch_bounds__(64) void prune_lists_kernel(PruneParams p) {
       s.ids[p.lk + j] = p.rlists[(int64_t)u * p.lk + j];
     }
     wave_lds_sync();
-    const int rows = 32 * robust_prune_tiles<DT>(p, s, u, 2 * p.lk);
+    const int rows = 32 * robust_prune_tiles<DT, tile_steps_rule<DT>()>(p, s, u, 2 * p.lk);
     if (p.counters && l == 0) atomicAdd(p.counters + 0, (unsigned long long)rows);
     wave_lds_sync();
   }
@@ -862,16 +862,23 @@ size_t prune_lds_bytes(int ccap, int R, int dt, int metric) {
   return (size_t)ccap * per + 8 * (size_t)R + 16;
 }
 
+// The tile steps per memory round trip: the tuning's (2 or 4), else the rule.
 template <int DT>
 static hipError_t launch_pf_t(const PruneParams &p, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((prune_forward_kernel<DT>), dim3(grid), dim3(64),
-                     prune_lds_bytes(p.vcap + p.R, p.R, DT, p.rows.metric), st, p);
+  const size_t lds = prune_lds_bytes(p.vcap + p.R, p.R, DT, p.rows.metric);
+  if ((p.sg ? p.sg : tile_steps_rule<DT>()) == 4)
+    hipLaunchKernelGGL((prune_forward_kernel<DT, 4>), dim3(grid), dim3(64), lds, st, p);
+  else
+    hipLaunchKernelGGL((prune_forward_kernel<DT, 2>), dim3(grid), dim3(64), lds, st, p);
   return hipGetLastError();
 }
 template <int DT>
 static hipError_t launch_pr_t(const PruneParams &p, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((prune_reverse_kernel<DT>), dim3(grid), dim3(64),
-                     prune_lds_bytes(p.R + p.capin, p.R, DT, p.rows.metric), st, p);
+  const size_t lds = prune_lds_bytes(p.R + p.capin, p.R, DT, p.rows.metric);
+  if ((p.sg ? p.sg : tile_steps_rule<DT>()) == 4)
+    hipLaunchKernelGGL((prune_reverse_kernel<DT, 4>), dim3(grid), dim3(64), lds, st, p);
+  else
+    hipLaunchKernelGGL((prune_reverse_kernel<DT, 2>), dim3(grid), dim3(64), lds, st, p);
   return hipGetLastError();
 }
 

@@ -51,7 +51,15 @@ __device__ __forceinline__ void mfma_chunk(uint4 a, uint4 b, v4f &accf, v4i &acc
   }
 }
 
-template <int DT, int NT>
+// Steps whose loads go out before their products (one memory round trip per
+// SG steps): the rule is four for float32 rows and two for the narrower
+// formats, which keeps the prune kernels at three waves per SIMD (measured:
+// 1M x 128 BF16 reverse prune 247 -> 197 ms per step, forward 87 -> 75;
+// float32 rows were 1 % faster with four); the autotuner may choose per shape.
+template <int DT>
+constexpr int tile_steps_rule() { return DT == PECANN_F32 ? 4 : 2; }
+
+template <int DT, int NT, int SG = tile_steps_rule<DT>()>
 __device__ __forceinline__ void dot_tiles(const Rows &r, int32_t arow, const int32_t (&brow)[NT],
                                           v4f (&out)[NT]) {
   const int g = lane_id() >> 4;
@@ -64,12 +72,6 @@ __device__ __forceinline__ void dot_tiles(const Rows &r, int32_t arow, const int
     accf[t] = v4f{0.f, 0.f, 0.f, 0.f};
     acci[t] = v4i{0, 0, 0, 0};
   }
-  // the loads of SG steps go out before any of their products (one memory
-  // round trip per SG steps instead of one per step).  Four steps for float32
-  // rows; two for the narrower formats, which keeps the prune kernels at three
-  // waves per SIMD (measured: 1M x 128 BF16 reverse prune 247 -> 197 ms per
-  // step, forward 87 -> 75; float32 rows were 1 % faster with four)
-  constexpr int SG = DT == PECANN_F32 ? 4 : 2;
   for (int st0 = 0; st0 < steps; st0 += SG) {
     uint4 a[SG], b[SG][NT];
 #pragma unroll

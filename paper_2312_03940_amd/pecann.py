@@ -57,7 +57,8 @@ class _NndParams(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("hash_bits_build", ctypes.c_int32), ("hash_bits_search", ctypes.c_int32),
-                ("grid_per_cu", ctypes.c_int32), ("scorer", ctypes.c_int32)]
+                ("grid_per_cu", ctypes.c_int32), ("scorer", ctypes.c_int32),
+                ("prune_steps", ctypes.c_int32)]
 
 
 class _Instances(ctypes.Structure):
@@ -259,12 +260,13 @@ def build_graph(ds: Dataset, R: int, L: int, alpha: float, num_starts: int = 8,
 
 
 def set_tuning(hash_bits_build: int = 0, hash_bits_search: int = 0, grid_per_cu: int = 0,
-               scorer: int = 0):
+               scorer: int = 0, prune_steps: int = 0):
     """Launch settings of this host thread (0 = the library's rule).  The hash
-    sizes and the grid change speed only; scorer (1 = vector units, 2 = matrix
+    sizes, the grid and prune_steps (the prune tiles' row steps per memory
+    round trip, 2 or 4) change speed only; scorer (1 = vector units, 2 = matrix
     cores) picks where BF16 / FP8 candidates are scored, which changes the
     rounding of their search measures."""
-    t = _Tuning(hash_bits_build, hash_bits_search, grid_per_cu, scorer)
+    t = _Tuning(hash_bits_build, hash_bits_search, grid_per_cu, scorer, prune_steps)
     _check(load().pecann_set_tuning(ctypes.byref(t)))
 
 
@@ -276,7 +278,7 @@ def get_tuning() -> dict:
     t = _Tuning()
     _check(load().pecann_get_tuning(ctypes.byref(t)))
     return {"hash_bits_build": t.hash_bits_build, "hash_bits_search": t.hash_bits_search,
-            "grid_per_cu": t.grid_per_cu, "scorer": t.scorer}
+            "grid_per_cu": t.grid_per_cu, "scorer": t.scorer, "prune_steps": t.prune_steps}
 
 
 def build_graph_nndescent(ds: Dataset, K: int, R: int, alpha: float, init: torch.Tensor,

@@ -176,14 +176,15 @@ def test_tuning_validation(lib):
     T = pecann._Tuning
     for bad, word in [(T(9, 0, 0, 0), b"hash"), (T(0, 14, 0, 0), b"hash"), (T(0, 0, 3, 0), b"grid"),
                       (T(0, 0, 65, 0), b"grid"), (T(0, 0, 0, 3), b"scorer"),
-                      (T(0, 0, 0, -1), b"scorer")]:
+                      (T(0, 0, 0, -1), b"scorer"), (T(0, 0, 0, 0, 3), b"prune_steps"),
+                      (T(0, 0, 0, 0, 8), b"prune_steps")]:
         assert lib.pecann_set_tuning(ctypes.byref(bad)) == 1 and word in lib.pecann_last_error()
-    pecann.set_tuning(12, 11, 16, 2)
+    pecann.set_tuning(12, 11, 16, 2, 4)
     assert pecann.get_tuning() == {"hash_bits_build": 12, "hash_bits_search": 11, "grid_per_cu": 16,
-                                   "scorer": 2}
+                                   "scorer": 2, "prune_steps": 4}
     pecann.reset_tuning()
     assert pecann.get_tuning() == {"hash_bits_build": 0, "hash_bits_search": 0, "grid_per_cu": 0,
-                                   "scorer": 0}
+                                   "scorer": 0, "prune_steps": 0}
 
 
 def test_workspace_sizes_host_only(lib):

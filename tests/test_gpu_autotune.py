@@ -11,7 +11,8 @@ from paper_2312_03940_amd import autotune, datagen, pecann
 
 pytestmark = pytest.mark.gpu
 
-SETTINGS = [(0, 0, 0), (10, 13, 4), (13, 10, 64), (11, 12, 12)]
+# (hash bits build, hash bits search, grid per CU, prune tile steps)
+SETTINGS = [(0, 0, 0, 0), (10, 13, 4, 4), (13, 10, 64, 2), (11, 12, 12, 4)]
 
 
 def _step(ds, perm, k):
@@ -22,7 +23,7 @@ def _step(ds, perm, k):
     return [t.cpu().numpy() for t in (adj, deg, idx, dist, key, dep, delta)]
 
 
-@pytest.mark.parametrize("sdt", ["bf16", "u8"])
+@pytest.mark.parametrize("sdt", ["bf16", "u8", "f32"])
 def test_tuning_does_not_change_results(sdt):
     dev = torch.device("cuda:0")
     X, _ = datagen.mixture(5000, 40, 10, seed=4, grid=255 if sdt == "u8" else None)
@@ -31,16 +32,16 @@ def test_tuning_does_not_change_results(sdt):
     ds = pecann.Dataset(x, "l2", sdt)
     try:
         ref = None
-        for hb, hs, g in SETTINGS:
-            pecann.set_tuning(hb, hs, g)
+        for hb, hs, g, ps in SETTINGS:
+            pecann.set_tuning(hb, hs, g, 0, ps)
             assert pecann.get_tuning() == {"hash_bits_build": hb, "hash_bits_search": hs, "grid_per_cu": g,
-                                           "scorer": 0}
+                                           "scorer": 0, "prune_steps": ps}
             got = _step(ds, perm, 8)
             if ref is None:
                 ref = got
             else:
                 for a, b in zip(got, ref):
-                    assert np.array_equal(a, b), (hb, hs, g)
+                    assert np.array_equal(a, b), (hb, hs, g, ps)
     finally:
         pecann.reset_tuning()
 
@@ -53,7 +54,7 @@ def test_autotune_picks_applies_and_caches(tmp_path):
     try:
         e = autotune.tune(ds, 24, 48, 1.2, 8, 48, path=path)
         assert not e["cached"]
-        chosen = {kk: e[kk] for kk in ("hash_bits_build", "hash_bits_search", "grid_per_cu", "scorer")}
+        chosen = {kk: e[kk] for kk in autotune.KNOBS}
         assert pecann.get_tuning() == chosen
         assert e["build_ms"] <= e["rule_build_ms"] and e["knn_ms"] > 0
         stored = json.load(open(path))
