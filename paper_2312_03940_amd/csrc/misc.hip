@@ -29,8 +29,6 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
   return (uint16_t)(u >> 16);
 }
 
-// T = values per lane (the row's padded length / 64, rounded up to a power of
-// two); every loop over them is unrolled so the row stays in registers.
 // MXFP6 element e2m3 (sign, 2 exponent bits with bias 1, 3 mantissa bits):
 // value of a 6-bit code
 __device__ __forceinline__ float e2m3_value(int c) {
@@ -98,6 +96,8 @@ __device__ __forceinline__ float write_mxfp6(const float (&v)[T], const RowsDesc
   return ng;
 }
 
+// T = values per lane (the row's padded length / 64, rounded up to a power of
+// two); every loop over them is unrolled so the row stays in registers.
 template <int T>
 __global__ __launch_bounds__(256) void prepare_kernel(const void *x, int32_t x_dtype, int64_t x_stride,
                                                       int64_t n, int32_t d, int32_t metric,
