@@ -269,6 +269,11 @@ hipError_t launch_nnd_out(const NndParams &p, const uint64_t *keys, int32_t *idx
 hipError_t launch_nnd_copy(const uint64_t *src, uint64_t *dst, int64_t n, int cus, hipStream_t s);
 
 // Plain (non-templated) kernels.
+// Center selection over one instance of at least kWideSelect points runs over the
+// whole GPU with a state of kSelWords 32-bit words in the cluster workspace.
+constexpr int64_t kWideSelect = 4096;
+constexpr int kSelWords = 320;
+
 hipError_t launch_prepare(const void *x, int32_t x_dtype, int64_t x_stride, int64_t n, int32_t d,
                           int32_t metric, int32_t sdt, const RowsDesc &rows, uint8_t *xs,
                           float *xr, float *scale, uint32_t *sqn, float *sqn_r, uint8_t *xg,
@@ -327,6 +332,7 @@ hipError_t launch_copy_count(const int32_t *src, int32_t *dst, int32_t nmax, hip
 hipError_t launch_cluster(int64_t n, const InstTable &inst, const float *rho, const int32_t *dep,
                           const float *delta, int32_t center_mode, float delta_min, float rho_min,
                           int32_t *labels, uint8_t *is_center, uint64_t *gkey, int32_t *flag,
+                          uint32_t *sel,
                           hipStream_t s);
 
 hipError_t launch_density(int64_t n, const InstTable &inst, int32_t kstride, int32_t fn,

@@ -668,6 +668,83 @@ __global__ __launch_bounds__(1024) void select_kernel(InstTable inst, const uint
   }
 }
 
+// The same select for one large instance over the whole GPU: per 8-bit digit,
+// every block counts the keys that match the prefix so far in an LDS
+// histogram and adds it to the state's, then one thread picks the digit (the
+// counts from the top until n_c is reached) and clears the histogram for the
+// next digit.  The result -- the n_c-th largest key as threshold, or 1 when at
+// most n_c points are not noise -- is the workgroup select's.
+struct SelState {
+  unsigned long long prefix;
+  int32_t need, nonnoise, done;
+  int32_t pad[59];
+  int32_t hist[256];
+};
+static_assert(sizeof(SelState) == 4 * kSelWords, "select state size");
+
+__global__ __launch_bounds__(256) void sel_init_kernel(SelState *st, const int32_t *nc) {
+  st->hist[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    st->prefix = 0;
+    st->need = nc[0];
+    st->nonnoise = 0;
+    st->done = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void sel_hist_kernel(int64_t n, const uint64_t *gkey, SelState *st,
+                                                        int32_t shift) {
+  __shared__ int32_t h[256];
+  __shared__ int32_t cnt;
+  if (st->done) return;
+  h[threadIdx.x] = 0;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  const uint64_t prefix = st->prefix;
+  const uint64_t hmask = shift == 56 ? 0ull : (~0ull << (shift + 8));
+  int c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const uint64_t k = gkey[i];
+    c += k != 0;
+    if ((k & hmask) == prefix) atomicAdd(&h[(k >> shift) & 0xff], 1);
+  }
+  if (shift == 56) {
+    c = wave_sum_i32(c);
+    if (lane_id() == 0) atomicAdd(&cnt, c);
+  }
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&st->hist[threadIdx.x], h[threadIdx.x]);
+  if (shift == 56 && threadIdx.x == 0 && cnt) atomicAdd(&st->nonnoise, cnt);
+}
+
+__global__ void sel_pick_kernel(SelState *st, int32_t shift) {
+  if (threadIdx.x != 0 || st->done) return;
+  if (shift == 56 && st->nonnoise <= st->need) {  // every non-noise point is a center
+    st->prefix = 1;
+    st->done = 1;
+    return;
+  }
+  int need = st->need;
+  int b = 255;
+  for (; b > 0; --b) {
+    const int hb = st->hist[b];
+    if (hb >= need) break;
+    need -= hb;
+  }
+  st->need = need;
+  st->prefix |= (unsigned long long)b << shift;
+  for (int t = 0; t < 256; ++t) st->hist[t] = 0;
+  if (shift == 0) st->done = 1;
+}
+
+__global__ __launch_bounds__(256) void sel_mark_kernel(int64_t n, const uint64_t *gkey, const SelState *st,
+                                                        uint8_t *is_center) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t thr = st->prefix, k = gkey[i];
+  is_center[i] = (k != 0 && k >= thr) ? 1 : 0;
+}
+
 __global__ void parent_kernel(int64_t n, const int32_t *dep, const uint8_t *is_center,
                               const uint64_t *gkey, const float *rho, float rho_min,
                               int32_t *labels) {
@@ -702,13 +779,26 @@ __global__ void jump_kernel(int64_t n, int32_t *labels, int32_t *flag) {
 hipError_t launch_cluster(int64_t n, const InstTable &inst, const float *rho, const int32_t *dep,
                           const float *delta, int32_t center_mode, float delta_min, float rho_min,
                           int32_t *labels, uint8_t *is_center, uint64_t *gkey, int32_t *flag,
-                          hipStream_t s) {
+                          uint32_t *sel, hipStream_t s) {
   const unsigned b = (unsigned)((n + 255) / 256);
   hipLaunchKernelGGL(gamma_kernel, dim3(b), dim3(256), 0, s, n, rho, delta, center_mode, delta_min,
                      rho_min, gkey, is_center);
-  if (center_mode == PECANN_CENTER_PRODUCT)
-    hipLaunchKernelGGL(select_kernel, dim3((unsigned)inst.count), dim3(1024), 0, s, inst, gkey,
-                       is_center);
+  if (center_mode == PECANN_CENTER_PRODUCT) {
+    if (inst.count == 1 && n >= kWideSelect) {
+      // one large instance: the select spread over the GPU (8 digit passes)
+      SelState *st = (SelState *)sel;
+      const unsigned hb = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
+      hipLaunchKernelGGL(sel_init_kernel, dim3(1), dim3(256), 0, s, st, inst.nc);
+      for (int shift = 56; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(sel_hist_kernel, dim3(hb), dim3(256), 0, s, n, gkey, st, shift);
+        hipLaunchKernelGGL(sel_pick_kernel, dim3(1), dim3(64), 0, s, st, shift);
+      }
+      hipLaunchKernelGGL(sel_mark_kernel, dim3(b), dim3(256), 0, s, n, gkey, st, is_center);
+    } else {
+      hipLaunchKernelGGL(select_kernel, dim3((unsigned)inst.count), dim3(1024), 0, s, inst, gkey,
+                         is_center);
+    }
+  }
   hipLaunchKernelGGL(parent_kernel, dim3(b), dim3(256), 0, s, n, dep, is_center, gkey, rho, rho_min,
                      labels);
   hipLaunchKernelGGL(jump_kernel, dim3(b), dim3(256), 0, s, n, labels, flag);

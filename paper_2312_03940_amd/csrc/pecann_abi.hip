@@ -1541,6 +1541,7 @@ static size_t cluster_ws_size(int64_t n, int ninst) {
   Carver c(nullptr);
   c.take<uint64_t>((size_t)n);
   c.take<int32_t>(64);
+  c.take<uint32_t>(kSelWords);
   InstDev d;
   carve_inst(c, ninst, &d);
   return c.size();
@@ -1576,6 +1577,7 @@ static pecann_status cluster_impl(int64_t n, const InstSpec &spec, const float *
   Carver c(ws);
   uint64_t *gkey = c.take<uint64_t>((size_t)n);
   int32_t *flag = c.take<int32_t>(64);
+  uint32_t *sel = c.take<uint32_t>(kSelWords);  // wide center-select state
   InstDev d;
   carve_inst(c, spec.count(), &d);
   hipStream_t s = (hipStream_t)stream;
@@ -1583,7 +1585,7 @@ static pecann_status cluster_impl(int64_t n, const InstSpec &spec, const float *
   HIP_TRY(upload_inst(spec, d, s));
   PROF(F_CLUSTER, s);
   HIP_TRY(launch_cluster(n, table_of(d, spec.count()), rho, dep, delta, center_mode, delta_min,
-                         rho_min, labels, is_center, gkey, flag, s));
+                         rho_min, labels, is_center, gkey, flag, sel, s));
   return PECANN_OK;
 }
 
@@ -1616,7 +1618,8 @@ extern "C" pecann_status pecann_cluster_batched(int64_t n, const pecann_instance
 
 // ---------------------------------------------------------------------------
 // pecann_cluster without a workspace argument.  Its scratch (the gamma keys,
-// the pointer-jumping flag, a one-instance table) lives in a file-scope
+// the pointer-jumping flag, the wide select's state, a one-instance table)
+// lives in a file-scope
 // device array: every GPU the library runs on holds its own copy until the
 // process ends.  The array's name is a host-side stand-in in host code, so the
 // device address is looked up once per device and only that address is used.
@@ -1666,6 +1669,7 @@ extern "C" pecann_status pecann_cluster_noalloc(int64_t n, const float *rho, con
   Carver c(base);
   uint64_t *gkey = c.take<uint64_t>((size_t)n);
   int32_t *flag = c.take<int32_t>(64);
+  uint32_t *sel = c.take<uint32_t>(kSelWords);  // wide center-select state
   InstDev d;
   carve_inst(c, 1, &d);
   if (c.size() > kScratchBytes) return fail(PECANN_EWORKSPACE, "scratch layout exceeds the array");
@@ -1682,7 +1686,7 @@ extern "C" pecann_status pecann_cluster_noalloc(int64_t n, const float *rho, con
   HIP_TRY(launch_put_i32(kk, 1, d.k, s));
   HIP_TRY(launch_put_i32(nc, 1, d.nc, s));
   HIP_TRY(launch_cluster(n, table_of(d, 1), rho, dep, delta, center_mode, delta_min, rho_min, labels,
-                         is_center, gkey, flag, s));
+                         is_center, gkey, flag, sel, s));
   return PECANN_OK;
 }
 
