@@ -161,9 +161,20 @@ struct SortedList {
 // id is reported as new, which only costs a repeated distance evaluation --
 // the sorted list drops the duplicate key, because a point's key is a
 // deterministic function of it.  The ids inserted by one call are distinct.
+//
+// Compact form (16-bit slots, half the LDS): ids < 2^kb are mapped by
+// h = id * c mod 2^kb (c odd: a bijection of [0, 2^kb)); the top bits of h
+// pick the home bucket and a slot keeps only the rest, rem = h mod 2^rb, with
+// the probe distance p in the next two bits.  (bucket - p, rem) gives h back,
+// hence the id: nothing is confused with anything else, so the set answers
+// exactly as the 32-bit one does (it may forget, never invent).  0xffff marks
+// an empty slot (rem | p << rb < 2^15 with rb <= 13).  A bucket (four slots,
+// 8 bytes) is read at once and claimed with a 64-bit compare-and-swap.
 struct IdHash {
   int32_t *slot;  // 16-byte aligned
   int bits;       // log2 of the slot count (>= 3)
+  int rb = -1;    // compact form: remainder bits (kb - bits + 2); -1: 32-bit slots
+  uint32_t kmask = 0;  // compact form: 2^kb - 1
   // buckets visited at most.  Eight instead of four cut the 1.28M x 1024 FP8
   // build search's fetched bytes by only 1.5 % (80.2 -> 79.0 GB per launch,
   // against 70.0 GB of algorithmic reads; most of the rest are the 64-byte
@@ -171,10 +182,45 @@ struct IdHash {
   static constexpr int kProbes = 4;
   __device__ __forceinline__ void clear() {
     const int H = 1 << bits;
+    if (rb >= 0) {
+      uint64_t *b64 = (uint64_t *)slot;
+      for (int s = lane_id(); s < (H >> 2); s += kWave) b64[s] = ~0ull;
+      return;
+    }
     for (int s = lane_id(); s < H; s += kWave) slot[s] = -1;
+  }
+  __device__ __forceinline__ bool insert16(int32_t id) {
+    const uint32_t mask = (1u << (bits - 2)) - 1u;
+    const uint32_t h = ((uint32_t)id * 2654435761u) & kmask;
+    uint32_t b = h >> rb;
+    const uint32_t rem = h & ((1u << rb) - 1u);
+    for (int probe = 0; probe < kProbes; ++probe) {
+      unsigned long long *bk = (unsigned long long *)slot + b;
+      const uint64_t tgt = rem | ((uint32_t)probe << rb);
+      uint64_t v = *bk;
+      for (;;) {
+        int empty = -1;
+        bool found = false;
+#pragma unroll
+        for (int e = 3; e >= 0; --e) {
+          const uint64_t x = (v >> (16 * e)) & 0xffffull;
+          found |= x == tgt;
+          if (x == 0xffffull) empty = e;
+        }
+        if (found) return false;
+        if (empty < 0) break;
+        const uint64_t nv = (v & ~(0xffffull << (16 * empty))) | (tgt << (16 * empty));
+        const uint64_t old = atomicCAS(bk, (unsigned long long)v, (unsigned long long)nv);
+        if (old == v) return true;
+        v = old;  // another lane took a slot of this bucket: look again
+      }
+      b = (b + 1) & mask;
+    }
+    return true;
   }
   // true if id was not in the set (and is now, if there was room)
   __device__ __forceinline__ bool insert(int32_t id) {
+    if (rb >= 0) return insert16(id);
     const int bb = bits - 2;
     const uint32_t mask = (1u << bb) - 1u;
     uint32_t b = ((uint32_t)id * 2654435761u) >> (32 - bb);

@@ -78,6 +78,7 @@ struct SearchParams {
   InstTable inst;             // instance of each query (k per instance, round limits)
   int32_t L;                  // beam width
   int32_t hbits;              // log2 of visited-hash slots
+  int32_t hid_bits;           // compact (16-bit) visited hash over ids < 2^hid_bits; 0: 32-bit slots
   int32_t mode;
   int32_t rerank;             // entries re-scored in float32 (0: none)
   int32_t mfma;               // BF16 / FP8 rows: score candidates on the matrix cores
@@ -110,7 +111,10 @@ struct SearchParams {
   unsigned long long *counters;
 };
 
-size_t search_lds_bytes(int L, int hbits);
+size_t search_lds_bytes(int L, int hbits, int hid_bits);
+// id bits of the compact visited hash for n points and 2^hbits slots, or 0
+// when the ids need more than 13 bits beside the home bucket (32-bit slots)
+int compact_hash_bits(int64_t n, int hbits);
 hipError_t launch_search(int32_t dt, int S, const SearchParams &p, int grid, hipStream_t s);
 // the matrix-core scoring variant (BF16 / FP8 rows); launch_search dispatches to it
 hipError_t launch_search_mfma(int32_t dt, int S, const SearchParams &p, int grid, hipStream_t s);

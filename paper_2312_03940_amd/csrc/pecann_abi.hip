@@ -726,6 +726,7 @@ static pecann_status build_impl(const pecann_dataset *ds, const pecann_build_par
   sp.items = w.items;
   sp.L = bp->L;
   sp.hbits = hash_bits_for(bp->L, L.xs_stride, true);
+  sp.hid_bits = compact_hash_bits(ds->n, sp.hbits);
   sp.mfma = use_mfma(ds->search_dtype, L.xs_stride);
   sp.mode = MODE_BUILD;
   sp.vis = w.vis;
@@ -1283,6 +1284,7 @@ static pecann_status knn_impl(const pecann_dataset *ds, const InstSpec &spec, co
   sp.inst = itab;
   sp.L = L_search;
   sp.hbits = hash_bits_for(L_search, L.xs_stride, false);
+  sp.hid_bits = compact_hash_bits(ds->n, sp.hbits);
   sp.mfma = use_mfma(ds->search_dtype, L.xs_stride);
   sp.mode = MODE_KNN;
   sp.rerank = rerank;
@@ -1455,6 +1457,7 @@ static pecann_status dep_impl(const pecann_dataset *ds, const InstSpec &spec, co
       sp.inst = itab;
       sp.L = (int32_t)std::max<int64_t>(kd, L_search);
       sp.hbits = hash_bits_for(sp.L, L.xs_stride, false);
+      sp.hid_bits = compact_hash_bits(ds->n, sp.hbits);
       sp.mfma = use_mfma(ds->search_dtype, L.xs_stride);
       sp.mode = MODE_DEP;
       sp.rerank = (int32_t)kd;

@@ -1,12 +1,21 @@
 // K2 greedy beam search: the vector-unit scoring variant of every row format,
 // and the dispatch between it and the matrix-core variant (search_mfma.hip).
+#include <algorithm>
+
 #include "search_impl.hpp"
 
 namespace pecann {
 
-size_t search_lds_bytes(int L, int hbits) {
+size_t search_lds_bytes(int L, int hbits, int hid_bits) {
   const size_t Lp = (size_t)((L + 15) & ~15);
-  return 8 * (2 * (size_t)L + 64) + 4 * 64 + 2 * Lp + 4 * ((size_t)1 << hbits);
+  return 8 * (2 * (size_t)L + 64) + 4 * 64 + 2 * Lp + (hid_bits ? 2 : 4) * ((size_t)1 << hbits);
+}
+
+int compact_hash_bits(int64_t n, int hbits) {
+  int kb = 1;
+  while (((int64_t)1 << kb) < n) ++kb;
+  kb = std::max(kb, hbits - 2);
+  return kb - (hbits - 2) <= 13 ? kb : 0;
 }
 
 template <int DT, int S>

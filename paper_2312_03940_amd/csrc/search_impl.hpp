@@ -34,7 +34,7 @@ struct Lds {
   unsigned long long n_exp, n_ids, n_rows;
 };
 
-__device__ __forceinline__ Lds carve(uint8_t *smem, int L, int hbits) {
+__device__ __forceinline__ Lds carve(uint8_t *smem, int L, int hbits, int hid_bits) {
   Lds s;
   uint64_t *p = (uint64_t *)smem;
   s.beam.a = p;
@@ -47,7 +47,11 @@ __device__ __forceinline__ Lds carve(uint8_t *smem, int L, int hbits) {
   s.beam.fb = f + Lp;
   s.hash.slot = (int32_t *)(f + 2 * Lp);
   s.hash.bits = hbits;
-  s.qp = (uint8_t *)(s.hash.slot + (1 << hbits));
+  if (hid_bits) {
+    s.hash.rb = hid_bits - (hbits - 2);
+    s.hash.kmask = hid_bits >= 32 ? ~0u : (1u << hid_bits) - 1u;
+  }
+  s.qp = (uint8_t *)s.hash.slot + (hid_bits ? 2 : 4) * (1 << hbits);
   s.beam.cap = L;
   s.beam.reset();
   s.n_exp = s.n_ids = s.n_rows = 0;
@@ -152,7 +156,7 @@ __device__ __forceinline__ void rerank_beam(const SearchParams &p, Lds &s, int32
 template <int DT, int S, int MODE, bool MF>
 __device__ __forceinline__ void search_body(const SearchParams &p) {
   extern __shared__ __align__(16) uint8_t smem[];
-  Lds s = carve(smem, p.L, p.hbits);
+  Lds s = carve(smem, p.L, p.hbits, p.hid_bits);
   const int l = lane_id();
   const int count = p.item_count ? *p.item_count : p.nitems;
   constexpr bool kNeedRerank = (DT == PECANN_BF16 || DT == PECANN_FP8E4M3 || DT == PECANN_MXFP6);
@@ -309,8 +313,13 @@ __device__ __forceinline__ void search_body(const SearchParams &p) {
   }
 }
 
+// Three waves per SIMD for the narrow row formats (at most 168 VGPRs, no
+// spills): with the compact visited hash their LDS holds about eleven waves per
+// CU, and the compiler's own choice (170 VGPRs) would allow only two per SIMD
+// (1.28M x 1024 FP8 build search 1,621 -> 1,480 ms per step).  Float32 rows
+// keep the compiler's choice (about 250 VGPRs for 784-d rows).
 template <int DT, int S, int MODE, bool MF>
-__global__ __launch_bounds__(64) void search_kernel(SearchParams p) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == PECANN_F32 ? 1 : 3))) void search_kernel(SearchParams p) {
   search_body<DT, S, MODE, MF>(p);
 }
 // The kNN search with a register budget for three waves per SIMD (168 VGPRs):
@@ -333,7 +342,7 @@ static hipError_t launch_search_t(const SearchParams &p, int grid, hipStream_t s
   if constexpr (S > max_shape(DT)) {
     return hipErrorInvalidValue;
   } else {
-    const size_t lds = search_lds_bytes(p.L, p.hbits) + scorer_lds_bytes<DT, S, MF>();
+    const size_t lds = search_lds_bytes(p.L, p.hbits, p.hid_bits) + scorer_lds_bytes<DT, S, MF>();
     switch (p.mode) {
       case MODE_KNN:
         hipLaunchKernelGGL((search_knn_kernel<DT, S, MF>), dim3(grid), dim3(64), lds, st, p);
