@@ -316,10 +316,19 @@ __device__ __forceinline__ void search_body(const SearchParams &p) {
 // Three waves per SIMD for the narrow row formats (at most 168 VGPRs, no
 // spills): with the compact visited hash their LDS holds about eleven waves per
 // CU, and the compiler's own choice (170 VGPRs) would allow only two per SIMD
-// (1.28M x 1024 FP8 build search 1,621 -> 1,480 ms per step).  Float32 rows
-// keep the compiler's choice (about 250 VGPRs for 784-d rows).
+// (1.28M x 1024 FP8 build search 1,621 -> 1,480 ms per step).  Build searches
+// scored on the matrix cores over short rows (at most 16 lanes per row) have
+// LDS for about twenty waves per CU and ask for five per SIMD (96 VGPRs, a few
+// bytes spilled; 1M x 128 BF16 build search 356 -> 344 ms per step).  Float32
+// rows keep the compiler's choice (about 250 VGPRs for 784-d rows).
 template <int DT, int S, int MODE, bool MF>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(DT == PECANN_F32 ? 1 : 3))) void search_kernel(SearchParams p) {
+constexpr int search_waves_per_simd() {
+  if (DT == PECANN_F32) return 1;
+  if (MF && MODE == MODE_BUILD && S <= 16) return 5;
+  return 3;
+}
+template <int DT, int S, int MODE, bool MF>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(search_waves_per_simd<DT, S, MODE, MF>()))) void search_kernel(SearchParams p) {
   search_body<DT, S, MODE, MF>(p);
 }
 // The kNN search with a register budget for three waves per SIMD (168 VGPRs):
