@@ -1,8 +1,8 @@
 // Exact kNN on the matrix cores (the BruteForce index of Sec. 4.1 at scale).
 //
 // scan:   a workgroup of 4 wavefronts takes 64 queries (16 per wavefront) and
-//         streams every point past them in blocks of 64 candidates, each block
-//         in rounds of kSPB 64-byte steps.  A round's candidate chunks are
+//         streams one of kParts consecutive parts of the points past them in
+//         blocks of 64 candidates, each block in rounds of kSPB 64-byte steps.  A round's candidate chunks are
 //         staged through a double-buffered LDS tile; the loads of the next
 //         round (candidate chunks, the wavefront's query chunks, the block's
 //         norms) are issued before the products of the current one, so the
@@ -12,7 +12,7 @@
 //         exact) and turns them into distance measures with the stored row
 //         norms.  Every lane keeps, for each of its 4 query rows, the kKQ
 //         smallest (measure, index) pairs of its column stream in registers.
-// rerank: one wavefront per query re-scores the 16 kKQ kept candidates by
+// rerank: one wavefront per query re-scores the kParts x 16 x kKQ kept candidates by
 //         direct differences -- the same float32 arithmetic as the brute-force
 //         kernel -- and keeps the k best.  A candidate the scan dropped had a
 //         matrix-core measure >= thr (the smallest value any queue dropped), so
@@ -33,15 +33,22 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kQT = 64;   // queries per workgroup
 constexpr int kCT = 64;   // candidates per block
-// queue length per lane and query row: 8 for float32 rows, 5 for uint8 rows,
-// whose measures are exact integers (a dropped threshold far below the 16 x 8
-// kept candidates cannot fail the exactness check by rounding); the inserts of
-// a wave are divergent, so a shorter queue is also a cheaper one.  Four per
-// lane sent ~0.3 % of the 70,000-point uint8 queries to the brute force (a
-// lane holding five of a query's ten nearest; 2.0 ms of fallback per step), five
-// cost 0.5 ms more scan and cut the fallback to its launch floor
-template <int SDT>
-constexpr int kq_of() { return SDT == PECANN_U8 ? 5 : kExactCand / 16; }
+// The points are scanned in kParts parts by separate workgroups, each keeping
+// its own queues: twice the workgroups of one full scan, so that the last
+// wave of workgroups fills the GPU better (70,000 points: 2,188 workgroups
+// over 768 resident at three waves per SIMD, against 1,094), and half the
+// queue length per lane for the same kExactCand kept candidates per query.
+// Measured on 70,000 x 784 rows: uint8 scan 20.3 -> 17.9 ms, float32 94.7 ->
+// 82.6 ms (plus 1.4 ms of brute force for the queries whose shorter queues
+// fail the exactness check); four waves per SIMD (1,024 resident, a short
+// last wave) made the uint8 scan slower, 24.7 ms.
+constexpr int kParts = kExactParts;
+// queue length per lane and query row (a lane's stream is one sixteenth of a
+// part); the inserts of a wave are divergent, so a shorter queue is also a
+// cheaper one.  With one part, four per lane sent ~0.3 % of the 70,000-point
+// uint8 queries to the brute force (a lane holding five of a query's ten
+// nearest); two parts give each query 32 streams of four.
+constexpr int kKQ = kExactCand / (16 * kParts);
 constexpr int kSPB = 4;   // 64-byte steps per round
 constexpr int kCand = kExactCand;
 
@@ -101,13 +108,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void e
                                                          int32_t *cand, uint64_t *thr) {
   __shared__ uint4 bs[2][kCT][4 * kSPB + 1];
   __shared__ uint32_t bn[2][kCT];
-  constexpr int kKQ = kq_of<SDT>();
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, c16 = l & 15;
   const int q0 = blockIdx.x * kQT + 16 * w;  // this wavefront's first query
   const int qa = q0 + c16;                    // the query row this lane feeds as A
   const int steps = (sr.nch + 3) >> 2;
   const int rpb = (steps + kSPB - 1) / kSPB;  // rounds per block
-  const int total = ((n + kCT - 1) / kCT) * rpb;
+  // this workgroup's part: candidate blocks [b0, b1) (possibly none)
+  const int part = blockIdx.y;
+  const int nblk = (n + kCT - 1) / kCT;
+  const int b0 = (int)((int64_t)nblk * part / kParts), b1 = (int)((int64_t)nblk * (part + 1) / kParts);
+  const int total = (b1 - b0) * rpb;
 
   // the lane's queue of row r: keys (measure bits << 32 | candidate), sorted;
   // one 64-bit comparison orders (measure, index) pairs
@@ -129,9 +139,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void e
 #pragma unroll
   for (int t = 0; t < 4; ++t) { accf[t] = v4f{0.f, 0.f, 0.f, 0.f}; acci[t] = v4i{0, 0, 0, 0}; }
   Round<SDT> nxt;
-  nxt.load(sr, n, tid, g, qa, 0, 0, true);
+  nxt.load(sr, n, tid, g, qa, b0 * kCT, 0, true);
   for (int rd = 0; rd < total; ++rd) {
-    const int blk = rd / rpb, rr = rd - blk * rpb, buf = rd & 1;
+    const int blk = b0 + rd / rpb, rr = rd % rpb, buf = rd & 1;
     // stage this round (its loads were issued during the previous round)
 #pragma unroll
     for (int u = 0; u < kSPB; ++u) bs[buf][tid >> 2][4 * u + (tid & 3)] = nxt.b[u];
@@ -143,7 +153,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void e
     // rd - 2, and every wavefront has passed this barrier's predecessor since
     __syncthreads();
     if (rd + 1 < total) {
-      const int nb = (rd + 1) / rpb, nr = rd + 1 - nb * rpb;
+      const int nb = b0 + (rd + 1) / rpb, nr = (rd + 1) % rpb;
       nxt.load(sr, n, tid, g, qa, nb * kCT, nr * kSPB, nr == 0);
     }
 #pragma unroll
@@ -205,8 +215,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void e
     for (int t = 0; t < 4; ++t) { accf[t] = v4f{0.f, 0.f, 0.f, 0.f}; acci[t] = v4i{0, 0, 0, 0}; }
   }
 
-  // queues out; thr = smallest measure any of the 16 lanes of a row dropped
-  // (a lane that kept all of a query's best candidates dropped none of them)
+  // queues out (this part's slice of the query's candidates); thr = smallest
+  // key any of the 16 lanes of a row dropped (a lane that kept all of a
+  // query's best candidates dropped none of them), one per part
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int q = q0 + 4 * g + r;
@@ -214,10 +225,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void e
 #pragma unroll
     for (int m = 8; m >= 1; m >>= 1) last = min(last, shfl_xor_u64(last, m));
     if (q < n) {
-      int32_t *o = cand + (int64_t)q * kCand + c16 * kKQ;
+      int32_t *o = cand + (int64_t)q * kCand + (part * 16 + c16) * kKQ;
 #pragma unroll
       for (int s = 0; s < kKQ; ++s) o[s] = key_id(qk[r][s]);  // an empty slot gives -1
-      if (c16 == 0) thr[q] = last;
+      if (c16 == 0) thr[(int64_t)q * kParts + part] = last;
     }
   }
 }
@@ -263,10 +274,10 @@ __global__ __launch_bounds__(64) void exact_rerank_kernel(ExactMfmaParams p, flo
     top.reset();
     wave_lds_sync();
     const int32_t *c = p.cand + (int64_t)q * kCand;
-    constexpr int kKept = 16 * kq_of<DT == PECANN_U8 ? PECANN_U8 : PECANN_F32>();
-    for (int base = 0; base < kKept; base += kWave) {
-      PECANN_CHECK(base + l >= kKept || (c[base + l] >= -1 && c[base + l] < p.n), CK_ITEM);  // (-1: none)
-      score_keys(eng, p.rows, kWave, [&](int i) { return base + i < kKept ? c[base + i] : -1; }, kb);
+    static_assert(kCand % kWave == 0, "candidates are re-scored 64 at a time");
+    for (int base = 0; base < kCand; base += kWave) {
+      PECANN_CHECK(c[base + l] >= -1 && c[base + l] < p.n, CK_ITEM);  // (-1: none)
+      score_keys(eng, p.rows, kWave, [&](int i) { return c[base + i]; }, kb);
       wave_lds_sync();
       const uint64_t key = kb[l];
       wave_lds_sync();
@@ -279,7 +290,8 @@ __global__ __launch_bounds__(64) void exact_rerank_kernel(ExactMfmaParams p, flo
       if (u8rows) nqv = 0.f;
       else nqv = p.rows.xr ? p.rows.sqn_r[q] : __uint_as_float(p.rows.sqn[q]);
       const float e = u8rows ? ce : ce * (nqv + *p.nmax);
-      const uint64_t tk = p.thr[q];
+      uint64_t tk = p.thr[(int64_t)q * kParts];
+      for (int t = 1; t < kParts; ++t) tk = min(tk, p.thr[(int64_t)q * kParts + t]);
       if (tk == kNoKey) ok = true;  // no queue dropped anything
       else if (u8rows) ok = top.a[k - 1] < tk;
       else ok = key_measure(top.a[k - 1]) < key_measure(tk) - e;
@@ -341,11 +353,11 @@ hipError_t launch_exact_mfma(int32_t dt, int S, const ExactMfmaParams &p, hipStr
   }
   const unsigned blocks = (unsigned)((p.n + kQT - 1) / kQT);
   if (u8) {
-    hipLaunchKernelGGL(exact_scan_kernel<PECANN_U8>, dim3(blocks), dim3(256), 0, st, sr, p.n, r.metric,
-                       p.cand, p.thr);
+    hipLaunchKernelGGL(exact_scan_kernel<PECANN_U8>, dim3(blocks, kParts), dim3(256), 0, st, sr, p.n,
+                       r.metric, p.cand, p.thr);
   } else {
     hipLaunchKernelGGL(norm_max_kernel, dim3(1), dim3(1024), 0, st, sr.norms, p.n, p.nmax);
-    hipLaunchKernelGGL(exact_scan_kernel<PECANN_F32>, dim3(blocks), dim3(256), 0, st, sr, p.n,
+    hipLaunchKernelGGL(exact_scan_kernel<PECANN_F32>, dim3(blocks, kParts), dim3(256), 0, st, sr, p.n,
                        r.metric, p.cand, p.thr);
   }
   hipError_t e = hipGetLastError();

@@ -288,6 +288,7 @@ hipError_t launch_prepare(const void *x, int32_t x_dtype, int64_t x_stride, int6
 // exact (direct-difference) re-score with a rounding-bound check.
 // candidates the exact matrix-core scan keeps per query (16 lanes x 8)
 constexpr int kExactCand = 128;
+constexpr int kExactParts = 2;  // parts of the points the exact scan's workgroups take
 
 struct ExactMfmaParams {
   RowsDesc rows;              // one instance's rows (row 0 = global index base)
@@ -296,7 +297,7 @@ struct ExactMfmaParams {
   int32_t kstride;            // row stride of knn_idx / knn_dist
   int32_t base;               // global index of row 0
   int32_t *cand;               // [n][kExactCand] candidate ids of the scan
-  uint64_t *thr;               // [n] smallest (measure, index) key a scan queue dropped (~0: none)
+  uint64_t *thr;               // [n][kExactParts] smallest (measure, index) key a scan queue of each part dropped (~0: none)
   float *nmax;                 // [1] largest row norm (device)
   int32_t *head;
   int32_t *knn_idx;

@@ -1097,7 +1097,7 @@ static constexpr int64_t kExactMfmaMin = 4096;
 
 struct KnnWs {
   int32_t *ctr, *fb, *cand;
-  uint64_t *thr;  // exact mode: smallest key each query's scan queues dropped
+  uint64_t *thr;  // exact mode: smallest key each query's scan queues dropped, per part
   float *nmax;
   uint64_t *part;  // exact mode: chunk-local best keys of the split brute force
   InstDev inst;
@@ -1120,7 +1120,7 @@ static void carve_knn(Carver &c, int64_t n, bool exact, bool exact_mfma, int nin
   w->fb = c.take<int32_t>((size_t)n);
   w->nmax = c.take<float>(64);
   w->cand = exact_mfma ? c.take<int32_t>((size_t)n * kExactCand) : nullptr;
-  w->thr = exact_mfma ? c.take<uint64_t>((size_t)n) : nullptr;
+  w->thr = exact_mfma ? c.take<uint64_t>((size_t)n * kExactParts) : nullptr;
   w->part = exact ? c.take<uint64_t>((size_t)kSplitCap * split_chunks(max_size) * k) : nullptr;
   carve_inst(c, ninst, &w->inst);
 }
@@ -1232,7 +1232,7 @@ static pecann_status knn_impl(const pecann_dataset *ds, const InstSpec &spec, co
       ep.kstride = k;
       ep.base = (int32_t)lo;
       ep.cand = w.cand + lo * kExactCand;
-      ep.thr = w.thr + lo;
+      ep.thr = w.thr + lo * kExactParts;
       ep.nmax = w.nmax;
       ep.head = ctr + 0;
       ep.knn_idx = knn_idx + lo * k;
