@@ -772,8 +772,15 @@ def main():
         if not args.no_graph and args.mode == "anns":
             log("graph replay variant")
             vsteps = args.variant_steps or (3 if args.config == 2 else 1)
-            variants[f"{search}_anns_graph_replay"] = measure_graph(
-                x, wl, search, args, perm, vsteps, inst, Ls=rec.get("tuning", {}).get("L_search"))
+            # the headline's step, so the headline's launch settings
+            from paper_2312_03940_amd import pecann
+            knobs = ("hash_bits_build", "hash_bits_search", "grid_per_cu", "scorer", "prune_steps")
+            pecann.set_tuning(**{kk: rec["tuning"][kk] for kk in knobs if kk in rec.get("tuning", {})})
+            try:
+                variants[f"{search}_anns_graph_replay"] = measure_graph(
+                    x, wl, search, args, perm, vsteps, inst, Ls=rec.get("tuning", {}).get("L_search"))
+            finally:
+                pecann.reset_tuning()
             torch.cuda.empty_cache()
         out["variants"] = variants
     if not args.no_cpu_baseline and inst is None:
