@@ -267,7 +267,7 @@ pecann_status pecann_build_graph_nndescent(const pecann_dataset *ds, const pecan
  * Without a graph (adj == NULL): exact brute force over all other points (the
  * paper's BruteForce index); distances always from float32 (or exact U8) rows.
  * From n >= 4096 on, the exact search runs as a matrix-core scan (float32 dot
- * products, or exact int8 ones on U8 rows) that keeps 256 candidates per
+ * products, or exact int8 ones on U8 rows) that keeps 128 candidates per
  * point, followed by a direct-difference re-score; a point whose k-th distance
  * is not separated from the dropped candidates by the scan's rounding bound is
  * searched again by the direct-difference kernel, so the result is the same.
