@@ -284,19 +284,30 @@ hipError_t launch_identity_perm(int32_t *p, int64_t n, hipStream_t s) {
 // into an XOR that is stored only if it equals a value the caller picks, so
 // the loads are kept and nothing but the reads reaches memory.
 // ---------------------------------------------------------------------------
+// Read of a buffer, eight 16-byte loads in flight per thread, grid-strided.
+// A single pass (a buffer far beyond the caches) uses non-temporal loads, the
+// best of the variants measured on MI355X for a 4 GiB buffer (6.5 TB/s, against
+// 5.6 TB/s with four plain loads per thread); repeated passes over a small
+// buffer keep plain loads, so that the data stays in the caches.
+template <bool NT>
 __global__ __launch_bounds__(256) void read_probe_kernel(const uint4 *p, int64_t n16, int32_t passes,
                                                          uint32_t key, uint32_t *sink) {
+  typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+  constexpr int U = 8;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const u4v *q = (const u4v *)p;
   uint32_t acc = 0;
   for (int32_t r = 0; r < passes; ++r) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n16; i += 4 * stride) {
-      const uint4 a = p[i], b = p[i + stride], c = p[i + 2 * stride], d = p[i + 3 * stride];
-      acc ^= (a.x ^ a.y ^ a.z ^ a.w) ^ (b.x ^ b.y ^ b.z ^ b.w) ^ (c.x ^ c.y ^ c.z ^ c.w) ^
-             (d.x ^ d.y ^ d.z ^ d.w);
+    for (; i + (U - 1) * stride < n16; i += U * stride) {
+      u4v v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = NT ? __builtin_nontemporal_load(q + i + u * stride) : q[i + u * stride];
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
     }
     for (; i < n16; i += stride) {
-      const uint4 a = p[i];
+      const u4v a = q[i];
       acc ^= a.x ^ a.y ^ a.z ^ a.w;
     }
     acc = acc * 2654435761u + (uint32_t)r;
@@ -305,8 +316,12 @@ __global__ __launch_bounds__(256) void read_probe_kernel(const uint4 *p, int64_t
 }
 hipError_t launch_read_probe(const void *buf, int64_t bytes, int32_t passes, uint32_t key,
                              uint32_t *sink, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(read_probe_kernel, dim3(grid), dim3(256), 0, s, (const uint4 *)buf, bytes / 16,
-                     passes, key, sink);
+  if (passes == 1)
+    hipLaunchKernelGGL(read_probe_kernel<true>, dim3(grid), dim3(256), 0, s, (const uint4 *)buf, bytes / 16,
+                       passes, key, sink);
+  else
+    hipLaunchKernelGGL(read_probe_kernel<false>, dim3(grid), dim3(256), 0, s, (const uint4 *)buf, bytes / 16,
+                       passes, key, sink);
   return hipGetLastError();
 }
 

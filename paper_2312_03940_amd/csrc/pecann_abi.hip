@@ -1782,7 +1782,7 @@ extern "C" pecann_status pecann_read_probe(const void *buf, size_t bytes, int32_
   if (bytes == 0 || bytes % 16 != 0 || !aligned(buf, 16))
     return fail(PECANN_EINVAL, "bytes must be a positive multiple of 16 and buf 16-byte aligned");
   if (passes < 1) return fail(PECANN_EINVAL, "passes must be >= 1");
-  HIP_TRY(launch_read_probe(buf, (int64_t)bytes, passes, key, sink, cu_count() * 8,
+  HIP_TRY(launch_read_probe(buf, (int64_t)bytes, passes, key, sink, cu_count() * 16,
                             (hipStream_t)stream));
   return PECANN_OK;
 }
