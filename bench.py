@@ -31,7 +31,7 @@ settings, which change speed only, and the kNN beam width.
 kernel's own work counters divided by its average launch time, both measured
 over the timed steps with HIP events on the launch stream, against the 8 TB/s
 HBM peak and beside read peaks measured on the box (a 4 GiB buffer read once;
-a 64 MiB buffer the Infinity Cache holds).  `traffic` is the bytes per launch
+a 64 MiB buffer the Infinity Cache holds, read 48 times).  `traffic` is the bytes per launch
 from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs in profiles/ (null when the
 kernel sources changed since); FETCH_SIZE counts L2 fills, which the Infinity
 Cache may serve.  `cpu_baseline` times the CPU oracle's exact DPC on a bounded
@@ -171,11 +171,12 @@ def cpu_baseline(X, metric, k, rank, rank_source, sample_size=0, target_s=15.0):
 def measured_peaks():
     """Achievable read bandwidth on this GPU, from the library's read probe timed
     with HIP events: HBM (a 4 GiB buffer, far beyond the 256 MB Infinity Cache,
-    read once) and cache-resident (64 MiB read 64 times)."""
+    read once) and Infinity-Cache-resident (64 MiB, twice the L2 of all eight
+    XCDs together, read 48 times, each pass from other XCDs than the last)."""
     import torch
     from paper_2312_03940_amd import pecann
     out = {}
-    for name, mib, passes in (("hbm_read", 4096, 1), ("cache_resident_read", 64, 64)):
+    for name, mib, passes in (("hbm_read", 4096, 1), ("cache_resident_read", 64, 48)):
         buf = torch.ones((mib << 20) // 4, dtype=torch.float32, device="cuda")
         sink = torch.zeros(1, dtype=torch.int32, device="cuda")
         pecann.read_probe(buf, passes, sink)  # warm-up

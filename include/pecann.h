@@ -540,8 +540,10 @@ pecann_status pecann_get_tuning(pecann_tuning *t);
 /* ---------------------------------------------------------------------------
  * Measurement aid, not a step of the method: reads `bytes` of device memory at
  * `buf` `passes` times with 16-byte vector loads spread over every compute
- * unit (eight in flight per thread; non-temporal loads when passes = 1),
- * asynchronously on `stream`, so that a caller timing the call gets the
+ * unit (eight in flight per thread; non-temporal loads when passes = 1; pass
+ * r gives each block the slice of block + r, so that repeated passes are not
+ * served by the L2 that read the data last), asynchronously on `stream`, so
+ * that a caller timing the call gets the
  * achievable read bandwidth -- of HBM for a buffer much larger than the 256 MB
  * Infinity Cache read once, of the cache for a smaller one read many times.
  * Roofline figures put the search kernels' algorithmic bandwidth beside it.

@@ -298,17 +298,21 @@ __global__ __launch_bounds__(256) void read_probe_kernel(const uint4 *p, int64_t
   const u4v *q = (const u4v *)p;
   uint32_t acc = 0;
   for (int32_t r = 0; r < passes; ++r) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + (U - 1) * stride < n16; i += U * stride) {
+    // pass r: block b reads the slice block b + r read in pass 0, so that on
+    // repeated passes no XCD re-reads data its own L2 took in the pass before
+    // (blocks are dealt to the XCDs in turn): the repeats measure the
+    // Infinity Cache, not the L2.  Every trip keeps U loads in flight, the
+    // last one with the entries past the end masked off.
+    const int64_t b = ((int64_t)blockIdx.x + r) % gridDim.x;
+    for (int64_t i = b * blockDim.x + threadIdx.x; i < n16; i += U * stride) {
       u4v v[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = NT ? __builtin_nontemporal_load(q + i + u * stride) : q[i + u * stride];
+      for (int u = 0; u < U; ++u) {
+        const int64_t j = i + u * stride;
+        v[u] = j < n16 ? (NT ? __builtin_nontemporal_load(q + j) : q[j]) : u4v{0u, 0u, 0u, 0u};
+      }
 #pragma unroll
       for (int u = 0; u < U; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
-    }
-    for (; i < n16; i += stride) {
-      const u4v a = q[i];
-      acc ^= a.x ^ a.y ^ a.z ^ a.w;
     }
     acc = acc * 2654435761u + (uint32_t)r;
   }
